@@ -1,0 +1,466 @@
+/*
+ * CPU oracle for seed-grid Kadir-Brady salient-region search in 3D.
+ *
+ * TEST INFRASTRUCTURE ONLY: a plain, slow, single-threaded restatement of the
+ * method, used to check the GPU library.  Every window histogram is built
+ * directly with nested loops over the clipped window; no shells, prefix sums or
+ * incremental updates.  Decision arithmetic is IEEE double in the fixed order
+ * stated below, compiled without contraction (-ffp-contract=off).
+ *
+ * Readings of the paper that this file implements (the paper leaves them open):
+ *  - bins: beta(v) = floor((v - vmin) * B / (vmax - vmin + 1)) over the volume's
+ *    own range (Eq. 4 uses beta without defining it);
+ *  - entropy uses the natural log (Eq. 1-2);
+ *  - windows are clipped to the volume and N is the in-volume voxel count;
+ *  - quadrant method in 3D uses the 8 octant cubes {P + sigma_j*u : u in [0,k]^3}
+ *    (Sec. 2.2, Alg. 1), displacement d_j = k*_j * sigma_j (the 3D analogue of
+ *    sqrt(2)*k_opt along the quadrant diagonal);
+ *  - the mean-shift kernel is flat over the cube P + [-s,s]^3, so p_b = c_b/N and
+ *    -K' is constant and cancels in Eq. 6;
+ *  - moves are rounded half away from zero to whole voxels and accepted only if
+ *    the objective strictly increases (best-so-far idea of Alg. 2), otherwise the
+ *    search stops at the last accepted position;
+ *  - saliency (Sec. 1, Sec. 2.1): entropy peaks over scale, pdf change
+ *    W(s) = s^2/(2s-1) * sum_b |p_s(b) - p_{s-1}(b)|, Y = H * W.
+ *
+ * Fixed summation order shared by definition (not by code) with the GPU path:
+ * every sum over bins is a pairwise halving tree over Bp terms, where Bp is the
+ * smallest power of two >= max(B, 64), absent bins contributing 0; the sum over
+ * the 8 octants is the halving tree ((e0+e1)+(e2+e3))+((e4+e5)+(e6+e7)).
+ */
+#include "ks_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- helpers */
+
+static int64_t vidx(const int32_t dims[3], int32_t x, int32_t y, int32_t z) {
+    return (int64_t)x + (int64_t)dims[0] * ((int64_t)y + (int64_t)dims[1] * (int64_t)z);
+}
+
+static int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static int32_t read_voxel(const void* vol, int32_t dtype, int64_t i) {
+    if (dtype == KSO_U8) return ((const uint8_t*)vol)[i];
+    if (dtype == KSO_U16) return ((const uint16_t*)vol)[i];
+    return ((const int16_t*)vol)[i];
+}
+
+static int32_t padded_terms(int32_t bins) {
+    int32_t n = 64;
+    while (n < bins) n *= 2;
+    return n;
+}
+
+/* Pairwise halving sum of v[lo .. lo+len), entries at index >= n count as 0. */
+static double pairwise(const double* v, int32_t n, int32_t lo, int32_t len) {
+    if (len == 1) return lo < n ? v[lo] : 0.0;
+    return pairwise(v, n, lo, len / 2) + pairwise(v, n, lo + len / 2, len / 2);
+}
+
+static double sum_bins(const double* v, int32_t bins) { return pairwise(v, bins, 0, padded_terms(bins)); }
+
+static double sum_octants(const double* e) { return ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7])); }
+
+/* ---------------------------------------------------------------- binning */
+
+int kso_bin_volume(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, uint8_t* out) {
+    int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+    int32_t vmin = read_voxel(vol, dtype, 0), vmax = vmin;
+    for (int64_t i = 1; i < n; ++i) {
+        int32_t v = read_voxel(vol, dtype, i);
+        if (v < vmin) vmin = v;
+        if (v > vmax) vmax = v;
+    }
+    int64_t width = (int64_t)vmax - vmin + 1;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = read_voxel(vol, dtype, i);
+        out[i] = (uint8_t)(((v - vmin) * bins) / width);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------- entropy */
+
+/* H64 = (N ln N - sum_b c_b ln c_b) / N, the decision-precision Shannon entropy
+ * of p_b = c_b / N (Eq. 1 with the natural log); a window whose voxels all fall in
+ * one bin gives exactly 0. */
+static double entropy64_n(const uint32_t* c, int32_t bins, int64_t N) {
+    if (N == 0) return 0.0;
+    double* t = (double*)malloc(sizeof(double) * (size_t)bins);
+    for (int32_t b = 0; b < bins; ++b) t[b] = c[b] > 0 ? (double)c[b] * log((double)c[b]) : 0.0;
+    double S = sum_bins(t, bins);
+    free(t);
+    return ((double)N * log((double)N) - S) / (double)N;
+}
+
+/* Accurate entropy -sum p ln p; for p > 1/2, ln p = log1p(-(N-c)/N). */
+static double entropy_ref_n(const uint32_t* c, int32_t bins, int64_t N) {
+    if (N == 0) return 0.0;
+    double h = 0.0;
+    for (int32_t b = 0; b < bins; ++b) {
+        if (c[b] == 0) continue;
+        double p = (double)c[b] / (double)N;
+        double lp = (2 * (int64_t)c[b] > N) ? log1p(-(double)(N - (int64_t)c[b]) / (double)N) : log(p);
+        h -= p * lp;
+    }
+    return h;
+}
+
+static int64_t total(const uint32_t* c, int32_t bins) {
+    int64_t n = 0;
+    for (int32_t b = 0; b < bins; ++b) n += c[b];
+    return n;
+}
+
+double kso_entropy64(const uint32_t* counts, int32_t bins) { return entropy64_n(counts, bins, total(counts, bins)); }
+double kso_entropy_ref(const uint32_t* counts, int32_t bins) { return entropy_ref_n(counts, bins, total(counts, bins)); }
+
+/* ---------------------------------------------------------------- windows */
+
+/* Counts of bins in the box [x0,x1]x[y0,y1]x[z0,z1] clipped to the volume. */
+static int64_t box_hist(const uint8_t* bv, const int32_t dims[3], int32_t bins, int32_t x0, int32_t x1, int32_t y0,
+                        int32_t y1, int32_t z0, int32_t z1, uint32_t* c) {
+    memset(c, 0, sizeof(uint32_t) * (size_t)bins);
+    x0 = x0 < 0 ? 0 : x0; y0 = y0 < 0 ? 0 : y0; z0 = z0 < 0 ? 0 : z0;
+    x1 = x1 >= dims[0] ? dims[0] - 1 : x1;
+    y1 = y1 >= dims[1] ? dims[1] - 1 : y1;
+    z1 = z1 >= dims[2] ? dims[2] - 1 : z1;
+    int64_t n = 0;
+    for (int32_t z = z0; z <= z1; ++z)
+        for (int32_t y = y0; y <= y1; ++y)
+            for (int32_t x = x0; x <= x1; ++x) {
+                c[bv[vidx(dims, x, y, z)]] += 1;
+                n += 1;
+            }
+    return n;
+}
+
+static int64_t box_volume(const int32_t dims[3], int32_t x0, int32_t x1, int32_t y0, int32_t y1, int32_t z0,
+                          int32_t z1) {
+    x0 = x0 < 0 ? 0 : x0; y0 = y0 < 0 ? 0 : y0; z0 = z0 < 0 ? 0 : z0;
+    x1 = x1 >= dims[0] ? dims[0] - 1 : x1;
+    y1 = y1 >= dims[1] ? dims[1] - 1 : y1;
+    z1 = z1 >= dims[2] ? dims[2] - 1 : z1;
+    if (x1 < x0 || y1 < y0 || z1 < z0) return 0;
+    return (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1);
+}
+
+/* Octant j: bit 0 -> x, bit 1 -> y, bit 2 -> z; a set bit means the + direction. */
+static int32_t octant_sign(int32_t j, int32_t axis) { return ((j >> axis) & 1) ? 1 : -1; }
+
+static int64_t octant_hist(const uint8_t* bv, const int32_t dims[3], int32_t bins, const int32_t p[3], int32_t j,
+                           int32_t k, uint32_t* c) {
+    int32_t lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (octant_sign(j, a) > 0) { lo[a] = p[a]; hi[a] = p[a] + k; }
+        else { lo[a] = p[a] - k; hi[a] = p[a]; }
+    }
+    return box_hist(bv, dims, bins, lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], c);
+}
+
+static int64_t cube_hist(const uint8_t* bv, const int32_t dims[3], int32_t bins, const int32_t p[3], int32_t s,
+                         uint32_t* c) {
+    return box_hist(bv, dims, bins, p[0] - s, p[0] + s, p[1] - s, p[1] + s, p[2] - s, p[2] + s, c);
+}
+
+int kso_hist_cube(const uint8_t* bv, const int32_t dims[3], int32_t bins, int32_t x, int32_t y, int32_t z, int32_t s,
+                  uint32_t* counts) {
+    int32_t p[3] = {x, y, z};
+    cube_hist(bv, dims, bins, p, s, counts);
+    return 0;
+}
+
+int kso_hist_octant(const uint8_t* bv, const int32_t dims[3], int32_t bins, int32_t x, int32_t y, int32_t z,
+                    int32_t j, int32_t k, uint32_t* counts) {
+    int32_t p[3] = {x, y, z};
+    octant_hist(bv, dims, bins, p, j, k, counts);
+    return 0;
+}
+
+/* ------------------------------------------------------- quadrant method */
+
+/* Alg. 1 body: per octant j and scale k the entropy eps_jk of W_jk(P); per octant
+ * the first maximising scale k*_j; normalised entropies eps_j / E; and the
+ * effective displacement delta = sum_j (eps_j / E) * k*_j * sigma_j, evaluated
+ * as (sum_j eps_j * k*_j * sigma_j) / E. */
+int kso_eval_quadrant(const uint8_t* bv, const int32_t dims[3], int32_t bins, const int32_t p[3], int32_t s_min,
+                      int32_t s_max, double* eps, int32_t* kstar, double* E, double* delta) {
+    int32_t S = s_max - s_min + 1;
+    uint32_t* c = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)bins);
+    double best[8];
+    for (int32_t j = 0; j < 8; ++j) {
+        kstar[j] = s_min;
+        best[j] = 0.0;
+        for (int32_t k = s_min; k <= s_max; ++k) {
+            int64_t N = octant_hist(bv, dims, bins, p, j, k, c);
+            double e = entropy64_n(c, bins, N);
+            eps[j * S + (k - s_min)] = e;
+            if (k == s_min || e > best[j]) { best[j] = e; kstar[j] = k; }
+        }
+    }
+    free(c);
+    *E = sum_octants(best);
+    for (int a = 0; a < 3; ++a) {
+        if (*E == 0.0) { delta[a] = 0.0; continue; }
+        double t[8];
+        for (int32_t j = 0; j < 8; ++j) t[j] = best[j] * (double)(kstar[j] * octant_sign(j, a));
+        delta[a] = sum_octants(t) / *E;
+    }
+    return 0;
+}
+
+/* -------------------------------------------------------- saliency shift */
+
+/* Eq. 4-6 with a flat kernel over C_s(P) and the uniform target q_b = 1/B:
+ * w(v) = sqrt(q_b / p_b) = sqrt(N / (B c_b)) for v in bin b, so
+ * x_new - P = sum_v w(v)(v-P) / sum_v w(v) = (sum_b M_b / sqrt(c_b)) / (sum_b sqrt(c_b)),
+ * with M_b = sum over the window voxels in bin b of (v - P).  The Bhattacharyya
+ * coefficient rho = sum_b sqrt(p_b q_b) is used without its constant factor
+ * 1/sqrt(B): rho~ = (sum_b sqrt(c_b)) / sqrt(N). */
+int kso_eval_meanshift(const uint8_t* bv, const int32_t dims[3], int32_t bins, const int32_t p[3], int32_t s,
+                       uint32_t* counts, int64_t* msum, double* delta, double* rho) {
+    memset(counts, 0, sizeof(uint32_t) * (size_t)bins);
+    memset(msum, 0, sizeof(int64_t) * 3 * (size_t)bins);
+    int64_t N = 0;
+    for (int32_t z = p[2] - s; z <= p[2] + s; ++z)
+        for (int32_t y = p[1] - s; y <= p[1] + s; ++y)
+            for (int32_t x = p[0] - s; x <= p[0] + s; ++x) {
+                if (x < 0 || y < 0 || z < 0 || x >= dims[0] || y >= dims[1] || z >= dims[2]) continue;
+                int32_t b = bv[vidx(dims, x, y, z)];
+                counts[b] += 1;
+                msum[3 * b + 0] += x - p[0];
+                msum[3 * b + 1] += y - p[1];
+                msum[3 * b + 2] += z - p[2];
+                N += 1;
+            }
+    double* t = (double*)malloc(sizeof(double) * (size_t)bins);
+    for (int32_t b = 0; b < bins; ++b) t[b] = counts[b] > 0 ? sqrt((double)counts[b]) : 0.0;
+    double D = sum_bins(t, bins);
+    for (int a = 0; a < 3; ++a) {
+        for (int32_t b = 0; b < bins; ++b)
+            t[b] = counts[b] > 0 ? (double)msum[3 * b + a] * (1.0 / sqrt((double)counts[b])) : 0.0;
+        double num = sum_bins(t, bins);
+        delta[a] = D > 0.0 ? num / D : 0.0;
+    }
+    free(t);
+    *rho = N > 0 ? D / sqrt((double)N) : 0.0;
+    return 0;
+}
+
+/* ------------------------------------------------------------- saliency */
+
+/* pdf change between scales s-1 and s: s^2/(2s-1) * sum_b |c_s/N_s - c_{s-1}/N_{s-1}|,
+ * the numerator taken exactly as sum_b |c_s N_{s-1} - c_{s-1} N_s|. */
+static double pdf_change(const uint32_t* cs, int64_t Ns, const uint32_t* cp, int64_t Np, int32_t bins, int32_t s) {
+    int64_t A = 0;
+    for (int32_t b = 0; b < bins; ++b) {
+        int64_t d = (int64_t)cs[b] * Np - (int64_t)cp[b] * Ns;
+        A += d < 0 ? -d : d;
+    }
+    return ((double)(s * s) / (double)(2 * s - 1)) * ((double)A / ((double)Ns * (double)Np));
+}
+
+/* Saliency at the converged position (Sec. 2.2 after Alg. 1; Sec. 2.3 before the
+ * ABMSOD paragraph): quadrant -> entropy peaks over s in [s_min, s_max] of the
+ * centred cube C_s(P*), best peak by H*W; mean-shift -> the trajectory's own scale. */
+static void saliency(const uint8_t* bv, const int32_t dims[3], int32_t bins, const int32_t p[3], int32_t method,
+                     int32_t s_min, int32_t s_max, int32_t own_s, double h_min, double y_min, kso_traj* t,
+                     kso_stats* st) {
+    int32_t lo = method == KSO_QUADRANT ? s_min - 1 : own_s - 1;
+    int32_t hi = method == KSO_QUADRANT ? s_max + 1 : own_s;
+    int32_t n = hi - lo + 1;
+    uint32_t* c = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)bins * (size_t)n);
+    int64_t* N = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    double* H = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        N[i] = cube_hist(bv, dims, bins, p, lo + i, c + (size_t)i * bins);
+        H[i] = entropy64_n(c + (size_t)i * bins, bins, N[i]);
+    }
+    st->window_evals += n;
+    st->voxel_visits += box_volume(dims, p[0] - hi, p[0] + hi, p[1] - hi, p[1] + hi, p[2] - hi, p[2] + hi);
+    int32_t best = -1;
+    double bestY = 0.0;
+    if (method == KSO_QUADRANT) {
+        for (int32_t s = s_min; s <= s_max; ++s) {
+            int32_t i = s - lo;
+            if (!(H[i] > H[i - 1] && H[i] > H[i + 1])) continue;
+            double W = pdf_change(c + (size_t)i * bins, N[i], c + (size_t)(i - 1) * bins, N[i - 1], bins, s);
+            double Y = H[i] * W;
+            if (best < 0 || Y > bestY) { best = s; bestY = Y; }
+        }
+    } else {
+        best = own_s;
+    }
+    t->scale = best < 0 ? 0 : best;
+    t->keep = 0;
+    t->h64 = t->w64 = t->y64 = t->h_ref = t->y_ref = 0.0;
+    if (best >= 0) {
+        int32_t i = best - lo;
+        double W = pdf_change(c + (size_t)i * bins, N[i], c + (size_t)(i - 1) * bins, N[i - 1], bins, best);
+        t->h64 = H[i];
+        t->w64 = W;
+        t->y64 = H[i] * W;
+        t->h_ref = entropy_ref_n(c + (size_t)i * bins, bins, N[i]);
+        t->y_ref = t->h_ref * W;
+        t->keep = (t->h64 > h_min && t->y64 > y_min) ? 1 : 0;
+    }
+    free(c); free(N); free(H);
+}
+
+/* ------------------------------------------------------------ trajectories */
+
+static void grid_dims(const int32_t dims[3], int32_t sp, int32_t g[3], int32_t o[3]) {
+    for (int a = 0; a < 3; ++a) {
+        o[a] = sp / 2;
+        if (o[a] >= dims[a]) o[a] = (dims[a] - 1) / 2;
+        g[a] = (dims[a] - 1 - o[a]) / sp + 1;
+    }
+}
+
+int64_t kso_num_trajectories(const int32_t dims[3], int32_t spacing, const int32_t scales[2], int32_t method) {
+    int32_t g[3], o[3];
+    grid_dims(dims, spacing, g, o);
+    int64_t n = (int64_t)g[0] * g[1] * g[2];
+    return method == KSO_MEANSHIFT ? n * (scales[1] - scales[0] + 1) : n;
+}
+
+typedef struct {
+    const uint8_t* bv;
+    const int32_t* dims;
+    int32_t bins, method, s_min, s_max;
+    double* eps;
+    uint32_t* counts;
+    int64_t* msum;
+} eval_ctx;
+
+/* One evaluation: objective and proposed displacement at P. */
+static void evaluate(eval_ctx* e, const int32_t p[3], int32_t s, double* obj, double delta[3], kso_stats* st) {
+    st->evals += 1;
+    if (e->method == KSO_QUADRANT) {
+        int32_t kstar[8];
+        kso_eval_quadrant(e->bv, e->dims, e->bins, p, e->s_min, e->s_max, e->eps, kstar, obj, delta);
+        st->window_evals += 8 * (e->s_max - e->s_min + 1);
+        int32_t r = e->s_max;
+        st->voxel_visits += box_volume(e->dims, p[0] - r, p[0] + r, p[1] - r, p[1] + r, p[2] - r, p[2] + r);
+    } else {
+        kso_eval_meanshift(e->bv, e->dims, e->bins, p, s, e->counts, e->msum, delta, obj);
+        st->window_evals += 1;
+        st->voxel_visits += box_volume(e->dims, p[0] - s, p[0] + s, p[1] - s, p[1] + s, p[2] - s, p[2] + s);
+    }
+}
+
+/* The search loop shared by both methods (Alg. 1 loop; Alg. 2 acceptance):
+ * round the proposed move, stop if it is zero, if clamping leaves P unchanged,
+ * if the objective does not strictly increase, or after max_iter accepted moves. */
+static void run_trajectory(eval_ctx* e, int32_t max_iter, const int32_t p0[3], int32_t s, kso_traj* t, kso_stats* st) {
+    int32_t p[3] = {p0[0], p0[1], p0[2]};
+    double obj, delta[3];
+    evaluate(e, p, s, &obj, delta, st);
+    int32_t it = 0, stop;
+    for (;;) {
+        if (it == max_iter) { stop = KSO_STOP_MAX_ITER; break; }
+        int32_t m[3];
+        for (int a = 0; a < 3; ++a) m[a] = (int32_t)round(delta[a]);
+        if (m[0] == 0 && m[1] == 0 && m[2] == 0) { stop = KSO_STOP_ZERO_MOVE; break; }
+        int32_t q[3];
+        for (int a = 0; a < 3; ++a) q[a] = clampi(p[a] + m[a], 0, e->dims[a] - 1);
+        if (q[0] == p[0] && q[1] == p[1] && q[2] == p[2]) { stop = KSO_STOP_CLAMPED; break; }
+        double obj2, delta2[3];
+        evaluate(e, q, s, &obj2, delta2, st);
+        if (!(obj2 > obj)) { stop = KSO_STOP_REJECTED; break; }
+        for (int a = 0; a < 3; ++a) { p[a] = q[a]; delta[a] = delta2[a]; }
+        obj = obj2;
+        it += 1;
+    }
+    t->x0 = p0[0]; t->y0 = p0[1]; t->z0 = p0[2];
+    t->x = p[0]; t->y = p[1]; t->z = p[2];
+    t->iters = it;
+    t->stop = stop;
+    t->objective = obj;
+}
+
+int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
+            const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+            const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats) {
+    int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
+    uint8_t* bv = (uint8_t*)malloc((size_t)nv);
+    kso_bin_volume(vol, dtype, dims, bins, bv);
+    int32_t g[3], o[3];
+    grid_dims(dims, spacing, g, o);
+    int32_t S = scales[1] - scales[0] + 1;
+    int64_t ntraj = kso_num_trajectories(dims, spacing, scales, method);
+    if (ids == NULL) n = ntraj;
+    eval_ctx e;
+    e.bv = bv; e.dims = dims; e.bins = bins; e.method = method; e.s_min = scales[0]; e.s_max = scales[1];
+    e.eps = (double*)malloc(sizeof(double) * 8 * (size_t)S);
+    e.counts = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)bins);
+    e.msum = (int64_t*)malloc(sizeof(int64_t) * 3 * (size_t)bins);
+    kso_stats st = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t id = ids ? ids[i] : i;
+        int64_t seed = method == KSO_MEANSHIFT ? id / S : id;
+        int32_t s = method == KSO_MEANSHIFT ? scales[0] + (int32_t)(id % S) : 0;
+        int32_t gx = (int32_t)(seed % g[0]);
+        int32_t gy = (int32_t)((seed / g[0]) % g[1]);
+        int32_t gz = (int32_t)(seed / ((int64_t)g[0] * g[1]));
+        int32_t p0[3] = {o[0] + gx * spacing, o[1] + gy * spacing, o[2] + gz * spacing};
+        kso_traj* t = out + i;
+        t->traj = id;
+        run_trajectory(&e, max_iter, p0, s, t, &st);
+        int32_t pf[3] = {t->x, t->y, t->z};
+        saliency(bv, dims, bins, pf, method, scales[0], scales[1], s, h_min, y_min, t, &st);
+    }
+    if (stats) *stats = st;
+    free(e.eps); free(e.counts); free(e.msum); free(bv);
+    return 0;
+}
+
+/* ------------------------------------------------------------- ranking */
+
+/* Order: saliency (decision precision) descending, then scale, z, y, x, seed
+ * ascending.  Equal (x,y,z,scale) records carry equal saliency, so duplicates are
+ * adjacent and the first one holds the smallest seed. */
+static int region_cmp(const void* pa, const void* pb) {
+    const kso_region* a = (const kso_region*)pa;
+    const kso_region* b = (const kso_region*)pb;
+    if (a->key != b->key) return a->key > b->key ? -1 : 1;
+    if (a->scale != b->scale) return a->scale < b->scale ? -1 : 1;
+    if (a->z != b->z) return a->z < b->z ? -1 : 1;
+    if (a->y != b->y) return a->y < b->y ? -1 : 1;
+    if (a->x != b->x) return a->x < b->x ? -1 : 1;
+    if (a->seed != b->seed) return a->seed < b->seed ? -1 : 1;
+    return 0;
+}
+
+int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
+               const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+               kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
+    int64_t n = kso_num_trajectories(dims, spacing, scales, method);
+    kso_traj* t = (kso_traj*)malloc(sizeof(kso_traj) * (size_t)n);
+    kso_run(vol, dtype, dims, bins, spacing, scales, method, max_iter, h_min, y_min, NULL, 0, t, stats);
+    kso_region* r = (kso_region*)malloc(sizeof(kso_region) * (size_t)(n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!t[i].keep) continue;
+        kso_region* g = r + m++;
+        g->x = t[i].x; g->y = t[i].y; g->z = t[i].z; g->scale = t[i].scale;
+        g->saliency = t[i].y_ref; g->entropy = t[i].h_ref; g->pdf_change = t[i].w64;
+        g->key = t[i].y64; g->seed = t[i].traj;
+    }
+    qsort(r, (size_t)m, sizeof(kso_region), region_cmp);
+    int64_t u = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (u > 0) {
+            kso_region* p = r + u - 1;
+            if (p->x == r[i].x && p->y == r[i].y && p->z == r[i].z && p->scale == r[i].scale) continue;
+        }
+        r[u++] = r[i];
+    }
+    for (int64_t i = 0; i < u && i < capacity; ++i) out[i] = r[i];
+    *n_found = (int32_t)u;
+    free(r); free(t);
+    return 0;
+}

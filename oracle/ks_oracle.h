@@ -1,0 +1,90 @@
+/*
+ * CPU oracle for seed-grid Kadir-Brady salient-region search in 3D.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded
+ * restatement of the method (quadrant method: Sec. 2.2, Alg. 1; saliency shift:
+ * Sec. 2.3, Eq. 4-6; Kadir-Brady saliency: Sec. 1 and Sec. 2.1) used to check
+ * the GPU library.  Only the tests, the package's smoke check and the CPU
+ * baseline leg of the benchmark may call it.  It shares no code with the GPU
+ * library.
+ *
+ * Volumes: dims = {X, Y, Z}, x fastest, index = x + X*(y + Y*z).
+ */
+#ifndef KS_ORACLE_H
+#define KS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { KSO_U8 = 0, KSO_U16 = 1, KSO_I16 = 2 };
+enum { KSO_QUADRANT = 0, KSO_MEANSHIFT = 1 };
+enum { KSO_STOP_MAX_ITER = 0, KSO_STOP_ZERO_MOVE = 1, KSO_STOP_CLAMPED = 2, KSO_STOP_REJECTED = 3 };
+
+/* Outcome of one trajectory (a grid seed for the quadrant method, a
+ * (grid seed, scale) pair for mean-shift). */
+typedef struct {
+    int64_t traj;          /* trajectory id */
+    int32_t x0, y0, z0;    /* start position */
+    int32_t x, y, z;       /* converged position P* */
+    int32_t scale;         /* s* (quadrant: 0 when there is no entropy peak) */
+    int32_t iters;         /* accepted moves */
+    int32_t stop;          /* KSO_STOP_* */
+    int32_t keep;          /* 1 if it yields a region */
+    double objective;      /* final objective: E (quadrant) or rho (mean-shift) */
+    double h64, w64, y64;  /* decision-precision entropy, pdf change, saliency at s* */
+    double h_ref, y_ref;   /* accurate entropy and saliency at s* */
+} kso_traj;
+
+typedef struct {
+    int32_t x, y, z, scale;
+    double saliency, entropy, pdf_change, key;
+    int64_t seed;
+} kso_region;
+
+typedef struct {
+    int64_t evals;          /* trajectory evaluations (search windows) */
+    int64_t window_evals;   /* seed-scale window evaluations incl. the final pass */
+    int64_t voxel_visits;   /* in-volume voxels of the evaluated bricks/windows */
+} kso_stats;
+
+/* Step 1 of the search: intensity -> bin index (the paper's beta(s), Eq. 4). */
+int kso_bin_volume(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, uint8_t* out);
+
+/* Entropies of one count vector: decision precision (H64) and accurate (Href). */
+double kso_entropy64(const uint32_t* counts, int32_t bins);
+double kso_entropy_ref(const uint32_t* counts, int32_t bins);
+
+/* Histograms of windows clipped to the volume, over a bin volume. */
+int kso_hist_cube(const uint8_t* bv, const int32_t dims[3], int32_t bins, int32_t x, int32_t y, int32_t z,
+                  int32_t s, uint32_t* counts);
+int kso_hist_octant(const uint8_t* bv, const int32_t dims[3], int32_t bins, int32_t x, int32_t y, int32_t z,
+                    int32_t j, int32_t k, uint32_t* counts);
+
+/* One quadrant evaluation at P: eps[8*S] (j-major), kstar[8], E, delta[3]. */
+int kso_eval_quadrant(const uint8_t* bv, const int32_t dims[3], int32_t bins, const int32_t p[3], int32_t s_min,
+                      int32_t s_max, double* eps, int32_t* kstar, double* E, double* delta);
+/* One mean-shift evaluation at (P, s): counts[B], msum[3B] (per bin sum of v-P),
+ * delta[3], rho. */
+int kso_eval_meanshift(const uint8_t* bv, const int32_t dims[3], int32_t bins, const int32_t p[3], int32_t s,
+                       uint32_t* counts, int64_t* msum, double* delta, double* rho);
+
+/* Number of trajectories of a search. */
+int64_t kso_num_trajectories(const int32_t dims[3], int32_t spacing, const int32_t scales[2], int32_t method);
+
+/* Run the trajectories listed in ids[0..n) (all when ids == NULL, n ignored). */
+int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
+            const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+            const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats);
+
+/* Full detection: run every trajectory, dedup and rank.  Writes min(capacity, n)
+ * regions; *n_found is the total. */
+int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
+               const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+               kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
