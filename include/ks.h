@@ -1,0 +1,215 @@
+/*
+ * ks.h -- C ABI of the MI355X (gfx950) library for seed-grid Kadir-Brady
+ * salient-region search in 3D volumes.
+ *
+ * The method (Thota, Vaswani, Kale, Vydyanathan, "Fast 3D Salient Region
+ * Detection in Medical Images using GPUs"): a sparse grid of seeds (Sec. 2.2,
+ * Alg. 1, first step) moves toward local entropy maxima, either by the
+ * quadrant method (Sec. 2.2, Alg. 1; 8 octants in 3D) or by saliency shift, a
+ * mean-shift toward the uniform pmf (Sec. 2.3, Eq. 4-6); the converged centres
+ * are scored by Kadir-Brady saliency, entropy times the change of the pdf with
+ * scale (Sec. 1; Sec. 2.2 after Alg. 1; Sec. 2.3 after Eq. 6), and the best are
+ * kept (Sec. 3.1 keeps the top 20).
+ *
+ * Conventions shared by every entry point:
+ *  - Volumes are dense arrays of voxels with dims = {X, Y, Z}, x fastest:
+ *    index = x + X*(y + Y*z).  dtype is one of ks_dtype.  Each dim is in
+ *    [1, 65535] and X*Y*Z < 2^31.
+ *  - bins in [2, 256]: a voxel v falls in bin floor((v - vmin)*bins / (vmax - vmin + 1))
+ *    over the volume's own [vmin, vmax] (the paper's beta(s), Eq. 4, left
+ *    undefined there).
+ *  - seed_spacing >= 1: seeds sit at o + k*seed_spacing on each axis with
+ *    o = seed_spacing/2 (or (dim-1)/2 when that is outside the volume); seed ids
+ *    run x fastest.  Quadrant: one trajectory per seed.  Mean-shift: one per
+ *    (seed, scale) pair, trajectory id = seed_id*S + (s - s_min), S = s_max-s_min+1.
+ *  - scales = {s_min, s_max}, 1 <= s_min <= s_max <= 32.  A scale s is a
+ *    half-width: the mean-shift window is the cube P + [-s, s]^3; the quadrant
+ *    octant window of scale k is {P + sigma*u : u in [0,k]^3}.
+ *  - max_iter >= 0 bounds the accepted moves of each trajectory.
+ *  - Histogram counts are exact integers.  Decisions (argmax over scale, moves,
+ *    acceptance, entropy peaks, ranking) use IEEE double in a fixed order and give
+ *    bit-identical results to the CPU reference; reported entropy, pdf change and
+ *    saliency are float32.
+ *  - Ownership: the caller owns every buffer it passes; the library owns
+ *    contexts and servers, freed only by the matching *_destroy.
+ *  - Errors: the return value is the status.  Outputs are written only on
+ *    KS_OK.  *n_found is the total number of regions; only min(capacity, *n_found)
+ *    are written (snprintf convention, not an error).  Argument checks happen
+ *    before any GPU call and return KS_E_INVALID.
+ *  - Threading: a context serves one host thread at a time.  The server API is
+ *    thread-safe.
+ *  - stream arguments are hipStream_t values passed as void* (NULL: the
+ *    default stream).
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KS_OK = 0,
+    KS_E_INVALID = -1,    /* bad argument */
+    KS_E_NOMEM = -2,      /* device or host allocation failed */
+    KS_E_DEVICE = -3,     /* a HIP call failed; the context should be destroyed */
+    KS_E_TOO_LARGE = -4,  /* request larger than the server's HBM budget */
+    KS_E_NOT_READY = -5,  /* server result not available yet */
+    KS_E_SHUTDOWN = -6    /* server is shutting down */
+} ks_status;
+
+typedef enum { KS_U8 = 0, KS_U16 = 1, KS_I16 = 2 } ks_dtype;
+typedef enum { KS_QUADRANT = 0, KS_MEANSHIFT = 1 } ks_method;
+typedef enum { KS_STOP_MAX_ITER = 0, KS_STOP_ZERO_MOVE = 1, KS_STOP_CLAMPED = 2, KS_STOP_REJECTED = 3 } ks_stop;
+
+/* One detected region: centre, scale s* (half-width), float32 saliency Y = H*W,
+ * entropy H and pdf change W at s*, and the id of the (lowest) trajectory that
+ * converged there. */
+typedef struct {
+    int32_t x, y, z, scale;
+    float saliency, entropy, pdf_change;
+    int32_t seed;
+} ks_region;
+
+/* Final state of one trajectory. */
+typedef struct {
+    int32_t x0, y0, z0;    /* start */
+    int32_t x, y, z;       /* converged position */
+    int32_t scale;         /* s* (quadrant: 0 if the entropy has no peak over scale) */
+    int32_t iters;         /* accepted moves */
+    int32_t stop;          /* ks_stop */
+    int32_t keep;          /* 1 if the trajectory yields a region */
+    double objective;      /* E (quadrant) or sum_b sqrt(c_b)/sqrt(N) (mean-shift) at the end */
+    double saliency64;     /* decision-precision saliency at s* */
+    float saliency, entropy, pdf_change;
+    int32_t pad;
+} ks_seed_trace;
+
+/* Work counters and device times of the last call on a context. */
+typedef struct {
+    int64_t trajectories;  /* trajectories searched */
+    int64_t evals;         /* trajectory evaluations in the search */
+    int64_t window_evals;  /* seed-scale windows evaluated, including the final saliency pass */
+    int64_t voxel_visits;  /* in-volume voxels read by the search evaluations */
+    int64_t final_visits;  /* in-volume voxels read by the final saliency pass */
+    int64_t regions;       /* regions found (sum over volumes) */
+    double ms_prep, ms_search, ms_rank, ms_total; /* device time per phase (only with profiling on) */
+} ks_run_stats;
+
+typedef struct ks_context ks_context;
+typedef struct ks_server ks_server;
+
+/* Human-readable name of a status. */
+const char* ks_status_str(ks_status s);
+
+/* Create a context on a HIP device: builds the decision tables and the work
+ * arena.  Destroy frees every device allocation of the context. */
+ks_status ks_context_create(int32_t device, ks_context** out);
+ks_status ks_context_destroy(ks_context* ctx);
+
+/* Turn per-phase device timing (HIP events) on or off; off by default. */
+ks_status ks_context_set_profiling(ks_context* ctx, int32_t on);
+
+/* Counters and times of the last detect/batch call on this context. */
+ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out);
+
+/* Detection on a host volume (synchronous).  Uses a library-owned context on
+ * device 0.  out: host array of capacity regions, ranked by saliency
+ * descending, then scale, z, y, x ascending; duplicates of (x,y,z,scale) keep
+ * the lowest trajectory id. */
+ks_status ks_detect(const void* volume, ks_dtype dtype, const int32_t dims[3], int32_t bins, int32_t seed_spacing,
+                    const int32_t scales[2], ks_method method, int32_t max_iter, ks_region* out, int32_t capacity,
+                    int32_t* n_found);
+
+/* Same, on a device-resident volume.  Work is queued on `stream`; the call
+ * returns after the results are in `out` (host).  d_volume must stay valid
+ * until then. */
+ks_status ks_detect_device(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                           int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                           int32_t max_iter, ks_region* out, int32_t capacity, int32_t* n_found, void* stream);
+
+/* Per-trajectory final states of a search on a device volume (test and debug
+ * hook).  out: host array of capacity traces in trajectory-id order; *n is the
+ * number of trajectories. */
+ks_status ks_seed_traces(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                         int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                         int32_t max_iter, ks_seed_trace* out, int32_t capacity, int32_t* n, void* stream);
+
+/* Bin volume of a device volume (test hook): out is a host array of X*Y*Z bytes,
+ * x fastest. */
+ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                        int32_t bins, uint8_t* out, void* stream);
+
+/* Window histograms on a device volume (test hook), through the same device
+ * code as the search.  xyz: host, 3n positions; scale: host, n half-widths.
+ *   KS_HIST_CUBE      counts of P + [-s,s]^3 clipped to the volume:      uint32 [n][B]
+ *   KS_HIST_OCTANTS   counts of the 8 octant cubes of every scale k in
+ *                     [range[0], range[1]] (Alg. 1 windows):             uint32 [n][8][K][B]
+ *   KS_HIST_MEANSHIFT counts and per-bin sums of (v - P) over the cube
+ *                     P + [-s,s]^3 (Eq. 4 with a flat kernel, Eq. 6):     int32  [n][4][B]
+ *                     (rows: count, sum dx, sum dy, sum dz)
+ *   KS_HIST_SHELLS    counts of the centred cubes of every half-width s in
+ *                     [range[0], range[1]] (saliency pass):               uint32 [n][K][B]
+ * K = range[1] - range[0] + 1.  out is a host buffer of the stated size. */
+enum { KS_HIST_CUBE = 0, KS_HIST_OCTANTS = 1, KS_HIST_MEANSHIFT = 2, KS_HIST_SHELLS = 3 };
+ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
+                        int32_t kind, const int32_t range[2], int32_t n, const int32_t* xyz, const int32_t* scale,
+                        void* out, void* stream);
+
+/* One request of a batch or of the server. */
+typedef struct {
+    const void* volume;    /* device pointer (ks_detect_batch) or host pointer (ks_server_submit) */
+    int32_t dtype;         /* ks_dtype */
+    int32_t dims[3];
+    int32_t bins;
+    int32_t seed_spacing;
+    int32_t scales[2];
+    int32_t method;        /* ks_method */
+    int32_t max_iter;
+} ks_request;
+
+typedef struct {
+    ks_region* regions;    /* host array supplied by the caller */
+    int32_t capacity;
+    int32_t n_found;       /* written by the library */
+    int32_t status;        /* ks_status of this request */
+    int32_t pad;
+} ks_result;
+
+/* Batched detection of n device-resident volumes of any sizes and methods in
+ * one captured launch sequence: per-volume range scan and binning, one
+ * persistent search over every trajectory of every volume, one ranking pass.
+ * Each volume's result equals ks_detect_device on it alone. */
+ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks_result* results, void* stream);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct {
+    int64_t submitted, admitted, completed, refused, queued_now, in_flight;
+    int64_t bytes_in_use, budget_bytes;
+    double p50_ms, p99_ms, mean_ms;      /* submit -> result ready, completed requests */
+    double volumes_per_s;                /* completed / (last completion - first submit) */
+} ks_server_stats_t;
+
+/* A server owns a context on `device`, a budget of device memory for admitted
+ * requests (hbm_budget bytes) and at most max_slots requests on the GPU at once.
+ * Requests that arrive while others run are admitted when a slot and enough
+ * budget are free, and their work overlaps on the device. */
+ks_status ks_server_create(int32_t device, size_t hbm_budget, int32_t max_slots, ks_server** out);
+/* Copies the host volume; returns a ticket.  KS_E_TOO_LARGE if the request can
+ * never fit the budget. */
+ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket);
+/* KS_E_NOT_READY until the request is done; then writes its regions once. */
+ks_status ks_server_poll(ks_server* s, uint64_t ticket, ks_region* out, int32_t capacity, int32_t* n_found);
+/* Blocks until every submitted request is done. */
+ks_status ks_server_drain(ks_server* s);
+ks_status ks_server_stats(ks_server* s, ks_server_stats_t* out);
+ks_status ks_server_destroy(ks_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

@@ -1,0 +1,96 @@
+// Device-side data layout shared by the kernels and their host launchers.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace ks {
+
+// Packed per-replica mean-shift accumulator (one uint64 per bin per replica):
+//   bits  0..9   voxel count
+//   bits 10..25  sum of (dx + s)      (or: count of voxels of the inner cube, final pass)
+//   bits 32..47  sum of (dy + s)
+//   bits 48..63  sum of (dz + s)
+// A replica takes at most kMaxPerReplica voxels between flushes, which keeps every
+// field below its width for s <= 32 (64 * 1023 < 65536).
+constexpr int kMaxPerReplica = 1023;
+constexpr int kSmaxLimit = 32;
+constexpr int kBinsLimit = 256;
+
+// Largest count a decision table must cover: the final quadrant pass reads the
+// centred cube of half-width s_max + 1.
+constexpr int32_t kTableMax = (2 * (kSmaxLimit + 1) + 1) * (2 * (kSmaxLimit + 1) + 1) * (2 * (kSmaxLimit + 1) + 1);
+
+// Decision tables, built once per context on the host (index = integer count):
+//   cl[c]  = c * ln c   (cl[0] = 0)
+//   sq[c]  = sqrt(c)
+//   rsq[c] = 1 / sqrt(c) (rsq[0] unused)
+struct Tables {
+    const double* cl;
+    const double* sq;
+    const double* rsq;
+};
+
+// One volume of a search.
+struct VolDesc {
+    const void* raw;        // input voxels, dense, x fastest
+    uint8_t* bins;          // bin volume, row pitch xp (multiple of 16)
+    int32_t X, Y, Z, xp;
+    int64_t slice;          // xp * Y
+    int32_t dtype, B, sp, s_min, s_max, method, max_iter;
+    int32_t gx, gy, gz, ox, oy, oz;  // seed grid
+    int32_t S;              // s_max - s_min + 1
+    int32_t pad0;
+    int64_t traj_base;      // first slot of this volume in the trajectory records
+    int64_t n_traj;
+    double h_min, y_min;
+    int32_t* minmax;        // [2] device scratch: vmin, vmax
+    int64_t reg_off;        // first slot of this volume in the region output
+    int32_t cap;            // region capacity of this volume
+    int32_t pad1;
+};
+
+// A run of tasks with the same window size: tasks [task_begin, task_begin + count)
+// are trajectories local_begin .. local_begin + count - 1 of volume `vol` (for
+// mean-shift, local ids of one scale, stride S).
+struct TaskSeg {
+    int64_t task_begin;
+    int64_t count;
+    int32_t vol;
+    int32_t scale;          // mean-shift: the fixed scale; quadrant: 0
+    int64_t seed_begin;     // first seed id of the run
+};
+
+// Result of one trajectory (64 bytes).
+struct TrajRec {
+    int32_t x0, y0, z0, x, y, z;
+    int32_t scale, iters, stop, keep;
+    double objective;
+    double y64;
+    float h32, w32, y32;
+    int32_t seed;           // trajectory id within its volume
+};
+
+// Sort record of a kept trajectory: ordered by vol, ky (= ~bits(y64): saliency
+// descending), kpos (= s<<48 | z<<32 | y<<16 | x), then seed.
+struct SortRec {
+    uint64_t vol;
+    uint64_t ky;
+    uint64_t kpos;
+    uint32_t seed;
+    uint32_t idx;           // index of the TrajRec
+};
+
+struct Counters {
+    unsigned long long evals, window_evals, voxel_visits, final_visits;
+    unsigned long long queue_head[2];   // task queues (quadrant, mean-shift)
+    unsigned long long n_sort;          // kept trajectories
+    unsigned long long pad;
+};
+
+// Launch-time tuning of the mean-shift evaluation.
+struct MsTune {
+    int32_t rep_log2;       // replicas per wave = 1 << rep_log2 (<= 6)
+};
+
+}  // namespace ks

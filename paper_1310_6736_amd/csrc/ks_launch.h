@@ -1,0 +1,72 @@
+// Host launchers of the kernels in ks_kernels.hip.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "ks_device.h"
+
+namespace ks {
+
+// Same layout as the public ks_region.
+struct ks_region_dev {
+    int32_t x, y, z, scale;
+    float saliency, entropy, pdf_change;
+    int32_t seed;
+};
+
+// Byte offsets of the quadrant kernel's dynamic LDS.
+struct LdsQuad {
+    size_t hist_off, cnt_off, eps_off, hrow_off, arow_off, res_off, bytes;
+    int hist_words;
+    int pad;
+};
+
+struct PrepArgs {
+    VolDesc* vols;
+    int nvol;
+    Counters* cnt;
+    int* vol_nfound;
+    int* vol_base;
+    long long max_voxels;   // largest X*Y*Z of the volumes
+    long long max_words;    // largest (xp/4)*Y*Z
+};
+
+struct SearchArgs {
+    const VolDesc* vols;
+    const TaskSeg* segs;
+    int nseg;
+    long long ntask;
+    Tables tb;
+    TrajRec* rec;
+    Counters* cnt;
+};
+
+struct RankArgs {
+    const VolDesc* vols;
+    int nvol;
+    const TrajRec* rec;
+    SortRec* sr;
+    Counters* cnt;
+    unsigned long long n_pad;   // power of two >= total trajectories, >= 2
+    long long max_traj;         // largest per-volume trajectory count
+    int* bsum;                  // n_pad/1024 + 1 ints
+    int* grank;                 // n_pad ints
+    int* vol_base;
+    int* vol_nfound;
+    ks_region_dev* regions;
+};
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+hipError_t launch_search_ms(const SearchArgs& a, int grid, int rl, int hist_words, hipStream_t st);
+hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, hipStream_t st);
+hipError_t launch_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc, int rl, int hist_words,
+                          void* out, hipStream_t st);
+hipError_t launch_hook_quad(const VolDesc* vols, int kind, int lo, int hi, int n, const int* xyz, int rq,
+                            const LdsQuad& lay, uint32_t* out, hipStream_t st);
+hipError_t launch_rank(const RankArgs& a, hipStream_t st);
+int max_blocks_ms(int hist_words);
+int max_blocks_quad(size_t lds_bytes);
+
+}  // namespace ks

@@ -1,0 +1,784 @@
+// Host runtime of the C ABI: contexts, argument checks, work planning, the launch
+// sequence (prep -> persistent searches -> device ranking), hooks and batching.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ks.h"
+#include "ks_device.h"
+#include "ks_launch.h"
+#include "ks_runtime.h"
+
+namespace ks {
+
+// ------------------------------------------------------------ validation
+
+static bool dims_ok(const int32_t* d) {
+    if (!d) return false;
+    for (int a = 0; a < 3; ++a)
+        if (d[a] < 1 || d[a] > 65535) return false;
+    return (int64_t)d[0] * d[1] * d[2] < (int64_t(1) << 31);
+}
+
+ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
+                        const int32_t* scales, int32_t method, int32_t max_iter) {
+    if (!vol || !dims || !scales) return KS_E_INVALID;
+    if (dtype < KS_U8 || dtype > KS_I16) return KS_E_INVALID;
+    if (!dims_ok(dims)) return KS_E_INVALID;
+    if (bins < 2 || bins > kBinsLimit) return KS_E_INVALID;
+    if (spacing < 1) return KS_E_INVALID;
+    if (scales[0] < 1 || scales[0] > scales[1] || scales[1] > kSmaxLimit) return KS_E_INVALID;
+    if (method != KS_QUADRANT && method != KS_MEANSHIFT) return KS_E_INVALID;
+    if (max_iter < 0) return KS_E_INVALID;
+    return KS_OK;
+}
+
+static int64_t grid_count(int32_t dim, int32_t sp, int32_t* o) {
+    int32_t off = sp / 2;
+    if (off >= dim) off = (dim - 1) / 2;
+    *o = off;
+    return (dim - 1 - off) / sp + 1;
+}
+
+int64_t num_trajectories(const int32_t* dims, int32_t spacing, const int32_t* scales, int32_t method) {
+    int32_t o;
+    int64_t n = grid_count(dims[0], spacing, &o) * grid_count(dims[1], spacing, &o) * grid_count(dims[2], spacing, &o);
+    return method == KS_MEANSHIFT ? n * (scales[1] - scales[0] + 1) : n;
+}
+
+size_t bins_bytes(const int32_t* dims) {
+    const size_t xp = ((size_t)dims[0] + 15) & ~(size_t)15;
+    return (xp * dims[1] * dims[2] + 255) & ~(size_t)255;
+}
+
+// ------------------------------------------------------------ context
+
+static ks_status hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? KS_E_NOMEM : KS_E_DEVICE; }
+#define KS_HIP(call)                                    \
+    do {                                                \
+        hipError_t _e = (call);                         \
+        if (_e != hipSuccess) return hip_fail(_e);      \
+    } while (0)
+
+ks_status Buffer::ensure(size_t bytes, int* generation) {
+    if (bytes <= cap) return KS_OK;
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    size_t want = std::max(bytes, cap * 3 / 2);
+    want = (want + 4095) & ~(size_t)4095;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return hip_fail(e);
+    }
+    cap = want;
+    if (generation) ++*generation;
+    return KS_OK;
+}
+
+void Buffer::release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+}
+
+ks_status PinnedBuffer::ensure(size_t bytes) {
+    if (bytes <= cap) return KS_OK;
+    if (ptr) hipHostFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    size_t want = (std::max(bytes, (size_t)4096) + 4095) & ~(size_t)4095;
+    if (hipHostMalloc(&ptr, want, hipHostMallocDefault) != hipSuccess) {
+        ptr = nullptr;
+        return KS_E_NOMEM;
+    }
+    cap = want;
+    return KS_OK;
+}
+
+void PinnedBuffer::release() {
+    if (ptr) hipHostFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+}
+
+ks_status Context::init(int32_t dev) {
+    device = dev;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || dev < 0 || dev >= n) return KS_E_DEVICE;
+    KS_HIP(hipSetDevice(dev));
+    hipDeviceProp_t prop;
+    KS_HIP(hipGetDeviceProperties(&prop, dev));
+    num_cu = prop.multiProcessorCount;
+    // Decision tables: the same libm calls a plain CPU implementation makes.
+    const size_t n_tab = (size_t)kTableMax + 1;
+    std::vector<double> cl(n_tab), sq(n_tab), rsq(n_tab);
+    for (size_t c = 0; c < n_tab; ++c) {
+        const double d = (double)c;
+        cl[c] = c > 0 ? d * std::log(d) : 0.0;
+        sq[c] = std::sqrt(d);
+        rsq[c] = c > 0 ? 1.0 / std::sqrt(d) : 0.0;
+    }
+    ks_status st = tables_buf.ensure(3 * n_tab * sizeof(double), nullptr);
+    if (st != KS_OK) return st;
+    double* base = static_cast<double*>(tables_buf.ptr);
+    KS_HIP(hipMemcpy(base, cl.data(), n_tab * sizeof(double), hipMemcpyHostToDevice));
+    KS_HIP(hipMemcpy(base + n_tab, sq.data(), n_tab * sizeof(double), hipMemcpyHostToDevice));
+    KS_HIP(hipMemcpy(base + 2 * n_tab, rsq.data(), n_tab * sizeof(double), hipMemcpyHostToDevice));
+    tables.cl = base;
+    tables.sq = base + n_tab;
+    tables.rsq = base + 2 * n_tab;
+    KS_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    for (int i = 0; i < kEvents; ++i) KS_HIP(hipEventCreate(&ev[i]));
+    KS_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+    KS_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+    return KS_OK;
+}
+
+void Context::destroy() {
+    hipSetDevice(device);
+    for (auto& g : graphs)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    graphs.clear();
+    Buffer* bufs[] = {&tables_buf, &d_vols, &d_segs, &d_bins, &d_rec, &d_sr, &d_bsum, &d_grank, &d_volint,
+                      &d_regions, &d_cnt, &d_hook, &d_hook_out, &d_raw};
+    for (Buffer* b : bufs) b->release();
+    h_stage.release();
+    h_out.release();
+    if (aux) hipStreamDestroy(aux);
+    if (batch_stream) hipStreamDestroy(batch_stream);
+    for (int i = 0; i < kEvents; ++i)
+        if (ev[i]) hipEventDestroy(ev[i]);
+    if (fork_ev) hipEventDestroy(fork_ev);
+    if (join_ev) hipEventDestroy(join_ev);
+}
+
+// ------------------------------------------------------------ planning
+
+static unsigned long long next_pow2(unsigned long long n) {
+    unsigned long long p = 2;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Replica counts: as many as fit a per-workgroup LDS budget (more replicas, fewer
+// same-address LDS atomics; fewer, cheaper merges).
+int pick_ms_rl(int maxB, int pref) {
+    int rl = pref;
+    while (rl > 0 && (size_t)(maxB + 1) * ((size_t)1 << rl) * 8 > 36 * 1024) --rl;
+    return rl;
+}
+
+LdsQuad quad_layout(int maxS, int maxB, int rq) {
+    LdsQuad L;
+    const size_t rows = (size_t)maxS + 3;
+    size_t off = 0;
+    L.hist_off = off;
+    L.hist_words = (int)(rows * maxB * ((size_t)1 << rq));
+    off += (size_t)L.hist_words * 4;
+    off = (off + 15) & ~(size_t)15;
+    L.cnt_off = off;
+    off += (rows - 1) * maxB * 4;
+    off = (off + 15) & ~(size_t)15;
+    L.eps_off = off;
+    off += 8 * (size_t)maxS * 8;
+    L.hrow_off = off;
+    off += (size_t)(maxS + 2) * 8;
+    L.arow_off = off;
+    off += (size_t)(maxS + 2) * 8;
+    L.res_off = off;
+    off += 4 * 8;
+    L.bytes = (off + 15) & ~(size_t)15;
+    L.pad = 0;
+    return L;
+}
+
+int pick_quad_rq(int maxS, int maxB, int pref) {
+    int rq = pref;
+    while (rq > 0 && quad_layout(maxS, maxB, rq).bytes > 40 * 1024) --rq;
+    return rq;
+}
+
+ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
+    p = Plan();
+    const int nvol = (int)in.size();
+    p.nvol = nvol;
+    p.vols.resize(nvol);
+    size_t bins_total = 0;
+    std::vector<size_t> bins_off(nvol);
+    int64_t traj = 0, regs = 0;
+    for (int i = 0; i < nvol; ++i) {
+        const VolIn& r = in[i];
+        VolDesc& v = p.vols[i];
+        std::memset(&v, 0, sizeof(v));
+        v.raw = r.raw;
+        v.X = r.dims[0]; v.Y = r.dims[1]; v.Z = r.dims[2];
+        v.xp = (v.X + 15) & ~15;
+        v.slice = (int64_t)v.xp * v.Y;
+        v.dtype = r.dtype; v.B = r.bins; v.sp = r.spacing;
+        v.s_min = r.scales[0]; v.s_max = r.scales[1]; v.S = v.s_max - v.s_min + 1;
+        v.method = r.method; v.max_iter = r.max_iter;
+        v.gx = (int32_t)grid_count(v.X, v.sp, &v.ox);
+        v.gy = (int32_t)grid_count(v.Y, v.sp, &v.oy);
+        v.gz = (int32_t)grid_count(v.Z, v.sp, &v.oz);
+        v.traj_base = traj;
+        v.n_traj = num_trajectories(r.dims, r.spacing, r.scales, r.method);
+        v.h_min = 0.0; v.y_min = 0.0;
+        v.reg_off = regs;
+        v.cap = r.capacity;
+        bins_off[i] = bins_total;
+        bins_total += bins_bytes(r.dims);
+        traj += v.n_traj;
+        regs += r.capacity;
+        p.max_traj = std::max<long long>(p.max_traj, v.n_traj);
+        p.max_voxels = std::max<long long>(p.max_voxels, (long long)v.X * v.Y * v.Z);
+        p.max_words = std::max<long long>(p.max_words, (long long)(v.xp / 4) * v.Y * v.Z);
+        if (v.method == KS_QUADRANT) {
+            p.maxS_quad = std::max(p.maxS_quad, v.S);
+            p.maxB_quad = std::max(p.maxB_quad, v.B);
+        } else {
+            p.maxB_ms = std::max(p.maxB_ms, v.B);
+        }
+    }
+    p.total_traj = traj;
+    p.total_regions = regs;
+    p.n_pad = next_pow2((unsigned long long)std::max<int64_t>(traj, 2));
+    // Task runs, longest windows first (largest-processing-time order).
+    struct Run { TaskSeg s; double cost; int method; };
+    std::vector<Run> runs;
+    for (int i = 0; i < nvol; ++i) {
+        const VolDesc& v = p.vols[i];
+        const int64_t seeds = (int64_t)v.gx * v.gy * v.gz;
+        if (v.method == KS_QUADRANT) {
+            Run r;
+            r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = 0; r.s.seed_begin = 0;
+            const double w = 2.0 * v.s_max + 2.0;
+            r.cost = w * w * w;
+            r.method = KS_QUADRANT;
+            runs.push_back(r);
+        } else {
+            for (int s = v.s_max; s >= v.s_min; --s) {
+                Run r;
+                r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = s; r.s.seed_begin = 0;
+                const double w = 2.0 * s + 1.0;
+                r.cost = w * w * w;
+                r.method = KS_MEANSHIFT;
+                runs.push_back(r);
+            }
+        }
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.cost > b.cost; });
+    for (const Run& r : runs) {
+        std::vector<TaskSeg>& segs = r.method == KS_QUADRANT ? p.segs_q : p.segs_m;
+        long long& nt = r.method == KS_QUADRANT ? p.ntask_q : p.ntask_m;
+        TaskSeg s = r.s;
+        s.task_begin = nt;
+        nt += s.count;
+        segs.push_back(s);
+    }
+    // Device memory.
+    ks_status st;
+    const size_t vol_bytes = sizeof(VolDesc) * (size_t)nvol;
+    const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
+    if ((st = d_vols.ensure(vol_bytes, &generation)) != KS_OK) return st;
+    if ((st = d_segs.ensure(seg_bytes, &generation)) != KS_OK) return st;
+    if ((st = d_bins.ensure(std::max<size_t>(bins_total, 256), &generation)) != KS_OK) return st;
+    if ((st = d_rec.ensure(sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1), &generation)) != KS_OK) return st;
+    if ((st = d_sr.ensure(sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
+    if ((st = d_bsum.ensure(sizeof(int) * (p.n_pad / 1024 + 2), &generation)) != KS_OK) return st;
+    if ((st = d_grank.ensure(sizeof(int) * p.n_pad, &generation)) != KS_OK) return st;
+    if ((st = d_volint.ensure(sizeof(int) * 4 * (size_t)nvol, &generation)) != KS_OK) return st;
+    if ((st = d_regions.ensure(sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 1), &generation)) != KS_OK)
+        return st;
+    if ((st = d_cnt.ensure(sizeof(Counters), &generation)) != KS_OK) return st;
+    int* volint = static_cast<int*>(d_volint.ptr);
+    for (int i = 0; i < nvol; ++i) {
+        p.vols[i].bins = static_cast<uint8_t*>(d_bins.ptr) + bins_off[i];
+        p.vols[i].minmax = volint + 2 * i;
+    }
+    p.vol_nfound = volint + 2 * nvol;
+    p.vol_base = volint + 3 * nvol;
+    // Host staging: vols, segs.
+    const size_t stage_bytes = vol_bytes + seg_bytes;
+    if ((st = h_stage.ensure(stage_bytes)) != KS_OK) return st;
+    const size_t out_bytes = sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 1) + sizeof(int) * nvol +
+                             sizeof(Counters);
+    if ((st = h_out.ensure(out_bytes)) != KS_OK) return st;
+    p.rl = pick_ms_rl(std::max(p.maxB_ms, 2), ms_rl_pref);
+    p.rq = pick_quad_rq(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), quad_rq_pref);
+    p.lay = quad_layout(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), p.rq);
+    p.ms_hist_words = (std::max(p.maxB_ms, 2) + 1) << p.rl;
+    return KS_OK;
+}
+
+// Writes the plan's tables into the pinned staging buffer and queues their upload.
+ks_status Context::upload(const Plan& p, hipStream_t st) {
+    char* h = static_cast<char*>(h_stage.ptr);
+    const size_t vol_bytes = sizeof(VolDesc) * (size_t)p.nvol;
+    std::memcpy(h, p.vols.data(), vol_bytes);
+    TaskSeg* hs = reinterpret_cast<TaskSeg*>(h + vol_bytes);
+    size_t ns = 0;
+    for (const TaskSeg& s : p.segs_q) hs[ns++] = s;
+    for (const TaskSeg& s : p.segs_m) hs[ns++] = s;
+    KS_HIP(hipMemcpyAsync(d_vols.ptr, h, vol_bytes, hipMemcpyHostToDevice, st));
+    if (ns) KS_HIP(hipMemcpyAsync(d_segs.ptr, hs, sizeof(TaskSeg) * ns, hipMemcpyHostToDevice, st));
+    return KS_OK;
+}
+
+ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed) {
+    VolDesc* dv = static_cast<VolDesc*>(d_vols.ptr);
+    TaskSeg* ds = static_cast<TaskSeg*>(d_segs.ptr);
+    Counters* dc = static_cast<Counters*>(d_cnt.ptr);
+    TrajRec* rec = static_cast<TrajRec*>(d_rec.ptr);
+    if (timed) KS_HIP(hipEventRecord(ev[0], st));
+    PrepArgs pa;
+    pa.vols = dv; pa.nvol = p.nvol; pa.cnt = dc; pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base;
+    pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    KS_HIP(launch_prep(pa, st));
+    if (timed) KS_HIP(hipEventRecord(ev[1], st));
+    SearchArgs sq;
+    sq.vols = dv; sq.segs = ds; sq.nseg = (int)p.segs_q.size(); sq.ntask = p.ntask_q; sq.tb = tables;
+    sq.rec = rec; sq.cnt = dc;
+    SearchArgs sm = sq;
+    sm.segs = ds + p.segs_q.size(); sm.nseg = (int)p.segs_m.size(); sm.ntask = p.ntask_m;
+    if (p.ntask_q > 0) {
+        const int per_cu = max_blocks_quad(p.lay.bytes);
+        const long long g = std::min<long long>(p.ntask_q, std::max<long long>(1, (long long)per_cu * num_cu * grid_pct / 100));
+        KS_HIP(launch_search_quad(sq, (int)g, p.rq, p.lay, st));
+    }
+    if (p.ntask_m > 0) {
+        const int per_cu = max_blocks_ms(p.ms_hist_words);
+        const long long g = std::min<long long>(p.ntask_m, std::max<long long>(1, (long long)per_cu * num_cu * grid_pct / 100));
+        KS_HIP(launch_search_ms(sm, (int)g, p.rl, p.ms_hist_words, st));
+    }
+    if (timed) KS_HIP(hipEventRecord(ev[2], st));
+    if (with_rank) {
+        RankArgs ra;
+        ra.vols = dv; ra.nvol = p.nvol; ra.rec = rec; ra.sr = static_cast<SortRec*>(d_sr.ptr); ra.cnt = dc;
+        ra.n_pad = p.n_pad; ra.max_traj = p.max_traj; ra.bsum = static_cast<int*>(d_bsum.ptr);
+        ra.grank = static_cast<int*>(d_grank.ptr); ra.vol_base = p.vol_base; ra.vol_nfound = p.vol_nfound;
+        ra.regions = static_cast<ks_region_dev*>(d_regions.ptr);
+        KS_HIP(launch_rank(ra, st));
+    }
+    if (timed) KS_HIP(hipEventRecord(ev[3], st));
+    return KS_OK;
+}
+
+ks_status Context::download(const Plan& p, hipStream_t st) {
+    char* h = static_cast<char*>(h_out.ptr);
+    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
+    if (rb) KS_HIP(hipMemcpyAsync(h, d_regions.ptr, rb, hipMemcpyDeviceToHost, st));
+    KS_HIP(hipMemcpyAsync(h + rb, p.vol_nfound, sizeof(int) * p.nvol, hipMemcpyDeviceToHost, st));
+    KS_HIP(hipMemcpyAsync(h + rb + sizeof(int) * p.nvol, d_cnt.ptr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    return KS_OK;
+}
+
+void Context::collect_stats(const Plan& p, bool timed) {
+    const char* h = static_cast<const char*>(h_out.ptr);
+    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
+    const int* nf = reinterpret_cast<const int*>(h + rb);
+    Counters c;
+    std::memcpy(&c, h + rb + sizeof(int) * p.nvol, sizeof(Counters));
+    std::memset(&last, 0, sizeof(last));
+    last.trajectories = p.total_traj;
+    last.evals = (int64_t)c.evals;
+    last.window_evals = (int64_t)c.window_evals;
+    last.voxel_visits = (int64_t)c.voxel_visits;
+    last.final_visits = (int64_t)c.final_visits;
+    for (int i = 0; i < p.nvol; ++i) last.regions += nf[i];
+    if (timed) {
+        float a = 0, b = 0, d = 0;
+        hipEventElapsedTime(&a, ev[0], ev[1]);
+        hipEventElapsedTime(&b, ev[1], ev[2]);
+        hipEventElapsedTime(&d, ev[2], ev[3]);
+        last.ms_prep = a; last.ms_search = b; last.ms_rank = d; last.ms_total = a + b + d;
+    }
+}
+
+ks_status Context::begin_detect(const std::vector<VolIn>& in, hipStream_t st, Plan& p) {
+    KS_HIP(hipSetDevice(device));
+    ks_status s = plan(in, p);
+    if (s != KS_OK) return s;
+    if ((s = upload(p, st)) != KS_OK) return s;
+    if ((s = enqueue_search(p, st, true, profiling)) != KS_OK) return s;
+    return download(p, st);
+}
+
+void Context::end_detect(const std::vector<VolIn>& in, const Plan& p, std::vector<std::vector<ks_region>>* out,
+                         std::vector<int>* nfound) {
+    collect_stats(p, profiling);
+    const char* h = static_cast<const char*>(h_out.ptr);
+    const ks_region* regs = reinterpret_cast<const ks_region*>(h);
+    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
+    const int* nf = reinterpret_cast<const int*>(h + rb);
+    out->assign(in.size(), {});
+    nfound->assign(in.size(), 0);
+    for (size_t i = 0; i < in.size(); ++i) {
+        (*nfound)[i] = nf[i];
+        const int w = std::min(nf[i], in[i].capacity);
+        (*out)[i].assign(regs + p.vols[i].reg_off, regs + p.vols[i].reg_off + w);
+    }
+}
+
+ks_status Context::detect_volumes(const std::vector<VolIn>& in, hipStream_t st, std::vector<std::vector<ks_region>>* out,
+                                  std::vector<int>* nfound) {
+    Plan p;
+    ks_status s = begin_detect(in, st, p);
+    if (s != KS_OK) return s;
+    KS_HIP(hipStreamSynchronize(st));
+    end_detect(in, p, out, nfound);
+    return KS_OK;
+}
+
+
+// Batched detection through a captured graph: the launch sequence of a batch
+// with a given shape is captured once and replayed; only the small tables are
+// re-uploaded before each replay.
+ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t st,
+                                      std::vector<std::vector<ks_region>>* out, std::vector<int>* nfound) {
+    KS_HIP(hipSetDevice(device));
+    if (!st) {
+        if (!batch_stream) KS_HIP(hipStreamCreateWithFlags(&batch_stream, hipStreamNonBlocking));
+        st = batch_stream;
+    }
+    Plan p;
+    ks_status s = plan(in, p);
+    if (s != KS_OK) return s;
+    std::vector<int64_t> key;
+    key.push_back(generation);
+    key.push_back(ms_rl_pref);
+    key.push_back(quad_rq_pref);
+    for (const VolIn& v : in) {
+        key.push_back((int64_t)(intptr_t)v.raw);
+        key.push_back(v.dtype); key.push_back(v.dims[0]); key.push_back(v.dims[1]); key.push_back(v.dims[2]);
+        key.push_back(v.bins); key.push_back(v.spacing); key.push_back(v.scales[0]); key.push_back(v.scales[1]);
+        key.push_back(v.method); key.push_back(v.max_iter); key.push_back(v.capacity);
+    }
+    hipGraphExec_t exec = nullptr;
+    for (const GraphEntry& g : graphs)
+        if (g.key == key) exec = g.exec;
+    if ((s = upload(p, st)) != KS_OK) return s;
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        KS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        ks_status cs = enqueue_search(p, st, true, false);
+        if (cs == KS_OK) cs = download(p, st);
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (cs != KS_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return cs;
+        }
+        if (e != hipSuccess) return hip_fail(e);
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e);
+        if (graphs.size() >= 8) {
+            hipGraphExecDestroy(graphs.front().exec);
+            graphs.erase(graphs.begin());
+        }
+        GraphEntry ge;
+        ge.key = key;
+        ge.exec = exec;
+        graphs.push_back(ge);
+    }
+    if (profiling) KS_HIP(hipEventRecord(ev[0], st));
+    KS_HIP(hipGraphLaunch(exec, st));
+    if (profiling) KS_HIP(hipEventRecord(ev[3], st));
+    KS_HIP(hipStreamSynchronize(st));
+    collect_stats(p, false);
+    if (profiling) {
+        float ms = 0;
+        hipEventElapsedTime(&ms, ev[0], ev[3]);
+        last.ms_total = ms;
+    }
+    const char* h = static_cast<const char*>(h_out.ptr);
+    const ks_region* regs = reinterpret_cast<const ks_region*>(h);
+    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
+    const int* nf = reinterpret_cast<const int*>(h + rb);
+    out->assign(in.size(), {});
+    nfound->assign(in.size(), 0);
+    for (size_t i = 0; i < in.size(); ++i) {
+        (*nfound)[i] = nf[i];
+        const int w = std::min(nf[i], in[i].capacity);
+        (*out)[i].assign(regs + p.vols[i].reg_off, regs + p.vols[i].reg_off + w);
+    }
+    return KS_OK;
+}
+
+}  // namespace ks
+
+// ================================================================ C ABI
+
+using namespace ks;
+
+struct ks_context : public Context {};
+
+extern "C" {
+
+const char* ks_status_str(ks_status s) {
+    switch (s) {
+        case KS_OK: return "ok";
+        case KS_E_INVALID: return "invalid argument";
+        case KS_E_NOMEM: return "out of memory";
+        case KS_E_DEVICE: return "device error";
+        case KS_E_TOO_LARGE: return "request larger than the budget";
+        case KS_E_NOT_READY: return "not ready";
+        case KS_E_SHUTDOWN: return "shutting down";
+    }
+    return "unknown status";
+}
+
+ks_status ks_context_create(int32_t device, ks_context** out) {
+    if (!out) return KS_E_INVALID;
+    ks_context* c = new (std::nothrow) ks_context();
+    if (!c) return KS_E_NOMEM;
+    ks_status s = c->init(device);
+    if (s != KS_OK) {
+        c->destroy();
+        delete c;
+        return s;
+    }
+    *out = c;
+    return KS_OK;
+}
+
+ks_status ks_context_destroy(ks_context* ctx) {
+    if (!ctx) return KS_E_INVALID;
+    ctx->destroy();
+    delete ctx;
+    return KS_OK;
+}
+
+ks_status ks_context_set_profiling(ks_context* ctx, int32_t on) {
+    if (!ctx) return KS_E_INVALID;
+    ctx->profiling = on != 0;
+    return KS_OK;
+}
+
+ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32_t quad_replicas_log2) {
+    if (!ctx || ms_replicas_log2 < 0 || ms_replicas_log2 > 6 || quad_replicas_log2 < 0 || quad_replicas_log2 > 3)
+        return KS_E_INVALID;
+    ctx->ms_rl_pref = ms_replicas_log2;
+    ctx->quad_rq_pref = quad_replicas_log2;
+    return KS_OK;
+}
+
+ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out) {
+    if (!ctx || !out) return KS_E_INVALID;
+    *out = ctx->last;
+    return KS_OK;
+}
+
+static ks_status check_out(ks_region* out, int32_t capacity, int32_t* n_found) {
+    if (!n_found || capacity < 0 || (capacity > 0 && !out)) return KS_E_INVALID;
+    return KS_OK;
+}
+
+ks_status ks_detect_device(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                           int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                           int32_t max_iter, ks_region* out, int32_t capacity, int32_t* n_found, void* stream) {
+    if (!ctx) return KS_E_INVALID;
+    ks_status s = check_request(d_volume, dtype, dims, bins, seed_spacing, scales, method, max_iter);
+    if (s != KS_OK) return s;
+    if ((s = check_out(out, capacity, n_found)) != KS_OK) return s;
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
+    v.max_iter = max_iter; v.capacity = capacity;
+    std::vector<std::vector<ks_region>> res;
+    std::vector<int> nf;
+    s = ctx->detect_volumes({v}, static_cast<hipStream_t>(stream), &res, &nf);
+    if (s != KS_OK) return s;
+    if (!res[0].empty()) std::memcpy(out, res[0].data(), sizeof(ks_region) * res[0].size());
+    *n_found = nf[0];
+    return KS_OK;
+}
+
+static std::mutex g_default_mu;
+static ks_context* g_default = nullptr;
+
+ks_status ks_detect(const void* volume, ks_dtype dtype, const int32_t dims[3], int32_t bins, int32_t seed_spacing,
+                    const int32_t scales[2], ks_method method, int32_t max_iter, ks_region* out, int32_t capacity,
+                    int32_t* n_found) {
+    ks_status s = check_request(volume, dtype, dims, bins, seed_spacing, scales, method, max_iter);
+    if (s != KS_OK) return s;
+    if ((s = check_out(out, capacity, n_found)) != KS_OK) return s;
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if (!g_default) {
+        s = ks_context_create(0, &g_default);
+        if (s != KS_OK) return s;
+    }
+    hipSetDevice(g_default->device);
+    const size_t esz = dtype == KS_U8 ? 1 : 2;
+    const size_t bytes = esz * (size_t)dims[0] * dims[1] * dims[2];
+    if ((s = g_default->d_raw.ensure(bytes, &g_default->generation)) != KS_OK) return s;
+    if (hipMemcpy(g_default->d_raw.ptr, volume, bytes, hipMemcpyHostToDevice) != hipSuccess) return KS_E_DEVICE;
+    return ks_detect_device(g_default, g_default->d_raw.ptr, dtype, dims, bins, seed_spacing, scales, method,
+                            max_iter, out, capacity, n_found, nullptr);
+}
+
+ks_status ks_seed_traces(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                         int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                         int32_t max_iter, ks_seed_trace* out, int32_t capacity, int32_t* n, void* stream) {
+    if (!ctx) return KS_E_INVALID;
+    ks_status s = check_request(d_volume, dtype, dims, bins, seed_spacing, scales, method, max_iter);
+    if (s != KS_OK) return s;
+    if (!n || capacity < 0 || (capacity > 0 && !out)) return KS_E_INVALID;
+    if (capacity == 0) {  // count only
+        *n = (int32_t)num_trajectories(dims, seed_spacing, scales, method);
+        return KS_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
+    v.max_iter = max_iter; v.capacity = 0;
+    Plan p;
+    if ((s = ctx->plan({v}, p)) != KS_OK) return s;
+    if ((s = ctx->upload(p, st)) != KS_OK) return s;
+    if ((s = ctx->enqueue_search(p, st, false, false)) != KS_OK) return s;
+    std::vector<TrajRec> rec((size_t)p.total_traj);
+    if (hipMemcpyAsync(rec.data(), ctx->d_rec.ptr, sizeof(TrajRec) * rec.size(), hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
+        return KS_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
+    const int64_t w = std::min<int64_t>(capacity, p.total_traj);
+    for (int64_t i = 0; i < w; ++i) {
+        const TrajRec& r = rec[(size_t)i];
+        ks_seed_trace& t = out[i];
+        t.x0 = r.x0; t.y0 = r.y0; t.z0 = r.z0; t.x = r.x; t.y = r.y; t.z = r.z;
+        t.scale = r.scale; t.iters = r.iters; t.stop = r.stop; t.keep = r.keep;
+        t.objective = r.objective; t.saliency64 = r.y64;
+        t.saliency = r.y32; t.entropy = r.h32; t.pdf_change = r.w32; t.pad = 0;
+    }
+    *n = (int32_t)p.total_traj;
+    return KS_OK;
+}
+
+ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
+                        uint8_t* out, void* stream) {
+    if (!ctx || !out) return KS_E_INVALID;
+    const int32_t sc[2] = {1, 1};
+    ks_status s = check_request(d_volume, dtype, dims, bins, 1, sc, KS_QUADRANT, 0);
+    if (s != KS_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = 1 << 20; v.scales[0] = 1; v.scales[1] = 1; v.method = KS_QUADRANT; v.max_iter = 0; v.capacity = 0;
+    Plan p;
+    if ((s = ctx->plan({v}, p)) != KS_OK) return s;
+    if ((s = ctx->upload(p, st)) != KS_OK) return s;
+    PrepArgs pa;
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
+    const VolDesc& d = p.vols[0];
+    if (hipMemcpy2DAsync(out, (size_t)d.X, d.bins, (size_t)d.xp, (size_t)d.X, (size_t)d.Y * d.Z,
+                         hipMemcpyDeviceToHost, st) != hipSuccess)
+        return KS_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
+    return KS_OK;
+}
+
+ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
+                        int32_t kind, const int32_t range[2], int32_t n, const int32_t* xyz, const int32_t* scale,
+                        void* out, void* stream) {
+    if (!ctx || !out || n < 0 || (n > 0 && !xyz)) return KS_E_INVALID;
+    if (kind < KS_HIST_CUBE || kind > KS_HIST_SHELLS) return KS_E_INVALID;
+    const int32_t sc[2] = {1, 1};
+    ks_status s = check_request(d_volume, dtype, dims, bins, 1, sc, KS_QUADRANT, 0);
+    if (s != KS_OK) return s;
+    const bool per_window = kind == KS_HIST_CUBE || kind == KS_HIST_MEANSHIFT;
+    if (per_window && n > 0 && !scale) return KS_E_INVALID;
+    if (!per_window && (!range || range[0] < 0 || range[0] > range[1] || range[1] > kSmaxLimit + 1))
+        return KS_E_INVALID;
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a)
+            if (xyz[3 * i + a] < 0 || xyz[3 * i + a] >= dims[a]) return KS_E_INVALID;
+        if (per_window && (scale[i] < 1 || scale[i] > kSmaxLimit)) return KS_E_INVALID;
+    }
+    if (n == 0) return KS_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = 1 << 20; v.scales[0] = 1; v.scales[1] = 1;
+    v.method = per_window ? KS_MEANSHIFT : KS_QUADRANT; v.max_iter = 0; v.capacity = 0;
+    Plan p;
+    if ((s = ctx->plan({v}, p)) != KS_OK) return s;
+    if ((s = ctx->upload(p, st)) != KS_OK) return s;
+    PrepArgs pa;
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
+    const size_t in_bytes = sizeof(int32_t) * 4 * (size_t)n;
+    if ((s = ctx->d_hook.ensure(in_bytes, &ctx->generation)) != KS_OK) return s;
+    std::vector<int32_t> hin((size_t)4 * n);
+    std::memcpy(hin.data(), xyz, sizeof(int32_t) * 3 * (size_t)n);
+    if (per_window) std::memcpy(hin.data() + 3 * (size_t)n, scale, sizeof(int32_t) * (size_t)n);
+    if (hipMemcpyAsync(ctx->d_hook.ptr, hin.data(), in_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return KS_E_DEVICE;
+    const int32_t* dxyz = static_cast<const int32_t*>(ctx->d_hook.ptr);
+    const int32_t* dsc = dxyz + 3 * (size_t)n;
+    const int K = per_window ? 1 : range[1] - range[0] + 1;
+    size_t out_bytes;
+    if (kind == KS_HIST_CUBE) out_bytes = sizeof(uint32_t) * (size_t)n * bins;
+    else if (kind == KS_HIST_MEANSHIFT) out_bytes = sizeof(int32_t) * (size_t)n * 4 * bins;
+    else if (kind == KS_HIST_OCTANTS) out_bytes = sizeof(uint32_t) * (size_t)n * 8 * K * bins;
+    else out_bytes = sizeof(uint32_t) * (size_t)n * K * bins;
+    if ((s = ctx->d_hook_out.ensure(out_bytes, &ctx->generation)) != KS_OK) return s;
+    hipError_t e;
+    if (per_window) {
+        const int rl = pick_ms_rl(bins, ctx->ms_rl_pref);
+        e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), kind == KS_HIST_CUBE ? 0 : 1, n, dxyz, dsc, rl,
+                           (bins + 1) << rl, ctx->d_hook_out.ptr, st);
+    } else {
+        const int rq = pick_quad_rq(K, bins, ctx->quad_rq_pref);
+        const LdsQuad lay = quad_layout(K, bins, rq);
+        e = launch_hook_quad(static_cast<VolDesc*>(ctx->d_vols.ptr), kind, range[0], range[1], n, dxyz, rq, lay,
+                             static_cast<uint32_t*>(ctx->d_hook_out.ptr), st);
+    }
+    if (e != hipSuccess) return KS_E_DEVICE;
+    if (hipMemcpyAsync(out, ctx->d_hook_out.ptr, out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return KS_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
+    return KS_OK;
+}
+
+ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks_result* results, void* stream) {
+    if (!ctx || n < 0 || (n > 0 && (!reqs || !results))) return KS_E_INVALID;
+    std::vector<VolIn> in((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const ks_request& r = reqs[i];
+        ks_status s = check_request(r.volume, r.dtype, r.dims, r.bins, r.seed_spacing, r.scales, r.method, r.max_iter);
+        if (s != KS_OK) return s;
+        if (results[i].capacity < 0 || (results[i].capacity > 0 && !results[i].regions)) return KS_E_INVALID;
+        VolIn& v = in[(size_t)i];
+        v.raw = r.volume; v.dtype = r.dtype; std::memcpy(v.dims, r.dims, sizeof(v.dims)); v.bins = r.bins;
+        v.spacing = r.seed_spacing; v.scales[0] = r.scales[0]; v.scales[1] = r.scales[1]; v.method = r.method;
+        v.max_iter = r.max_iter; v.capacity = results[i].capacity;
+    }
+    if (n == 0) return KS_OK;
+    std::vector<std::vector<ks_region>> res;
+    std::vector<int> nf;
+    ks_status s = ctx->detect_batch_graph(in, static_cast<hipStream_t>(stream), &res, &nf);
+    if (s != KS_OK) return s;
+    for (int i = 0; i < n; ++i) {
+        if (!res[(size_t)i].empty())
+            std::memcpy(results[i].regions, res[(size_t)i].data(), sizeof(ks_region) * res[(size_t)i].size());
+        results[i].n_found = nf[(size_t)i];
+        results[i].status = KS_OK;
+    }
+    return KS_OK;
+}
+
+}  // extern "C"

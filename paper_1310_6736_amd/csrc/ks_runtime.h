@@ -1,0 +1,105 @@
+// Host-side context and planning structures of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/ks.h"
+#include "ks_device.h"
+#include "ks_launch.h"
+
+namespace ks {
+
+// Grow-only device allocation.
+struct Buffer {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    ks_status ensure(size_t bytes, int* generation);
+    void release();
+};
+
+struct PinnedBuffer {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    ks_status ensure(size_t bytes);
+    void release();
+};
+
+// One volume of a request as the runtime sees it.
+struct VolIn {
+    const void* raw;
+    int32_t dtype;
+    int32_t dims[3];
+    int32_t bins, spacing;
+    int32_t scales[2];
+    int32_t method, max_iter;
+    int32_t capacity;
+};
+
+struct Plan {
+    int nvol = 0;
+    std::vector<VolDesc> vols;
+    std::vector<TaskSeg> segs_q, segs_m;
+    long long ntask_q = 0, ntask_m = 0;
+    long long total_traj = 0, total_regions = 0, max_traj = 0, max_voxels = 0, max_words = 0;
+    unsigned long long n_pad = 2;
+    int maxS_quad = 0, maxB_quad = 0, maxB_ms = 0;
+    int rl = 6, rq = 3, ms_hist_words = 0;
+    LdsQuad lay{};
+    int* vol_nfound = nullptr;
+    int* vol_base = nullptr;
+};
+
+struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct Context {
+    static constexpr int kEvents = 4;
+    int device = 0;
+    int num_cu = 256;
+    bool profiling = false;
+    int ms_rl_pref = 6;
+    int quad_rq_pref = 3;
+    int grid_pct = 100;     // persistent grid size, percent of the resident capacity
+    int generation = 0;
+    Tables tables{};
+    Buffer tables_buf, d_vols, d_segs, d_bins, d_rec, d_sr, d_bsum, d_grank, d_volint, d_regions, d_cnt, d_hook,
+        d_hook_out, d_raw;
+    PinnedBuffer h_stage, h_out;
+    hipStream_t aux = nullptr;
+    hipStream_t batch_stream = nullptr;
+    hipEvent_t ev[kEvents] = {};
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    std::vector<GraphEntry> graphs;
+    ks_run_stats last{};
+
+    ks_status init(int32_t dev);
+    void destroy();
+    ks_status plan(const std::vector<VolIn>& in, Plan& p);
+    ks_status upload(const Plan& p, hipStream_t st);
+    ks_status enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed);
+    ks_status download(const Plan& p, hipStream_t st);
+    void collect_stats(const Plan& p, bool timed);
+    ks_status begin_detect(const std::vector<VolIn>& in, hipStream_t st, Plan& p);
+    void end_detect(const std::vector<VolIn>& in, const Plan& p, std::vector<std::vector<ks_region>>* out,
+                    std::vector<int>* nfound);
+    ks_status detect_volumes(const std::vector<VolIn>& in, hipStream_t st, std::vector<std::vector<ks_region>>* out,
+                             std::vector<int>* nfound);
+    ks_status detect_batch_graph(const std::vector<VolIn>& in, hipStream_t st,
+                                 std::vector<std::vector<ks_region>>* out, std::vector<int>* nfound);
+};
+
+ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
+                        const int32_t* scales, int32_t method, int32_t max_iter);
+int64_t num_trajectories(const int32_t* dims, int32_t spacing, const int32_t* scales, int32_t method);
+size_t bins_bytes(const int32_t* dims);
+int pick_ms_rl(int maxB, int pref);
+int pick_quad_rq(int maxS, int maxB, int pref);
+LdsQuad quad_layout(int maxS, int maxB, int rq);
+
+}  // namespace ks
+
+extern "C" ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32_t quad_replicas_log2);

@@ -1,0 +1,378 @@
+// Continuous-batching detection server.
+//
+// A scheduler thread owns the GPU work.  Each tick it admits, oldest first, every
+// pending request whose device footprint fits the remaining HBM budget, groups
+// the admitted requests into one batched launch sequence on a free slot (own
+// context and stream), and retires slots whose completion event has fired.  Slots
+// run concurrently on the device, so requests that arrive while others are on
+// the GPU start as soon as a slot and budget are free and overlap with them.  A
+// request's result does not depend on what it was batched with: every trajectory
+// is computed independently and ranked within its own volume.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/ks.h"
+#include "ks_runtime.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count();
+}
+
+struct SrvReq {
+    ks::VolIn in;
+    std::vector<uint8_t> host;     // copy of the submitted volume
+    size_t footprint = 0;
+    double t_submit = 0, t_done = 0;
+    int status = KS_E_NOT_READY;
+    std::vector<ks_region> regions;
+    int n_found = 0;
+};
+
+struct Slot {
+    ks::Context ctx;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    ks::Buffer raw;                // device copies of the batch's volumes
+    ks::PinnedBuffer staging;      // pinned copies for the uploads
+    std::vector<uint64_t> tickets;
+    std::vector<ks::VolIn> in;
+    ks::Plan plan;
+    bool busy = false;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ks_server {
+    int device = 0;
+    size_t budget = 0;
+    int max_slots = 1;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::condition_variable done_cv;
+    std::thread worker;
+    bool stop = false;
+    ks_status fatal = KS_OK;
+    uint64_t next_ticket = 1;
+    std::deque<uint64_t> pending;
+    std::map<uint64_t, SrvReq> reqs;
+    std::vector<Slot*> slots;
+    size_t in_use = 0;
+    int64_t submitted = 0, admitted = 0, completed = 0, refused = 0, in_flight = 0;
+    double first_submit = -1, last_done = 0;
+    std::vector<double> latencies;
+    bool ready = false;
+    ks_status init_status = KS_OK;
+
+    void run();
+    bool tick();
+};
+
+// Device bytes a request holds while admitted: its volume, bin volume, trajectory
+// and sort records.
+static size_t footprint(const ks::VolIn& v) {
+    const size_t esz = v.dtype == KS_U8 ? 1 : 2;
+    const size_t raw = esz * (size_t)v.dims[0] * v.dims[1] * v.dims[2];
+    const size_t n = (size_t)ks::num_trajectories(v.dims, v.spacing, v.scales, v.method);
+    size_t pad = 2;
+    while (pad < n) pad <<= 1;
+    return raw + ks::bins_bytes(v.dims) + n * sizeof(ks::TrajRec) + pad * (sizeof(ks::SortRec) + 2 * sizeof(int)) +
+           (size_t)v.capacity * sizeof(ks_region) + (1 << 16);
+}
+
+static double percentile(std::vector<double> v, double q) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+// One scheduler step; returns true if it did any work.
+bool ks_server::tick() {
+    bool worked = false;
+    // Retire finished slots.
+    for (Slot* sl : slots) {
+        if (!sl->busy) continue;
+        hipError_t q = hipEventQuery(sl->done);
+        if (q == hipErrorNotReady) continue;
+        std::vector<std::vector<ks_region>> res;
+        std::vector<int> nf;
+        if (q == hipSuccess) sl->ctx.end_detect(sl->in, sl->plan, &res, &nf);
+        const double t = now_ms();
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t i = 0; i < sl->tickets.size(); ++i) {
+            auto it = reqs.find(sl->tickets[i]);
+            if (it == reqs.end()) continue;
+            SrvReq& r = it->second;
+            if (q == hipSuccess) {
+                r.regions = std::move(res[i]);
+                r.n_found = nf[i];
+                r.status = KS_OK;
+            } else {
+                r.status = KS_E_DEVICE;
+                fatal = KS_E_DEVICE;
+            }
+            r.t_done = t;
+            r.host.clear();
+            r.host.shrink_to_fit();
+            latencies.push_back(t - r.t_submit);
+            completed += 1;
+            in_flight -= 1;
+            last_done = t;
+        }
+        in_use -= sl->bytes;
+        sl->busy = false;
+        sl->tickets.clear();
+        worked = true;
+        done_cv.notify_all();
+    }
+    // Admit pending requests into a free slot as one batch.
+    Slot* free_slot = nullptr;
+    for (Slot* sl : slots)
+        if (!sl->busy) { free_slot = sl; break; }
+    if (!free_slot) return worked;
+    std::vector<uint64_t> take;
+    size_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        while (!pending.empty()) {
+            SrvReq& r = reqs[pending.front()];
+            if (in_use + bytes + r.footprint > budget) break;   // oldest first: no overtaking
+            bytes += r.footprint;
+            take.push_back(pending.front());
+            pending.pop_front();
+        }
+        in_use += bytes;
+        admitted += (int64_t)take.size();
+        in_flight += (int64_t)take.size();
+    }
+    if (take.empty()) return worked;
+    Slot* sl = free_slot;
+    sl->busy = true;
+    sl->bytes = bytes;
+    sl->tickets = take;
+    sl->in.clear();
+    size_t raw_total = 0;
+    std::vector<size_t> offs;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (uint64_t t : take) {
+            offs.push_back(raw_total);
+            raw_total += (reqs[t].host.size() + 255) & ~(size_t)255;
+        }
+    }
+    ks_status st = sl->raw.ensure(std::max<size_t>(raw_total, 256), nullptr);
+    if (st == KS_OK) st = sl->staging.ensure(std::max<size_t>(raw_total, 256));
+    if (st == KS_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t i = 0; i < take.size(); ++i) {
+            SrvReq& r = reqs[take[i]];
+            std::memcpy(static_cast<char*>(sl->staging.ptr) + offs[i], r.host.data(), r.host.size());
+            ks::VolIn v = r.in;
+            v.raw = static_cast<char*>(sl->raw.ptr) + offs[i];
+            sl->in.push_back(v);
+        }
+    }
+    if (st == KS_OK && hipMemcpyAsync(sl->raw.ptr, sl->staging.ptr, raw_total, hipMemcpyHostToDevice, sl->stream) !=
+                           hipSuccess)
+        st = KS_E_DEVICE;
+    if (st == KS_OK) st = sl->ctx.begin_detect(sl->in, sl->stream, sl->plan);
+    if (st == KS_OK && hipEventRecord(sl->done, sl->stream) != hipSuccess) st = KS_E_DEVICE;
+    if (st != KS_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (uint64_t t : take) {
+            SrvReq& r = reqs[t];
+            r.status = st;
+            r.t_done = now_ms();
+            completed += 1;
+            in_flight -= 1;
+        }
+        in_use -= bytes;
+        sl->busy = false;
+        if (st == KS_E_DEVICE) fatal = st;
+        done_cv.notify_all();
+    }
+    return true;
+}
+
+void ks_server::run() {
+    ks_status st = KS_OK;
+    if (hipSetDevice(device) != hipSuccess) st = KS_E_DEVICE;
+    for (int i = 0; i < max_slots && st == KS_OK; ++i) {
+        Slot* sl = new Slot();
+        st = sl->ctx.init(device);
+        // concurrent slots share the device: each persistent launch takes a share
+        sl->ctx.grid_pct = std::max(25, 100 / std::max(1, std::min(max_slots, 4)));
+        if (st == KS_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) st = KS_E_DEVICE;
+        if (st == KS_OK && hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) st = KS_E_DEVICE;
+        slots.push_back(sl);
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        init_status = st;
+        ready = true;
+    }
+    cv.notify_all();
+    if (st != KS_OK) return;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (stop && pending.empty() && in_flight == 0) break;
+        }
+        const bool worked = tick();
+        if (!worked) {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait_for(lk, std::chrono::microseconds(100));
+        }
+    }
+}
+
+extern "C" {
+
+ks_status ks_server_create(int32_t device, size_t hbm_budget, int32_t max_slots, ks_server** out) {
+    if (!out || hbm_budget == 0 || max_slots < 1 || max_slots > 16 || device < 0) return KS_E_INVALID;
+    ks_server* s = new (std::nothrow) ks_server();
+    if (!s) return KS_E_NOMEM;
+    s->device = device;
+    s->budget = hbm_budget;
+    s->max_slots = max_slots;
+    s->worker = std::thread([s] { s->run(); });
+    ks_status st;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv.wait(lk, [s] { return s->ready; });
+        st = s->init_status;
+    }
+    if (st != KS_OK) {
+        ks_server_destroy(s);
+        return st;
+    }
+    *out = s;
+    return KS_OK;
+}
+
+ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket) {
+    if (!s || !req || !ticket) return KS_E_INVALID;
+    ks_status st = ks::check_request(req->volume, req->dtype, req->dims, req->bins, req->seed_spacing, req->scales,
+                                     req->method, req->max_iter);
+    if (st != KS_OK) return st;
+    SrvReq r;
+    r.in.raw = nullptr;
+    r.in.dtype = req->dtype;
+    std::memcpy(r.in.dims, req->dims, sizeof(r.in.dims));
+    r.in.bins = req->bins;
+    r.in.spacing = req->seed_spacing;
+    r.in.scales[0] = req->scales[0];
+    r.in.scales[1] = req->scales[1];
+    r.in.method = req->method;
+    r.in.max_iter = req->max_iter;
+    r.in.capacity = (int32_t)std::min<int64_t>(ks::num_trajectories(req->dims, req->seed_spacing, req->scales,
+                                                                    req->method), 1 << 20);
+    r.footprint = footprint(r.in);
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->stop) return KS_E_SHUTDOWN;
+    if (s->fatal != KS_OK) return s->fatal;
+    if (r.footprint > s->budget) {
+        s->refused += 1;
+        return KS_E_TOO_LARGE;
+    }
+    const size_t esz = req->dtype == KS_U8 ? 1 : 2;
+    const size_t bytes = esz * (size_t)req->dims[0] * req->dims[1] * req->dims[2];
+    lk.unlock();
+    r.host.assign(static_cast<const uint8_t*>(req->volume), static_cast<const uint8_t*>(req->volume) + bytes);
+    lk.lock();
+    r.t_submit = now_ms();
+    if (s->first_submit < 0) s->first_submit = r.t_submit;
+    const uint64_t t = s->next_ticket++;
+    s->reqs.emplace(t, std::move(r));
+    s->pending.push_back(t);
+    s->submitted += 1;
+    *ticket = t;
+    lk.unlock();
+    s->cv.notify_all();
+    return KS_OK;
+}
+
+ks_status ks_server_poll(ks_server* s, uint64_t ticket, ks_region* out, int32_t capacity, int32_t* n_found) {
+    if (!s || !n_found || capacity < 0 || (capacity > 0 && !out)) return KS_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return KS_E_INVALID;
+    SrvReq& r = it->second;
+    if (r.status == KS_E_NOT_READY) return KS_E_NOT_READY;
+    const ks_status st = (ks_status)r.status;
+    if (st == KS_OK) {
+        const int w = std::min<int>(capacity, (int)r.regions.size());
+        if (w > 0) std::memcpy(out, r.regions.data(), sizeof(ks_region) * (size_t)w);
+        *n_found = r.n_found;
+    }
+    s->reqs.erase(it);
+    return st;
+}
+
+ks_status ks_server_drain(ks_server* s) {
+    if (!s) return KS_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->done_cv.wait(lk, [s] { return (s->pending.empty() && s->in_flight == 0) || s->fatal != KS_OK; });
+    return s->fatal;
+}
+
+ks_status ks_server_stats(ks_server* s, ks_server_stats_t* out) {
+    if (!s || !out) return KS_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->admitted = s->admitted;
+    out->completed = s->completed;
+    out->refused = s->refused;
+    out->queued_now = (int64_t)s->pending.size();
+    out->in_flight = s->in_flight;
+    out->bytes_in_use = (int64_t)s->in_use;
+    out->budget_bytes = (int64_t)s->budget;
+    out->p50_ms = percentile(s->latencies, 0.50);
+    out->p99_ms = percentile(s->latencies, 0.99);
+    double sum = 0;
+    for (double x : s->latencies) sum += x;
+    out->mean_ms = s->latencies.empty() ? 0.0 : sum / (double)s->latencies.size();
+    const double span = s->last_done - s->first_submit;
+    out->volumes_per_s = (s->completed > 0 && span > 0) ? (double)s->completed / (span / 1000.0) : 0.0;
+    return KS_OK;
+}
+
+ks_status ks_server_destroy(ks_server* s) {
+    if (!s) return KS_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (Slot* sl : s->slots) {
+        if (sl->stream) hipStreamSynchronize(sl->stream);
+        sl->ctx.destroy();
+        sl->raw.release();
+        sl->staging.release();
+        if (sl->done) hipEventDestroy(sl->done);
+        if (sl->stream) hipStreamDestroy(sl->stream);
+        delete sl;
+    }
+    delete s;
+    return KS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,346 @@
+"""ctypes binding of libks.so (the gfx950 library), one function per C entry point.
+
+Argument marshalling only: every step of the detection runs in the library's
+kernels.  Device volumes are torch tensors on a ROCm device, shape (Z, Y, X),
+dtype uint8, uint16 or int16, contiguous.  Importing this module does not load
+the library; the first call does, and raises if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libks.so")
+
+KS_OK, KS_E_INVALID, KS_E_NOMEM, KS_E_DEVICE, KS_E_TOO_LARGE, KS_E_NOT_READY, KS_E_SHUTDOWN = 0, -1, -2, -3, -4, -5, -6
+KS_U8, KS_U16, KS_I16 = 0, 1, 2
+KS_QUADRANT, KS_MEANSHIFT = 0, 1
+KS_HIST_CUBE, KS_HIST_OCTANTS, KS_HIST_MEANSHIFT, KS_HIST_SHELLS = 0, 1, 2, 3
+
+EXPORTS = [
+    "ks_status_str", "ks_context_create", "ks_context_destroy", "ks_context_set_profiling", "ks_context_set_tuning",
+    "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
+    "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
+    "ks_server_stats", "ks_server_destroy",
+]
+
+
+class KsError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+class Region(C.Structure):
+    _fields_ = [("x", C.c_int32), ("y", C.c_int32), ("z", C.c_int32), ("scale", C.c_int32),
+                ("saliency", C.c_float), ("entropy", C.c_float), ("pdf_change", C.c_float), ("seed", C.c_int32)]
+
+
+class SeedTrace(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("z0", C.c_int32), ("x", C.c_int32), ("y", C.c_int32),
+                ("z", C.c_int32), ("scale", C.c_int32), ("iters", C.c_int32), ("stop", C.c_int32),
+                ("keep", C.c_int32), ("objective", C.c_double), ("saliency64", C.c_double),
+                ("saliency", C.c_float), ("entropy", C.c_float), ("pdf_change", C.c_float), ("pad", C.c_int32)]
+
+
+class RunStats(C.Structure):
+    _fields_ = [("trajectories", C.c_int64), ("evals", C.c_int64), ("window_evals", C.c_int64),
+                ("voxel_visits", C.c_int64), ("final_visits", C.c_int64), ("regions", C.c_int64),
+                ("ms_prep", C.c_double), ("ms_search", C.c_double), ("ms_rank", C.c_double),
+                ("ms_total", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("volume", C.c_void_p), ("dtype", C.c_int32), ("dims", C.c_int32 * 3), ("bins", C.c_int32),
+                ("seed_spacing", C.c_int32), ("scales", C.c_int32 * 2), ("method", C.c_int32),
+                ("max_iter", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("regions", C.POINTER(Region)), ("capacity", C.c_int32), ("n_found", C.c_int32),
+                ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("refused", C.c_int64),
+                ("queued_now", C.c_int64), ("in_flight", C.c_int64), ("bytes_in_use", C.c_int64),
+                ("budget_bytes", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("mean_ms", C.c_double), ("volumes_per_s", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libks.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i32p = C.c_void_p, C.c_int32, C.POINTER(C.c_int32)
+    L.ks_status_str.argtypes = [i32]
+    L.ks_status_str.restype = C.c_char_p
+    L.ks_context_create.argtypes = [i32, C.POINTER(vp)]
+    L.ks_context_destroy.argtypes = [vp]
+    L.ks_context_set_profiling.argtypes = [vp, i32]
+    L.ks_context_set_tuning.argtypes = [vp, i32, i32]
+    L.ks_last_stats.argtypes = [vp, C.POINTER(RunStats)]
+    L.ks_detect.argtypes = [vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p]
+    L.ks_detect_device.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p, vp]
+    L.ks_seed_traces.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p, vp]
+    L.ks_bin_volume.argtypes = [vp, vp, i32, i32p, i32, vp, vp]
+    L.ks_histograms.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, vp, vp, vp, vp]
+    L.ks_detect_batch.argtypes = [vp, i32, C.POINTER(Request), C.POINTER(Result), vp]
+    L.ks_server_create.argtypes = [i32, C.c_size_t, i32, C.POINTER(vp)]
+    L.ks_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+    L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
+    L.ks_server_drain.argtypes = [vp]
+    L.ks_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.ks_server_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        if name != "ks_status_str":
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    try:
+        return lib().ks_status_str(status).decode()
+    except Exception:  # library missing: still format the error
+        return str(status)
+
+
+def _check(status: int, what: str):
+    if status != KS_OK:
+        raise KsError(status, what)
+
+
+def _i3(v):
+    return (C.c_int32 * 3)(*[int(a) for a in v])
+
+
+def _i2(v):
+    return (C.c_int32 * 2)(*[int(a) for a in v])
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+_NP_DTYPE = {np.dtype(np.uint8): KS_U8, np.dtype(np.uint16): KS_U16, np.dtype(np.int16): KS_I16}
+
+
+def _torch_dtype_code(t):
+    import torch
+    codes = {torch.uint8: KS_U8, torch.int16: KS_I16}
+    if hasattr(torch, "uint16"):
+        codes[torch.uint16] = KS_U16
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported volume dtype {t.dtype}")
+    return codes[t.dtype]
+
+
+def _volume_args(t):
+    """(device pointer, dtype code, dims) of a (Z, Y, X) device tensor."""
+    if not t.is_cuda:
+        raise ValueError("volume must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("volume must be contiguous")
+    if t.dim() != 3:
+        raise ValueError("volume must have shape (Z, Y, X)")
+    z, y, x = t.shape
+    return C.c_void_p(t.data_ptr()), _torch_dtype_code(t), _i3((x, y, z))
+
+
+def regions_to_numpy(arr, n):
+    return np.ctypeslib.as_array(arr)[:n].copy() if n > 0 else np.zeros(0, dtype=np.ctypeslib.as_array(arr).dtype)
+
+
+class Context:
+    """A library context on one device (tables, work arena, graph cache)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().ks_context_create(int(device), C.byref(h)), "ks_context_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().ks_context_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ks_context_set_profiling(ctx: Context, on: bool):
+    _check(lib().ks_context_set_profiling(ctx.handle, 1 if on else 0), "ks_context_set_profiling")
+
+
+def ks_context_set_tuning(ctx: Context, ms_replicas_log2: int, quad_replicas_log2: int):
+    _check(lib().ks_context_set_tuning(ctx.handle, ms_replicas_log2, quad_replicas_log2), "ks_context_set_tuning")
+
+
+def ks_last_stats(ctx: Context) -> dict:
+    st = RunStats()
+    _check(lib().ks_last_stats(ctx.handle, C.byref(st)), "ks_last_stats")
+    return {f: getattr(st, f) for f, _ in RunStats._fields_}
+
+
+def ks_detect(volume: np.ndarray, bins, seed_spacing, scales, method, max_iter, capacity=1024):
+    """Host volume (Z, Y, X) numpy array -> (regions, n_found)."""
+    vol = np.ascontiguousarray(volume)
+    z, y, x = vol.shape
+    out = (Region * max(int(capacity), 1))()
+    nf = C.c_int32()
+    _check(lib().ks_detect(C.c_void_p(vol.ctypes.data), _NP_DTYPE[vol.dtype], _i3((x, y, z)), bins, seed_spacing,
+                           _i2(scales), method, max_iter, out, int(capacity), C.byref(nf)), "ks_detect")
+    return regions_to_numpy(out, min(nf.value, int(capacity))), nf.value
+
+
+def ks_detect_device(ctx: Context, volume, bins, seed_spacing, scales, method, max_iter, capacity=1024, stream=None):
+    ptr, dt, dims = _volume_args(volume)
+    out = (Region * max(int(capacity), 1))()
+    nf = C.c_int32()
+    _check(lib().ks_detect_device(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter, out,
+                                  int(capacity), C.byref(nf), _stream_ptr(stream)), "ks_detect_device")
+    return regions_to_numpy(out, min(nf.value, int(capacity))), nf.value
+
+
+def ks_seed_traces(ctx: Context, volume, bins, seed_spacing, scales, method, max_iter, stream=None):
+    ptr, dt, dims = _volume_args(volume)
+    z, y, x = volume.shape
+    n_est = C.c_int32()
+    # first call with capacity 0 gives the trajectory count
+    _check(lib().ks_seed_traces(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter, None, 0,
+                                C.byref(n_est), _stream_ptr(stream)), "ks_seed_traces")
+    out = (SeedTrace * max(n_est.value, 1))()
+    n = C.c_int32()
+    _check(lib().ks_seed_traces(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter, out,
+                                n_est.value, C.byref(n), _stream_ptr(stream)), "ks_seed_traces")
+    return np.ctypeslib.as_array(out)[:n.value].copy()
+
+
+def ks_bin_volume(ctx: Context, volume, bins, stream=None) -> np.ndarray:
+    ptr, dt, dims = _volume_args(volume)
+    out = np.empty(tuple(volume.shape), np.uint8)
+    _check(lib().ks_bin_volume(ctx.handle, ptr, dt, dims, bins, C.c_void_p(out.ctypes.data), _stream_ptr(stream)),
+           "ks_bin_volume")
+    return out
+
+
+def ks_histograms(ctx: Context, volume, bins, kind, xyz, scale=None, scale_range=(1, 1), stream=None) -> np.ndarray:
+    ptr, dt, dims = _volume_args(volume)
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+    n = xyz.shape[0]
+    K = scale_range[1] - scale_range[0] + 1
+    if kind == KS_HIST_CUBE:
+        out = np.zeros((n, bins), np.uint32)
+    elif kind == KS_HIST_MEANSHIFT:
+        out = np.zeros((n, 4, bins), np.int32)
+    elif kind == KS_HIST_OCTANTS:
+        out = np.zeros((n, 8, K, bins), np.uint32)
+    else:
+        out = np.zeros((n, K, bins), np.uint32)
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.int32)
+    _check(lib().ks_histograms(ctx.handle, ptr, dt, dims, bins, kind, _i2(scale_range), n,
+                               C.c_void_p(xyz.ctypes.data), None if sc is None else C.c_void_p(sc.ctypes.data),
+                               C.c_void_p(out.ctypes.data), _stream_ptr(stream)), "ks_histograms")
+    return out
+
+
+def make_request(volume, bins, seed_spacing, scales, method, max_iter, host=False) -> Request:
+    r = Request()
+    if host:
+        vol = np.ascontiguousarray(volume)
+        z, y, x = vol.shape
+        r.volume = vol.ctypes.data
+        r.dtype = _NP_DTYPE[vol.dtype]
+    else:
+        ptr, dt, _ = _volume_args(volume)
+        z, y, x = volume.shape
+        r.volume = ptr.value
+        r.dtype = dt
+    r.dims[0], r.dims[1], r.dims[2] = x, y, z
+    r.bins, r.seed_spacing = bins, seed_spacing
+    r.scales[0], r.scales[1] = scales
+    r.method, r.max_iter = method, max_iter
+    return r
+
+
+def ks_detect_batch(ctx: Context, requests, capacity=1024, stream=None):
+    """requests: list of Request (device volumes).  Returns a list of (regions, n_found)."""
+    n = len(requests)
+    reqs = (Request * max(n, 1))(*requests)
+    bufs = [(Region * max(int(capacity), 1))() for _ in range(n)]
+    res = (Result * max(n, 1))()
+    for i in range(n):
+        res[i].regions = C.cast(bufs[i], C.POINTER(Region))
+        res[i].capacity = int(capacity)
+    _check(lib().ks_detect_batch(ctx.handle, n, reqs, res, _stream_ptr(stream) if stream is not None else None),
+           "ks_detect_batch")
+    return [(regions_to_numpy(bufs[i], min(res[i].n_found, int(capacity))), res[i].n_found) for i in range(n)]
+
+
+class Server:
+    """Continuous-batching detection server (ks_server_*)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_slots: int = 8):
+        h = C.c_void_p()
+        _check(lib().ks_server_create(int(device), C.c_size_t(int(hbm_budget)), int(max_slots), C.byref(h)),
+               "ks_server_create")
+        self.handle = h
+
+    def submit(self, volume: np.ndarray, bins, seed_spacing, scales, method, max_iter) -> int:
+        r = make_request(volume, bins, seed_spacing, scales, method, max_iter, host=True)
+        t = C.c_uint64()
+        _check(lib().ks_server_submit(self.handle, C.byref(r), C.byref(t)), "ks_server_submit")
+        return t.value
+
+    def poll(self, ticket: int, capacity=1024):
+        out = (Region * max(int(capacity), 1))()
+        nf = C.c_int32()
+        st = lib().ks_server_poll(self.handle, C.c_uint64(ticket), out, int(capacity), C.byref(nf))
+        if st == KS_E_NOT_READY:
+            return None
+        _check(st, "ks_server_poll")
+        return regions_to_numpy(out, min(nf.value, int(capacity))), nf.value
+
+    def drain(self):
+        _check(lib().ks_server_drain(self.handle), "ks_server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ks_server_stats(self.handle, C.byref(st)), "ks_server_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().ks_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

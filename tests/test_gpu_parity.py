@@ -1,0 +1,289 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Integer results (bins, histograms, positions, iterations, stop reasons, scales,
+kept flags, seeds, region order) must be bit-identical; the double-precision
+decision values (objective, saliency used for ranking) must be equal; the
+float32 reported entropy / pdf change / saliency must be within 1e-5 relative of
+the oracle's accurate double values, and exactly zero where those are zero.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_6736_amd import ks, synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    c = ks.Context(0)
+    yield c
+    c.close()
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, vol):
+    return torch.from_numpy(np.ascontiguousarray(vol)).to("cuda:0")
+
+
+def close32(got, want):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    zero = want == 0.0
+    ok = np.abs(got - want) <= RTOL * np.abs(want)
+    return bool(np.all(np.where(zero, got == 0.0, ok)))
+
+
+def random_volume(seed, shape, dtype, lo, hi):
+    rng = np.random.default_rng(seed)
+    v = rng.integers(lo, hi + 1, shape).astype(dtype)
+    # a smoother low-entropy region and a textured block, for skewed histograms
+    z, y, x = shape
+    v[: z // 2, : y // 2, :] = (lo + (hi - lo) // 3)
+    v[z // 3: z // 3 + 5, y // 4: y // 4 + 6, x // 5: x // 5 + 7] = rng.integers(lo, hi + 1, (min(5, z - z // 3),
+                                                                                               min(6, y - y // 4),
+                                                                                               min(7, x - x // 5)))
+    return v
+
+
+# ------------------------------------------------------------------ binning
+
+@pytest.mark.parametrize("case", [
+    ("u8", np.uint8, (13, 17, 23), 0, 255, 32),
+    ("u16", np.uint16, (9, 31, 37), 0, 4095, 64),
+    ("i16", np.int16, (11, 7, 65), -900, 1400, 7),
+    ("i16full", np.int16, (4, 8, 17), -32768, 32767, 256),
+    ("u8narrow", np.uint8, (5, 6, 19), 17, 23, 64),
+])
+def test_bin_volume_bit_exact(torch_dev, ctx, case):
+    name, dt, shape, lo, hi, bins = case
+    note(f"bin_volume {name} {shape} B={bins}")
+    v = random_volume(1, shape, dt, lo, hi)
+    got = ks.ks_bin_volume(ctx, dev(torch_dev, v), bins)
+    assert np.array_equal(got, oracle.bin_volume(v, bins))
+
+
+def test_bin_volume_full_size_workloads(torch_dev, ctx):
+    for w in (synth.pet_shell(ks.KS_QUADRANT), synth.mr_blobs()):
+        note(f"bin_volume {w.name}")
+        got = ks.ks_bin_volume(ctx, dev(torch_dev, w.volume), w.bins)
+        assert np.array_equal(got, oracle.bin_volume(w.volume, w.bins))
+
+
+# --------------------------------------------------------------- histograms
+
+def positions(shape, n, seed):
+    z, y, x = shape
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (x - 1, y - 1, z - 1), (x - 1, 0, z // 2), (x // 2, y // 2, z // 2), (1, y - 2, 3 % z)]
+    pts += [tuple(int(a) for a in rng.integers(0, (x, y, z))) for _ in range(n)]
+    return np.array(pts, np.int32)
+
+
+@pytest.mark.parametrize("bins", [2, 32, 64, 100, 256])
+@pytest.mark.parametrize("rl", [6, 4, 2])
+def test_meanshift_window_stats_bit_exact(torch_dev, ctx, bins, rl):
+    note(f"hist meanshift B={bins} rl={rl}")
+    v = random_volume(bins + rl, (37, 41, 45), np.uint16, 0, 4095)
+    bv = oracle.bin_volume(v, bins)
+    pts = positions(v.shape, 20, 7)
+    rng = np.random.default_rng(3)
+    sc = rng.integers(1, 33, len(pts)).astype(np.int32)
+    sc[:3] = [32, 1, 16]
+    ks.ks_context_set_tuning(ctx, rl, 3)
+    try:
+        got = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_MEANSHIFT, pts, sc)
+        cube = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_CUBE, pts, sc)
+    finally:
+        ks.ks_context_set_tuning(ctx, 6, 3)
+    for i, p in enumerate(pts):
+        counts, msum, _, _ = oracle.eval_meanshift(bv, bins, p, int(sc[i]))
+        assert np.array_equal(got[i, 0], counts.astype(np.int32)), (i, p, sc[i])
+        assert np.array_equal(got[i, 1:].T, msum.astype(np.int32)), (i, p, sc[i])
+        assert np.array_equal(cube[i], counts), (i, p, sc[i])
+
+
+@pytest.mark.parametrize("bins,rng_", [(32, (3, 8)), (64, (4, 16)), (256, (1, 5)), (13, (2, 2)), (64, (1, 32))])
+@pytest.mark.parametrize("rq", [3, 0])
+def test_octant_histograms_bit_exact(torch_dev, ctx, bins, rng_, rq):
+    note(f"hist octants B={bins} range={rng_} rq={rq}")
+    v = random_volume(5, (30, 33, 71), np.uint8, 0, 255)
+    bv = oracle.bin_volume(v, bins)
+    pts = positions(v.shape, 6, 11)
+    ks.ks_context_set_tuning(ctx, 6, rq)
+    try:
+        got = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_OCTANTS, pts, scale_range=rng_)
+    finally:
+        ks.ks_context_set_tuning(ctx, 6, 3)
+    for i, p in enumerate(pts):
+        for j in range(8):
+            for kk, k in enumerate(range(rng_[0], rng_[1] + 1)):
+                assert np.array_equal(got[i, j, kk], oracle.hist_octant(bv, bins, p, j, k)), (i, j, k)
+
+
+@pytest.mark.parametrize("bins,rng_", [(32, (2, 9)), (64, (3, 17)), (256, (0, 4)), (64, (0, 33))])
+def test_centred_shell_histograms_bit_exact(torch_dev, ctx, bins, rng_):
+    note(f"hist shells B={bins} range={rng_}")
+    v = random_volume(6, (40, 29, 50), np.int16, -300, 2000)
+    bv = oracle.bin_volume(v, bins)
+    pts = positions(v.shape, 6, 12)
+    got = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_SHELLS, pts, scale_range=rng_)
+    for i, p in enumerate(pts):
+        for kk, s in enumerate(range(rng_[0], rng_[1] + 1)):
+            assert np.array_equal(got[i, kk], oracle.hist_cube(bv, bins, p, s)), (i, s)
+
+
+# -------------------------------------------------------------- trajectories
+
+def compare_traces(got, want, label):
+    assert len(got) == len(want), label
+    for f in ("x0", "y0", "z0", "x", "y", "z", "scale", "iters", "stop", "keep"):
+        bad = np.nonzero(got[f] != want[f])[0]
+        assert bad.size == 0, f"{label}: {f} differs at {bad[:10]} got {got[f][bad[:5]]} want {want[f][bad[:5]]}"
+    assert np.array_equal(got["objective"], want["objective"]), label
+    assert np.array_equal(got["saliency64"], want["y64"]), label
+    keep = want["keep"] == 1
+    assert close32(got["entropy"][keep], want["h_ref"][keep]), label
+    assert close32(got["pdf_change"][keep], want["w64"][keep]), label
+    assert close32(got["saliency"][keep], want["y_ref"][keep]), label
+
+
+def test_traces_spheres64_quadrant(torch_dev, ctx):
+    w = synth.spheres_64()
+    note(f"traces {w.name}")
+    got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    compare_traces(got, want, w.name)
+
+
+@pytest.mark.parametrize("method", [ks.KS_QUADRANT, ks.KS_MEANSHIFT])
+def test_traces_pet_shell_full(torch_dev, ctx, method):
+    w = synth.pet_shell(method)
+    note(f"traces {w.name}")
+    got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    compare_traces(got, want, w.name)
+
+
+def test_traces_mr_blobs_sampled(torch_dev, ctx):
+    w = synth.mr_blobs()
+    note(f"traces {w.name} (full GPU run, sampled oracle)")
+    got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    S = w.scales[1] - w.scales[0] + 1
+    n_seeds = len(got) // S
+    seeds = np.arange(0, n_seeds, 97)
+    ids = (seeds[:, None] * S + np.arange(S)[None, :]).ravel()
+    want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, ids=ids)
+    compare_traces(got[ids], want, w.name)
+
+
+EDGE_CASES = [
+    ("tiny1", np.uint8, (1, 1, 1), 4, 1, (1, 2), 0, 5),
+    ("line_x", np.uint16, (1, 1, 37), 8, 3, (1, 4), 1, 10),
+    ("flat_z", np.int16, (2, 19, 23), 16, 4, (2, 6), 0, 10),
+    ("scale_exceeds_volume", np.uint8, (6, 7, 9), 32, 2, (10, 12), 1, 10),
+    ("spacing_exceeds_volume", np.uint8, (9, 10, 11), 32, 50, (1, 3), 0, 10),
+    ("max_iter_zero", np.uint8, (20, 21, 22), 32, 5, (2, 4), 1, 0),
+    ("bins2", np.uint8, (17, 18, 19), 2, 4, (1, 3), 0, 10),
+    ("bins256", np.int16, (17, 18, 33), 256, 5, (2, 5), 1, 10),
+    ("bins200_quadrant", np.uint16, (15, 22, 27), 200, 6, (2, 4), 0, 10),
+    ("smax32_meanshift", np.uint8, (70, 69, 71), 64, 30, (31, 32), 1, 4),
+    ("smax32_quadrant", np.uint8, (70, 69, 67), 64, 40, (31, 32), 0, 3),
+    ("smin1_quadrant", np.uint8, (25, 26, 27), 32, 5, (1, 4), 0, 20),
+]
+
+
+@pytest.mark.parametrize("case", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+def test_traces_edge_cases(torch_dev, ctx, case):
+    name, dt, shape, bins, sp, scales, method, max_iter = case
+    note(f"traces edge {name}")
+    hi = 255 if dt == np.uint8 else 4000
+    v = random_volume(zlib.crc32(name.encode()) % 1000, shape, dt, 0, hi)
+    got = ks.ks_seed_traces(ctx, dev(torch_dev, v), bins, sp, scales, method, max_iter)
+    want, _ = oracle.run(v, bins, sp, scales, method, max_iter)
+    compare_traces(got, want, name)
+
+
+def test_constant_volume_finds_nothing(torch_dev, ctx):
+    v = np.full((12, 13, 14), 77, np.uint8)
+    for method in (ks.KS_QUADRANT, ks.KS_MEANSHIFT):
+        note(f"constant volume method={method}")
+        regs, n = ks.ks_detect_device(ctx, dev(torch_dev, v), 32, 3, (1, 3), method, 10)
+        assert n == 0
+        tr = ks.ks_seed_traces(ctx, dev(torch_dev, v), 32, 3, (1, 3), method, 10)
+        assert np.all(tr["keep"] == 0)
+        assert np.all(tr["iters"] == 0)
+
+
+# ------------------------------------------------------------------ detect
+
+def compare_regions(got, n_got, want, n_want, label):
+    assert n_got == n_want, (label, n_got, n_want)
+    assert len(got) == len(want), label
+    for f in ("x", "y", "z", "scale", "seed"):
+        assert np.array_equal(got[f], want[f]), (label, f)
+    assert close32(got["saliency"], want["saliency"]), label
+    assert close32(got["entropy"], want["entropy"]), label
+    assert close32(got["pdf_change"], want["pdf_change"]), label
+
+
+@pytest.mark.parametrize("which", ["spheres64", "pet_quadrant", "pet_meanshift"])
+def test_detect_matches_oracle(torch_dev, ctx, which):
+    w = {"spheres64": synth.spheres_64, "pet_quadrant": lambda: synth.pet_shell(ks.KS_QUADRANT),
+         "pet_meanshift": lambda: synth.pet_shell(ks.KS_MEANSHIFT)}[which]()
+    note(f"detect {w.name}")
+    cap = 100000
+    got, n = ks.ks_detect_device(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter,
+                                 capacity=cap)
+    want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
+    compare_regions(got, n, want, n_want, w.name)
+    # truncation: capacity 20 keeps the top 20 and still reports the total
+    top, n2 = ks.ks_detect_device(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter,
+                                  capacity=20)
+    assert n2 == n_want and np.array_equal(top, got[:20])
+
+
+def test_detect_host_entry_point(torch_dev):
+    w = synth.spheres_64()
+    note("ks_detect host volume")
+    got, n = ks.ks_detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=50)
+    want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=50)
+    compare_regions(got, n, want, n_want, "host")
+
+
+def test_detect_is_deterministic(torch_dev, ctx):
+    w = synth.pet_shell(ks.KS_MEANSHIFT)
+    note("determinism")
+    t = dev(torch_dev, w.volume)
+    a = ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=5000)
+    b = ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=5000)
+    assert a[1] == b[1] and np.array_equal(a[0], b[0])
+
+
+def test_stats_count_the_work(torch_dev, ctx):
+    w = synth.spheres_64()
+    note("stats")
+    ks.ks_detect_device(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    st = ks.ks_last_stats(ctx)
+    _, ost = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    assert st["evals"] == ost["evals"]
+    assert st["window_evals"] == ost["window_evals"]
+    assert st["voxel_visits"] + st["final_visits"] == ost["voxel_visits"]
