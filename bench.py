@@ -35,8 +35,6 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-stride", type=int, default=2)
-    ap.add_argument("--serve", action="store_true", help="also run the serving comparison")
-    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_meanshift_pet.json"))
     return ap.parse_args()
 
@@ -141,8 +139,8 @@ def main():
         "regions": {"quadrant": int(res[0][0]), "meanshift": int(res[1][0])},
         "window_evals_per_step": int(window_evals),
         "device_ms": {"quadrant_search": q_kernel_ms, "meanshift_search": ms_kernel_ms,
-                      "prep_ms": float(np.mean([s["ms_prep"] for s in prof])),
-                      "rank_ms": float(np.mean([s["ms_rank"] for s in prof]))},
+                      "prep_ms": float(np.mean([s["ms_prep"] for _, s in prof])),
+                      "rank_ms": float(np.mean([s["ms_rank"] for _, s in prof]))},
         "roofline": {"bound": "hbm", "kernel": "k_search_ms", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": int(ms_bytes),
@@ -150,9 +148,6 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride)
-    if args.serve:
-        from serve_bench import run_serving  # noqa
-        line["serving"] = run_serving(args.serve_requests)
     ctx.close()
     print(json.dumps(line), flush=True)
 

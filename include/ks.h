@@ -14,7 +14,7 @@
  * Conventions shared by every entry point:
  *  - Volumes are dense arrays of voxels with dims = {X, Y, Z}, x fastest:
  *    index = x + X*(y + Y*z).  dtype is one of ks_dtype.  Each dim is in
- *    [1, 65535] and X*Y*Z < 2^31.
+ *    [1, 65535] and ceil(X/16)*16*Y*Z < 2^31.
  *  - bins in [2, 256]: a voxel v falls in bin floor((v - vmin)*bins / (vmax - vmin + 1))
  *    over the volume's own [vmin, vmax] (the paper's beta(s), Eq. 4, left
  *    undefined there).

@@ -9,12 +9,17 @@
 //                  sums in one 64-bit LDS add), merges them lane-per-bin and takes
 //                  the move and the Bhattacharyya objective by butterfly sums
 //   k_search_quad  persistent; one 256-thread workgroup runs one quadrant
-//                  trajectory (Sec. 2.2, Alg. 1): per evaluation, 8 octant passes
-//                  scatter the octant brick into shell-bucketed LDS histograms,
-//                  prefix them over the shell radius and take all entropies
+//                  trajectory (Sec. 2.2, Alg. 1): per evaluation it scatters the 8
+//                  octant bricks into shell-bucketed LDS histograms (one region per
+//                  octant), prefixes them over the shell radius and takes all 8*S
+//                  entropies in one pass
 //   both kernels end each trajectory with the Kadir-Brady saliency pass at the
 //   converged position and write one TrajRec
 //   k_compact / bitonic / dedup / emit    rank on the device
+//
+// Voxel bricks are read with buffer loads: the lane part of the address is fixed
+// for a whole window and each step adds one scalar offset, with several steps'
+// loads in flight before their bytes are scattered.
 //
 // Decision arithmetic (argmax over scale, moves, acceptance, peaks, ranking) is
 // IEEE double with contraction disabled (-ffp-contract=off) and every sum over
@@ -28,6 +33,8 @@
 namespace ks {
 
 // ------------------------------------------------------------------ helpers
+
+constexpr int kUnroll = 4;  // window rows whose loads are in flight together
 
 __device__ __forceinline__ double bfly_sum(double v) {
 #pragma unroll
@@ -47,14 +54,13 @@ __device__ __forceinline__ long long bfly_sumll(long long v) {
     return v;
 }
 
-// Halving tree over a lane's m (1, 2 or 4) contiguous bins.
-__device__ __forceinline__ double local_pw(const double* v, int m) {
-    if (m == 1) return v[0];
-    if (m == 2) return v[0] + v[1];
+// Halving tree over a lane's M (1, 2 or 4) contiguous bins.
+template <int M>
+__device__ __forceinline__ double local_pw(const double* v) {
+    if (M == 1) return v[0];
+    if (M == 2) return v[0] + v[1];
     return (v[0] + v[1]) + (v[2] + v[3]);
 }
-
-__device__ __forceinline__ int bins_per_lane(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -68,30 +74,104 @@ __device__ __forceinline__ int64_t cube_count(const VolDesc& v, int px, int py, 
     return clipped_len(px, r, v.X) * clipped_len(py, r, v.Y) * clipped_len(pz, r, v.Z);
 }
 
-// Lane layout of a box scan: each active lane owns one dword column d of a row
-// (oy, oz) inside a tile of ty x tz rows; tiles then sweep the box.
-struct TileMap {
-    int ty, tz;
-    int oy, oz, d;
-    bool on;
-};
-
-__device__ __forceinline__ TileMap tile_map(int nd, int ny, int nz, int nt, int tid) {
-    TileMap m;
-    m.ty = min(ny, nt / nd);
-    m.tz = min(nz, nt / (m.ty * nd));
-    int per_z = m.ty * nd;
-    m.on = tid < m.tz * per_z;
-    m.oz = tid / per_z;
-    int rem = tid - m.oz * per_z;
-    m.oy = rem / nd;
-    m.d = rem - m.oy * nd;
-    return m;
+// Buffer descriptor of the bin volume; base and size are made scalar explicitly
+// so that every load of a sweep uses one descriptor held in SGPRs.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bins_rsrc(const VolDesc& v) {
+    const uint64_t a = reinterpret_cast<uint64_t>(v.bins);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+    const int bytes = __builtin_amdgcn_readfirstlane((int)(v.slice * v.Z));
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
 }
 
-__device__ __forceinline__ uint32_t load_word(const VolDesc& v, int y, int z, int x0) {
-    const uint8_t* p = v.bins + (size_t)z * (size_t)v.slice + (size_t)y * (size_t)v.xp + (size_t)x0;
-    return *reinterpret_cast<const uint32_t*>(p);
+// A box [xa,xb]x[ya,yb]x[za,zb] swept by NT lanes: each active lane owns one
+// dword column of one row of a ty x tz tile of rows; the tile then steps through
+// the box, first along y, then along z.  All fields except the lane ones are
+// uniform.
+struct Sweep {
+    int ny, nz, nd, ty, tz, nsteps;
+    int xa, ya, za;
+    // lane part
+    bool on;
+    int oy, oz, x0;
+    uint32_t voff;      // byte offset of the lane's dword at the first step
+};
+
+template <int NT>
+__device__ __forceinline__ Sweep make_sweep(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb,
+                                            int tid) {
+    Sweep w;
+    w.xa = xa; w.ya = ya; w.za = za;
+    w.ny = yb - ya + 1;
+    w.nz = zb - za + 1;
+    const int da = xa >> 2;
+    w.nd = (xb >> 2) - da + 1;
+    w.ty = min(w.ny, NT / w.nd);
+    w.tz = min(w.nz, NT / (w.ty * w.nd));
+    const int steps_y = (w.ny + w.ty - 1) / w.ty;
+    w.nsteps = steps_y * ((w.nz + w.tz - 1) / w.tz);
+    const int per_z = w.ty * w.nd;
+    w.on = tid < w.tz * per_z;
+    w.oz = tid / per_z;
+    const int rem = tid - w.oz * per_z;
+    w.oy = rem / w.nd;
+    const int d = rem - w.oy * w.nd;
+    w.x0 = (da + d) * 4;
+    w.voff = (uint32_t)(za + w.oz) * (uint32_t)v.slice + (uint32_t)(ya + w.oy) * (uint32_t)v.xp + (uint32_t)w.x0;
+    return w;
+}
+
+// Walks the sweep's steps, kUnroll rows per group, with the next group's loads
+// issued before the current group is scattered; calls f(word, iy0, iz0) for every
+// step in which the lane's row lies inside the box.  After each group that brings
+// the step count to `every`, flush() runs (uniformly).
+template <typename F, typename G>
+__device__ __forceinline__ void run_sweep(const VolDesc& v, const Sweep& w, int every, F&& f, G&& flush) {
+    const __amdgpu_buffer_rsrc_t rs = bins_rsrc(v);
+    const uint32_t xp = (uint32_t)uniform(v.xp), slice = (uint32_t)uniform((int)v.slice);
+    const int ny = uniform(w.ny), ty = uniform(w.ty), tz = uniform(w.tz), nsteps = uniform(w.nsteps);
+    const int lim_y = w.ny - w.oy, lim_z = w.nz - w.oz;
+    int iy0 = 0, iz0 = 0, since = 0;
+    uint32_t cur[kUnroll];
+    int cy[kUnroll], cz[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        cy[u] = iy0;
+        cz[u] = iz0;
+        cur[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
+        iy0 += ty;
+        if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
+    }
+    for (int t = 0; t < nsteps; t += kUnroll) {
+        // loads past the last step read beyond the box (or past the descriptor's
+        // end, which returns 0) and are never used
+        uint32_t nxt[kUnroll];
+        int ny_[kUnroll], nz_[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            ny_[u] = iy0;
+            nz_[u] = iz0;
+            nxt[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
+            iy0 += ty;
+            if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (w.on && cy[u] < lim_y && cz[u] < lim_z) f(cur[u], cy[u], cz[u]);
+        }
+        since += kUnroll;
+        if (since >= every) {
+            since = 0;
+            flush();
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            cur[u] = nxt[u];
+            cy[u] = ny_[u];
+            cz[u] = nz_[u];
+        }
+    }
 }
 
 // ------------------------------------------------------------------ prep
@@ -117,7 +197,9 @@ __device__ __forceinline__ int read_raw(const void* raw, int dtype, int64_t i) {
     return static_cast<const int16_t*>(raw)[i];
 }
 
+// Range scan: per-thread, per-wave and per-block reduction, one atomic pair per block.
 __global__ __launch_bounds__(256) void k_minmax(const VolDesc* vols) {
+    __shared__ int slo[4], shi[4];
     const VolDesc& v = vols[blockIdx.y];
     const int64_t n = (int64_t)v.X * v.Y * v.Z;
     int lo = INT_MAX, hi = INT_MIN;
@@ -132,6 +214,15 @@ __global__ __launch_bounds__(256) void k_minmax(const VolDesc* vols) {
         hi = max(hi, __shfl_xor(hi, m, 64));
     }
     if ((threadIdx.x & 63) == 0) {
+        slo[threadIdx.x >> 6] = lo;
+        shi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            lo = min(lo, slo[w]);
+            hi = max(hi, shi[w]);
+        }
         atomicMin(&v.minmax[0], lo);
         atomicMax(&v.minmax[1], hi);
     }
@@ -165,108 +256,101 @@ __global__ __launch_bounds__(256) void k_quantize(const VolDesc* vols) {
 
 // ------------------------------------------------- mean-shift window scatter
 
-// Scatter the cube P + [-s, s]^3 (clipped) of one wavefront into its packed
-// per-replica LDS histogram hist[(bin << rl) + replica] and flush into per-lane
-// bin totals c/f1/f2/f3 (bins lane*m .. lane*m+m-1).  Search mode: f1..f3 are the
-// sums of (dx+s), (dy+s), (dz+s).  Final mode: f1 counts the voxels of the inner
-// cube of half-width s-1, f2 = f3 = 0.
-template <bool FINAL>
-__device__ void ms_window(const VolDesc& v, int px, int py, int pz, int s, int rl, unsigned long long* hist, int lane,
-                          int* c, int* f1, int* f2, int* f3) {
-    const int B = v.B;
-    const int m = bins_per_lane(B);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) c[t] = f1[t] = f2[t] = f3[t] = 0;
-    const int xa = max(px - s, 0), xb = min(px + s, v.X - 1);
-    const int ya = max(py - s, 0), yb = min(py + s, v.Y - 1);
-    const int za = max(pz - s, 0), zb = min(pz + s, v.Z - 1);
-    const int ny = yb - ya + 1, nz = zb - za + 1;
-    const int da = xa >> 2, nd = (xb >> 2) - da + 1;
-    const TileMap tm = tile_map(nd, ny, nz, 64, lane);
+// Per-lane totals of the lane's M bins lane*M .. lane*M+M-1.
+template <int M>
+struct BinAcc {
+    int c[M], f1[M], f2[M], f3[M];
+};
+
+template <int M>
+__device__ __forceinline__ void ms_flush(unsigned long long* hist, int rl, int B, int lane, BinAcc<M>& a) {
     const int R = 1 << rl;
-    const int rep = lane & (R - 1);
-    const uint32_t shift = (uint32_t)rl + 3;
-    const uint32_t trash = ((uint32_t)((B << rl) | rep)) << 3;
-    const uint32_t repoff = (uint32_t)rep << 3;
-    const int x0 = (da + tm.d) * 4;
-    uint32_t lo[4], off[4], wid[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int x = x0 + k;
-        const bool ok = x >= xa && x <= xb;
-        const int dx = x - px;
-        lo[k] = FINAL ? (1u | ((uint32_t)(dx < s && dx > -s) << 10)) : (1u | ((uint32_t)(dx + s) << 10));
-        off[k] = ok ? repoff : trash;
-        wid[k] = ok ? 8u : 0u;
-    }
-    // Each replica may take kMaxPerReplica voxels between flushes: a step adds at
-    // most 4 voxels per lane and 64/R lanes share a replica.
-    const int flush_every = (kMaxPerReplica << rl) >> 8;
-    int since = 0;
-    for (int iz0 = 0; iz0 < nz; iz0 += tm.tz) {
-        for (int iy0 = 0; iy0 < ny; iy0 += tm.ty) {
-            const int iy = iy0 + tm.oy, iz = iz0 + tm.oz;
-            if (tm.on && iy < ny && iz < nz) {
-                const int y = ya + iy, z = za + iz;
-                const uint32_t w = load_word(v, y, z, x0);
-                uint32_t hi;
-                uint32_t le[4];
-                if (FINAL) {
-                    const bool inner = (y - py < s) && (py - y < s) && (z - pz < s) && (pz - z < s);
-                    hi = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) le[k] = inner ? lo[k] : 1u;
-                } else {
-                    hi = (uint32_t)(y - py + s) | ((uint32_t)(z - pz + s) << 16);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) le[k] = lo[k];
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t b = __builtin_amdgcn_ubfe(w, 8 * k, wid[k]);
-                    const uint32_t addr = (b << shift) + off[k];
-                    atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(hist) + addr),
-                              ((unsigned long long)hi << 32) | le[k]);
-                }
-            }
-            if (++since == flush_every) {
-                since = 0;
-                __syncthreads();
-                for (int t = 0; t < m; ++t) {
-                    const int b = lane * m + t;
-                    if (b < B) {
-                        unsigned long long* e = hist + ((size_t)b << rl);
-                        for (int i = 0; i < R; ++i) {
-                            const int r = (i + lane) & (R - 1);
-                            const unsigned long long val = e[r];
-                            e[r] = 0ull;
-                            c[t] += (int)(val & 0x3FFull);
-                            f1[t] += (int)((val >> 10) & 0xFFFFull);
-                            f2[t] += (int)((val >> 32) & 0xFFFFull);
-                            f3[t] += (int)(val >> 48);
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-    }
-    __syncthreads();
-    for (int t = 0; t < m; ++t) {
-        const int b = lane * m + t;
+    for (int t = 0; t < M; ++t) {
+        const int b = lane * M + t;
         if (b < B) {
             unsigned long long* e = hist + ((size_t)b << rl);
             for (int i = 0; i < R; ++i) {
                 const int r = (i + lane) & (R - 1);
                 const unsigned long long val = e[r];
                 e[r] = 0ull;
-                c[t] += (int)(val & 0x3FFull);
-                f1[t] += (int)((val >> 10) & 0xFFFFull);
-                f2[t] += (int)((val >> 32) & 0xFFFFull);
-                f3[t] += (int)(val >> 48);
+                a.c[t] += (int)(val & 0x3FFull);
+                a.f1[t] += (int)((val >> 10) & 0xFFFFull);
+                a.f2[t] += (int)((val >> 32) & 0xFFFFull);
+                a.f3[t] += (int)(val >> 48);
             }
         }
     }
+}
+
+// Scatter the cube P + [-s, s]^3 (clipped) into the wavefront's packed
+// per-replica LDS histogram hist[(bin << rl) + replica] and flush into per-lane
+// bin totals.  Search mode: f1..f3 are the sums of (dx+s), (dy+s), (dz+s).  Final
+// mode: f1 counts the voxels of the inner cube of half-width s-1, f2 = f3 = 0.
+template <bool FINAL, int M>
+__device__ void ms_window(const VolDesc& v, int px, int py, int pz, int s, int rl, unsigned long long* hist, int lane,
+                          BinAcc<M>& acc) {
+    px = uniform(px); py = uniform(py); pz = uniform(pz); s = uniform(s); rl = uniform(rl);
+    const int B = v.B;
+#pragma unroll
+    for (int t = 0; t < M; ++t) acc.c[t] = acc.f1[t] = acc.f2[t] = acc.f3[t] = 0;
+    const int xa = max(px - s, 0), xb = min(px + s, v.X - 1);
+    const int ya = max(py - s, 0), yb = min(py + s, v.Y - 1);
+    const int za = max(pz - s, 0), zb = min(pz + s, v.Z - 1);
+    const Sweep w = make_sweep<64>(v, xa, xb, ya, yb, za, zb, lane);
+    const int R = 1 << rl;
+    const int rep = lane & (R - 1);
+    const uint32_t shift = (uint32_t)rl + 3;
+    const uint32_t trash = ((uint32_t)((B << rl) | rep)) << 3;
+    const uint32_t repoff = (uint32_t)rep << 3;
+    uint32_t lo[4], off[4], wid[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = w.x0 + k;
+        const bool ok = x >= xa && x <= xb;
+        const int dx = x - px;
+        lo[k] = FINAL ? (1u | ((uint32_t)(dx < s && dx > -s) << 10)) : (1u | ((uint32_t)(dx + s) << 10));
+        off[k] = ok ? repoff : trash;
+        wid[k] = ok ? 8u : 0u;
+    }
+    // offsets of the lane's first row, biased by s
+    const uint32_t hi0 = (uint32_t)(ya + w.oy - py + s) | ((uint32_t)(za + w.oz - pz + s) << 16);
+    const uint32_t two_s = 2u * (uint32_t)s;
+    // Each replica may take kMaxPerReplica voxels between flushes: a step adds at
+    // most 4 voxels per lane and 64/R lanes share a replica.
+    const int every = max(kUnroll, (((kMaxPerReplica << rl) >> 8) / kUnroll) * kUnroll);
+    run_sweep(
+        v, w, every,
+        [&](uint32_t word, int iy0, int iz0) {
+            const uint32_t hi = hi0 + ((uint32_t)iy0 | ((uint32_t)iz0 << 16));
+            uint32_t le[4];
+            uint32_t hv;
+            if (FINAL) {
+                const uint32_t fy = hi & 0xFFFFu, fz = hi >> 16;
+                const bool inner = fy >= 1u && fy < two_s && fz >= 1u && fz < two_s;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) le[k] = inner ? lo[k] : 1u;
+                hv = 0u;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) le[k] = lo[k];
+                hv = hi;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t b = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
+                const uint32_t addr = (b << shift) + off[k];
+                atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(hist) + addr),
+                          ((unsigned long long)hv << 32) | le[k]);
+            }
+        },
+        [&]() {
+            __syncthreads();
+            ms_flush<M>(hist, rl, B, lane, acc);
+            __syncthreads();
+        });
+    __syncthreads();
+    ms_flush<M>(hist, rl, B, lane, acc);
     __syncthreads();
 }
 
@@ -276,25 +360,25 @@ struct EvalOut {
 
 // Eq. 4-6 with a flat kernel and the uniform target: move = (sum_b M_b/sqrt(c_b)) /
 // (sum_b sqrt(c_b)), objective rho~ = (sum_b sqrt(c_b)) / sqrt(N).
+template <int M>
 __device__ EvalOut ms_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, int rl,
                            unsigned long long* hist, int lane) {
-    int c[4], f1[4], f2[4], f3[4];
-    ms_window<false>(v, px, py, pz, s, rl, hist, lane, c, f1, f2, f3);
-    const int m = bins_per_lane(v.B);
-    double sq[4], tx[4], ty[4], tz[4];
+    BinAcc<M> a;
+    ms_window<false, M>(v, px, py, pz, s, rl, hist, lane, a);
+    double sq[M], tx[M], ty[M], tz[M];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const bool nz = t < m && c[t] > 0;
-        const double rs = nz ? tb.rsq[c[t]] : 0.0;
-        sq[t] = nz ? tb.sq[c[t]] : 0.0;
-        tx[t] = nz ? (double)(f1[t] - c[t] * s) * rs : 0.0;
-        ty[t] = nz ? (double)(f2[t] - c[t] * s) * rs : 0.0;
-        tz[t] = nz ? (double)(f3[t] - c[t] * s) * rs : 0.0;
+    for (int t = 0; t < M; ++t) {
+        const bool nz = a.c[t] > 0;
+        const double rs = nz ? tb.rsq[a.c[t]] : 0.0;
+        sq[t] = nz ? tb.sq[a.c[t]] : 0.0;
+        tx[t] = nz ? (double)(a.f1[t] - a.c[t] * s) * rs : 0.0;
+        ty[t] = nz ? (double)(a.f2[t] - a.c[t] * s) * rs : 0.0;
+        tz[t] = nz ? (double)(a.f3[t] - a.c[t] * s) * rs : 0.0;
     }
-    const double D = bfly_sum(local_pw(sq, m));
-    const double nx = bfly_sum(local_pw(tx, m));
-    const double ny = bfly_sum(local_pw(ty, m));
-    const double nzs = bfly_sum(local_pw(tz, m));
+    const double D = bfly_sum(local_pw<M>(sq));
+    const double nx = bfly_sum(local_pw<M>(tx));
+    const double ny = bfly_sum(local_pw<M>(ty));
+    const double nzs = bfly_sum(local_pw<M>(tz));
     const int64_t N = cube_count(v, px, py, pz, s);
     EvalOut e;
     e.obj = D / tb.sq[N];
@@ -318,27 +402,25 @@ __device__ __forceinline__ float entropy_term32(int c, int64_t N) {
 }
 
 // Kadir-Brady saliency at the trajectory's own scale (mean-shift).
+template <int M>
 __device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, int rl,
                                 unsigned long long* hist, int lane) {
-    int c[4], in[4], u2[4], u3[4];
-    ms_window<true>(v, px, py, pz, s, rl, hist, lane, c, in, u2, u3);
-    const int m = bins_per_lane(v.B);
+    BinAcc<M> a;
+    ms_window<true, M>(v, px, py, pz, s, rl, hist, lane, a);
     const int64_t Ns = cube_count(v, px, py, pz, s);
     const int64_t Np = cube_count(v, px, py, pz, s - 1);
-    double cl[4];
-    long long a = 0;
+    double cl[M];
+    long long am = 0;
     float h = 0.0f;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        cl[t] = t < m ? tb.cl[c[t]] : 0.0;
-        if (t < m) {
-            long long d = (long long)c[t] * Np - (long long)in[t] * Ns;
-            a += d < 0 ? -d : d;
-            h += entropy_term32(c[t], Ns);
-        }
+    for (int t = 0; t < M; ++t) {
+        cl[t] = tb.cl[a.c[t]];
+        long long d = (long long)a.c[t] * Np - (long long)a.f1[t] * Ns;
+        am += d < 0 ? -d : d;
+        h += entropy_term32(a.c[t], Ns);
     }
-    const double S = bfly_sum(local_pw(cl, m));
-    const long long A = bfly_sumll(a);
+    const double S = bfly_sum(local_pw<M>(cl));
+    const long long A = bfly_sumll(am);
     const float H32 = bfly_sumf(h);
     const double H64 = (tb.cl[Ns] - S) / (double)Ns;
     const double W64 = ((double)(s * s) / (double)(2 * s - 1)) * ((double)A / ((double)Ns * (double)Np));
@@ -381,8 +463,66 @@ struct LocalCounts {
     unsigned long long evals, window_evals, voxel_visits, final_visits;
 };
 
+// The search loop shared by both methods: round the proposed move, stop if it is
+// zero, if clamping leaves P unchanged, if the objective does not strictly
+// increase, or after max_iter accepted moves.  Every lane holds the same values;
+// positions and the stop decision are made scalar with readfirstlane.
+struct TrajOut {
+    int p[3];
+    int iters, stop;
+    double obj;
+};
+
+template <typename Eval>
+__device__ __forceinline__ TrajOut run_trajectory(const VolDesc& v, const int* p0, Eval&& eval, LocalCounts& lc,
+                                                  int visit_r, int win_evals) {
+    TrajOut o;
+    o.p[0] = p0[0]; o.p[1] = p0[1]; o.p[2] = p0[2];
+    EvalOut cur = eval(o.p[0], o.p[1], o.p[2]);
+    lc.evals += 1;
+    lc.window_evals += (unsigned long long)win_evals;
+    lc.voxel_visits += cube_count(v, o.p[0], o.p[1], o.p[2], visit_r);
+    int it = 0, stop;
+    for (;;) {
+        if (it == v.max_iter) { stop = 0; break; }
+        const int mx = uniform((int)round(cur.dx));
+        const int my = uniform((int)round(cur.dy));
+        const int mz = uniform((int)round(cur.dz));
+        if (mx == 0 && my == 0 && mz == 0) { stop = 1; break; }
+        const int qx = clampi(o.p[0] + mx, 0, v.X - 1);
+        const int qy = clampi(o.p[1] + my, 0, v.Y - 1);
+        const int qz = clampi(o.p[2] + mz, 0, v.Z - 1);
+        if (qx == o.p[0] && qy == o.p[1] && qz == o.p[2]) { stop = 2; break; }
+        const EvalOut nxt = eval(qx, qy, qz);
+        lc.evals += 1;
+        lc.window_evals += (unsigned long long)win_evals;
+        lc.voxel_visits += cube_count(v, qx, qy, qz, visit_r);
+        if (!uniform(nxt.obj > cur.obj ? 1 : 0)) { stop = 3; break; }
+        o.p[0] = qx; o.p[1] = qy; o.p[2] = qz;
+        cur = nxt;
+        it += 1;
+    }
+    o.iters = it;
+    o.stop = stop;
+    o.obj = cur.obj;
+    return o;
+}
+
+__device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const TrajOut& o, const Saliency& sal,
+                                          int32_t id) {
+    TrajRec r;
+    r.x0 = p0[0]; r.y0 = p0[1]; r.z0 = p0[2];
+    r.x = o.p[0]; r.y = o.p[1]; r.z = o.p[2];
+    r.scale = sal.scale; r.iters = o.iters; r.stop = o.stop; r.keep = sal.keep;
+    r.objective = o.obj; r.y64 = sal.y64;
+    r.h32 = sal.h32; r.w32 = sal.w32; r.y32 = sal.y32;
+    r.seed = id;
+    *dst = r;
+}
+
 // ------------------------------------------------------- mean-shift kernel
 
+template <int M>
 __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* vols, const TaskSeg* segs, int nseg, long long ntask,
                                                   Tables tb, TrajRec* out, Counters* cnt, int rl, int hist_words) {
     extern __shared__ unsigned long long hist[];
@@ -402,42 +542,14 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* vols, const Tas
         const int s = sg.scale;
         int p0[3];
         seed_pos(v, seed, p0);
-        int p[3] = {p0[0], p0[1], p0[2]};
-        EvalOut cur = ms_eval(v, tb, p[0], p[1], p[2], s, rl, hist, lane);
-        lc.evals += 1;
-        lc.window_evals += 1;
-        lc.voxel_visits += cube_count(v, p[0], p[1], p[2], s);
-        int it = 0, stop;
-        for (;;) {
-            if (it == v.max_iter) { stop = 0; break; }
-            const int mx = (int)round(cur.dx), my = (int)round(cur.dy), mz = (int)round(cur.dz);
-            if (mx == 0 && my == 0 && mz == 0) { stop = 1; break; }
-            const int qx = clampi(p[0] + mx, 0, v.X - 1);
-            const int qy = clampi(p[1] + my, 0, v.Y - 1);
-            const int qz = clampi(p[2] + mz, 0, v.Z - 1);
-            if (qx == p[0] && qy == p[1] && qz == p[2]) { stop = 2; break; }
-            const EvalOut nxt = ms_eval(v, tb, qx, qy, qz, s, rl, hist, lane);
-            lc.evals += 1;
-            lc.window_evals += 1;
-            lc.voxel_visits += cube_count(v, qx, qy, qz, s);
-            if (!(nxt.obj > cur.obj)) { stop = 3; break; }
-            p[0] = qx; p[1] = qy; p[2] = qz;
-            cur = nxt;
-            it += 1;
-        }
-        const Saliency sal = ms_saliency(v, tb, p[0], p[1], p[2], s, rl, hist, lane);
-        lc.final_visits += cube_count(v, p[0], p[1], p[2], s);
+        const TrajOut o = run_trajectory(
+            v, p0, [&](int x, int y, int z) { return ms_eval<M>(v, tb, x, y, z, s, rl, hist, lane); }, lc, s, 1);
+        const Saliency sal = ms_saliency<M>(v, tb, o.p[0], o.p[1], o.p[2], s, rl, hist, lane);
+        lc.final_visits += cube_count(v, o.p[0], o.p[1], o.p[2], s);
         lc.window_evals += 2;
         if (lane == 0) {
             const long long local = seed * v.S + (s - v.s_min);
-            TrajRec r;
-            r.x0 = p0[0]; r.y0 = p0[1]; r.z0 = p0[2];
-            r.x = p[0]; r.y = p[1]; r.z = p[2];
-            r.scale = sal.scale; r.iters = it; r.stop = stop; r.keep = sal.keep;
-            r.objective = cur.obj; r.y64 = sal.y64;
-            r.h32 = sal.h32; r.w32 = sal.w32; r.y32 = sal.y32;
-            r.seed = (int32_t)local;
-            out[v.traj_base + local] = r;
+            write_rec(out + v.traj_base + local, p0, o, sal, (int32_t)local);
         }
     }
     if (lane == 0) {
@@ -450,146 +562,245 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* vols, const Tas
 
 // ------------------------------------------------ quadrant: bucketed scatter
 
-// Scatter the box [xa,xb]x[ya,yb]x[za,zb] into hist[((row*B + bin) << rq) + replica]
-// (uint32), row = max(max(|x-cx|,|y-cy|,|z-cz|) - base, 0); bytes outside the box go
-// to row trash_row.
+// Scatter the box into hist (uint32 counters) at byte offset
+//   region + ((row*B + bin) << rq)*4 + replica*4,
+// row = max(max(|x-cx|,|y-cy|,|z-cz|) - base, 0); bytes outside the box go to
+// row trash_row.
 template <int NT>
 __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx, int cy,
-                               int cz, int base, int trash_row, int rq, uint32_t* hist, int tid) {
-    const int ny = yb - ya + 1, nz = zb - za + 1;
-    const int da = xa >> 2, nd = (xb >> 2) - da + 1;
-    const TileMap tm = tile_map(nd, ny, nz, NT, tid);
+                               int cz, int base, int trash_row, int rq, uint32_t region, uint32_t* hist, int tid) {
+    const Sweep w = make_sweep<NT>(v, xa, xb, ya, yb, za, zb, tid);
     const uint32_t rowbytes = (uint32_t)v.B << (rq + 2);
-    const uint32_t rep4 = (uint32_t)(tid & ((1 << rq) - 1)) << 2;
+    const uint32_t rep4 = ((uint32_t)(tid & ((1 << rq) - 1)) << 2) + region;
     const uint32_t bshift = (uint32_t)rq + 2;
-    const int x0 = (da + tm.d) * 4;
     uint32_t rx[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int x = x0 + k;
+        const int x = w.x0 + k;
         const bool ok = x >= xa && x <= xb;
         const int r = ok ? max(abs(x - cx) - base, 0) : trash_row;
         rx[k] = (uint32_t)r * rowbytes + rep4;
     }
-    for (int iz0 = 0; iz0 < nz; iz0 += tm.tz) {
-        for (int iy0 = 0; iy0 < ny; iy0 += tm.ty) {
-            const int iy = iy0 + tm.oy, iz = iz0 + tm.oz;
-            if (tm.on && iy < ny && iz < nz) {
-                const int y = ya + iy, z = za + iz;
-                const uint32_t w = load_word(v, y, z, x0);
-                const int rr = max(max(abs(y - cy), abs(z - cz)) - base, 0);
-                const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
+    const int dy0 = ya + w.oy - cy, dz0 = za + w.oz - cz;
+    run_sweep(
+        v, w, INT_MAX,
+        [&](uint32_t word, int iy0, int iz0) {
+            const int rr = max(max(abs(dy0 + iy0), abs(dz0 + iz0)) - base, 0);
+            const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t b = (w >> (8 * k)) & 0xFFu;
-                    const uint32_t addr = max(rx[k], RR) + (b << bshift);
-                    atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(hist) + addr), 1u);
-                }
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t b = (word >> (8 * k)) & 0xFFu;
+                const uint32_t addr = max(rx[k], RR) + (b << bshift);
+                atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(hist) + addr), 1u);
             }
-        }
-    }
+        },
+        []() {});
 }
 
-// Sum replicas, prefix over rows: cnt[r][b] = voxels of bin b in rows 0..r.
-// Clears the histogram rows 0..nrows (the last one is the trash row).
+// One sweep over the brick P + [-s_max, s_max]^3 (clipped) for all 8 octants:
+// a voxel at offset d goes to octant j (bit a set when d_a > 0), and to the
+// mirrored octants along every axis with d_a = 0 (the planes through P belong to
+// both sides); row = max(max|d_a| - base, 0), region j at byte j * region_bytes.
 template <int NT>
-__device__ void bucket_merge(uint32_t* hist, uint32_t* cnt, int nrows, int B, int rq, int tid) {
+__device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int R, int base, int trash_row, int rq,
+                               uint32_t region_bytes, uint32_t* hist, int tid) {
+    const int xa = max(px - R, 0), xb = min(px + R, v.X - 1);
+    const int ya = max(py - R, 0), yb = min(py + R, v.Y - 1);
+    const int za = max(pz - R, 0), zb = min(pz + R, v.Z - 1);
+    const Sweep w = make_sweep<NT>(v, xa, xb, ya, yb, za, zb, tid);
+    const uint32_t rowbytes = (uint32_t)v.B << (rq + 2);
+    const uint32_t rep4 = (uint32_t)(tid & ((1 << rq) - 1)) << 2;
+    const uint32_t bshift = (uint32_t)rq + 2;
+    uint32_t rx[4], jx[4];
+    bool xdup[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = w.x0 + k;
+        const bool ok = x >= xa && x <= xb;
+        const int r = ok ? max(abs(x - px) - base, 0) : trash_row;
+        rx[k] = (uint32_t)r * rowbytes + rep4;
+        jx[k] = x > px ? 1u : 0u;
+        xdup[k] = ok && x == px;
+    }
+    const int dy0 = ya + w.oy - py, dz0 = za + w.oz - pz;
+    char* hb = reinterpret_cast<char*>(hist);
+    run_sweep(
+        v, w, INT_MAX,
+        [&](uint32_t word, int iy0, int iz0) {
+            const int dy = dy0 + iy0, dz = dz0 + iz0;
+            const int rr = max(max(abs(dy), abs(dz)) - base, 0);
+            const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
+            const uint32_t jyz = (dy > 0 ? 2u : 0u) | (dz > 0 ? 4u : 0u);
+            const bool ydup = dy == 0, zdup = dz == 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t b = (word >> (8 * k)) & 0xFFu;
+                const uint32_t a = max(rx[k], RR) + (b << bshift);
+                const uint32_t j = jx[k] | jyz;
+                atomicAdd(reinterpret_cast<uint32_t*>(hb + a + j * region_bytes), 1u);
+                if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 1u) * region_bytes), 1u);
+                if (ydup) {
+                    atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 2u) * region_bytes), 1u);
+                    if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 3u) * region_bytes), 1u);
+                }
+                if (zdup) {
+                    atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 4u) * region_bytes), 1u);
+                    if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 5u) * region_bytes), 1u);
+                    if (ydup) {
+                        atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 6u) * region_bytes), 1u);
+                        if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 7u) * region_bytes), 1u);
+                    }
+                }
+            }
+        },
+        []() {});
+}
+
+// Sum the replicas of every (region, bin) and prefix over rows 0..nrows-1, in
+// place: replica 0 of row r then holds the voxels of bin b in rows 0..r; other
+// replicas and the trash row are cleared.
+template <int NT>
+__device__ void bucket_merge(uint32_t* hist, int nreg, int nrows, int B, int rq, int tid) {
     const int R = 1 << rq;
-    for (int b = tid; b < B; b += NT) {
+    const int rows_total = nrows + 1;
+    for (int p = tid; p < nreg * B; p += NT) {
+        const int g = p / B, b = p - g * B;
         uint32_t acc = 0;
         for (int r = 0; r <= nrows; ++r) {
+            const int e = ((g * rows_total + r) * B + b) << rq;
             uint32_t sum = 0;
             for (int q = 0; q < R; ++q) {
-                const int idx = ((r * B + b) << rq) + ((q + b) & (R - 1));
-                sum += hist[idx];
-                hist[idx] = 0u;
+                sum += hist[e + q];
+                hist[e + q] = 0u;
             }
             if (r < nrows) {
                 acc += sum;
-                cnt[r * B + b] = acc;
+                hist[e] = acc;
             }
         }
     }
 }
 
-// H64 = (cl[N] - sum_b cl[c_b]) / N of row r, summed by the lane butterfly.
-__device__ __forceinline__ double row_entropy64(const uint32_t* row, int B, int64_t N, const Tables& tb, int lane) {
-    const int m = bins_per_lane(B);
-    double v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int b = lane * m + t;
-        v[t] = (t < m && b < B) ? tb.cl[row[b]] : 0.0;
-    }
-    const double S = bfly_sum(local_pw(v, m));
-    return (tb.cl[N] - S) / (double)N;
+__device__ __forceinline__ uint32_t merged(const uint32_t* hist, int g, int rows_total, int r, int B, int b, int rq) {
+    return hist[((g * rows_total + r) * B + b) << rq];
 }
 
 struct QuadLds {
     uint32_t* hist;
-    uint32_t* cnt;
-    double* eps;    // [8][S]
-    double* hrow;   // [S+2]
+    double* eps;     // [8][S]
+    double* hrow;    // [S+2]
     long long* arow; // [S+2]
-    double* res;    // [4]
+    float* h32row;   // [S+2]
+    double* res;     // [4]
 };
 
 __device__ __forceinline__ QuadLds quad_lds(char* smem, const LdsQuad& L) {
     QuadLds q;
     q.hist = reinterpret_cast<uint32_t*>(smem + L.hist_off);
-    q.cnt = reinterpret_cast<uint32_t*>(smem + L.cnt_off);
     q.eps = reinterpret_cast<double*>(smem + L.eps_off);
     q.hrow = reinterpret_cast<double*>(smem + L.hrow_off);
     q.arow = reinterpret_cast<long long*>(smem + L.arow_off);
+    q.h32row = reinterpret_cast<float*>(smem + L.h32_off);
     q.res = reinterpret_cast<double*>(smem + L.res_off);
     return q;
 }
 
-// Alg. 1 body in 3D: octant entropies for every scale, per octant the first
-// maximising scale, E = sum of the 8 maxima, move = sum_j eps_j k*_j sigma_j / E.
-template <int NT>
-__device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq, const QuadLds& L,
-                             int tid) {
-    const int S = v.S, B = v.B;
+// Entropy H64 = (cl[N] - sum_b cl[c_b]) / N of merged rows; wave w takes rows
+// w, w + NW, ..., kRowBatch at a time so that their table loads are in flight
+// together; N of a row from nrow(g, r).  The replica-0 counters read here are
+// cleared.
+constexpr int kRowBatch = 8;
+
+template <int NT, int M, typename NF>
+__device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows, int B, int rq, const Tables& tb,
+                                             NF&& nrow, double* out, int tid) {
     const int wave = tid >> 6, lane = tid & 63;
-    for (int j = 0; j < 8; ++j) {
-        const int sx = (j & 1) ? 1 : -1, sy = (j & 2) ? 1 : -1, sz = (j & 4) ? 1 : -1;
-        const int xa = sx > 0 ? px : max(px - v.s_max, 0), xb = sx > 0 ? min(px + v.s_max, v.X - 1) : px;
-        const int ya = sy > 0 ? py : max(py - v.s_max, 0), yb = sy > 0 ? min(py + v.s_max, v.Y - 1) : py;
-        const int za = sz > 0 ? pz : max(pz - v.s_max, 0), zb = sz > 0 ? min(pz + v.s_max, v.Z - 1) : pz;
-        bucket_scatter<NT>(v, xa, xb, ya, yb, za, zb, px, py, pz, v.s_min, S, rq, L.hist, tid);
-        __syncthreads();
-        bucket_merge<NT>(L.hist, L.cnt, S, B, rq, tid);
-        __syncthreads();
-        const int rx = sx > 0 ? v.X - 1 - px : px, ry = sy > 0 ? v.Y - 1 - py : py, rz = sz > 0 ? v.Z - 1 - pz : pz;
-        for (int r = wave; r < S; r += NT / 64) {
-            const int k = v.s_min + r;
-            const int64_t N = (int64_t)(min(k, rx) + 1) * (min(k, ry) + 1) * (min(k, rz) + 1);
-            const double h = row_entropy64(L.cnt + r * B, B, N, tb, lane);
-            if (lane == 0) L.eps[j * S + r] = h;
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double best[8];
-        int ks[8];
-        for (int j = 0; j < 8; ++j) {
-            best[j] = L.eps[j * S];
-            ks[j] = v.s_min;
-            for (int r = 1; r < S; ++r) {
-                const double e = L.eps[j * S + r];
-                if (e > best[j]) { best[j] = e; ks[j] = v.s_min + r; }
+    const int rows_total = nrows + 1;
+    const int nq = nreg * nrows;
+    for (int q0 = wave; q0 < nq; q0 += kRowBatch * (NT / 64)) {
+        double v[kRowBatch][M];
+#pragma unroll
+        for (int i = 0; i < kRowBatch; ++i) {
+            const int q = q0 + i * (NT / 64);
+            const int g = q / nrows, r = q - g * nrows;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                const int b = lane * M + t;
+                uint32_t c = 0;
+                if (q < nq && b < B) {
+                    const int e = ((g * rows_total + r) * B + b) << rq;
+                    c = hist[e];
+                    hist[e] = 0u;
+                }
+                v[i][t] = tb.cl[c];
             }
         }
-        const double E = ((best[0] + best[1]) + (best[2] + best[3])) + ((best[4] + best[5]) + (best[6] + best[7]));
-        double d[3];
-        for (int a = 0; a < 3; ++a) {
-            double t[8];
-            for (int j = 0; j < 8; ++j) t[j] = best[j] * (double)(ks[j] * (((j >> a) & 1) ? 1 : -1));
-            const double num = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
-            d[a] = E == 0.0 ? 0.0 : num / E;
+#pragma unroll
+        for (int i = 0; i < kRowBatch; ++i) {
+            const int q = q0 + i * (NT / 64);
+            const double S = bfly_sum(local_pw<M>(v[i]));
+            if (lane == 0 && q < nq) {
+                const int g = q / nrows, r = q - g * nrows;
+                const int64_t N = nrow(g, r);
+                out[q] = (tb.cl[N] - S) / (double)N;
+            }
         }
-        L.res[0] = E; L.res[1] = d[0]; L.res[2] = d[1]; L.res[3] = d[2];
+    }
+}
+
+// Alg. 1 body in 3D: octant entropies for every scale, per octant the first
+// maximising scale, E = sum of the 8 maxima, move = sum_j eps_j k*_j sigma_j / E.
+template <int NT, int M>
+__device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq, const QuadLds& L,
+                             int tid) {
+    px = uniform(px); py = uniform(py); pz = uniform(pz);
+    const int S = v.S, B = v.B;
+    const uint32_t region_bytes = (uint32_t)(S + 1) * (uint32_t)B << (rq + 2);
+    octant_scatter<NT>(v, px, py, pz, v.s_max, v.s_min, S, rq, region_bytes, L.hist, tid);
+    __syncthreads();
+    bucket_merge<NT>(L.hist, 8, S, B, rq, tid);
+    __syncthreads();
+    rows_entropy<NT, M>(
+        L.hist, 8, S, B, rq, tb,
+        [&](int j, int r) {
+            const int k = v.s_min + r;
+            const int rx = (j & 1) ? v.X - 1 - px : px, ry = (j & 2) ? v.Y - 1 - py : py;
+            const int rz = (j & 4) ? v.Z - 1 - pz : pz;
+            return (int64_t)(min(k, rx) + 1) * (min(k, ry) + 1) * (min(k, rz) + 1);
+        },
+        L.eps, tid);
+    __syncthreads();
+    if (tid < 64) {
+        // lane j < 8 scans octant j over k (first maximum); lane 0 combines
+        double best = 0.0;
+        int ks = v.s_min;
+        if (tid < 8) {
+            best = L.eps[tid * S];
+            for (int r = 1; r < S; ++r) {
+                const double e = L.eps[tid * S + r];
+                if (e > best) { best = e; ks = v.s_min + r; }
+            }
+        }
+        double b8[8];
+        int k8[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            b8[j] = __shfl(best, j, 64);
+            k8[j] = __shfl(ks, j, 64);
+        }
+        if (tid == 0) {
+            const double E = ((b8[0] + b8[1]) + (b8[2] + b8[3])) + ((b8[4] + b8[5]) + (b8[6] + b8[7]));
+            double d[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double t[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) t[j] = b8[j] * (double)(k8[j] * (((j >> a) & 1) ? 1 : -1));
+                const double num = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+                d[a] = E == 0.0 ? 0.0 : num / E;
+            }
+            L.res[0] = E; L.res[1] = d[0]; L.res[2] = d[1]; L.res[3] = d[2];
+        }
     }
     __syncthreads();
     EvalOut e;
@@ -601,38 +812,50 @@ __device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py,
 // Kadir-Brady saliency at P* for the quadrant method: centred cubes of every
 // half-width s in [s_min-1, s_max+1], entropy peaks over s in [s_min, s_max], the
 // peak with the largest H*W (first on ties).
-template <int NT>
+template <int NT, int M>
 __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq,
                                   const QuadLds& L, int tid) {
+    px = uniform(px); py = uniform(py); pz = uniform(pz);
     const int S = v.S, B = v.B;
     const int nrows = S + 2;
     const int base = v.s_min - 1;
     const int wave = tid >> 6, lane = tid & 63;
     const int R = v.s_max + 1;
     bucket_scatter<NT>(v, max(px - R, 0), min(px + R, v.X - 1), max(py - R, 0), min(py + R, v.Y - 1),
-                       max(pz - R, 0), min(pz + R, v.Z - 1), px, py, pz, base, nrows, rq, L.hist, tid);
+                       max(pz - R, 0), min(pz + R, v.Z - 1), px, py, pz, base, nrows, rq, 0u, L.hist, tid);
     __syncthreads();
-    bucket_merge<NT>(L.hist, L.cnt, nrows, B, rq, tid);
+    bucket_merge<NT>(L.hist, 1, nrows, B, rq, tid);
     __syncthreads();
-    const int m = bins_per_lane(B);
+    // pdf change numerators and float entropies need the counts: read them before
+    // rows_entropy clears them
     for (int r = wave; r < nrows; r += NT / 64) {
         const int s = base + r;
         const int64_t N = cube_count(v, px, py, pz, s);
-        const double h = row_entropy64(L.cnt + r * B, B, N, tb, lane);
+        const int64_t Np = r > 0 ? cube_count(v, px, py, pz, s - 1) : 1;
         long long a = 0;
-        if (r > 0) {
-            const int64_t Np = cube_count(v, px, py, pz, s - 1);
-            for (int t = 0; t < m; ++t) {
-                const int b = lane * m + t;
-                if (b < B) {
-                    long long d = (long long)L.cnt[r * B + b] * Np - (long long)L.cnt[(r - 1) * B + b] * N;
+        float h = 0.0f;
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const int b = lane * M + t;
+            if (b < B) {
+                const uint32_t c = merged(L.hist, 0, nrows + 1, r, B, b, rq);
+                h += entropy_term32((int)c, N);
+                if (r > 0) {
+                    long long d = (long long)c * Np - (long long)merged(L.hist, 0, nrows + 1, r - 1, B, b, rq) * N;
                     a += d < 0 ? -d : d;
                 }
             }
         }
         a = bfly_sumll(a);
-        if (lane == 0) { L.hrow[r] = h; L.arow[r] = a; }
+        h = bfly_sumf(h);
+        if (lane == 0) {
+            L.arow[r] = a;
+            L.h32row[r] = h;
+        }
     }
+    __syncthreads();
+    rows_entropy<NT, M>(
+        L.hist, 1, nrows, B, rq, tb, [&](int, int r) { return cube_count(v, px, py, pz, base + r); }, L.hrow, tid);
     __syncthreads();
     if (tid == 0) {
         int best = -1;
@@ -651,7 +874,7 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
     }
     __syncthreads();
     Saliency out;
-    const int best = (int)L.res[0];
+    const int best = uniform((int)L.res[0]);
     out.scale = best < 0 ? 0 : best;
     out.y64 = best < 0 ? 0.0 : L.res[1];
     out.keep = 0;
@@ -660,13 +883,8 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
         const int r = best - base;
         const int64_t N = cube_count(v, px, py, pz, best);
         const int64_t Np = cube_count(v, px, py, pz, best - 1);
-        float h = 0.0f;
-        for (int t = 0; t < m; ++t) {
-            const int b = lane * m + t;
-            if (b < B) h += entropy_term32((int)L.cnt[r * B + b], N);
-        }
-        out.h32 = bfly_sumf(h);
         const long long A = L.arow[r];
+        out.h32 = L.h32row[r];
         out.w32 = ((float)(best * best) / (float)(2 * best - 1)) * ((float)A / ((float)N * (float)Np));
         out.y32 = out.h32 * out.w32;
         out.keep = (L.hrow[r] > v.h_min && out.y64 > v.y_min) ? 1 : 0;
@@ -677,6 +895,7 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
 
 // --------------------------------------------------------- quadrant kernel
 
+template <int M>
 __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* vols, const TaskSeg* segs, int nseg,
                                                      long long ntask, Tables tb, TrajRec* out, Counters* cnt,
                                                      int rq, LdsQuad lay) {
@@ -702,42 +921,13 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* vols, const 
         const long long seed = sg.seed_begin + (t - sg.task_begin);
         int p0[3];
         seed_pos(v, seed, p0);
-        int p[3] = {p0[0], p0[1], p0[2]};
-        EvalOut cur = quad_eval<256>(v, tb, p[0], p[1], p[2], rq, L, tid);
-        lc.evals += 1;
-        lc.window_evals += 8ull * v.S;
-        lc.voxel_visits += cube_count(v, p[0], p[1], p[2], v.s_max);
-        int it = 0, stop;
-        for (;;) {
-            if (it == v.max_iter) { stop = 0; break; }
-            const int mx = (int)round(cur.dx), my = (int)round(cur.dy), mz = (int)round(cur.dz);
-            if (mx == 0 && my == 0 && mz == 0) { stop = 1; break; }
-            const int qx = clampi(p[0] + mx, 0, v.X - 1);
-            const int qy = clampi(p[1] + my, 0, v.Y - 1);
-            const int qz = clampi(p[2] + mz, 0, v.Z - 1);
-            if (qx == p[0] && qy == p[1] && qz == p[2]) { stop = 2; break; }
-            const EvalOut nxt = quad_eval<256>(v, tb, qx, qy, qz, rq, L, tid);
-            lc.evals += 1;
-            lc.window_evals += 8ull * v.S;
-            lc.voxel_visits += cube_count(v, qx, qy, qz, v.s_max);
-            if (!(nxt.obj > cur.obj)) { stop = 3; break; }
-            p[0] = qx; p[1] = qy; p[2] = qz;
-            cur = nxt;
-            it += 1;
-        }
-        const Saliency sal = quad_saliency<256>(v, tb, p[0], p[1], p[2], rq, L, tid);
-        lc.final_visits += cube_count(v, p[0], p[1], p[2], v.s_max + 1);
+        const TrajOut o = run_trajectory(
+            v, p0, [&](int x, int y, int z) { return quad_eval<256, M>(v, tb, x, y, z, rq, L, tid); }, lc, v.s_max,
+            8 * v.S);
+        const Saliency sal = quad_saliency<256, M>(v, tb, o.p[0], o.p[1], o.p[2], rq, L, tid);
+        lc.final_visits += cube_count(v, o.p[0], o.p[1], o.p[2], v.s_max + 1);
         lc.window_evals += (unsigned long long)v.S + 2ull;
-        if (tid == 0) {
-            TrajRec r;
-            r.x0 = p0[0]; r.y0 = p0[1]; r.z0 = p0[2];
-            r.x = p[0]; r.y = p[1]; r.z = p[2];
-            r.scale = sal.scale; r.iters = it; r.stop = stop; r.keep = sal.keep;
-            r.objective = cur.obj; r.y64 = sal.y64;
-            r.h32 = sal.h32; r.w32 = sal.w32; r.y32 = sal.y32;
-            r.seed = (int32_t)seed;
-            out[v.traj_base + seed] = r;
-        }
+        if (tid == 0) write_rec(out + v.traj_base + seed, p0, o, sal, (int32_t)seed);
     }
     if (tid == 0) {
         atomicAdd(&cnt->evals, lc.evals);
@@ -749,6 +939,7 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* vols, const 
 
 // ------------------------------------------------------------ test hooks
 
+template <int M>
 __global__ __launch_bounds__(64) void k_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc,
                                                 int rl, int hist_words, void* outp) {
     extern __shared__ unsigned long long hist[];
@@ -756,23 +947,24 @@ __global__ __launch_bounds__(64) void k_hook_ms(const VolDesc* vols, int kind, i
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
     __syncthreads();
     const VolDesc v = vols[0];
-    const int B = v.B, m = bins_per_lane(B);
+    const int B = v.B;
     for (int w = blockIdx.x; w < n; w += gridDim.x) {
         const int px = xyz[3 * w], py = xyz[3 * w + 1], pz = xyz[3 * w + 2], s = sc[w];
-        int c[4], f1[4], f2[4], f3[4];
-        if (kind == 0) ms_window<true>(v, px, py, pz, s, rl, hist, lane, c, f1, f2, f3);
-        else ms_window<false>(v, px, py, pz, s, rl, hist, lane, c, f1, f2, f3);
-        for (int t = 0; t < m; ++t) {
-            const int b = lane * m + t;
+        BinAcc<M> a;
+        if (kind == 0) ms_window<true, M>(v, px, py, pz, s, rl, hist, lane, a);
+        else ms_window<false, M>(v, px, py, pz, s, rl, hist, lane, a);
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const int b = lane * M + t;
             if (b >= B) continue;
             if (kind == 0) {
-                static_cast<uint32_t*>(outp)[(size_t)w * B + b] = (uint32_t)c[t];
+                static_cast<uint32_t*>(outp)[(size_t)w * B + b] = (uint32_t)a.c[t];
             } else {
                 int* o = static_cast<int*>(outp) + (size_t)w * 4 * B;
-                o[b] = c[t];
-                o[B + b] = f1[t] - c[t] * s;
-                o[2 * B + b] = f2[t] - c[t] * s;
-                o[3 * B + b] = f3[t] - c[t] * s;
+                o[b] = a.c[t];
+                o[B + b] = a.f1[t] - a.c[t] * s;
+                o[2 * B + b] = a.f2[t] - a.c[t] * s;
+                o[3 * B + b] = a.f3[t] - a.c[t] * s;
             }
         }
     }
@@ -790,30 +982,30 @@ __global__ __launch_bounds__(256) void k_hook_quad(const VolDesc* vols, int kind
     __syncthreads();
     const VolDesc v = vols[0];
     const int B = v.B, K = hi - lo + 1;
+    const uint32_t region_bytes = (uint32_t)(K + 1) * (uint32_t)B << (rq + 2);
     for (int w = blockIdx.x; w < n; w += gridDim.x) {
         const int px = xyz[3 * w], py = xyz[3 * w + 1], pz = xyz[3 * w + 2];
+        const int nreg = kind == 1 ? 8 : 1;
         if (kind == 1) {
-            for (int j = 0; j < 8; ++j) {
-                const int sx = (j & 1) ? 1 : -1, sy = (j & 2) ? 1 : -1, sz = (j & 4) ? 1 : -1;
-                const int xa = sx > 0 ? px : max(px - hi, 0), xb = sx > 0 ? min(px + hi, v.X - 1) : px;
-                const int ya = sy > 0 ? py : max(py - hi, 0), yb = sy > 0 ? min(py + hi, v.Y - 1) : py;
-                const int za = sz > 0 ? pz : max(pz - hi, 0), zb = sz > 0 ? min(pz + hi, v.Z - 1) : pz;
-                bucket_scatter<256>(v, xa, xb, ya, yb, za, zb, px, py, pz, lo, K, rq, L.hist, tid);
-                __syncthreads();
-                bucket_merge<256>(L.hist, L.cnt, K, B, rq, tid);
-                __syncthreads();
-                for (int i = tid; i < K * B; i += 256) outp[((size_t)w * 8 + j) * K * B + i] = L.cnt[i];
-                __syncthreads();
-            }
+            octant_scatter<256>(v, px, py, pz, hi, lo, K, rq, region_bytes, L.hist, tid);
         } else {
             bucket_scatter<256>(v, max(px - hi, 0), min(px + hi, v.X - 1), max(py - hi, 0), min(py + hi, v.Y - 1),
-                                max(pz - hi, 0), min(pz + hi, v.Z - 1), px, py, pz, lo, K, rq, L.hist, tid);
-            __syncthreads();
-            bucket_merge<256>(L.hist, L.cnt, K, B, rq, tid);
-            __syncthreads();
-            for (int i = tid; i < K * B; i += 256) outp[(size_t)w * K * B + i] = L.cnt[i];
-            __syncthreads();
+                                max(pz - hi, 0), min(pz + hi, v.Z - 1), px, py, pz, lo, K, rq, 0u, L.hist, tid);
         }
+        __syncthreads();
+        bucket_merge<256>(L.hist, nreg, K, B, rq, tid);
+        __syncthreads();
+        for (int i = tid; i < nreg * K * B; i += 256) {
+            const int g = i / (K * B), rem = i - g * K * B, r = rem / B, b = rem - r * B;
+            const int e = ((g * (K + 1) + r) * B + b) << rq;
+            outp[(size_t)w * nreg * K * B + i] = L.hist[e];
+        }
+        __syncthreads();
+        for (int i = tid; i < nreg * K * B; i += 256) {
+            const int g = i / (K * B), rem = i - g * K * B, r = rem / B, b = rem - r * B;
+            L.hist[((g * (K + 1) + r) * B + b) << rq] = 0u;
+        }
+        __syncthreads();
     }
 }
 
@@ -924,21 +1116,29 @@ __device__ __forceinline__ bool first_of_region(const SortRec* sr, unsigned long
     return a.vol != b.vol || a.kpos != b.kpos;
 }
 
-// Per 1024-element block: number of distinct regions; per volume: regions found.
+// Per 1024-element block: number of distinct regions; per volume: regions found
+// (one atomic per wavefront and volume).
 __global__ __launch_bounds__(1024) void k_dedup_count(const SortRec* sr, const Counters* cnt, int* bsum,
                                                       int* vol_nfound) {
     __shared__ int wsum[16];
     const unsigned long long count = cnt->n_sort;
     const unsigned long long i = (unsigned long long)blockIdx.x * 1024 + threadIdx.x;
-    int f = 0;
-    if (i < count && first_of_region(sr, i)) {
-        f = 1;
-        atomicAdd(&vol_nfound[sr[i].vol], 1);
+    const int lane = threadIdx.x & 63;
+    const int f = (i < count && first_of_region(sr, i)) ? 1 : 0;
+    const int vol = i < count ? (int)sr[i].vol : -1;
+    const unsigned long long fmask = __ballot(f);
+    if (fmask) {
+        const int lead = __ffsll((long long)fmask) - 1;
+        const int lv = __shfl(vol, lead, 64);
+        const bool same = f && vol == lv;
+        const unsigned long long smask = __ballot(same);
+        if (lane == lead) atomicAdd(&vol_nfound[lv], (int)__popcll(smask));
+        if (f && !same) atomicAdd(&vol_nfound[vol], 1);
     }
     int s = f;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) s += __shfl_xor(s, m, 64);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    if (lane == 0) wsum[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
@@ -1014,6 +1214,7 @@ __global__ __launch_bounds__(256) void k_emit(const SortRec* sr, const Counters*
 }
 
 // ------------------------------------------------------------ launchers
+// ------------------------------------------------------------ launchers
 
 static int grid_for(long long n, int threads, int cap) {
     long long g = (n + threads - 1) / threads;
@@ -1024,32 +1225,59 @@ static int grid_for(long long n, int threads, int cap) {
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_prep_init, dim3((a.nvol + 255) / 256), dim3(256), 0, st, a.vols, a.nvol, a.cnt,
                        a.vol_nfound, a.vol_base);
-    const int gx = grid_for(a.max_voxels, 256, 2048);
+    const int gx = grid_for(a.max_voxels, 256 * 16, 512);
     hipLaunchKernelGGL(k_minmax, dim3(gx, a.nvol), dim3(256), 0, st, a.vols);
     const int gq = grid_for(a.max_words, 256, 4096);
     hipLaunchKernelGGL(k_quantize, dim3(gq, a.nvol), dim3(256), 0, st, a.vols);
     return hipGetLastError();
 }
 
-hipError_t launch_search_ms(const SearchArgs& a, int grid, int rl, int hist_words, hipStream_t st) {
+int bins_per_lane_host(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
+
+hipError_t launch_search_ms(const SearchArgs& a, int grid, int rl, int hist_words, int maxB, hipStream_t st) {
     if (a.ntask <= 0) return hipSuccess;
     const size_t lds = (size_t)hist_words * 8;
-    hipLaunchKernelGGL(k_search_ms, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb, a.rec,
-                       a.cnt, rl, hist_words);
+    const int M = bins_per_lane_host(maxB);
+    if (M == 1)
+        hipLaunchKernelGGL(k_search_ms<1>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
+                           a.rec, a.cnt, rl, hist_words);
+    else if (M == 2)
+        hipLaunchKernelGGL(k_search_ms<2>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
+                           a.rec, a.cnt, rl, hist_words);
+    else
+        hipLaunchKernelGGL(k_search_ms<4>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
+                           a.rec, a.cnt, rl, hist_words);
     return hipGetLastError();
 }
 
-hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, hipStream_t st) {
+hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, int maxB, hipStream_t st) {
     if (a.ntask <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_search_quad, dim3(grid), dim3(256), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
-                       a.rec, a.cnt, rq, lay);
+    const int M = bins_per_lane_host(maxB);
+    if (M == 1)
+        hipLaunchKernelGGL(k_search_quad<1>, dim3(grid), dim3(256), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
+                           a.tb, a.rec, a.cnt, rq, lay);
+    else if (M == 2)
+        hipLaunchKernelGGL(k_search_quad<2>, dim3(grid), dim3(256), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
+                           a.tb, a.rec, a.cnt, rq, lay);
+    else
+        hipLaunchKernelGGL(k_search_quad<4>, dim3(grid), dim3(256), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
+                           a.tb, a.rec, a.cnt, rq, lay);
     return hipGetLastError();
 }
 
 hipError_t launch_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc, int rl, int hist_words,
-                          void* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_hook_ms, dim3(grid_for(n, 1, 4096)), dim3(64), (size_t)hist_words * 8, st, vols, kind, n,
-                       xyz, sc, rl, hist_words, out);
+                          int maxB, void* out, hipStream_t st) {
+    const int M = bins_per_lane_host(maxB);
+    const size_t lds = (size_t)hist_words * 8;
+    if (M == 1)
+        hipLaunchKernelGGL(k_hook_ms<1>, dim3(grid_for(n, 1, 4096)), dim3(64), lds, st, vols, kind, n, xyz, sc, rl,
+                           hist_words, out);
+    else if (M == 2)
+        hipLaunchKernelGGL(k_hook_ms<2>, dim3(grid_for(n, 1, 4096)), dim3(64), lds, st, vols, kind, n, xyz, sc, rl,
+                           hist_words, out);
+    else
+        hipLaunchKernelGGL(k_hook_ms<4>, dim3(grid_for(n, 1, 4096)), dim3(64), lds, st, vols, kind, n, xyz, sc, rl,
+                           hist_words, out);
     return hipGetLastError();
 }
 
@@ -1089,16 +1317,24 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-int max_blocks_ms(int hist_words) {
+int max_blocks_ms(int hist_words, int maxB) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms, 64, (size_t)hist_words * 8) != hipSuccess)
-        return 1;
+    const int M = bins_per_lane_host(maxB);
+    const size_t lds = (size_t)hist_words * 8;
+    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<1>, 64, lds)
+                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<2>, 64, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<4>, 64, lds);
+    if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 
-int max_blocks_quad(size_t lds_bytes) {
+int max_blocks_quad(size_t lds_bytes, int maxB) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad, 256, lds_bytes) != hipSuccess) return 1;
+    const int M = bins_per_lane_host(maxB);
+    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<1>, 256, lds_bytes)
+                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<2>, 256, lds_bytes)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<4>, 256, lds_bytes);
+    if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 

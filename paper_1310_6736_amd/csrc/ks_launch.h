@@ -18,7 +18,7 @@ struct ks_region_dev {
 
 // Byte offsets of the quadrant kernel's dynamic LDS.
 struct LdsQuad {
-    size_t hist_off, cnt_off, eps_off, hrow_off, arow_off, res_off, bytes;
+    size_t hist_off, eps_off, hrow_off, arow_off, h32_off, res_off, bytes;
     int hist_words;
     int pad;
 };
@@ -59,14 +59,14 @@ struct RankArgs {
 };
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
-hipError_t launch_search_ms(const SearchArgs& a, int grid, int rl, int hist_words, hipStream_t st);
-hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, hipStream_t st);
+hipError_t launch_search_ms(const SearchArgs& a, int grid, int rl, int hist_words, int maxB, hipStream_t st);
+hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, int maxB, hipStream_t st);
 hipError_t launch_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc, int rl, int hist_words,
-                          void* out, hipStream_t st);
+                          int maxB, void* out, hipStream_t st);
 hipError_t launch_hook_quad(const VolDesc* vols, int kind, int lo, int hi, int n, const int* xyz, int rq,
                             const LdsQuad& lay, uint32_t* out, hipStream_t st);
 hipError_t launch_rank(const RankArgs& a, hipStream_t st);
-int max_blocks_ms(int hist_words);
-int max_blocks_quad(size_t lds_bytes);
+int max_blocks_ms(int hist_words, int maxB);
+int max_blocks_quad(size_t lds_bytes, int maxB);
 
 }  // namespace ks

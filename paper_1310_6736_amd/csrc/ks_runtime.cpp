@@ -23,7 +23,8 @@ static bool dims_ok(const int32_t* d) {
     if (!d) return false;
     for (int a = 0; a < 3; ++a)
         if (d[a] < 1 || d[a] > 65535) return false;
-    return (int64_t)d[0] * d[1] * d[2] < (int64_t(1) << 31);
+    // the bin volume, rows padded to 16 bytes, is addressed with 32-bit offsets
+    return (int64_t)((d[0] + 15) & ~15) * d[1] * d[2] < (int64_t(1) << 31);
 }
 
 ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
@@ -176,16 +177,14 @@ int pick_ms_rl(int maxB, int pref) {
     return rl;
 }
 
+// Quadrant LDS: 8 octant regions of (S+1) rows (S shells and a trash row) x B bins
+// x replicas; the saliency pass reuses it as one region of S+3 rows.
 LdsQuad quad_layout(int maxS, int maxB, int rq) {
     LdsQuad L;
-    const size_t rows = (size_t)maxS + 3;
     size_t off = 0;
     L.hist_off = off;
-    L.hist_words = (int)(rows * maxB * ((size_t)1 << rq));
+    L.hist_words = (int)(8 * ((size_t)maxS + 1) * maxB * ((size_t)1 << rq));
     off += (size_t)L.hist_words * 4;
-    off = (off + 15) & ~(size_t)15;
-    L.cnt_off = off;
-    off += (rows - 1) * maxB * 4;
     off = (off + 15) & ~(size_t)15;
     L.eps_off = off;
     off += 8 * (size_t)maxS * 8;
@@ -193,6 +192,9 @@ LdsQuad quad_layout(int maxS, int maxB, int rq) {
     off += (size_t)(maxS + 2) * 8;
     L.arow_off = off;
     off += (size_t)(maxS + 2) * 8;
+    L.h32_off = off;
+    off += (size_t)(maxS + 2) * 4;
+    off = (off + 15) & ~(size_t)15;
     L.res_off = off;
     off += 4 * 8;
     L.bytes = (off + 15) & ~(size_t)15;
@@ -202,7 +204,7 @@ LdsQuad quad_layout(int maxS, int maxB, int rq) {
 
 int pick_quad_rq(int maxS, int maxB, int pref) {
     int rq = pref;
-    while (rq > 0 && quad_layout(maxS, maxB, rq).bytes > 40 * 1024) --rq;
+    while (rq > 0 && quad_layout(maxS, maxB, rq).bytes > 64 * 1024) --rq;
     return rq;
 }
 
@@ -349,14 +351,14 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
     SearchArgs sm = sq;
     sm.segs = ds + p.segs_q.size(); sm.nseg = (int)p.segs_m.size(); sm.ntask = p.ntask_m;
     if (p.ntask_q > 0) {
-        const int per_cu = max_blocks_quad(p.lay.bytes);
+        const int per_cu = max_blocks_quad(p.lay.bytes, p.maxB_quad);
         const long long g = std::min<long long>(p.ntask_q, std::max<long long>(1, (long long)per_cu * num_cu * grid_pct / 100));
-        KS_HIP(launch_search_quad(sq, (int)g, p.rq, p.lay, st));
+        KS_HIP(launch_search_quad(sq, (int)g, p.rq, p.lay, p.maxB_quad, st));
     }
     if (p.ntask_m > 0) {
-        const int per_cu = max_blocks_ms(p.ms_hist_words);
+        const int per_cu = max_blocks_ms(p.ms_hist_words, p.maxB_ms);
         const long long g = std::min<long long>(p.ntask_m, std::max<long long>(1, (long long)per_cu * num_cu * grid_pct / 100));
-        KS_HIP(launch_search_ms(sm, (int)g, p.rl, p.ms_hist_words, st));
+        KS_HIP(launch_search_ms(sm, (int)g, p.rl, p.ms_hist_words, p.maxB_ms, st));
     }
     if (timed) KS_HIP(hipEventRecord(ev[2], st));
     if (with_rank) {
@@ -740,7 +742,7 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if (per_window) {
         const int rl = pick_ms_rl(bins, ctx->ms_rl_pref);
         e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), kind == KS_HIST_CUBE ? 0 : 1, n, dxyz, dsc, rl,
-                           (bins + 1) << rl, ctx->d_hook_out.ptr, st);
+                           (bins + 1) << rl, bins, ctx->d_hook_out.ptr, st);
     } else {
         const int rq = pick_quad_rq(K, bins, ctx->quad_rq_pref);
         const LdsQuad lay = quad_layout(K, bins, rq);

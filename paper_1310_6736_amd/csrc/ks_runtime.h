@@ -61,8 +61,8 @@ struct Context {
     int device = 0;
     int num_cu = 256;
     bool profiling = false;
-    int ms_rl_pref = 6;
-    int quad_rq_pref = 3;
+    int ms_rl_pref = 4;
+    int quad_rq_pref = 1;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
     Tables tables{};
