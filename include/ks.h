@@ -185,6 +185,17 @@ typedef struct {
  * Each volume's result equals ks_detect_device on it alone. */
 ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks_result* results, void* stream);
 
+/* ------------------------------------------------------------- measurement */
+
+/* Roofline microbenchmarks behind the reported fractions (for callers measuring
+ * the library, not part of a detection).  Runs one benchmark on `device`; *rate
+ * is bytes/s (KS_ROOF_COPY: bytes read + written by a streaming copy of 1 GiB) or
+ * lane-level LDS atomic additions per second (the others: every lane its own
+ * address; SHARED4: four lanes per address, all equal).  KS_E_INVALID for an
+ * unknown kind or a null rate. */
+enum { KS_ROOF_COPY = 0, KS_ROOF_LDS_ADD64 = 1, KS_ROOF_LDS_ADD32 = 2, KS_ROOF_LDS_ADD64_SHARED4 = 3 };
+ks_status ks_roofline(int32_t device, int32_t kind, double* rate);
+
 /* ---------------------------------------------------------------- serving */
 
 typedef struct {

@@ -34,7 +34,8 @@ namespace ks {
 
 // ------------------------------------------------------------------ helpers
 
-constexpr int kUnroll = 4;  // window rows whose loads are in flight together
+constexpr int kUnroll = 4;  // window rows per group of loads
+constexpr int kDepth = 4;   // groups of loads in flight per wavefront
 
 __device__ __forceinline__ double bfly_sum(double v) {
 #pragma unroll
@@ -122,10 +123,12 @@ __device__ __forceinline__ Sweep make_sweep(const VolDesc& v, int xa, int xb, in
     return w;
 }
 
-// Walks the sweep's steps, kUnroll rows per group, with the next group's loads
-// issued before the current group is scattered; calls f(word, iy0, iz0) for every
-// step in which the lane's row lies inside the box.  After each group that brings
-// the step count to `every`, flush() runs (uniformly).
+// Walks the sweep's steps in groups of kUnroll rows, keeping kDepth groups of
+// loads in flight: the loads of group g + kDepth are issued right after group g
+// is scattered.  Calls f(word, iy0, iz0) for every step in which the lane's row
+// lies inside the box.  After each group that brings the step count to `every`,
+// flush() runs (uniformly).  Loads past the last step read beyond the box (or
+// past the descriptor's end, which returns 0) and are never used.
 template <typename F, typename G>
 __device__ __forceinline__ void run_sweep(const VolDesc& v, const Sweep& w, int every, F&& f, G&& flush) {
     const __amdgpu_buffer_rsrc_t rs = bins_rsrc(v);
@@ -133,43 +136,41 @@ __device__ __forceinline__ void run_sweep(const VolDesc& v, const Sweep& w, int 
     const int ny = uniform(w.ny), ty = uniform(w.ty), tz = uniform(w.tz), nsteps = uniform(w.nsteps);
     const int lim_y = w.ny - w.oy, lim_z = w.nz - w.oz;
     int iy0 = 0, iz0 = 0, since = 0;
-    uint32_t cur[kUnroll];
-    int cy[kUnroll], cz[kUnroll];
+    uint32_t buf[kDepth][kUnroll];
+    int by[kDepth][kUnroll], bz[kDepth][kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        cy[u] = iy0;
-        cz[u] = iz0;
-        cur[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
-        iy0 += ty;
-        if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
-    }
-    for (int t = 0; t < nsteps; t += kUnroll) {
-        // loads past the last step read beyond the box (or past the descriptor's
-        // end, which returns 0) and are never used
-        uint32_t nxt[kUnroll];
-        int ny_[kUnroll], nz_[kUnroll];
+    for (int g = 0; g < kDepth; ++g) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            ny_[u] = iy0;
-            nz_[u] = iz0;
-            nxt[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
+            by[g][u] = iy0;
+            bz[g][u] = iz0;
+            buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
             iy0 += ty;
             if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
         }
+    }
+    for (int t = 0; t < nsteps; t += kUnroll * kDepth) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            if (w.on && cy[u] < lim_y && cz[u] < lim_z) f(cur[u], cy[u], cz[u]);
-        }
-        since += kUnroll;
-        if (since >= every) {
-            since = 0;
-            flush();
-        }
+        for (int g = 0; g < kDepth; ++g) {
+            if (t + g * kUnroll < nsteps) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            cur[u] = nxt[u];
-            cy[u] = ny_[u];
-            cz[u] = nz_[u];
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (w.on && by[g][u] < lim_y && bz[g][u] < lim_z) f(buf[g][u], by[g][u], bz[g][u]);
+                }
+                since += kUnroll;
+                if (since >= every) {
+                    since = 0;
+                    flush();
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                by[g][u] = iy0;
+                bz[g][u] = iz0;
+                buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
+                iy0 += ty;
+                if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
+            }
         }
     }
 }
@@ -597,59 +598,68 @@ __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb,
         []() {});
 }
 
-// One sweep over the brick P + [-s_max, s_max]^3 (clipped) for all 8 octants:
-// a voxel at offset d goes to octant j (bit a set when d_a > 0), and to the
-// mirrored octants along every axis with d_a = 0 (the planes through P belong to
-// both sides); row = max(max|d_a| - base, 0), region j at byte j * region_bytes.
+// One sweep over the brick P + [-R, R]^3 (clipped) for all 8 octants: a voxel
+// at offset d goes to octant j (bit a set when d_a > 0), and to the mirrored
+// octants along every axis with d_a = 0 (the planes through P belong to both
+// sides); row = max(max|d_a| - base, 0), octant j's region at byte
+// j * region_bytes.  Per voxel: one bit-field extract, one max, two adds and one
+// LDS add; the x-plane voxel of a lane costs one more add per step, and the rare
+// rows on the y or z plane take a separate path.
 template <int NT>
-__device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int R, int base, int trash_row, int rq,
+__device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base, int trash_row, int rq,
                                uint32_t region_bytes, uint32_t* hist, int tid) {
-    const int xa = max(px - R, 0), xb = min(px + R, v.X - 1);
-    const int ya = max(py - R, 0), yb = min(py + R, v.Y - 1);
-    const int za = max(pz - R, 0), zb = min(pz + R, v.Z - 1);
+    const int xa = max(px - Rr, 0), xb = min(px + Rr, v.X - 1);
+    const int ya = max(py - Rr, 0), yb = min(py + Rr, v.Y - 1);
+    const int za = max(pz - Rr, 0), zb = min(pz + Rr, v.Z - 1);
     const Sweep w = make_sweep<NT>(v, xa, xb, ya, yb, za, zb, tid);
     const uint32_t rowbytes = (uint32_t)v.B << (rq + 2);
     const uint32_t rep4 = (uint32_t)(tid & ((1 << rq) - 1)) << 2;
     const uint32_t bshift = (uint32_t)rq + 2;
-    uint32_t rx[4], jx[4];
-    bool xdup[4];
+    uint32_t rx[4], ax[4];
+    int kx = -1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int x = w.x0 + k;
         const bool ok = x >= xa && x <= xb;
         const int r = ok ? max(abs(x - px) - base, 0) : trash_row;
-        rx[k] = (uint32_t)r * rowbytes + rep4;
-        jx[k] = x > px ? 1u : 0u;
-        xdup[k] = ok && x == px;
+        rx[k] = __umul24((uint32_t)r, rowbytes) + rep4;
+        ax[k] = x > px ? region_bytes : 0u;
+        if (ok && x == px) kx = k;
     }
+    // the lane's voxel on the plane x = px (if any): byte kx, mirrored to the + side
+    const bool xdup = kx >= 0;
+    const uint32_t kxs = xdup ? 8u * (uint32_t)kx : 0u;
+    const uint32_t rxd = rep4;  // |x - px| = 0: row max(-base, 0) = 0
     const int dy0 = ya + w.oy - py, dz0 = za + w.oz - pz;
+    const uint32_t ry2 = 2u * region_bytes, rz4 = 4u * region_bytes;
     char* hb = reinterpret_cast<char*>(hist);
     run_sweep(
         v, w, INT_MAX,
         [&](uint32_t word, int iy0, int iz0) {
             const int dy = dy0 + iy0, dz = dz0 + iz0;
-            const int rr = max(max(abs(dy), abs(dz)) - base, 0);
-            const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
-            const uint32_t jyz = (dy > 0 ? 2u : 0u) | (dz > 0 ? 4u : 0u);
-            const bool ydup = dy == 0, zdup = dz == 0;
+            const uint32_t RR = __umul24((uint32_t)max(max(abs(dy), abs(dz)) - base, 0), rowbytes) + rep4;
+            const uint32_t ayz = (dy > 0 ? ry2 : 0u) + (dz > 0 ? rz4 : 0u);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t b = (word >> (8 * k)) & 0xFFu;
-                const uint32_t a = max(rx[k], RR) + (b << bshift);
-                const uint32_t j = jx[k] | jyz;
-                atomicAdd(reinterpret_cast<uint32_t*>(hb + a + j * region_bytes), 1u);
-                if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 1u) * region_bytes), 1u);
-                if (ydup) {
-                    atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 2u) * region_bytes), 1u);
-                    if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 3u) * region_bytes), 1u);
-                }
-                if (zdup) {
-                    atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 4u) * region_bytes), 1u);
-                    if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 5u) * region_bytes), 1u);
-                    if (ydup) {
-                        atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 6u) * region_bytes), 1u);
-                        if (xdup[k]) atomicAdd(reinterpret_cast<uint32_t*>(hb + a + (j ^ 7u) * region_bytes), 1u);
-                    }
+                const uint32_t b = __builtin_amdgcn_ubfe(word, 8 * k, 8);
+                atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rx[k], RR) + (b << bshift) + ax[k] + ayz)), 1u);
+            }
+            if (xdup) {
+                const uint32_t b = __builtin_amdgcn_ubfe(word, kxs, 8);
+                atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rxd, RR) + (b << bshift) + region_bytes + ayz)), 1u);
+            }
+            if (dy == 0 || dz == 0) {
+                // rows on the y or z plane: the mirrored copies
+                const uint32_t ym = dy == 0 ? ry2 : 0u, zm = dz == 0 ? rz4 : 0u;
+                for (int k = 0; k < 5; ++k) {
+                    if (k == 4 && !xdup) break;
+                    const uint32_t b = __builtin_amdgcn_ubfe(word, k < 4 ? 8u * (uint32_t)k : kxs, 8);
+                    const uint32_t rk = k == 0 ? rx[0] : k == 1 ? rx[1] : k == 2 ? rx[2] : k == 3 ? rx[3] : rxd;
+                    const uint32_t xk = k == 0 ? ax[0] : k == 1 ? ax[1] : k == 2 ? ax[2] : k == 3 ? ax[3] : region_bytes;
+                    const uint32_t ak = max(rk, RR) + (b << bshift) + xk + ayz;
+                    if (ym) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + ym), 1u);
+                    if (zm) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + zm), 1u);
+                    if (ym && zm) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + ym + zm), 1u);
                 }
             }
         },

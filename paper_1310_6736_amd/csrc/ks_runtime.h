@@ -62,7 +62,7 @@ struct Context {
     int num_cu = 256;
     bool profiling = false;
     int ms_rl_pref = 4;
-    int quad_rq_pref = 1;
+    int quad_rq_pref = 0;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
     Tables tables{};

@@ -24,7 +24,7 @@ EXPORTS = [
     "ks_status_str", "ks_context_create", "ks_context_destroy", "ks_context_set_profiling", "ks_context_set_tuning",
     "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
-    "ks_server_stats", "ks_server_destroy",
+    "ks_server_stats", "ks_server_destroy", "ks_roofline",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
     L.ks_server_drain.argtypes = [vp]
     L.ks_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
     L.ks_server_destroy.argtypes = [vp]
+    L.ks_roofline.argtypes = [i32, i32, C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name != "ks_status_str":
             getattr(L, name).restype = i32
@@ -300,6 +301,16 @@ def ks_detect_batch(ctx: Context, requests, capacity=1024, stream=None):
     _check(lib().ks_detect_batch(ctx.handle, n, reqs, res, _stream_ptr(stream) if stream is not None else None),
            "ks_detect_batch")
     return [(regions_to_numpy(bufs[i], min(res[i].n_found, int(capacity))), res[i].n_found) for i in range(n)]
+
+
+KS_ROOF_COPY, KS_ROOF_LDS_ADD64, KS_ROOF_LDS_ADD32, KS_ROOF_LDS_ADD64_SHARED4 = 0, 1, 2, 3
+
+
+def ks_roofline(kind: int, device: int = 0) -> float:
+    """Measured ceiling: bytes/s (copy) or lane-level LDS atomic adds/s."""
+    r = C.c_double()
+    _check(lib().ks_roofline(int(device), int(kind), C.byref(r)), "ks_roofline")
+    return r.value
 
 
 class Server:
