@@ -9,8 +9,10 @@ host).  The input is in HBM before the timed region starts.
 
 Prints one JSON line.  Extra fields: volumes/s, per-method device times, the
 roofline of the dominant kernel (the mean-shift search) measured with HIP events
-on the launch stream, and the CPU oracle timed on a bounded sample.  Optional
---serve adds a Poisson serving run against a plain one-launch-per-volume loop.
+on the launch stream, the CPU oracle timed on a bounded sample, the uneven
+64-volume batch (one captured launch sequence) against plain per-volume
+launches, and a Poisson serving stream against a plain one-launch-per-volume
+loop with p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -36,7 +38,120 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-stride", type=int, default=2)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_meanshift_pet.json"))
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
     return ap.parse_args()
+
+
+def batch_section(ks, torch, ctx):
+    """The 64-volume uneven batch: one ks_detect_batch (captured graph, replayed)
+    against one ks_detect_device per volume, same volumes, same results."""
+    from paper_1310_6736_amd import synth
+
+    ws = synth.batch_workloads()
+    vols = [torch.from_numpy(w.volume).to("cuda:0") for w in ws]
+    reqs = [ks.make_request(v, w.bins, w.spacing, w.scales, w.method, w.max_iter) for v, w in zip(vols, ws)]
+    cap = 256
+    ks.ks_detect_batch(ctx, reqs, capacity=cap)  # capture
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res_b = ks.ks_detect_batch(ctx, reqs, capacity=cap)
+    tb = (time.perf_counter() - t0) / reps
+    for v, w in zip(vols, ws):  # warm
+        ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res_p = [ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
+                 for v, w in zip(vols, ws)]
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / reps
+    same = all(a[1] == b[1] and np.array_equal(a[0], b[0]) for a, b in zip(res_b, res_p))
+    return {"workload": "64 volumes, x,y in 64..192, z in 64..128, types 50/30/20 (spheres u8 / PET-like u16 / "
+                        "MR-like i16), per-type bins, spacing, scales and method",
+            "batched_volumes_per_s": len(ws) / tb, "plain_volumes_per_s": len(ws) / tp,
+            "batched_ms": tb * 1e3, "plain_ms": tp * 1e3, "speedup": tp / tb, "identical_results": bool(same)}
+
+
+def serving_section(ks, torch, ctx, n_req):
+    """Poisson stream of the 50/30/20 mix at native sizes: the continuous-batching
+    server against a plain loop that serves requests one launch sequence at a
+    time in arrival order (both copy each host volume to the device)."""
+    import threading
+
+    from paper_1310_6736_amd import synth
+
+    pool = {0: [synth.typed_workload(0, 2000 + i, synth.TYPE_DIMS[0]) for i in range(4)],
+            1: [synth.typed_workload(1, 2100 + i, synth.TYPE_DIMS[1], method_parity=i) for i in range(4)],
+            2: [synth.typed_workload(2, 2200 + i, synth.TYPE_DIMS[2]) for i in range(2)]}
+    cap = 64
+    dev_buf = {k: [torch.empty(w.volume.shape, dtype={np.dtype(np.uint8): torch.uint8,
+                                                      np.dtype(np.int16): torch.int16}.get(w.volume.dtype,
+                                                                                           getattr(torch, "uint16", None)),
+                               device="cuda:0") for w in ws] for k, ws in pool.items()}
+
+    def plain_one(kind, j):
+        w = pool[kind][j]
+        d = dev_buf[kind][j]
+        d.copy_(torch.from_numpy(w.volume))
+        return ks.ks_detect_device(ctx, d, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
+
+    # plain capacity on the mix (saturated, arrival order)
+    trace = synth.arrival_trace(1.0, n=n_req)
+    order = [(k, (seed % len(pool[k]))) for _, k, seed, _ in trace]
+    for k, j in order[:6]:
+        plain_one(k, j)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, j in order:
+        plain_one(k, j)
+    torch.cuda.synchronize()
+    c_plain = n_req / (time.perf_counter() - t0)
+
+    def run_plain(trace):
+        lat = []
+        start = time.perf_counter()
+        for t_arr, k, seed, _ in trace:
+            now = time.perf_counter() - start
+            if now < t_arr:
+                time.sleep(t_arr - now)
+            plain_one(k, seed % len(pool[k]))
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - start - t_arr) * 1e3)
+        span = time.perf_counter() - start
+        return {"volumes_per_s": len(trace) / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(np.mean(lat))}
+
+    def run_server(trace):
+        srv = ks.Server(0, hbm_budget=8 << 30, max_slots=4)
+        tickets = []
+        start = time.perf_counter()
+        for t_arr, k, seed, _ in trace:
+            now = time.perf_counter() - start
+            if now < t_arr:
+                time.sleep(t_arr - now)
+            w = pool[k][seed % len(pool[k])]
+            tickets.append(srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter))
+        srv.drain()
+        st = srv.stats()
+        for t in tickets:
+            srv.poll(t, capacity=cap)
+        srv.close()
+        return {"volumes_per_s": st["volumes_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                "mean_ms": st["mean_ms"]}
+
+    out = {"workload": "%d requests, Poisson arrivals, 50/30/20 mix of the 64^3 spheres, 128x128x64 PET-like "
+                       "(quadrant/mean-shift alternating) and 256x256x160 MR-like generators" % n_req,
+           "plain_capacity_volumes_per_s": c_plain}
+    sat = [(0.0, k, seed, i) for _, k, seed, i in trace]
+    out["saturated"] = {"server": run_server(sat), "plain": run_plain(sat)}
+    lam = 0.7 * c_plain
+    tr = synth.arrival_trace(lam, n=n_req)
+    out["rate_0.7"] = {"rate_per_s": lam, "server": run_server(tr), "plain": run_plain(tr)}
+    return out
 
 
 def cpu_baseline(stride: int):
@@ -146,6 +261,10 @@ def main():
                      "algorithmic_bytes_per_launch": int(ms_bytes),
                      "quadrant_achieved": q_bytes / (q_kernel_ms * 1e-3) / 1e9},
     }
+    if not args.no_batch:
+        line["batch"] = batch_section(ks, torch, ctx)
+    if not args.no_serve:
+        line["serving"] = serving_section(ks, torch, ctx, args.serve_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride)
     ctx.close()

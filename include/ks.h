@@ -113,6 +113,19 @@ ks_status ks_context_destroy(ks_context* ctx);
 /* Turn per-phase device timing (HIP events) on or off; off by default. */
 ks_status ks_context_set_profiling(ks_context* ctx, int32_t on);
 
+/* Tuning of the scatter kernels (the values the built-in tuner picks by default).
+ * ms_replicas_log2 in [1,6]: packed LDS histogram replicas per wavefront of the
+ * mean-shift scatter, 2^value (also sets the small-window value);
+ * quad_replicas_log2 in [0,3]: replicas per workgroup of the octant scatter.
+ * Fewer replicas: more same-address LDS atomics, fewer slots to clear; more
+ * replicas: more LDS per wavefront, lower occupancy.  Results do not depend on
+ * the tuning.  Values that do not fit the LDS budget of a call are lowered. */
+ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32_t quad_replicas_log2);
+
+/* Mean-shift windows of half-width <= s_small use 2^ms_small_replicas_log2
+ * replicas (ms_small_replicas_log2 in [1,6], s_small >= 0). */
+ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas_log2, int32_t s_small);
+
 /* Counters and times of the last detect/batch call on this context. */
 ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out);
 

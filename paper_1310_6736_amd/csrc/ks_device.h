@@ -88,9 +88,10 @@ struct Counters {
     unsigned long long pad;
 };
 
-// Launch-time tuning of the mean-shift evaluation.
+// Launch-time tuning of the mean-shift evaluation: replicas per wavefront,
+// 1 << rl for windows of half-width > s_small and 1 << rl_small otherwise.
 struct MsTune {
-    int32_t rep_log2;       // replicas per wave = 1 << rep_log2 (<= 6)
+    int32_t rl, rl_small, s_small, pad;
 };
 
 }  // namespace ks

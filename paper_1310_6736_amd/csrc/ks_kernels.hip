@@ -37,10 +37,32 @@ namespace ks {
 constexpr int kUnroll = 4;  // window rows per group of loads
 constexpr int kDepth = 4;   // groups of loads in flight per wavefront
 
+// Moves a double across lanes with a DPP pattern (VALU only, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_double(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Pairwise halving-tree sum over the 64 lanes (lane i holds term i): pairs of
+// lanes, then groups of 4, 8 and 16 by DPP (xor 1, xor 2, half-row mirror, row
+// mirror: each pairs a block with its neighbour block), then the four row sums
+// as (r0 + r1) + (r2 + r3).  Every lane returns the same total.
 __device__ __forceinline__ double bfly_sum(double v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m, 64);
-    return v;
+    v = v + dpp_double<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = v + dpp_double<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = v + dpp_double<0x141>(v);  // row_half_mirror
+    v = v + dpp_double<0x140>(v);  // row_mirror
+    return (lane_double(v, 0) + lane_double(v, 16)) + (lane_double(v, 32) + lane_double(v, 48));
 }
 
 __device__ __forceinline__ float bfly_sumf(float v) {
@@ -64,6 +86,10 @@ __device__ __forceinline__ double local_pw(const double* v) {
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Row stride (in counters) of the shell-bucketed histograms: odd, so that equal
+// bins of neighbouring rows fall in different LDS banks.
+__device__ __forceinline__ int row_stride(int B) { return B | 1; }
 
 __device__ __forceinline__ int64_t clipped_len(int c, int r, int n) {
     int lo = c - r < 0 ? 0 : c - r;
@@ -265,20 +291,21 @@ struct BinAcc {
 
 template <int M>
 __device__ __forceinline__ void ms_flush(unsigned long long* hist, int rl, int B, int lane, BinAcc<M>& a) {
-    const int R = 1 << rl;
+    const int half = 1 << (rl - 1);  // replica pairs; rl >= 1
 #pragma unroll
     for (int t = 0; t < M; ++t) {
         const int b = lane * M + t;
         if (b < B) {
             unsigned long long* e = hist + ((size_t)b << rl);
-            for (int i = 0; i < R; ++i) {
-                const int r = (i + lane) & (R - 1);
-                const unsigned long long val = e[r];
-                e[r] = 0ull;
-                a.c[t] += (int)(val & 0x3FFull);
-                a.f1[t] += (int)((val >> 10) & 0xFFFFull);
-                a.f2[t] += (int)((val >> 32) & 0xFFFFull);
-                a.f3[t] += (int)(val >> 48);
+            for (int i = 0; i < half; ++i) {
+                const int r = ((i + lane) & (half - 1)) << 1;
+                uint4* p = reinterpret_cast<uint4*>(e + r);
+                const uint4 q = *p;
+                *p = make_uint4(0u, 0u, 0u, 0u);
+                a.c[t] += (int)(q.x & 0x3FFu) + (int)(q.z & 0x3FFu);
+                a.f1[t] += (int)((q.x >> 10) & 0xFFFFu) + (int)((q.z >> 10) & 0xFFFFu);
+                a.f2[t] += (int)(q.y & 0xFFFFu) + (int)(q.w & 0xFFFFu);
+                a.f3[t] += (int)(q.y >> 16) + (int)(q.w >> 16);
             }
         }
     }
@@ -286,11 +313,13 @@ __device__ __forceinline__ void ms_flush(unsigned long long* hist, int rl, int B
 
 // Scatter the cube P + [-s, s]^3 (clipped) into the wavefront's packed
 // per-replica LDS histogram hist[(bin << rl) + replica] and flush into per-lane
-// bin totals.  Search mode: f1..f3 are the sums of (dx+s), (dy+s), (dz+s).  Final
+// bin totals.  rl may differ between windows (fewer replicas for small windows):
+// every bin slot is cleared by the flushes, and the slots for bytes outside the
+// window sit at trash_base, past every layout.  Search mode: f1..f3 are the sums of (dx+s), (dy+s), (dz+s).  Final
 // mode: f1 counts the voxels of the inner cube of half-width s-1, f2 = f3 = 0.
 template <bool FINAL, int M>
-__device__ void ms_window(const VolDesc& v, int px, int py, int pz, int s, int rl, unsigned long long* hist, int lane,
-                          BinAcc<M>& acc) {
+__device__ void ms_window(const VolDesc& v, int px, int py, int pz, int s, int rl, int trash_base,
+                          unsigned long long* hist, int lane, BinAcc<M>& acc) {
     px = uniform(px); py = uniform(py); pz = uniform(pz); s = uniform(s); rl = uniform(rl);
     const int B = v.B;
 #pragma unroll
@@ -302,7 +331,8 @@ __device__ void ms_window(const VolDesc& v, int px, int py, int pz, int s, int r
     const int R = 1 << rl;
     const int rep = lane & (R - 1);
     const uint32_t shift = (uint32_t)rl + 3;
-    const uint32_t trash = ((uint32_t)((B << rl) | rep)) << 3;
+    // bytes outside the window go to a per-replica slot past every bin layout
+    const uint32_t trash = (uint32_t)(trash_base + rep) << 3;
     const uint32_t repoff = (uint32_t)rep << 3;
     uint32_t lo[4], off[4], wid[4];
 #pragma unroll
@@ -362,10 +392,10 @@ struct EvalOut {
 // Eq. 4-6 with a flat kernel and the uniform target: move = (sum_b M_b/sqrt(c_b)) /
 // (sum_b sqrt(c_b)), objective rho~ = (sum_b sqrt(c_b)) / sqrt(N).
 template <int M>
-__device__ EvalOut ms_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, int rl,
+__device__ EvalOut ms_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, int rl, int trash_base,
                            unsigned long long* hist, int lane) {
     BinAcc<M> a;
-    ms_window<false, M>(v, px, py, pz, s, rl, hist, lane, a);
+    ms_window<false, M>(v, px, py, pz, s, rl, trash_base, hist, lane, a);
     double sq[M], tx[M], ty[M], tz[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) {
@@ -405,9 +435,9 @@ __device__ __forceinline__ float entropy_term32(int c, int64_t N) {
 // Kadir-Brady saliency at the trajectory's own scale (mean-shift).
 template <int M>
 __device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, int rl,
-                                unsigned long long* hist, int lane) {
+                                int trash_base, unsigned long long* hist, int lane) {
     BinAcc<M> a;
-    ms_window<true, M>(v, px, py, pz, s, rl, hist, lane, a);
+    ms_window<true, M>(v, px, py, pz, s, rl, trash_base, hist, lane, a);
     const int64_t Ns = cube_count(v, px, py, pz, s);
     const int64_t Np = cube_count(v, px, py, pz, s - 1);
     double cl[M];
@@ -525,7 +555,8 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 
 template <int M>
 __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* vols, const TaskSeg* segs, int nseg, long long ntask,
-                                                  Tables tb, TrajRec* out, Counters* cnt, int rl, int hist_words) {
+                                                  Tables tb, TrajRec* out, Counters* cnt, MsTune tune,
+                                                  int hist_words) {
     extern __shared__ unsigned long long hist[];
     const int lane = threadIdx.x;
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
@@ -543,9 +574,13 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* vols, const Tas
         const int s = sg.scale;
         int p0[3];
         seed_pos(v, seed, p0);
+        // replicas per wavefront by window size class
+        const int rl = s <= tune.s_small ? tune.rl_small : tune.rl;
+        const int trash_base = hist_words - 64;
         const TrajOut o = run_trajectory(
-            v, p0, [&](int x, int y, int z) { return ms_eval<M>(v, tb, x, y, z, s, rl, hist, lane); }, lc, s, 1);
-        const Saliency sal = ms_saliency<M>(v, tb, o.p[0], o.p[1], o.p[2], s, rl, hist, lane);
+            v, p0, [&](int x, int y, int z) { return ms_eval<M>(v, tb, x, y, z, s, rl, trash_base, hist, lane); },
+            lc, s, 1);
+        const Saliency sal = ms_saliency<M>(v, tb, o.p[0], o.p[1], o.p[2], s, rl, trash_base, hist, lane);
         lc.final_visits += cube_count(v, o.p[0], o.p[1], o.p[2], s);
         lc.window_evals += 2;
         if (lane == 0) {
@@ -571,7 +606,7 @@ template <int NT>
 __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx, int cy,
                                int cz, int base, int trash_row, int rq, uint32_t region, uint32_t* hist, int tid) {
     const Sweep w = make_sweep<NT>(v, xa, xb, ya, yb, za, zb, tid);
-    const uint32_t rowbytes = (uint32_t)v.B << (rq + 2);
+    const uint32_t rowbytes = (uint32_t)row_stride(v.B) << (rq + 2);
     const uint32_t rep4 = ((uint32_t)(tid & ((1 << rq) - 1)) << 2) + region;
     const uint32_t bshift = (uint32_t)rq + 2;
     uint32_t rx[4];
@@ -612,7 +647,7 @@ __device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr,
     const int ya = max(py - Rr, 0), yb = min(py + Rr, v.Y - 1);
     const int za = max(pz - Rr, 0), zb = min(pz + Rr, v.Z - 1);
     const Sweep w = make_sweep<NT>(v, xa, xb, ya, yb, za, zb, tid);
-    const uint32_t rowbytes = (uint32_t)v.B << (rq + 2);
+    const uint32_t rowbytes = (uint32_t)row_stride(v.B) << (rq + 2);
     const uint32_t rep4 = (uint32_t)(tid & ((1 << rq) - 1)) << 2;
     const uint32_t bshift = (uint32_t)rq + 2;
     uint32_t rx[4], ax[4];
@@ -673,11 +708,12 @@ template <int NT>
 __device__ void bucket_merge(uint32_t* hist, int nreg, int nrows, int B, int rq, int tid) {
     const int R = 1 << rq;
     const int rows_total = nrows + 1;
+    const int Bs = row_stride(B);
     for (int p = tid; p < nreg * B; p += NT) {
         const int g = p / B, b = p - g * B;
         uint32_t acc = 0;
         for (int r = 0; r <= nrows; ++r) {
-            const int e = ((g * rows_total + r) * B + b) << rq;
+            const int e = ((g * rows_total + r) * Bs + b) << rq;
             uint32_t sum = 0;
             for (int q = 0; q < R; ++q) {
                 sum += hist[e + q];
@@ -692,7 +728,7 @@ __device__ void bucket_merge(uint32_t* hist, int nreg, int nrows, int B, int rq,
 }
 
 __device__ __forceinline__ uint32_t merged(const uint32_t* hist, int g, int rows_total, int r, int B, int b, int rq) {
-    return hist[((g * rows_total + r) * B + b) << rq];
+    return hist[((g * rows_total + r) * row_stride(B) + b) << rq];
 }
 
 struct QuadLds {
@@ -738,7 +774,7 @@ __device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows
                 const int b = lane * M + t;
                 uint32_t c = 0;
                 if (q < nq && b < B) {
-                    const int e = ((g * rows_total + r) * B + b) << rq;
+                    const int e = ((g * rows_total + r) * row_stride(B) + b) << rq;
                     c = hist[e];
                     hist[e] = 0u;
                 }
@@ -765,7 +801,7 @@ __device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py,
                              int tid) {
     px = uniform(px); py = uniform(py); pz = uniform(pz);
     const int S = v.S, B = v.B;
-    const uint32_t region_bytes = (uint32_t)(S + 1) * (uint32_t)B << (rq + 2);
+    const uint32_t region_bytes = (uint32_t)(S + 1) * (uint32_t)row_stride(B) << (rq + 2);
     octant_scatter<NT>(v, px, py, pz, v.s_max, v.s_min, S, rq, region_bytes, L.hist, tid);
     __syncthreads();
     bucket_merge<NT>(L.hist, 8, S, B, rq, tid);
@@ -961,8 +997,8 @@ __global__ __launch_bounds__(64) void k_hook_ms(const VolDesc* vols, int kind, i
     for (int w = blockIdx.x; w < n; w += gridDim.x) {
         const int px = xyz[3 * w], py = xyz[3 * w + 1], pz = xyz[3 * w + 2], s = sc[w];
         BinAcc<M> a;
-        if (kind == 0) ms_window<true, M>(v, px, py, pz, s, rl, hist, lane, a);
-        else ms_window<false, M>(v, px, py, pz, s, rl, hist, lane, a);
+        if (kind == 0) ms_window<true, M>(v, px, py, pz, s, rl, hist_words - 64, hist, lane, a);
+        else ms_window<false, M>(v, px, py, pz, s, rl, hist_words - 64, hist, lane, a);
 #pragma unroll
         for (int t = 0; t < M; ++t) {
             const int b = lane * M + t;
@@ -992,7 +1028,7 @@ __global__ __launch_bounds__(256) void k_hook_quad(const VolDesc* vols, int kind
     __syncthreads();
     const VolDesc v = vols[0];
     const int B = v.B, K = hi - lo + 1;
-    const uint32_t region_bytes = (uint32_t)(K + 1) * (uint32_t)B << (rq + 2);
+    const uint32_t region_bytes = (uint32_t)(K + 1) * (uint32_t)row_stride(B) << (rq + 2);
     for (int w = blockIdx.x; w < n; w += gridDim.x) {
         const int px = xyz[3 * w], py = xyz[3 * w + 1], pz = xyz[3 * w + 2];
         const int nreg = kind == 1 ? 8 : 1;
@@ -1007,13 +1043,13 @@ __global__ __launch_bounds__(256) void k_hook_quad(const VolDesc* vols, int kind
         __syncthreads();
         for (int i = tid; i < nreg * K * B; i += 256) {
             const int g = i / (K * B), rem = i - g * K * B, r = rem / B, b = rem - r * B;
-            const int e = ((g * (K + 1) + r) * B + b) << rq;
+            const int e = ((g * (K + 1) + r) * row_stride(B) + b) << rq;
             outp[(size_t)w * nreg * K * B + i] = L.hist[e];
         }
         __syncthreads();
         for (int i = tid; i < nreg * K * B; i += 256) {
             const int g = i / (K * B), rem = i - g * K * B, r = rem / B, b = rem - r * B;
-            L.hist[((g * (K + 1) + r) * B + b) << rq] = 0u;
+            L.hist[((g * (K + 1) + r) * row_stride(B) + b) << rq] = 0u;
         }
         __syncthreads();
     }
@@ -1061,61 +1097,59 @@ __device__ __forceinline__ void cswap(SortRec* a, unsigned i, unsigned j) {
     if (rec_less(y, x)) { a[i] = y; a[j] = x; }
 }
 
-// Stages with block size <= L (L = 2 * blockDim) in LDS: flip step then halving
-// steps, every block ascending.  start_k: first stage to run (2 for a full local
-// sort; a stage's halving steps only when start_k == 0).
-__global__ __launch_bounds__(1024) void k_sort_local(SortRec* sr, unsigned L, unsigned k_first, unsigned j_first,
-                                                     const Counters* cnt) {
+// Sorts each block of L records (L = 2 * blockDim) in LDS with a bitonic network
+// whose every stage leaves its blocks ascending (first step compares i with its
+// mirror in the block, the rest are half-cleaners).  Blocks past the real records
+// are skipped; padding records sort to the end of the last real block.
+__global__ __launch_bounds__(1024) void k_sort_local(SortRec* sr, unsigned L, const Counters* cnt) {
     extern __shared__ SortRec lsr[];
     const unsigned long long count = cnt->n_sort;
     const unsigned long long start = (unsigned long long)blockIdx.x * L;
     if (start >= count) return;
     for (unsigned i = threadIdx.x; i < L; i += blockDim.x) lsr[i] = sr[start + i];
     __syncthreads();
-    if (k_first == 0) {
-        // halving steps j_first .. 1 of a stage whose flip already ran
-        for (unsigned j = j_first; j >= 1; j >>= 1) {
+    for (unsigned k = 2; k <= L; k <<= 1) {
+        for (unsigned p = threadIdx.x; p < L / 2; p += blockDim.x) {
+            const unsigned i = (p / (k / 2)) * k + (p % (k / 2));
+            cswap(lsr, i, i ^ (k - 1));
+        }
+        __syncthreads();
+        for (unsigned j = k / 4; j >= 1; j >>= 1) {
             for (unsigned p = threadIdx.x; p < L / 2; p += blockDim.x) {
                 const unsigned i = (p / j) * 2 * j + (p % j);
                 cswap(lsr, i, i + j);
             }
             __syncthreads();
         }
-    } else {
-        for (unsigned k = 2; k <= L; k <<= 1) {
-            for (unsigned p = threadIdx.x; p < L / 2; p += blockDim.x) {
-                const unsigned i = (p / (k / 2)) * k + (p % (k / 2));
-                cswap(lsr, i, i ^ (k - 1));
-            }
-            __syncthreads();
-            for (unsigned j = k / 4; j >= 1; j >>= 1) {
-                for (unsigned p = threadIdx.x; p < L / 2; p += blockDim.x) {
-                    const unsigned i = (p / j) * 2 * j + (p % j);
-                    cswap(lsr, i, i + j);
-                }
-                __syncthreads();
-            }
-        }
     }
     for (unsigned i = threadIdx.x; i < L; i += blockDim.x) sr[start + i] = lsr[i];
 }
 
-__global__ __launch_bounds__(256) void k_sort_global(SortRec* sr, unsigned long long n_pad, unsigned long long k,
-                                                     unsigned long long j, int flip, const Counters* cnt) {
+// One merge level: src holds sorted runs of `width` records (keys distinct);
+// run pairs are merged into dst.  Each record's output position is its index in
+// its own run plus the number of records of the partner run ordered before it
+// (binary search).  Only the first `count` records are real; padding is skipped.
+__global__ __launch_bounds__(256) void k_merge(const SortRec* src, SortRec* dst, unsigned long long width,
+                                               const Counters* cnt) {
     const unsigned long long count = cnt->n_sort;
-    for (unsigned long long p = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; p < n_pad / 2;
-         p += (unsigned long long)gridDim.x * blockDim.x) {
-        unsigned long long i, q;
-        if (flip) {
-            i = (p / (k / 2)) * k + (p % (k / 2));
-            q = i ^ (k - 1);
-        } else {
-            i = (p / j) * 2 * j + (p % j);
-            q = i + j;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long pair = i / (2 * width);
+        const unsigned long long a0 = pair * 2 * width, b0 = a0 + width;
+        const bool in_a = i < b0;
+        const unsigned long long o0 = in_a ? b0 : a0;   // partner run
+        unsigned long long olen = 0;
+        if (count > o0) olen = count - o0 < width ? count - o0 : width;
+        const SortRec x = src[i];
+        // number of partner records ordered before x
+        unsigned long long lo = 0, hi = olen;
+        while (lo < hi) {
+            const unsigned long long mid = (lo + hi) >> 1;
+            if (rec_less(src[o0 + mid], x)) lo = mid + 1;
+            else hi = mid;
         }
-        if (i >= count) continue;
-        const SortRec x = sr[i], y = sr[q];
-        if (rec_less(y, x)) { sr[i] = y; sr[q] = x; }
+        const unsigned long long own = i - (in_a ? a0 : b0);
+        dst[a0 + own + lo] = x;
     }
 }
 
@@ -1244,19 +1278,20 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
 
 int bins_per_lane_host(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
 
-hipError_t launch_search_ms(const SearchArgs& a, int grid, int rl, int hist_words, int maxB, hipStream_t st) {
+hipError_t launch_search_ms(const SearchArgs& a, int grid, const MsTune& tune, int hist_words, int maxB,
+                            hipStream_t st) {
     if (a.ntask <= 0) return hipSuccess;
     const size_t lds = (size_t)hist_words * 8;
     const int M = bins_per_lane_host(maxB);
     if (M == 1)
         hipLaunchKernelGGL(k_search_ms<1>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
-                           a.rec, a.cnt, rl, hist_words);
+                           a.rec, a.cnt, tune, hist_words);
     else if (M == 2)
         hipLaunchKernelGGL(k_search_ms<2>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
-                           a.rec, a.cnt, rl, hist_words);
+                           a.rec, a.cnt, tune, hist_words);
     else
         hipLaunchKernelGGL(k_search_ms<4>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
-                           a.rec, a.cnt, rl, hist_words);
+                           a.rec, a.cnt, tune, hist_words);
     return hipGetLastError();
 }
 
@@ -1304,25 +1339,28 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     const unsigned long long n_pad = a.n_pad;
     hipLaunchKernelGGL(k_sort_fill, dim3(grid_for((long long)n_pad, 256, 4096)), dim3(256), 0, st, a.sr, n_pad,
                        a.cnt);
-    const unsigned L = n_pad < 2048 ? (unsigned)n_pad : 2048u;
+    // sorted runs of L records in LDS, then merge levels ping-ponging between the
+    // two halves of the sort buffer
+    const unsigned L = n_pad < 512 ? (unsigned)n_pad : 512u;
     const unsigned nblk_local = (unsigned)(n_pad / L);
     const size_t lds = (size_t)L * sizeof(SortRec);
-    const unsigned threads = L / 2 < 1024 ? (L / 2 > 0 ? L / 2 : 1) : 1024;
-    hipLaunchKernelGGL(k_sort_local, dim3(nblk_local), dim3(threads), lds, st, a.sr, L, 2u, 0u, a.cnt);
-    for (unsigned long long k = 2ull * L; k <= n_pad; k <<= 1) {
-        hipLaunchKernelGGL(k_sort_global, dim3(grid_for((long long)(n_pad / 2), 256, 8192)), dim3(256), 0, st, a.sr,
-                           n_pad, k, 0ull, 1, a.cnt);
-        for (unsigned long long j = k / 4; j >= L; j >>= 1) {
-            hipLaunchKernelGGL(k_sort_global, dim3(grid_for((long long)(n_pad / 2), 256, 8192)), dim3(256), 0, st,
-                               a.sr, n_pad, k, j, 0, a.cnt);
-        }
-        hipLaunchKernelGGL(k_sort_local, dim3(nblk_local), dim3(threads), lds, st, a.sr, L, 0u, L / 2, a.cnt);
+    const unsigned threads = L / 2;
+    hipLaunchKernelGGL(k_sort_local, dim3(nblk_local), dim3(threads), lds, st, a.sr, L, a.cnt);
+    SortRec* src = a.sr;
+    SortRec* dst = a.sr + n_pad;
+    for (unsigned long long width = L; width < n_pad; width <<= 1) {
+        hipLaunchKernelGGL(k_merge, dim3(grid_for((long long)n_pad, 256, 8192)), dim3(256), 0, st, src, dst, width,
+                           a.cnt);
+        SortRec* t = src;
+        src = dst;
+        dst = t;
     }
+    const SortRec* sorted = src;
     const int nblk = (int)((n_pad + 1023) / 1024);
-    hipLaunchKernelGGL(k_dedup_count, dim3(nblk), dim3(1024), 0, st, a.sr, a.cnt, a.bsum, a.vol_nfound);
+    hipLaunchKernelGGL(k_dedup_count, dim3(nblk), dim3(1024), 0, st, sorted, a.cnt, a.bsum, a.vol_nfound);
     hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, a.bsum, nblk);
-    hipLaunchKernelGGL(k_dedup_rank, dim3(nblk), dim3(1024), 0, st, a.sr, a.cnt, a.bsum, a.grank, a.vol_base);
-    hipLaunchKernelGGL(k_emit, dim3(grid_for((long long)n_pad, 256, 4096)), dim3(256), 0, st, a.sr, a.cnt, a.grank,
+    hipLaunchKernelGGL(k_dedup_rank, dim3(nblk), dim3(1024), 0, st, sorted, a.cnt, a.bsum, a.grank, a.vol_base);
+    hipLaunchKernelGGL(k_emit, dim3(grid_for((long long)n_pad, 256, 4096)), dim3(256), 0, st, sorted, a.cnt, a.grank,
                        a.vol_base, a.vols, a.rec, a.regions);
     return hipGetLastError();
 }

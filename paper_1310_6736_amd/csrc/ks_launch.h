@@ -47,7 +47,7 @@ struct RankArgs {
     const VolDesc* vols;
     int nvol;
     const TrajRec* rec;
-    SortRec* sr;
+    SortRec* sr;                // 2 * n_pad records (merge ping-pong)
     Counters* cnt;
     unsigned long long n_pad;   // power of two >= total trajectories, >= 2
     long long max_traj;         // largest per-volume trajectory count
@@ -59,7 +59,8 @@ struct RankArgs {
 };
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
-hipError_t launch_search_ms(const SearchArgs& a, int grid, int rl, int hist_words, int maxB, hipStream_t st);
+hipError_t launch_search_ms(const SearchArgs& a, int grid, const MsTune& tune, int hist_words, int maxB,
+                            hipStream_t st);
 hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, int maxB, hipStream_t st);
 hipError_t launch_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc, int rl, int hist_words,
                           int maxB, void* out, hipStream_t st);

@@ -173,7 +173,7 @@ static unsigned long long next_pow2(unsigned long long n) {
 // same-address LDS atomics; fewer, cheaper merges).
 int pick_ms_rl(int maxB, int pref) {
     int rl = pref;
-    while (rl > 0 && (size_t)(maxB + 1) * ((size_t)1 << rl) * 8 > 36 * 1024) --rl;
+    while (rl > 1 && ((size_t)maxB * ((size_t)1 << rl) + 64) * 8 > 36 * 1024) --rl;
     return rl;
 }
 
@@ -183,7 +183,7 @@ LdsQuad quad_layout(int maxS, int maxB, int rq) {
     LdsQuad L;
     size_t off = 0;
     L.hist_off = off;
-    L.hist_words = (int)(8 * ((size_t)maxS + 1) * maxB * ((size_t)1 << rq));
+    L.hist_words = (int)(8 * ((size_t)maxS + 1) * ((size_t)maxB | 1) * ((size_t)1 << rq));
     off += (size_t)L.hist_words * 4;
     off = (off + 15) & ~(size_t)15;
     L.eps_off = off;
@@ -293,7 +293,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     if ((st = d_segs.ensure(seg_bytes, &generation)) != KS_OK) return st;
     if ((st = d_bins.ensure(std::max<size_t>(bins_total, 256), &generation)) != KS_OK) return st;
     if ((st = d_rec.ensure(sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1), &generation)) != KS_OK) return st;
-    if ((st = d_sr.ensure(sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
+    if ((st = d_sr.ensure(2 * sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
     if ((st = d_bsum.ensure(sizeof(int) * (p.n_pad / 1024 + 2), &generation)) != KS_OK) return st;
     if ((st = d_grank.ensure(sizeof(int) * p.n_pad, &generation)) != KS_OK) return st;
     if ((st = d_volint.ensure(sizeof(int) * 4 * (size_t)nvol, &generation)) != KS_OK) return st;
@@ -314,9 +314,11 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
                              sizeof(Counters);
     if ((st = h_out.ensure(out_bytes)) != KS_OK) return st;
     p.rl = pick_ms_rl(std::max(p.maxB_ms, 2), ms_rl_pref);
+    p.rl_small = pick_ms_rl(std::max(p.maxB_ms, 2), ms_rl_small_pref);
     p.rq = pick_quad_rq(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), quad_rq_pref);
     p.lay = quad_layout(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), p.rq);
-    p.ms_hist_words = (std::max(p.maxB_ms, 2) + 1) << p.rl;
+    // bins of the larger layout plus one trash slot per replica
+    p.ms_hist_words = (std::max(p.maxB_ms, 2) << std::max(p.rl, p.rl_small)) + 64;
     return KS_OK;
 }
 
@@ -358,7 +360,12 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
     if (p.ntask_m > 0) {
         const int per_cu = max_blocks_ms(p.ms_hist_words, p.maxB_ms);
         const long long g = std::min<long long>(p.ntask_m, std::max<long long>(1, (long long)per_cu * num_cu * grid_pct / 100));
-        KS_HIP(launch_search_ms(sm, (int)g, p.rl, p.ms_hist_words, p.maxB_ms, st));
+        MsTune tune;
+        tune.rl = p.rl;
+        tune.rl_small = p.rl_small;
+        tune.s_small = ms_s_small;
+        tune.pad = 0;
+        KS_HIP(launch_search_ms(sm, (int)g, tune, p.ms_hist_words, p.maxB_ms, st));
     }
     if (timed) KS_HIP(hipEventRecord(ev[2], st));
     if (with_rank) {
@@ -456,6 +463,8 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     std::vector<int64_t> key;
     key.push_back(generation);
     key.push_back(ms_rl_pref);
+    key.push_back(ms_rl_small_pref);
+    key.push_back(ms_s_small);
     key.push_back(quad_rq_pref);
     for (const VolIn& v : in) {
         key.push_back((int64_t)(intptr_t)v.raw);
@@ -565,10 +574,18 @@ ks_status ks_context_set_profiling(ks_context* ctx, int32_t on) {
 }
 
 ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32_t quad_replicas_log2) {
-    if (!ctx || ms_replicas_log2 < 0 || ms_replicas_log2 > 6 || quad_replicas_log2 < 0 || quad_replicas_log2 > 3)
+    if (!ctx || ms_replicas_log2 < 1 || ms_replicas_log2 > 6 || quad_replicas_log2 < 0 || quad_replicas_log2 > 3)
         return KS_E_INVALID;
     ctx->ms_rl_pref = ms_replicas_log2;
+    ctx->ms_rl_small_pref = ms_replicas_log2;
     ctx->quad_rq_pref = quad_replicas_log2;
+    return KS_OK;
+}
+
+ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas_log2, int32_t s_small) {
+    if (!ctx || ms_small_replicas_log2 < 1 || ms_small_replicas_log2 > 6 || s_small < 0) return KS_E_INVALID;
+    ctx->ms_rl_small_pref = ms_small_replicas_log2;
+    ctx->ms_s_small = s_small;
     return KS_OK;
 }
 
@@ -742,7 +759,7 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if (per_window) {
         const int rl = pick_ms_rl(bins, ctx->ms_rl_pref);
         e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), kind == KS_HIST_CUBE ? 0 : 1, n, dxyz, dsc, rl,
-                           (bins + 1) << rl, bins, ctx->d_hook_out.ptr, st);
+                           (bins << rl) + 64, bins, ctx->d_hook_out.ptr, st);
     } else {
         const int rq = pick_quad_rq(K, bins, ctx->quad_rq_pref);
         const LdsQuad lay = quad_layout(K, bins, rq);

@@ -45,7 +45,7 @@ struct Plan {
     long long total_traj = 0, total_regions = 0, max_traj = 0, max_voxels = 0, max_words = 0;
     unsigned long long n_pad = 2;
     int maxS_quad = 0, maxB_quad = 0, maxB_ms = 0;
-    int rl = 6, rq = 3, ms_hist_words = 0;
+    int rl = 4, rl_small = 3, rq = 0, ms_hist_words = 0;
     LdsQuad lay{};
     int* vol_nfound = nullptr;
     int* vol_base = nullptr;
@@ -62,6 +62,8 @@ struct Context {
     int num_cu = 256;
     bool profiling = false;
     int ms_rl_pref = 4;
+    int ms_rl_small_pref = 3;
+    int ms_s_small = 8;
     int quad_rq_pref = 0;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
@@ -103,3 +105,4 @@ LdsQuad quad_layout(int maxS, int maxB, int rq);
 }  // namespace ks
 
 extern "C" ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32_t quad_replicas_log2);
+extern "C" ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas_log2, int32_t s_small);

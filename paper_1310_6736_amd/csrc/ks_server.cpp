@@ -89,7 +89,7 @@ static size_t footprint(const ks::VolIn& v) {
     const size_t n = (size_t)ks::num_trajectories(v.dims, v.spacing, v.scales, v.method);
     size_t pad = 2;
     while (pad < n) pad <<= 1;
-    return raw + ks::bins_bytes(v.dims) + n * sizeof(ks::TrajRec) + pad * (sizeof(ks::SortRec) + 2 * sizeof(int)) +
+    return raw + ks::bins_bytes(v.dims) + n * sizeof(ks::TrajRec) + pad * (2 * sizeof(ks::SortRec) + 2 * sizeof(int)) +
            (size_t)v.capacity * sizeof(ks_region) + (1 << 16);
 }
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "ks_status_str", "ks_context_create", "ks_context_destroy", "ks_context_set_profiling", "ks_context_set_tuning",
     "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
-    "ks_server_stats", "ks_server_destroy", "ks_roofline",
+    "ks_server_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
 ]
 
 
@@ -89,6 +89,7 @@ def lib():
     L.ks_context_destroy.argtypes = [vp]
     L.ks_context_set_profiling.argtypes = [vp, i32]
     L.ks_context_set_tuning.argtypes = [vp, i32, i32]
+    L.ks_context_set_tuning_small.argtypes = [vp, i32, i32]
     L.ks_last_stats.argtypes = [vp, C.POINTER(RunStats)]
     L.ks_detect.argtypes = [vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p]
     L.ks_detect_device.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p, vp]
@@ -200,6 +201,11 @@ def ks_context_set_profiling(ctx: Context, on: bool):
 
 def ks_context_set_tuning(ctx: Context, ms_replicas_log2: int, quad_replicas_log2: int):
     _check(lib().ks_context_set_tuning(ctx.handle, ms_replicas_log2, quad_replicas_log2), "ks_context_set_tuning")
+
+
+def ks_context_set_tuning_small(ctx: Context, ms_small_replicas_log2: int, s_small: int):
+    _check(lib().ks_context_set_tuning_small(ctx.handle, ms_small_replicas_log2, s_small),
+           "ks_context_set_tuning_small")
 
 
 def ks_last_stats(ctx: Context) -> dict:

@@ -1,0 +1,164 @@
+"""GPU tests of the batched launch (one captured graph over many volumes) and of
+the continuous-batching server: every volume's result must equal the same
+volume run alone (bit-identical regions) and, on a subset, the CPU oracle."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_6736_amd import ks, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    c = ks.Context(0)
+    yield c
+    c.close()
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def small_mix():
+    """Eight volumes of uneven sizes and all three voxel types, both methods,
+    several bin counts and scale ranges."""
+    dims = [(40, 33, 29), (37, 52, 31), (64, 48, 33), (45, 45, 45), (70, 35, 40), (33, 61, 37), (50, 50, 34),
+            (66, 41, 43)]
+    dtypes = [np.uint8, np.uint16, np.int16]
+    out = []
+    for i, (X, Y, Z) in enumerate(dims):
+        rng = np.random.default_rng(500 + i)
+        dt = dtypes[i % 3]
+        hi = 255 if dt == np.uint8 else 3000
+        v = np.clip(rng.normal(hi * 0.2, hi * 0.03, (Z, Y, X)), 0, hi)
+        zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+        for _ in range(2):
+            r = int(rng.integers(4, 9))
+            c = [int(rng.integers(r, d - r)) for d in (X, Y, Z)]
+            m = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2 <= r * r
+            v[m] = rng.integers(0, hi + 1, int(m.sum()))
+        vol = np.rint(v).astype(dt)
+        bins = [32, 64, 48][i % 3]
+        scales = [(3, 8), (2, 7), (4, 10)][i % 3]
+        out.append(synth.Workload(f"mix{i}", vol, bins, 5 + i % 3, scales, i % 2, 30))
+    return out
+
+
+def same_regions(a, b):
+    return a[1] == b[1] and np.array_equal(a[0], b[0])
+
+
+def test_batch_equals_alone_and_oracle(torch_dev, ctx):
+    ws = small_mix()
+    note(f"batch of {len(ws)} small volumes")
+    vols = [torch_dev.from_numpy(w.volume).to("cuda:0") for w in ws]
+    reqs = [ks.make_request(v, w.bins, w.spacing, w.scales, w.method, w.max_iter) for v, w in zip(vols, ws)]
+    cap = 4096
+    batch = ks.ks_detect_batch(ctx, reqs, capacity=cap)
+    for i, (w, v) in enumerate(zip(ws, vols)):
+        alone = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
+        assert same_regions(batch[i], alone), i
+        want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
+        assert batch[i][1] == n_want, i
+        for f in ("x", "y", "z", "scale", "seed"):
+            assert np.array_equal(batch[i][0][f], want[f]), (i, f)
+
+
+def test_batch_graph_replays_are_stable(torch_dev, ctx):
+    ws = small_mix()[:5]
+    note("batch graph replay x3 with eager work between")
+    vols = [torch_dev.from_numpy(w.volume).to("cuda:0") for w in ws]
+    reqs = [ks.make_request(v, w.bins, w.spacing, w.scales, w.method, w.max_iter) for v, w in zip(vols, ws)]
+    first = ks.ks_detect_batch(ctx, reqs, capacity=512)
+    for _ in range(3):
+        # unrelated eager work on the same context between replays
+        ks.ks_detect_device(ctx, vols[0], 16, 5, (2, 4), ks.KS_MEANSHIFT, 5, capacity=8)
+        again = ks.ks_detect_batch(ctx, reqs, capacity=512)
+        for a, b in zip(first, again):
+            assert same_regions(a, b)
+
+
+def test_batch_of_64_uneven_volumes(torch_dev, ctx):
+    """The uneven 64-volume batch: each result equals the volume run alone; the
+    oracle checks every sphere-type volume and the two smallest of each other type."""
+    specs = synth.batch_specs()
+    note("generating the 64-volume batch")
+    ws = synth.batch_workloads()
+    vols = [torch_dev.from_numpy(w.volume).to("cuda:0") for w in ws]
+    reqs = [ks.make_request(v, w.bins, w.spacing, w.scales, w.method, w.max_iter) for v, w in zip(vols, ws)]
+    note("batch of 64")
+    batch = ks.ks_detect_batch(ctx, reqs, capacity=256)
+    def size(i):
+        return specs[i][1][0] * specs[i][1][1] * specs[i][1][2]
+
+    oracle_ids = [i for i, s in enumerate(specs) if s[0] == 0]
+    for kind in (1, 2):
+        oracle_ids += sorted((i for i, s in enumerate(specs) if s[0] == kind), key=size)[:2]
+    for i, (w, v) in enumerate(zip(ws, vols)):
+        alone = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=256)
+        assert same_regions(batch[i], alone), i
+    for i in oracle_ids:
+        w = ws[i]
+        note(f"oracle on batch volume {i} ({w.name})")
+        want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=256)
+        assert batch[i][1] == n_want, i
+        for f in ("x", "y", "z", "scale", "seed"):
+            assert np.array_equal(batch[i][0][f], want[f]), (i, f)
+
+
+def test_server_results_equal_alone(torch_dev, ctx):
+    ws = small_mix()
+    note("server: 16 requests, 4 slots")
+    srv = ks.Server(0, hbm_budget=2 << 30, max_slots=4)
+    try:
+        tickets = []
+        for rep in range(2):
+            for w in ws:
+                tickets.append((w, srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)))
+                time.sleep(0.002)
+        srv.drain()
+        for w, t in tickets:
+            got = srv.poll(t, capacity=4096)
+            assert got is not None
+            v = torch_dev.from_numpy(w.volume).to("cuda:0")
+            alone = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=4096)
+            assert same_regions(got, alone), w.name
+        st = srv.stats()
+        assert st["completed"] == len(tickets) and st["p99_ms"] >= st["p50_ms"] > 0
+    finally:
+        srv.close()
+
+
+def test_server_small_budget_queues_and_refuses(torch_dev, ctx):
+    ws = small_mix()[:4]
+    note("server: small budget")
+    one = 3 << 20
+    srv = ks.Server(0, hbm_budget=one, max_slots=2)
+    try:
+        with pytest.raises(ks.KsError) as e:
+            srv.submit(synth.spheres_64().volume, 32, 2, (3, 8), ks.KS_MEANSHIFT, 10)
+        assert e.value.status == ks.KS_E_TOO_LARGE
+        ts = [srv.submit(x.volume, x.bins, x.spacing, x.scales, x.method, x.max_iter) for x in ws]
+        srv.drain()
+        for x, t in zip(ws, ts):
+            got = srv.poll(t, capacity=1024)
+            v = torch_dev.from_numpy(x.volume).to("cuda:0")
+            alone = ks.ks_detect_device(ctx, v, x.bins, x.spacing, x.scales, x.method, x.max_iter, capacity=1024)
+            assert same_regions(got, alone)
+        assert srv.stats()["refused"] == 1
+    finally:
+        srv.close()
