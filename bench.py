@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-stride", type=int, default=2)
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_meanshift_pet.json"))
+    ap.add_argument("--cpu-sample-stride", type=int, default=1)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_k_search_ms_pet128x128x64.json"))
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
@@ -125,8 +125,10 @@ def serving_section(ks, torch, ctx, n_req):
         return {"volumes_per_s": len(trace) / span, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(np.mean(lat))}
 
+    srv = ks.Server(0, hbm_budget=8 << 30, max_slots=4)
+
     def run_server(trace):
-        srv = ks.Server(0, hbm_budget=8 << 30, max_slots=4)
+        srv.reset_stats()
         tickets = []
         start = time.perf_counter()
         for t_arr, k, seed, _ in trace:
@@ -139,7 +141,6 @@ def serving_section(ks, torch, ctx, n_req):
         st = srv.stats()
         for t in tickets:
             srv.poll(t, capacity=cap)
-        srv.close()
         return {"volumes_per_s": st["volumes_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                 "mean_ms": st["mean_ms"]}
 
@@ -147,11 +148,34 @@ def serving_section(ks, torch, ctx, n_req):
                        "(quadrant/mean-shift alternating) and 256x256x160 MR-like generators" % n_req,
            "plain_capacity_volumes_per_s": c_plain}
     sat = [(0.0, k, seed, i) for _, k, seed, i in trace]
+    run_server(sat)  # warm-up: the slots' device buffers grow to the mix's sizes
     out["saturated"] = {"server": run_server(sat), "plain": run_plain(sat)}
     lam = 0.7 * c_plain
     tr = synth.arrival_trace(lam, n=n_req)
     out["rate_0.7"] = {"rate_per_s": lam, "server": run_server(tr), "plain": run_plain(tr)}
+    srv.close()
     return out
+
+
+def measured_traffic(path):
+    """HBM bytes per launch of the mean-shift search from the committed counter
+    summary, or None when the kernel sources have changed since the counters were
+    taken (the summary records a SHA-256 of the files that define the kernel)."""
+    import hashlib
+
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in rec["source_files"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(stride: int):
@@ -172,8 +196,9 @@ def cpu_baseline(stride: int):
         total_evals += st["window_evals"]
         sample.append(f"{w.name}: {len(ids)}/{n} trajectories")
     return {"value": total_evals / total_s, "unit": "window_evals/s", "cores": 1, "kind": "oracle",
-            "sample": "every %dth trajectory of the PET-like volume, both methods (%s); %.1f s" %
-                      (stride, "; ".join(sample), total_s)}
+            "sample": "%s of the PET-like volume, both methods (%s); %.1f s" %
+                      ("every trajectory" if stride == 1 else "every %d-th trajectory" % stride, "; ".join(sample),
+                       total_s)}
 
 
 def main():
@@ -226,12 +251,7 @@ def main():
     ms_bytes = ms_stats[-1]["voxel_visits"] + ms_stats[-1]["final_visits"]
     q_bytes = q_stats[-1]["voxel_visits"] + q_stats[-1]["final_visits"]
     achieved = ms_bytes / (ms_kernel_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic(args.traffic_json)
 
     line = {
         "metric": "seed-scale window evals/sec",

@@ -218,10 +218,12 @@ typedef struct {
     double volumes_per_s;                /* completed / (last completion - first submit) */
 } ks_server_stats_t;
 
-/* A server owns a context on `device`, a budget of device memory for admitted
- * requests (hbm_budget bytes) and at most max_slots requests on the GPU at once.
- * Requests that arrive while others run are admitted when a slot and enough
- * budget are free, and their work overlaps on the device. */
+/* A server owns max_slots contexts on `device`, each with its own stream, and a
+ * budget of device memory for admitted requests (hbm_budget bytes).  Pending
+ * requests are admitted oldest first while their footprint fits the budget,
+ * grouped into batches of about ten milliseconds of estimated device work, one
+ * batch per free slot; a batch that arrives while others run is launched at
+ * once on its own stream and its work overlaps theirs on the device. */
 ks_status ks_server_create(int32_t device, size_t hbm_budget, int32_t max_slots, ks_server** out);
 /* Copies the host volume; returns a ticket.  KS_E_TOO_LARGE if the request can
  * never fit the budget. */
@@ -231,6 +233,12 @@ ks_status ks_server_poll(ks_server* s, uint64_t ticket, ks_region* out, int32_t 
 /* Blocks until every submitted request is done. */
 ks_status ks_server_drain(ks_server* s);
 ks_status ks_server_stats(ks_server* s, ks_server_stats_t* out);
+/* Starts a new measurement window: clears the latency samples and the
+ * submitted/admitted/completed/refused counts and the throughput clock; requests
+ * already queued or in flight are still served and counted when they complete.
+ * Lets a caller warm a server (device buffers grow to the workload's sizes on
+ * first use) before measuring it. */
+ks_status ks_server_reset_stats(ks_server* s);
 ks_status ks_server_destroy(ks_server* s);
 
 #ifdef __cplusplus

@@ -554,7 +554,7 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 // ------------------------------------------------------- mean-shift kernel
 
 template <int M>
-__global__ __launch_bounds__(64) void k_search_ms(const VolDesc* vols, const TaskSeg* segs, int nseg, long long ntask,
+__global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg, long long ntask,
                                                   Tables tb, TrajRec* out, Counters* cnt, MsTune tune,
                                                   int hist_words) {
     extern __shared__ unsigned long long hist[];
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* vols, const Tas
         if (t >= ntask) break;
         const int si = uniform(find_seg(segs, nseg, t));
         const TaskSeg sg = segs[si];
-        const VolDesc v = vols[sg.vol];
+        const VolDesc& v = vols[sg.vol];
         const long long seed = sg.seed_begin + (t - sg.task_begin);
         const int s = sg.scale;
         int p0[3];
@@ -942,7 +942,7 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
 // --------------------------------------------------------- quadrant kernel
 
 template <int M>
-__global__ __launch_bounds__(256) void k_search_quad(const VolDesc* vols, const TaskSeg* segs, int nseg,
+__global__ __launch_bounds__(256) void k_search_quad(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg,
                                                      long long ntask, Tables tb, TrajRec* out, Counters* cnt,
                                                      int rq, LdsQuad lay) {
     extern __shared__ __align__(16) char smem[];
@@ -963,7 +963,7 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* vols, const 
         if (t >= ntask) break;
         const int si = uniform(find_seg(segs, nseg, t));
         const TaskSeg sg = segs[si];
-        const VolDesc v = vols[sg.vol];
+        const VolDesc& v = vols[sg.vol];
         const long long seed = sg.seed_begin + (t - sg.task_begin);
         int p0[3];
         seed_pos(v, seed, p0);

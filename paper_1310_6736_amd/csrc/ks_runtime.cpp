@@ -69,11 +69,12 @@ static ks_status hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? KS_E
 
 ks_status Buffer::ensure(size_t bytes, int* generation) {
     if (bytes <= cap) return KS_OK;
+    // grow by at least 1.5x so that a slowly rising size reallocates rarely
+    size_t want = std::max(bytes, cap + cap / 2);
+    want = (want + 4095) & ~(size_t)4095;
     if (ptr) hipFree(ptr);
     ptr = nullptr;
     cap = 0;
-    size_t want = std::max(bytes, cap * 3 / 2);
-    want = (want + 4095) & ~(size_t)4095;
     hipError_t e = hipMalloc(&ptr, want);
     if (e != hipSuccess) {
         ptr = nullptr;
@@ -92,10 +93,10 @@ void Buffer::release() {
 
 ks_status PinnedBuffer::ensure(size_t bytes) {
     if (bytes <= cap) return KS_OK;
+    size_t want = (std::max(std::max(bytes, (size_t)4096), cap + cap / 2) + 4095) & ~(size_t)4095;
     if (ptr) hipHostFree(ptr);
     ptr = nullptr;
     cap = 0;
-    size_t want = (std::max(bytes, (size_t)4096) + 4095) & ~(size_t)4095;
     if (hipHostMalloc(&ptr, want, hipHostMallocDefault) != hipSuccess) {
         ptr = nullptr;
         return KS_E_NOMEM;

@@ -62,8 +62,8 @@ struct Context {
     int num_cu = 256;
     bool profiling = false;
     int ms_rl_pref = 4;
-    int ms_rl_small_pref = 3;
-    int ms_s_small = 8;
+    int ms_rl_small_pref = 2;
+    int ms_s_small = 6;
     int quad_rq_pref = 0;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;

@@ -1,11 +1,12 @@
 // Continuous-batching detection server.
 //
-// A scheduler thread owns the GPU work.  Each tick it admits, oldest first, every
-// pending request whose device footprint fits the remaining HBM budget, groups
-// the admitted requests into one batched launch sequence on a free slot (own
-// context and stream), and retires slots whose completion event has fired.  Slots
-// run concurrently on the device, so requests that arrive while others are on
-// the GPU start as soon as a slot and budget are free and overlap with them.  A
+// A scheduler thread owns the GPU work.  Each tick it admits, oldest first, the
+// pending requests whose device footprint fits the remaining HBM budget, up to
+// about ten milliseconds of estimated device work, groups them into one batched
+// launch sequence on a free slot (own context and stream), and retires slots
+// whose completion event has fired.  Several slots are in flight at once, so the
+// next batch's upload and launch overlap the current one and its blocks fill
+// the device as the current launch's tail drains.  A
 // request's result does not depend on what it was batched with: every trajectory
 // is computed independently and ranked within its own volume.
 #include <hip/hip_runtime.h>
@@ -35,6 +36,7 @@ struct SrvReq {
     ks::VolIn in;
     std::vector<uint8_t> host;     // copy of the submitted volume
     size_t footprint = 0;
+    double work = 0;               // estimated voxel visits
     double t_submit = 0, t_done = 0;
     int status = KS_E_NOT_READY;
     std::vector<ks_region> regions;
@@ -102,6 +104,29 @@ static double percentile(std::vector<double> v, double q) {
     return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
 }
 
+// Estimated voxel visits of a request's search: seeds x the window voxels of one
+// evaluation round x a typical evaluation count per trajectory.  Used only to
+// bound a batch's work so that results come back in pieces of a few ms of device
+// time instead of one long launch.
+static double work_estimate(const ks::VolIn& v) {
+    const double seeds = (double)ks::num_trajectories(v.dims, v.spacing, v.scales, KS_QUADRANT);
+    double win = 0;
+    if (v.method == KS_QUADRANT) {
+        const double w = 2.0 * v.scales[1] + 1.0;
+        win = 5.0 * w * w * w;
+    } else {
+        for (int s = v.scales[0]; s <= v.scales[1]; ++s) {
+            const double w = 2.0 * s + 1.0;
+            win += 6.0 * w * w * w;
+        }
+    }
+    const double vox = (double)v.dims[0] * v.dims[1] * v.dims[2];
+    return seeds * std::min(win, 64.0 * vox);
+}
+
+// Work of one batch: about 10 ms of device time at the measured visit rates.
+constexpr double kBatchWork = 2.0e10;
+
 // One scheduler step; returns true if it did any work.
 bool ks_server::tick() {
     bool worked = false;
@@ -150,9 +175,12 @@ bool ks_server::tick() {
     size_t bytes = 0;
     {
         std::lock_guard<std::mutex> lk(mu);
+        double work = 0;
         while (!pending.empty()) {
             SrvReq& r = reqs[pending.front()];
             if (in_use + bytes + r.footprint > budget) break;   // oldest first: no overtaking
+            if (!take.empty() && work + r.work > kBatchWork) break;
+            work += r.work;
             bytes += r.footprint;
             take.push_back(pending.front());
             pending.pop_front();
@@ -215,9 +243,10 @@ void ks_server::run() {
     if (hipSetDevice(device) != hipSuccess) st = KS_E_DEVICE;
     for (int i = 0; i < max_slots && st == KS_OK; ++i) {
         Slot* sl = new Slot();
+        // every launch takes the full persistent grid: a slot's blocks start as the
+        // blocks of the launch before it retire, so the device never runs a
+        // partial grid once the other slots have drained
         st = sl->ctx.init(device);
-        // concurrent slots share the device: each persistent launch takes a share
-        sl->ctx.grid_pct = std::max(25, 100 / std::max(1, std::min(max_slots, 4)));
         if (st == KS_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) st = KS_E_DEVICE;
         if (st == KS_OK && hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) st = KS_E_DEVICE;
         slots.push_back(sl);
@@ -284,6 +313,7 @@ ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket
     r.in.capacity = (int32_t)std::min<int64_t>(ks::num_trajectories(req->dims, req->seed_spacing, req->scales,
                                                                     req->method), 1 << 20);
     r.footprint = footprint(r.in);
+    r.work = work_estimate(r.in);
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->stop) return KS_E_SHUTDOWN;
     if (s->fatal != KS_OK) return s->fatal;
@@ -351,6 +381,17 @@ ks_status ks_server_stats(ks_server* s, ks_server_stats_t* out) {
     out->mean_ms = s->latencies.empty() ? 0.0 : sum / (double)s->latencies.size();
     const double span = s->last_done - s->first_submit;
     out->volumes_per_s = (s->completed > 0 && span > 0) ? (double)s->completed / (span / 1000.0) : 0.0;
+    return KS_OK;
+}
+
+ks_status ks_server_reset_stats(ks_server* s) {
+    if (!s) return KS_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->latencies.clear();
+    s->submitted = s->admitted = s->completed = s->refused = 0;
+    // with work still queued or running the window starts now, else at the next submit
+    s->first_submit = (s->in_flight > 0 || !s->pending.empty()) ? now_ms() : -1;
+    s->last_done = 0;
     return KS_OK;
 }
 

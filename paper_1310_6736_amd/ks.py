@@ -24,7 +24,7 @@ EXPORTS = [
     "ks_status_str", "ks_context_create", "ks_context_destroy", "ks_context_set_profiling", "ks_context_set_tuning",
     "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
-    "ks_server_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
+    "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
     L.ks_server_drain.argtypes = [vp]
     L.ks_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.ks_server_reset_stats.argtypes = [vp]
     L.ks_server_destroy.argtypes = [vp]
     L.ks_roofline.argtypes = [i32, i32, C.POINTER(C.c_double)]
     for name in EXPORTS:
@@ -350,6 +351,9 @@ class Server:
         st = ServerStats()
         _check(lib().ks_server_stats(self.handle, C.byref(st)), "ks_server_stats")
         return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        _check(lib().ks_server_reset_stats(self.handle), "ks_server_reset_stats")
 
     def close(self):
         if self.handle:

@@ -139,6 +139,18 @@ def test_server_results_equal_alone(torch_dev, ctx):
             assert same_regions(got, alone), w.name
         st = srv.stats()
         assert st["completed"] == len(tickets) and st["p99_ms"] >= st["p50_ms"] > 0
+        # a new measurement window counts only what is submitted after it
+        srv.reset_stats()
+        st = srv.stats()
+        assert st["completed"] == 0 and st["submitted"] == 0 and st["p50_ms"] == 0 and st["volumes_per_s"] == 0
+        t2 = [srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter) for w in ws[:2]]
+        srv.drain()
+        st = srv.stats()
+        assert st["completed"] == 2 and st["submitted"] == 2 and st["volumes_per_s"] > 0
+        for w, t in zip(ws[:2], t2):
+            v = torch_dev.from_numpy(w.volume).to("cuda:0")
+            alone = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=4096)
+            assert same_regions(srv.poll(t, capacity=4096), alone), w.name
     finally:
         srv.close()
 
