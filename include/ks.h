@@ -97,6 +97,8 @@ typedef struct {
     int64_t final_visits;  /* in-volume voxels read by the final saliency pass */
     int64_t regions;       /* regions found (sum over volumes) */
     double ms_prep, ms_search, ms_rank, ms_total; /* device time per phase (only with profiling on) */
+    int64_t swept_voxels;  /* voxels the searches actually swept: with running-window updates
+                              of the mean-shift search, fewer than voxel_visits + final_visits */
 } ks_run_stats;
 
 typedef struct ks_context ks_context;
@@ -114,7 +116,7 @@ ks_status ks_context_destroy(ks_context* ctx);
 ks_status ks_context_set_profiling(ks_context* ctx, int32_t on);
 
 /* Tuning of the scatter kernels (the values the built-in tuner picks by default).
- * ms_replicas_log2 in [1,6]: packed LDS histogram replicas per wavefront of the
+ * ms_replicas_log2 in [2,6]: packed LDS histogram replicas per wavefront of the
  * mean-shift scatter, 2^value (also sets the small-window value);
  * quad_replicas_log2 in [0,3]: replicas per workgroup of the octant scatter.
  * Fewer replicas: more same-address LDS atomics, fewer slots to clear; more
@@ -123,8 +125,18 @@ ks_status ks_context_set_profiling(ks_context* ctx, int32_t on);
 ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32_t quad_replicas_log2);
 
 /* Mean-shift windows of half-width <= s_small use 2^ms_small_replicas_log2
- * replicas (ms_small_replicas_log2 in [1,6], s_small >= 0). */
+ * replicas (ms_small_replicas_log2 in [2,6], s_small >= 0). */
 ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas_log2, int32_t s_small);
+
+/* Running-window updates of the mean-shift search (Sec. 2.3 evaluates Eq. 4-6 on
+ * the window at every new position; consecutive windows of a trajectory
+ * overlap).  A later evaluation of a trajectory takes the voxels that leave the
+ * window out of its totals and adds those that enter, when the two regions
+ * together hold fewer than incremental_pct percent of the window's voxels
+ * (0..200; 0: every evaluation sweeps its whole window; default 100).  The final
+ * pass reuses the counts of the window at P*.  Counts and offset sums are
+ * integers, so results do not depend on the value. */
+ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct);
 
 /* Counters and times of the last detect/batch call on this context. */
 ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out);
@@ -166,8 +178,21 @@ ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
  *                     (rows: count, sum dx, sum dy, sum dz)
  *   KS_HIST_SHELLS    counts of the centred cubes of every half-width s in
  *                     [range[0], range[1]] (saliency pass):               uint32 [n][K][B]
+ *   KS_HIST_MS_MOVE   as KS_HIST_MEANSHIFT at Q, reached by the running-window
+ *                     update from the window at P; xyz holds 6n values, P then
+ *                     Q per window (any two positions in the volume):     int32  [n][4][B]
+ *   KS_HIST_MS_INNER  counts of P + [-s,s]^3, of P + [-(s-1),s-1]^3 through
+ *                     the shell subtraction, and of the same inner cube swept
+ *                     directly (mean-shift final pass):                  uint32 [n][3][B]
  * K = range[1] - range[0] + 1.  out is a host buffer of the stated size. */
-enum { KS_HIST_CUBE = 0, KS_HIST_OCTANTS = 1, KS_HIST_MEANSHIFT = 2, KS_HIST_SHELLS = 3 };
+enum {
+    KS_HIST_CUBE = 0,
+    KS_HIST_OCTANTS = 1,
+    KS_HIST_MEANSHIFT = 2,
+    KS_HIST_SHELLS = 3,
+    KS_HIST_MS_MOVE = 4,
+    KS_HIST_MS_INNER = 5
+};
 ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
                         int32_t kind, const int32_t range[2], int32_t n, const int32_t* xyz, const int32_t* scale,
                         void* out, void* stream);

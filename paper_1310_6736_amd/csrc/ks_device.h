@@ -6,14 +6,14 @@
 
 namespace ks {
 
-// Packed per-replica mean-shift accumulator (one uint64 per bin per replica):
-//   bits  0..9   voxel count
-//   bits 10..25  sum of (dx + s)      (or: count of voxels of the inner cube, final pass)
-//   bits 32..47  sum of (dy + s)
-//   bits 48..63  sum of (dz + s)
-// A replica takes at most kMaxPerReplica voxels between flushes, which keeps every
-// field below its width for s <= 32 (64 * 1023 < 65536).
-constexpr int kMaxPerReplica = 1023;
+// Packed per-replica mean-shift accumulator (one uint64 per bin per replica),
+// two's-complement fields of a sum of signed voxel terms (mod 2^64):
+//   bits  0..9   net voxel count
+//   bits 10..31  sum of dx'
+//   bits 32..47  sum of dy'
+//   bits 48..63  sum of dz'
+// (d' = offset from the sweep's reference point + s).  A replica takes at most
+// 511 voxels between flushes and 511 * max|d'| < 2^15, so every field decodes.
 constexpr int kSmaxLimit = 32;
 constexpr int kBinsLimit = 256;
 
@@ -34,9 +34,12 @@ struct Tables {
 // One volume of a search.
 struct VolDesc {
     const void* raw;        // input voxels, dense, x fastest
-    uint8_t* bins;          // bin volume, row pitch xp (multiple of 16)
+    uint8_t* bins;          // bin volume, x fastest, row pitch xp (multiple of 16)
+    uint8_t* bins_t;        // the same bins, y fastest: byte (x * Z + z) * yp + y
     int32_t X, Y, Z, xp;
     int64_t slice;          // xp * Y
+    int32_t yp, pad2;       // y pitch of bins_t (multiple of 16)
+    int64_t slice_t;        // yp * Z
     int32_t dtype, B, sp, s_min, s_max, method, max_iter;
     int32_t gx, gy, gz, ox, oy, oz;  // seed grid
     int32_t S;              // s_max - s_min + 1
@@ -85,13 +88,16 @@ struct Counters {
     unsigned long long evals, window_evals, voxel_visits, final_visits;
     unsigned long long queue_head[2];   // task queues (quadrant, mean-shift)
     unsigned long long n_sort;          // kept trajectories
-    unsigned long long pad;
+    unsigned long long swept;           // voxels actually swept by the searches
 };
 
 // Launch-time tuning of the mean-shift evaluation: replicas per wavefront,
-// 1 << rl for windows of half-width > s_small and 1 << rl_small otherwise.
+// 1 << rl for windows of half-width > s_small and 1 << rl_small otherwise; a
+// later evaluation of a trajectory updates its running window when the voxels
+// that leave and enter it are fewer than incr_pct percent of the window (0:
+// never).
 struct MsTune {
-    int32_t rl, rl_small, s_small, pad;
+    int32_t rl, rl_small, s_small, incr_pct;
 };
 
 }  // namespace ks

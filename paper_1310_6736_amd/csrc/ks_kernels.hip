@@ -36,6 +36,9 @@ namespace ks {
 
 constexpr int kUnroll = 4;  // window rows per group of loads
 constexpr int kDepth = 4;   // groups of loads in flight per wavefront
+// Load offset past the end of every bin volume (volumes stay below 2^31 bytes):
+// the buffer range check turns such a load into 0 without a memory access.
+constexpr uint32_t kPastEnd = 0x80000000u;
 
 // Moves a double across lanes with a DPP pattern (VALU only, no LDS traffic).
 template <int CTRL>
@@ -101,39 +104,60 @@ __device__ __forceinline__ int64_t cube_count(const VolDesc& v, int px, int py, 
     return clipped_len(px, r, v.X) * clipped_len(py, r, v.Y) * clipped_len(pz, r, v.Z);
 }
 
-// Buffer descriptor of the bin volume; base and size are made scalar explicitly
-// so that every load of a sweep uses one descriptor held in SGPRs.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t bins_rsrc(const VolDesc& v) {
-    const uint64_t a = reinterpret_cast<uint64_t>(v.bins);
+// A copy of the bin volume as seen by a sweep: bytes along the fast axis are
+// contiguous, rows along the row axis are `pitch` bytes apart and slices along
+// the slice axis `slab` bytes apart.  Two copies exist: x fast (rows y, slices
+// z; every volume) and y fast (rows z, slices x; mean-shift volumes), so that
+// a box thin in x is swept along y instead of touching one cache line per voxel.
+struct Layout {
+    const uint8_t* base;
+    uint32_t pitch, slab;
+    int32_t bytes;
+};
+
+__device__ __forceinline__ Layout layout_x(const VolDesc& v) {
+    return Layout{v.bins, (uint32_t)v.xp, (uint32_t)v.slice, (int32_t)(v.slice * v.Z)};
+}
+
+__device__ __forceinline__ Layout layout_t(const VolDesc& v) {
+    return Layout{v.bins_t, (uint32_t)v.yp, (uint32_t)v.slice_t, (int32_t)(v.slice_t * v.X)};
+}
+
+// Buffer descriptor of a layout; base and size are made scalar explicitly so that
+// every load of a sweep uses one descriptor held in SGPRs.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t layout_rsrc(const Layout& L) {
+    const uint64_t a = reinterpret_cast<uint64_t>(L.base);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
     void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
-    const int bytes = __builtin_amdgcn_readfirstlane((int)(v.slice * v.Z));
+    const int bytes = __builtin_amdgcn_readfirstlane(L.bytes);
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
 }
 
-// A box [xa,xb]x[ya,yb]x[za,zb] swept by NT lanes: each active lane owns one
+// A box of a layout swept by NT lanes: fast coordinates [fa, fb], nr rows
+// ra, ra + rstep, ... and ns slices sa, sa + sstep, ...  Each active lane owns one
 // dword column of one row of a ty x tz tile of rows; the tile then steps through
-// the box, first along y, then along z.  All fields except the lane ones are
-// uniform.
+// the box, first along the rows, then along the slices.  All fields except the
+// lane ones are uniform.
 struct Sweep {
     int ny, nz, nd, ty, tz, nsteps;
-    int xa, ya, za;
+    uint32_t pr, ps;    // bytes between consecutive rows, slices of the box
     // lane part
     bool on;
-    int oy, oz, x0;
+    int oy, oz, x0;     // row and slice index in the tile, fast coordinate of byte 0
     uint32_t voff;      // byte offset of the lane's dword at the first step
 };
 
 template <int NT>
-__device__ __forceinline__ Sweep make_sweep(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb,
-                                            int tid) {
+__device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int ra, int nr, int rstep, int sa,
+                                            int ns, int sstep, int tid) {
     Sweep w;
-    w.xa = xa; w.ya = ya; w.za = za;
-    w.ny = yb - ya + 1;
-    w.nz = zb - za + 1;
-    const int da = xa >> 2;
-    w.nd = (xb >> 2) - da + 1;
+    w.ny = nr;
+    w.nz = ns;
+    w.pr = L.pitch * (uint32_t)rstep;
+    w.ps = L.slab * (uint32_t)sstep;
+    const int da = fa >> 2;
+    w.nd = (fb >> 2) - da + 1;
     w.ty = min(w.ny, NT / w.nd);
     w.tz = min(w.nz, NT / (w.ty * w.nd));
     const int steps_y = (w.ny + w.ty - 1) / w.ty;
@@ -145,23 +169,29 @@ __device__ __forceinline__ Sweep make_sweep(const VolDesc& v, int xa, int xb, in
     w.oy = rem / w.nd;
     const int d = rem - w.oy * w.nd;
     w.x0 = (da + d) * 4;
-    w.voff = (uint32_t)(za + w.oz) * (uint32_t)v.slice + (uint32_t)(ya + w.oy) * (uint32_t)v.xp + (uint32_t)w.x0;
+    w.voff = (uint32_t)sa * L.slab + (uint32_t)ra * L.pitch + (uint32_t)w.oz * w.ps + (uint32_t)w.oy * w.pr +
+             (uint32_t)w.x0;
     return w;
 }
 
 // Walks the sweep's steps in groups of kUnroll rows, keeping kDepth groups of
 // loads in flight: the loads of group g + kDepth are issued right after group g
 // is scattered.  Calls f(word, iy0, iz0) for every step in which the lane's row
-// lies inside the box.  After each group that brings the step count to `every`,
-// flush() runs (uniformly).  Loads past the last step read beyond the box (or
-// past the descriptor's end, which returns 0) and are never used.
+// lies inside the box (word: 4 voxels; iy0, iz0: the step's row and slice offset).
+// `used` counts the voxels each lane has scattered since the last flush, across
+// calls: before a group that would take it past `limit`, flush() runs
+// (uniformly) and the count restarts.  Loads for steps past the last one get an
+// offset beyond the descriptor's end: they return 0 without a memory access.
 template <typename F, typename G>
-__device__ __forceinline__ void run_sweep(const VolDesc& v, const Sweep& w, int every, F&& f, G&& flush) {
-    const __amdgpu_buffer_rsrc_t rs = bins_rsrc(v);
-    const uint32_t xp = (uint32_t)uniform(v.xp), slice = (uint32_t)uniform((int)v.slice);
+__device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, int& used, int limit, F&& f,
+                                          G&& flush) {
+    const __amdgpu_buffer_rsrc_t rs = layout_rsrc(L);
+    const uint32_t xp = (uint32_t)uniform((int)w.pr), slice = (uint32_t)uniform((int)w.ps);
+    const int nz = uniform(w.nz);
     const int ny = uniform(w.ny), ty = uniform(w.ty), tz = uniform(w.tz), nsteps = uniform(w.nsteps);
     const int lim_y = w.ny - w.oy, lim_z = w.nz - w.oz;
-    int iy0 = 0, iz0 = 0, since = 0;
+    constexpr int kGroupVoxels = kUnroll * 4;
+    int iy0 = 0, iz0 = 0;
     uint32_t buf[kDepth][kUnroll];
     int by[kDepth][kUnroll], bz[kDepth][kUnroll];
 #pragma unroll
@@ -170,7 +200,7 @@ __device__ __forceinline__ void run_sweep(const VolDesc& v, const Sweep& w, int 
         for (int u = 0; u < kUnroll; ++u) {
             by[g][u] = iy0;
             bz[g][u] = iz0;
-            buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
+            buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? iz0 * slice + iy0 * xp : kPastEnd, 0);
             iy0 += ty;
             if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
         }
@@ -179,21 +209,21 @@ __device__ __forceinline__ void run_sweep(const VolDesc& v, const Sweep& w, int 
 #pragma unroll
         for (int g = 0; g < kDepth; ++g) {
             if (t + g * kUnroll < nsteps) {
+                if (used + kGroupVoxels > limit) {
+                    used = 0;
+                    flush();
+                }
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     if (w.on && by[g][u] < lim_y && bz[g][u] < lim_z) f(buf[g][u], by[g][u], bz[g][u]);
                 }
-                since += kUnroll;
-                if (since >= every) {
-                    since = 0;
-                    flush();
-                }
+                used += kGroupVoxels;
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 by[g][u] = iy0;
                 bz[g][u] = iz0;
-                buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 * slice + iy0 * xp, 0);
+                buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? iz0 * slice + iy0 * xp : kPastEnd, 0);
                 iy0 += ty;
                 if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
             }
@@ -215,6 +245,7 @@ __global__ void k_prep_init(VolDesc* vols, int nvol, Counters* cnt, int* vol_nfo
         cnt->evals = cnt->window_evals = cnt->voxel_visits = cnt->final_visits = 0;
         cnt->queue_head[0] = cnt->queue_head[1] = 0;
         cnt->n_sort = 0;
+        cnt->swept = 0;
     }
 }
 
@@ -281,15 +312,84 @@ __global__ __launch_bounds__(256) void k_quantize(const VolDesc* vols) {
     }
 }
 
-// ------------------------------------------------- mean-shift window scatter
+// The y-fastest copy of a mean-shift volume's bins: one 64 x 64 (x, y) tile of
+// one z plane per workgroup, transposed through LDS.  Bytes past Y in a row of
+// the copy are written as 0.
+__global__ __launch_bounds__(256) void k_transpose(const VolDesc* vols, int tiles_x) {
+    __shared__ uint32_t tile[64][17];
+    const VolDesc& v = vols[blockIdx.z];
+    if (v.method != 1 || (int)blockIdx.y >= v.Z) return;
+    const int x0 = (int)(blockIdx.x % (unsigned)tiles_x) * 64, y0 = (int)(blockIdx.x / (unsigned)tiles_x) * 64;
+    if (x0 >= v.X || y0 >= v.yp) return;
+    const int z = blockIdx.y;
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+        const int r = i >> 4, c = i & 15;
+        const int y = y0 + r, x = x0 + 4 * c;
+        uint32_t w = 0;
+        if (y < v.Y && x < v.xp) w = *reinterpret_cast<const uint32_t*>(v.bins + z * v.slice + (int64_t)y * v.xp + x);
+        tile[r][c] = w;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+        const int xr = i >> 4, c = i & 15;
+        const int x = x0 + xr, y = y0 + 4 * c;
+        if (x >= v.X || y >= v.yp) continue;
+        uint32_t w = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w |= ((tile[4 * c + k][xr >> 2] >> (8 * (xr & 3))) & 0xFFu) << (8 * k);
+        *reinterpret_cast<uint32_t*>(v.bins_t + ((int64_t)x * v.Z + z) * v.yp + y) = w;
+    }
+}
 
-// Per-lane totals of the lane's M bins lane*M .. lane*M+M-1.
+// ------------------------------------------------- mean-shift window scatter
+//
+// A wavefront sweeps the voxels of one or more boxes into 2^rl replicas of a
+// packed 64-bit LDS counter per bin, hist[(bin << rl) + replica], and flushes
+// them into per-lane totals of its M bins.  A voxel at offset d from the
+// reference point adds
+//     sign * (1 + dx' * 2^10 + dy' * 2^32 + dz' * 2^48)   (mod 2^64),  d' = d + s,
+// so a replica word holds the net count (bits 0-9) and the sums of dx' (10-31),
+// dy' (32-47) and dz' (48-63) of its voxels.  Voxels leave a window with sign -1;
+// the fields are then two's complement, and they decode exactly while each stays
+// in its signed range: at most 511 voxels per replica between flushes and
+// 511 * max|d'| < 2^15.  Sweeps that only add keep every field non-negative and
+// take up to 1023 voxels per replica (1023 * 2s < 2^16).
+
 template <int M>
 struct BinAcc {
     int c[M], f1[M], f2[M], f3[M];
 };
 
 template <int M>
+__device__ __forceinline__ void acc_clear(BinAcc<M>& a) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) a.c[t] = a.f1[t] = a.f2[t] = a.f3[t] = 0;
+}
+
+// Adds the four fields of a replica word to the totals of bin t.  SIGNED: the
+// fields are two's complement (a sweep with voxels leaving the window); else all
+// are non-negative.  With the low word L = c + dx'*2^10 in 32-bit range, the high
+// word of w - L is hi + (L < 0) and holds dy' + dz'*2^16.
+template <int M, bool SIGNED>
+__device__ __forceinline__ void unpack_add(unsigned long long w, int t, BinAcc<M>& a) {
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    if (SIGNED) {
+        const int c = __builtin_amdgcn_sbfe((int)lo, 0, 10);
+        const int fx = (int)(lo - (uint32_t)c) >> 10;
+        const uint32_t h = hi + (lo >> 31);
+        const int fy = __builtin_amdgcn_sbfe((int)h, 0, 16);
+        const int fz = (int)(h - (uint32_t)fy) >> 16;
+        a.c[t] += c; a.f1[t] += fx; a.f2[t] += fy; a.f3[t] += fz;
+    } else {
+        a.c[t] += (int)(lo & 0x3FFu);
+        a.f1[t] += (int)(lo >> 10);
+        a.f2[t] += (int)(hi & 0xFFFFu);
+        a.f3[t] += (int)(hi >> 16);
+    }
+}
+
+// Adds the replica words of the lane's bins to its totals and clears them.
+template <int M, bool SIGNED>
 __device__ __forceinline__ void ms_flush(unsigned long long* hist, int rl, int B, int lane, BinAcc<M>& a) {
     const int half = 1 << (rl - 1);  // replica pairs; rl >= 1
 #pragma unroll
@@ -299,90 +399,227 @@ __device__ __forceinline__ void ms_flush(unsigned long long* hist, int rl, int B
             unsigned long long* e = hist + ((size_t)b << rl);
             for (int i = 0; i < half; ++i) {
                 const int r = ((i + lane) & (half - 1)) << 1;
-                uint4* p = reinterpret_cast<uint4*>(e + r);
-                const uint4 q = *p;
-                *p = make_uint4(0u, 0u, 0u, 0u);
-                a.c[t] += (int)(q.x & 0x3FFu) + (int)(q.z & 0x3FFu);
-                a.f1[t] += (int)((q.x >> 10) & 0xFFFFu) + (int)((q.z >> 10) & 0xFFFFu);
-                a.f2[t] += (int)(q.y & 0xFFFFu) + (int)(q.w & 0xFFFFu);
-                a.f3[t] += (int)(q.y >> 16) + (int)(q.w >> 16);
+                ulonglong2* p = reinterpret_cast<ulonglong2*>(e + r);
+                const ulonglong2 q = *p;
+                *p = make_ulonglong2(0ull, 0ull);
+                unpack_add<M, SIGNED>(q.x, t, a);
+                unpack_add<M, SIGNED>(q.y, t, a);
             }
         }
     }
 }
 
-// Scatter the cube P + [-s, s]^3 (clipped) into the wavefront's packed
-// per-replica LDS histogram hist[(bin << rl) + replica] and flush into per-lane
-// bin totals.  rl may differ between windows (fewer replicas for small windows):
-// every bin slot is cleared by the flushes, and the slots for bytes outside the
-// window sit at trash_base, past every layout.  Search mode: f1..f3 are the sums of (dx+s), (dy+s), (dz+s).  Final
-// mode: f1 counts the voxels of the inner cube of half-width s-1, f2 = f3 = 0.
-template <bool FINAL, int M>
-__device__ void ms_window(const VolDesc& v, int px, int py, int pz, int s, int rl, int trash_base,
-                          unsigned long long* hist, int lane, BinAcc<M>& acc) {
-    px = uniform(px); py = uniform(py); pz = uniform(pz); s = uniform(s); rl = uniform(rl);
-    const int B = v.B;
-#pragma unroll
-    for (int t = 0; t < M; ++t) acc.c[t] = acc.f1[t] = acc.f2[t] = acc.f3[t] = 0;
-    const int xa = max(px - s, 0), xb = min(px + s, v.X - 1);
-    const int ya = max(py - s, 0), yb = min(py + s, v.Y - 1);
-    const int za = max(pz - s, 0), zb = min(pz + s, v.Z - 1);
-    const Sweep w = make_sweep<64>(v, xa, xb, ya, yb, za, zb, lane);
+// --------------------------------------------------- mean-shift box sets
+//
+// Between two evaluations of a trajectory the window moves from P to Q = P + D
+// with |D_a| <= s and most of its voxels stay.  The totals at Q follow from those
+// at P: shift the offset sums of all of P's voxels by -c_b * D, then sweep the
+// voxels of W(P) \ W(Q) with sign -1 and those of W(Q) \ W(P) with sign +1, all
+// relative to Q.  Counts and offset sums are integers, so the totals equal a
+// fresh sweep of W(Q) exactly.  The final pass needs the counts of the inner
+// cube P + [-(s-1), s-1]^3: the window's counts less its shell (the voxels at
+// Chebyshev distance exactly s), or the inner cube swept directly, whichever is
+// smaller.
+
+// Coordinates xa, xa + xs, ..., up to xb along x (likewise y, z); steps other
+// than 1 take the two opposite faces of a shell in one sweep.
+struct Box {
+    int xa, xb, ya, yb, za, zb;
+    int xs, ys, zs;
+};
+
+__device__ __forceinline__ int64_t box_volume(const Box& b) {
+    if (b.xa > b.xb || b.ya > b.yb || b.za > b.zb) return 0;
+    return (int64_t)((b.xb - b.xa) / b.xs + 1) * ((b.yb - b.ya) / b.ys + 1) * ((b.zb - b.za) / b.zs + 1);
+}
+
+// The one or two face coordinates c - s, c + s that lie in [0, n-1], as a strided
+// range lo, hi, step (empty: lo > hi).
+__device__ __forceinline__ void face_range(int c, int s, int n, int& lo, int& hi, int& step) {
+    const bool a = c - s >= 0, b = c + s < n;
+    lo = a ? c - s : c + s;
+    hi = b ? c + s : c - s;
+    step = 2 * s;
+    if (!a && !b) { lo = 0; hi = -1; }
+}
+
+// [p-s, p+s] minus [q-s, q+s], clipped to [0, n-1] (one interval; empty: lo > hi).
+__device__ __forceinline__ void range_minus(int p, int q, int s, int n, int& lo, int& hi) {
+    if (q > p) {
+        lo = p - s; hi = min(p + s, q - s - 1);
+    } else if (q < p) {
+        lo = max(p - s, q + s + 1); hi = p + s;
+    } else {
+        lo = 0; hi = -1;
+    }
+    lo = max(lo, 0);
+    hi = min(hi, n - 1);
+}
+
+// Box i (0..2) of the clipped cube P + [-s,s]^3 minus the clipped cube
+// Q + [-s,s]^3: outside Q's x range; inside it but outside Q's y range; inside
+// both but outside Q's z range.
+__device__ __forceinline__ Box minus_box(const VolDesc& v, int px, int py, int pz, int qx, int qy, int qz, int s,
+                                         int i) {
+    Box b;
+    b.xs = b.ys = b.zs = 1;
+    b.xa = max(max(px, qx) - s, 0); b.xb = min(min(px, qx) + s, v.X - 1);
+    b.ya = max(py - s, 0); b.yb = min(py + s, v.Y - 1);
+    b.za = max(pz - s, 0); b.zb = min(pz + s, v.Z - 1);
+    if (i == 0) {
+        range_minus(px, qx, s, v.X, b.xa, b.xb);
+    } else if (i == 1) {
+        range_minus(py, qy, s, v.Y, b.ya, b.yb);
+    } else {
+        b.ya = max(max(py, qy) - s, 0); b.yb = min(min(py, qy) + s, v.Y - 1);
+        range_minus(pz, qz, s, v.Z, b.za, b.zb);
+    }
+    return b;
+}
+
+// Sets of disjoint boxes, described by scalars so that box i is computed where it
+// is swept:
+//   kFull   the clipped cube P + [-s,s]^3                        (sign +1, ref P)
+//   kMove   W(P) \ W(Q) (boxes 0-2, sign -1), W(Q) \ W(P) (3-5, +1)  (ref Q)
+//   kShell  the faces of the clipped cube P + [-s,s]^3 (s >= 1), its voxels at
+//           Chebyshev distance exactly s: both x faces, both y faces (x inside),
+//           both z faces (x, y inside)                            (+1, ref P)
+//   kInner  the clipped cube P + [-(s-1), s-1]^3                 (+1, ref P)
+constexpr int kFull = 0, kMove = 1, kShell = 2, kInner = 3;
+
+struct BoxSet {
+    int kind, px, py, pz, qx, qy, qz, s;
+};
+
+__device__ __forceinline__ int box_count(const BoxSet& bs) {
+    return bs.kind == kMove ? 6 : bs.kind == kShell ? 3 : 1;
+}
+
+__device__ __forceinline__ Box box_at(const VolDesc& v, const BoxSet& bs, int i, int& sign) {
+    const int s = bs.s, px = bs.px, py = bs.py, pz = bs.pz;
+    sign = 1;
+    Box b;
+    if (bs.kind == kMove) {
+        if (i < 3) {
+            sign = -1;
+            b = minus_box(v, px, py, pz, bs.qx, bs.qy, bs.qz, s, i);
+        } else {
+            b = minus_box(v, bs.qx, bs.qy, bs.qz, px, py, pz, s, i - 3);
+        }
+    } else if (bs.kind == kShell) {
+        b.xs = b.ys = b.zs = 1;
+        // across the faces of axis i: the full range along axes before i, the
+        // inner range along axes after it
+        b.xa = max(px - s + 1, 0); b.xb = min(px + s - 1, v.X - 1);
+        b.ya = i < 1 ? max(py - s, 0) : max(py - s + 1, 0);
+        b.yb = i < 1 ? min(py + s, v.Y - 1) : min(py + s - 1, v.Y - 1);
+        b.za = max(pz - s, 0); b.zb = min(pz + s, v.Z - 1);
+        if (i == 0) face_range(px, s, v.X, b.xa, b.xb, b.xs);
+        else if (i == 1) face_range(py, s, v.Y, b.ya, b.yb, b.ys);
+        else face_range(pz, s, v.Z, b.za, b.zb, b.zs);
+    } else {
+        const int r = bs.kind == kInner ? s - 1 : s;
+        b.xs = b.ys = b.zs = 1;
+        b.xa = max(px - r, 0); b.xb = min(px + r, v.X - 1);
+        b.ya = max(py - r, 0); b.yb = min(py + r, v.Y - 1);
+        b.za = max(pz - r, 0); b.zb = min(pz + r, v.Z - 1);
+    }
+    return b;
+}
+
+__device__ __forceinline__ int64_t boxes_volume(const VolDesc& v, const BoxSet& bs) {
+    int64_t n = 0;
+    const int nb = box_count(bs);
+    for (int i = 0; i < nb; ++i) {
+        int sg;
+        n += box_volume(box_at(v, bs, i, sg));
+    }
+    return n;
+}
+
+// Sweeps the boxes of bs into the packed LDS histogram and adds them (with their
+// signs) to acc: counts and sums of d + s, d relative to the set's reference
+// point.  Each box is swept a dword column per lane; bytes outside it go to the
+// trash slots at trash_base, past every bin layout.  The flush budget runs across
+// the boxes.
+template <int M>
+__device__ __forceinline__ void ms_sweep(const VolDesc& v, BoxSet bs, int rl, int trash_base,
+                                         unsigned long long* hist, int lane, BinAcc<M>& acc) {
+    bs.kind = uniform(bs.kind); bs.px = uniform(bs.px); bs.py = uniform(bs.py); bs.pz = uniform(bs.pz);
+    bs.qx = uniform(bs.qx); bs.qy = uniform(bs.qy); bs.qz = uniform(bs.qz); bs.s = uniform(bs.s);
+    rl = uniform(rl);
+    const int s = bs.s, B = v.B;
+    const bool mv = bs.kind == kMove;
+    const int rx = mv ? bs.qx : bs.px, ry = mv ? bs.qy : bs.py, rz = mv ? bs.qz : bs.pz;
     const int R = 1 << rl;
     const int rep = lane & (R - 1);
     const uint32_t shift = (uint32_t)rl + 3;
-    // bytes outside the window go to a per-replica slot past every bin layout
     const uint32_t trash = (uint32_t)(trash_base + rep) << 3;
     const uint32_t repoff = (uint32_t)rep << 3;
-    uint32_t lo[4], off[4], wid[4];
+    // Voxels per replica between flushes: without leaving voxels every field is
+    // non-negative and 1023 * 2s < 2^16; with them the fields are signed and
+    // |d'| <= 3s.
+    const int per_rep = mv ? min(511, 32767 / (3 * s)) : 1023;
+    const int limit = (per_rep << rl) >> 6;
+    char* hb = reinterpret_cast<char*>(hist);
+    auto flush = [&]() {
+        __syncthreads();
+        if (mv) ms_flush<M, true>(hist, rl, B, lane, acc);
+        else ms_flush<M, false>(hist, rl, B, lane, acc);
+        __syncthreads();
+    };
+    int used = 0;
+    const int nb = box_count(bs);
+#pragma unroll 1
+    for (int i = 0; i < nb; ++i) {
+        int sg;
+        const Box b = box_at(v, bs, i, sg);
+        const int xa = uniform(b.xa), xb = uniform(b.xb), ya = uniform(b.ya), yb = uniform(b.yb);
+        const int za = uniform(b.za), zb = uniform(b.zb);
+        const int xs = uniform(b.xs), ys = uniform(b.ys), zs = uniform(b.zs);
+        sg = uniform(sg);
+        if (xa > xb || ya > yb || za > zb) continue;
+        // sweep along y (the y-fast copy) when x is strided or the box is thinner
+        // in x than in y; the fast axis is never strided
+        const bool tr = xs != 1 || (ys == 1 && xb - xa < yb - ya);
+        const Layout L = tr ? layout_t(v) : layout_x(v);
+        const int ny = (yb - ya) / ys + 1, nz = (zb - za) / zs + 1, nx = (xb - xa) / xs + 1;
+        const Sweep w = tr ? make_sweep<64>(L, ya, yb, za, nz, zs, xa, nx, xs, lane)
+                           : make_sweep<64>(L, xa, xb, ya, ny, ys, za, nz, zs, lane);
+        // axes (fast, row, slice) -> packed fields: x at bit 10, y at 32, z at 48
+        const int fa = tr ? ya : xa, fb = tr ? yb : xb, ra = tr ? za : ya, sa = tr ? xa : za;
+        const int rst = tr ? zs : ys, sst = tr ? xs : zs;
+        const int fr = tr ? ry : rx, rr = tr ? rz : ry, sr = tr ? rx : rz;
+        const long long mf = tr ? (1ll << 32) : (1ll << 10);
+        const long long mr = (tr ? (1ll << 48) : (1ll << 32)) * rst;
+        const long long ms = (tr ? (1ll << 10) : (1ll << 48)) * sst;
+        const long long lanepart = (long long)(ra - rr + s) * (tr ? (1ll << 48) : (1ll << 32)) + (long long)w.oy * mr +
+                                   (long long)(sa - sr + s) * (tr ? (1ll << 10) : (1ll << 48)) + (long long)w.oz * ms;
+        unsigned long long cp[4];
+        uint32_t off[4], wid[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int x = w.x0 + k;
-        const bool ok = x >= xa && x <= xb;
-        const int dx = x - px;
-        lo[k] = FINAL ? (1u | ((uint32_t)(dx < s && dx > -s) << 10)) : (1u | ((uint32_t)(dx + s) << 10));
-        off[k] = ok ? repoff : trash;
-        wid[k] = ok ? 8u : 0u;
+        for (int k = 0; k < 4; ++k) {
+            const int f = w.x0 + k;
+            const bool ok = f >= fa && f <= fb;
+            cp[k] = (unsigned long long)((long long)sg * (1ll + (long long)(f - fr + s) * mf + lanepart));
+            off[k] = ok ? repoff : trash;
+            wid[k] = ok ? 8u : 0u;
+        }
+        const unsigned long long smr = (unsigned long long)((long long)sg * mr);
+        const unsigned long long sms = (unsigned long long)((long long)sg * ms);
+        run_sweep(
+            L, w, used, limit,
+            [&](uint32_t word, int iy0, int iz0) {
+                const unsigned long long step = (unsigned long long)(uint32_t)iy0 * smr + (unsigned long long)(uint32_t)iz0 * sms;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t bin = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(hb + (bin << shift) + off[k]), cp[k] + step);
+                }
+            },
+            flush);
     }
-    // offsets of the lane's first row, biased by s
-    const uint32_t hi0 = (uint32_t)(ya + w.oy - py + s) | ((uint32_t)(za + w.oz - pz + s) << 16);
-    const uint32_t two_s = 2u * (uint32_t)s;
-    // Each replica may take kMaxPerReplica voxels between flushes: a step adds at
-    // most 4 voxels per lane and 64/R lanes share a replica.
-    const int every = max(kUnroll, (((kMaxPerReplica << rl) >> 8) / kUnroll) * kUnroll);
-    run_sweep(
-        v, w, every,
-        [&](uint32_t word, int iy0, int iz0) {
-            const uint32_t hi = hi0 + ((uint32_t)iy0 | ((uint32_t)iz0 << 16));
-            uint32_t le[4];
-            uint32_t hv;
-            if (FINAL) {
-                const uint32_t fy = hi & 0xFFFFu, fz = hi >> 16;
-                const bool inner = fy >= 1u && fy < two_s && fz >= 1u && fz < two_s;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) le[k] = inner ? lo[k] : 1u;
-                hv = 0u;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) le[k] = lo[k];
-                hv = hi;
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t b = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
-                const uint32_t addr = (b << shift) + off[k];
-                atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(hist) + addr),
-                          ((unsigned long long)hv << 32) | le[k]);
-            }
-        },
-        [&]() {
-            __syncthreads();
-            ms_flush<M>(hist, rl, B, lane, acc);
-            __syncthreads();
-        });
-    __syncthreads();
-    ms_flush<M>(hist, rl, B, lane, acc);
-    __syncthreads();
+    if (used > 0) flush();
 }
 
 struct EvalOut {
@@ -390,12 +627,10 @@ struct EvalOut {
 };
 
 // Eq. 4-6 with a flat kernel and the uniform target: move = (sum_b M_b/sqrt(c_b)) /
-// (sum_b sqrt(c_b)), objective rho~ = (sum_b sqrt(c_b)) / sqrt(N).
+// (sum_b sqrt(c_b)), objective rho~ = (sum_b sqrt(c_b)) / sqrt(N), from the
+// window totals (f = sums of d + s).
 template <int M>
-__device__ EvalOut ms_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, int rl, int trash_base,
-                           unsigned long long* hist, int lane) {
-    BinAcc<M> a;
-    ms_window<false, M>(v, px, py, pz, s, rl, trash_base, hist, lane, a);
+__device__ EvalOut ms_moments(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, const BinAcc<M>& a) {
     double sq[M], tx[M], ty[M], tz[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) {
@@ -432,12 +667,11 @@ __device__ __forceinline__ float entropy_term32(int c, int64_t N) {
     return -p * lp;
 }
 
-// Kadir-Brady saliency at the trajectory's own scale (mean-shift).
+// Kadir-Brady saliency at the trajectory's own scale (mean-shift) from the
+// counts of the window (cs) and of its inner cube of half-width s-1 (cin).
 template <int M>
-__device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, int rl,
-                                int trash_base, unsigned long long* hist, int lane) {
-    BinAcc<M> a;
-    ms_window<true, M>(v, px, py, pz, s, rl, trash_base, hist, lane, a);
+__device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, const int* cs,
+                                const int* cin) {
     const int64_t Ns = cube_count(v, px, py, pz, s);
     const int64_t Np = cube_count(v, px, py, pz, s - 1);
     double cl[M];
@@ -445,10 +679,10 @@ __device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int 
     float h = 0.0f;
 #pragma unroll
     for (int t = 0; t < M; ++t) {
-        cl[t] = tb.cl[a.c[t]];
-        long long d = (long long)a.c[t] * Np - (long long)a.f1[t] * Ns;
+        cl[t] = tb.cl[cs[t]];
+        long long d = (long long)cs[t] * Np - (long long)cin[t] * Ns;
         am += d < 0 ? -d : d;
-        h += entropy_term32(a.c[t], Ns);
+        h += entropy_term32(cs[t], Ns);
     }
     const double S = bfly_sum(local_pw<M>(cl));
     const long long A = bfly_sumll(am);
@@ -491,7 +725,7 @@ __device__ __forceinline__ void seed_pos(const VolDesc& v, long long seed, int* 
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
 struct LocalCounts {
-    unsigned long long evals, window_evals, voxel_visits, final_visits;
+    unsigned long long evals, window_evals, voxel_visits, final_visits, swept;
 };
 
 // The search loop shared by both methods: round the proposed move, stop if it is
@@ -553,15 +787,21 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 
 // ------------------------------------------------------- mean-shift kernel
 
+// Per trajectory: the window totals follow the trajectory (one sweep per
+// evaluation: the whole window first, later the difference regions when they
+// are the smaller sweep), and the final pass reuses the counts of the window at
+// P*.  Every sweep of the kernel goes through the one ms_sweep call below, so
+// the scatter code is instantiated once.
 template <int M>
-__global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg, long long ntask,
-                                                  Tables tb, TrajRec* out, Counters* cnt, MsTune tune,
-                                                  int hist_words) {
+__global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg,
+                                                  long long ntask, Tables tb, TrajRec* out, Counters* cnt,
+                                                  MsTune tune, int hist_words) {
     extern __shared__ unsigned long long hist[];
     const int lane = threadIdx.x;
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
     __syncthreads();
-    LocalCounts lc = {0, 0, 0, 0};
+    LocalCounts lc = {0, 0, 0, 0, 0};
+    const int trash_base = hist_words - 64;
     for (;;) {
         long long t = 0;
         if (lane == 0) t = (long long)atomicAdd(&cnt->queue_head[1], 1ull);
@@ -576,14 +816,95 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         seed_pos(v, seed, p0);
         // replicas per wavefront by window size class
         const int rl = s <= tune.s_small ? tune.rl_small : tune.rl;
-        const int trash_base = hist_words - 64;
-        const TrajOut o = run_trajectory(
-            v, p0, [&](int x, int y, int z) { return ms_eval<M>(v, tb, x, y, z, s, rl, trash_base, hist, lane); },
-            lc, s, 1);
-        const Saliency sal = ms_saliency<M>(v, tb, o.p[0], o.p[1], o.p[2], s, rl, trash_base, hist, lane);
-        lc.final_visits += cube_count(v, o.p[0], o.p[1], o.p[2], s);
+        // Search state (Sec. 2.3): accepted position P, window of the totals W,
+        // candidate Q; phase 0 evaluates P0, 1 a candidate, 2 the final pass.
+        int px = p0[0], py = p0[1], pz = p0[2];
+        int wx = px, wy = py, wz = pz;
+        int qx = px, qy = py, qz = pz;
+        int phase = 0, it = 0, stop = 0;
+        EvalOut cur = {0.0, 0.0, 0.0, 0.0};
+        BinAcc<M> a;
+        acc_clear<M>(a);
+        int cprev[M], cs[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) cprev[k] = cs[k] = 0;
+        bool use_shell = false;
+        for (;;) {
+            BoxSet bs = {kFull, px, py, pz, 0, 0, 0, s};
+            if (phase == 1) {
+                const int64_t nq = cube_count(v, qx, qy, qz, s);
+                const BoxSet mv = {kMove, wx, wy, wz, qx, qy, qz, s};
+                const int64_t nd = boxes_volume(v, mv);
+#pragma unroll
+                for (int k = 0; k < M; ++k) cprev[k] = a.c[k];
+                if (100 * nd < (int64_t)tune.incr_pct * nq) {
+                    const int dx = qx - wx, dy = qy - wy, dz = qz - wz;
+#pragma unroll
+                    for (int k = 0; k < M; ++k) {
+                        a.f1[k] -= a.c[k] * dx;
+                        a.f2[k] -= a.c[k] * dy;
+                        a.f3[k] -= a.c[k] * dz;
+                    }
+                    bs = mv;
+                    lc.swept += (unsigned long long)nd;
+                } else {
+                    acc_clear<M>(a);
+                    bs = BoxSet{kFull, qx, qy, qz, 0, 0, 0, s};
+                    lc.swept += (unsigned long long)nq;
+                }
+                wx = qx; wy = qy; wz = qz;
+            } else if (phase == 2) {
+                const bool here = wx == px && wy == py && wz == pz;
+#pragma unroll
+                for (int k = 0; k < M; ++k) cs[k] = here ? a.c[k] : cprev[k];
+                const int64_t Ns = cube_count(v, px, py, pz, s), Np = cube_count(v, px, py, pz, s - 1);
+                use_shell = Ns - Np < Np;
+                acc_clear<M>(a);
+                bs = BoxSet{use_shell ? kShell : kInner, px, py, pz, 0, 0, 0, s};
+                lc.swept += (unsigned long long)(use_shell ? Ns - Np : Np);
+            } else {
+                lc.swept += (unsigned long long)cube_count(v, px, py, pz, s);
+            }
+            ms_sweep<M>(v, bs, rl, trash_base, hist, lane, a);
+            if (phase == 2) break;
+            // an evaluation at W (= P0 in phase 0, Q in phase 1)
+            const EvalOut e = ms_moments<M>(v, tb, wx, wy, wz, s, a);
+            lc.evals += 1;
+            lc.window_evals += 1;
+            lc.voxel_visits += cube_count(v, wx, wy, wz, s);
+            if (phase == 1) {
+                if (!uniform(e.obj > cur.obj ? 1 : 0)) {
+                    stop = 3;
+                    phase = 2;
+                    continue;
+                }
+                px = qx; py = qy; pz = qz;
+                it += 1;
+            }
+            cur = e;
+            // the next move from P: stop on max_iter, a zero move or a clamped one
+            phase = 2;
+            if (it == v.max_iter) { stop = 0; continue; }
+            const int mx = uniform((int)round(cur.dx));
+            const int my = uniform((int)round(cur.dy));
+            const int mz = uniform((int)round(cur.dz));
+            if (mx == 0 && my == 0 && mz == 0) { stop = 1; continue; }
+            qx = clampi(px + mx, 0, v.X - 1);
+            qy = clampi(py + my, 0, v.Y - 1);
+            qz = clampi(pz + mz, 0, v.Z - 1);
+            if (qx == px && qy == py && qz == pz) { stop = 2; continue; }
+            phase = 1;
+        }
+        int cin[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) cin[k] = use_shell ? cs[k] - a.c[k] : a.c[k];
+        const Saliency sal = ms_saliency<M>(v, tb, px, py, pz, s, cs, cin);
+        lc.final_visits += cube_count(v, px, py, pz, s);
         lc.window_evals += 2;
         if (lane == 0) {
+            TrajOut o;
+            o.p[0] = px; o.p[1] = py; o.p[2] = pz;
+            o.iters = it; o.stop = stop; o.obj = cur.obj;
             const long long local = seed * v.S + (s - v.s_min);
             write_rec(out + v.traj_base + local, p0, o, sal, (int32_t)local);
         }
@@ -593,6 +914,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         atomicAdd(&cnt->window_evals, lc.window_evals);
         atomicAdd(&cnt->voxel_visits, lc.voxel_visits);
         atomicAdd(&cnt->final_visits, lc.final_visits);
+        atomicAdd(&cnt->swept, lc.swept);
     }
 }
 
@@ -605,7 +927,8 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
 template <int NT>
 __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx, int cy,
                                int cz, int base, int trash_row, int rq, uint32_t region, uint32_t* hist, int tid) {
-    const Sweep w = make_sweep<NT>(v, xa, xb, ya, yb, za, zb, tid);
+    const Layout L = layout_x(v);
+    const Sweep w = make_sweep<NT>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, tid);
     const uint32_t rowbytes = (uint32_t)row_stride(v.B) << (rq + 2);
     const uint32_t rep4 = ((uint32_t)(tid & ((1 << rq) - 1)) << 2) + region;
     const uint32_t bshift = (uint32_t)rq + 2;
@@ -618,8 +941,9 @@ __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb,
         rx[k] = (uint32_t)r * rowbytes + rep4;
     }
     const int dy0 = ya + w.oy - cy, dz0 = za + w.oz - cz;
+    int used = 0;
     run_sweep(
-        v, w, INT_MAX,
+        L, w, used, INT_MAX,
         [&](uint32_t word, int iy0, int iz0) {
             const int rr = max(max(abs(dy0 + iy0), abs(dz0 + iz0)) - base, 0);
             const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
@@ -646,7 +970,8 @@ __device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr,
     const int xa = max(px - Rr, 0), xb = min(px + Rr, v.X - 1);
     const int ya = max(py - Rr, 0), yb = min(py + Rr, v.Y - 1);
     const int za = max(pz - Rr, 0), zb = min(pz + Rr, v.Z - 1);
-    const Sweep w = make_sweep<NT>(v, xa, xb, ya, yb, za, zb, tid);
+    const Layout L = layout_x(v);
+    const Sweep w = make_sweep<NT>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, tid);
     const uint32_t rowbytes = (uint32_t)row_stride(v.B) << (rq + 2);
     const uint32_t rep4 = (uint32_t)(tid & ((1 << rq) - 1)) << 2;
     const uint32_t bshift = (uint32_t)rq + 2;
@@ -668,8 +993,9 @@ __device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr,
     const int dy0 = ya + w.oy - py, dz0 = za + w.oz - pz;
     const uint32_t ry2 = 2u * region_bytes, rz4 = 4u * region_bytes;
     char* hb = reinterpret_cast<char*>(hist);
+    int used = 0;
     run_sweep(
-        v, w, INT_MAX,
+        L, w, used, INT_MAX,
         [&](uint32_t word, int iy0, int iz0) {
             const int dy = dy0 + iy0, dz = dz0 + iz0;
             const uint32_t RR = __umul24((uint32_t)max(max(abs(dy), abs(dz)) - base, 0), rowbytes) + rep4;
@@ -954,7 +1280,7 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* __restrict__
     }
     const QuadLds L = quad_lds(smem, lay);
     __syncthreads();
-    LocalCounts lc = {0, 0, 0, 0};
+    LocalCounts lc = {0, 0, 0, 0, 0};
     for (;;) {
         if (tid == 0) s_task = (long long)atomicAdd(&cnt->queue_head[0], 1ull);
         __syncthreads();
@@ -973,6 +1299,7 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* __restrict__
         const Saliency sal = quad_saliency<256, M>(v, tb, o.p[0], o.p[1], o.p[2], rq, L, tid);
         lc.final_visits += cube_count(v, o.p[0], o.p[1], o.p[2], v.s_max + 1);
         lc.window_evals += (unsigned long long)v.S + 2ull;
+        lc.swept = lc.voxel_visits + lc.final_visits;
         if (tid == 0) write_rec(out + v.traj_base + seed, p0, o, sal, (int32_t)seed);
     }
     if (tid == 0) {
@@ -980,11 +1307,16 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* __restrict__
         atomicAdd(&cnt->window_evals, lc.window_evals);
         atomicAdd(&cnt->voxel_visits, lc.voxel_visits);
         atomicAdd(&cnt->final_visits, lc.final_visits);
+        atomicAdd(&cnt->swept, lc.swept);
     }
 }
 
 // ------------------------------------------------------------ test hooks
 
+// kind 0: counts of the cube; 1: counts and offset sums of the cube at P; 2: the
+// same at Q, reached by the running-window update from P (xyz holds P then Q);
+// 3: counts of the cube, of its inner cube through the shell, and of the inner
+// cube swept directly.
 template <int M>
 __global__ __launch_bounds__(64) void k_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc,
                                                 int rl, int hist_words, void* outp) {
@@ -992,19 +1324,46 @@ __global__ __launch_bounds__(64) void k_hook_ms(const VolDesc* vols, int kind, i
     const int lane = threadIdx.x;
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
     __syncthreads();
-    const VolDesc v = vols[0];
+    const VolDesc& v = vols[0];
     const int B = v.B;
+    const int trash_base = hist_words - 64;
+    const int stride = kind == 2 ? 6 : 3;
     for (int w = blockIdx.x; w < n; w += gridDim.x) {
-        const int px = xyz[3 * w], py = xyz[3 * w + 1], pz = xyz[3 * w + 2], s = sc[w];
-        BinAcc<M> a;
-        if (kind == 0) ms_window<true, M>(v, px, py, pz, s, rl, hist_words - 64, hist, lane, a);
-        else ms_window<false, M>(v, px, py, pz, s, rl, hist_words - 64, hist, lane, a);
+        const int px = xyz[stride * w], py = xyz[stride * w + 1], pz = xyz[stride * w + 2], s = sc[w];
+        BinAcc<M> a, e;
+        acc_clear<M>(a);
+        acc_clear<M>(e);
+        ms_sweep<M>(v, BoxSet{kFull, px, py, pz, 0, 0, 0, s}, rl, trash_base, hist, lane, a);
+        int sh[M], bx[M];
+        if (kind == 2) {
+            const int qx = xyz[6 * w + 3], qy = xyz[6 * w + 4], qz = xyz[6 * w + 5];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                a.f1[k] -= a.c[k] * (qx - px);
+                a.f2[k] -= a.c[k] * (qy - py);
+                a.f3[k] -= a.c[k] * (qz - pz);
+            }
+            ms_sweep<M>(v, BoxSet{kMove, px, py, pz, qx, qy, qz, s}, rl, trash_base, hist, lane, a);
+        } else if (kind == 3) {
+            ms_sweep<M>(v, BoxSet{kShell, px, py, pz, 0, 0, 0, s}, rl, trash_base, hist, lane, e);
+#pragma unroll
+            for (int k = 0; k < M; ++k) sh[k] = a.c[k] - e.c[k];
+            acc_clear<M>(e);
+            ms_sweep<M>(v, BoxSet{kInner, px, py, pz, 0, 0, 0, s}, rl, trash_base, hist, lane, e);
+#pragma unroll
+            for (int k = 0; k < M; ++k) bx[k] = e.c[k];
+        }
 #pragma unroll
         for (int t = 0; t < M; ++t) {
             const int b = lane * M + t;
             if (b >= B) continue;
             if (kind == 0) {
                 static_cast<uint32_t*>(outp)[(size_t)w * B + b] = (uint32_t)a.c[t];
+            } else if (kind == 3) {
+                uint32_t* o = static_cast<uint32_t*>(outp) + (size_t)w * 3 * B;
+                o[b] = (uint32_t)a.c[t];
+                o[B + b] = (uint32_t)sh[t];
+                o[2 * B + b] = (uint32_t)bx[t];
             } else {
                 int* o = static_cast<int*>(outp) + (size_t)w * 4 * B;
                 o[b] = a.c[t];
@@ -1273,6 +1632,9 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_minmax, dim3(gx, a.nvol), dim3(256), 0, st, a.vols);
     const int gq = grid_for(a.max_words, 256, 4096);
     hipLaunchKernelGGL(k_quantize, dim3(gq, a.nvol), dim3(256), 0, st, a.vols);
+    if (a.max_z > 0)
+        hipLaunchKernelGGL(k_transpose, dim3(a.max_tx * a.max_ty, a.max_z, a.nvol), dim3(256), 0, st, a.vols,
+                           a.max_tx);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ struct PrepArgs {
     int* vol_base;
     long long max_voxels;   // largest X*Y*Z of the volumes
     long long max_words;    // largest (xp/4)*Y*Z
+    int max_tx, max_ty;     // largest 64-voxel tile counts in x and y of a mean-shift volume
+    int max_z;              // largest Z of a mean-shift volume (0: none)
 };
 
 struct SearchArgs {

@@ -53,9 +53,15 @@ int64_t num_trajectories(const int32_t* dims, int32_t spacing, const int32_t* sc
     return method == KS_MEANSHIFT ? n * (scales[1] - scales[0] + 1) : n;
 }
 
-size_t bins_bytes(const int32_t* dims) {
+// Bin volume x fastest (rows padded to 16 bytes), then the y-fastest copy.
+static size_t bins_x_bytes(const int32_t* dims) {
     const size_t xp = ((size_t)dims[0] + 15) & ~(size_t)15;
     return (xp * dims[1] * dims[2] + 255) & ~(size_t)255;
+}
+
+size_t bins_bytes(const int32_t* dims) {
+    const size_t yp = ((size_t)dims[1] + 15) & ~(size_t)15;
+    return bins_x_bytes(dims) + ((yp * dims[2] * dims[0] + 255) & ~(size_t)255);
 }
 
 // ------------------------------------------------------------ context
@@ -174,7 +180,7 @@ static unsigned long long next_pow2(unsigned long long n) {
 // same-address LDS atomics; fewer, cheaper merges).
 int pick_ms_rl(int maxB, int pref) {
     int rl = pref;
-    while (rl > 1 && ((size_t)maxB * ((size_t)1 << rl) + 64) * 8 > 36 * 1024) --rl;
+    while (rl > 2 && ((size_t)maxB * ((size_t)1 << rl) + 64) * 8 > 36 * 1024) --rl;
     return rl;
 }
 
@@ -225,6 +231,8 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         v.X = r.dims[0]; v.Y = r.dims[1]; v.Z = r.dims[2];
         v.xp = (v.X + 15) & ~15;
         v.slice = (int64_t)v.xp * v.Y;
+        v.yp = (v.Y + 15) & ~15;
+        v.slice_t = (int64_t)v.yp * v.Z;
         v.dtype = r.dtype; v.B = r.bins; v.sp = r.spacing;
         v.s_min = r.scales[0]; v.s_max = r.scales[1]; v.S = v.s_max - v.s_min + 1;
         v.method = r.method; v.max_iter = r.max_iter;
@@ -243,6 +251,11 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         p.max_traj = std::max<long long>(p.max_traj, v.n_traj);
         p.max_voxels = std::max<long long>(p.max_voxels, (long long)v.X * v.Y * v.Z);
         p.max_words = std::max<long long>(p.max_words, (long long)(v.xp / 4) * v.Y * v.Z);
+        if (v.method == KS_MEANSHIFT) {
+            p.max_tx = std::max(p.max_tx, (v.X + 63) / 64);
+            p.max_ty = std::max(p.max_ty, (v.yp + 63) / 64);
+            p.max_z = std::max(p.max_z, v.Z);
+        }
         if (v.method == KS_QUADRANT) {
             p.maxS_quad = std::max(p.maxS_quad, v.S);
             p.maxB_quad = std::max(p.maxB_quad, v.B);
@@ -304,6 +317,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     int* volint = static_cast<int*>(d_volint.ptr);
     for (int i = 0; i < nvol; ++i) {
         p.vols[i].bins = static_cast<uint8_t*>(d_bins.ptr) + bins_off[i];
+        p.vols[i].bins_t = p.vols[i].bins + bins_x_bytes(in[i].dims);
         p.vols[i].minmax = volint + 2 * i;
     }
     p.vol_nfound = volint + 2 * nvol;
@@ -346,6 +360,7 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
     PrepArgs pa;
     pa.vols = dv; pa.nvol = p.nvol; pa.cnt = dc; pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base;
     pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     KS_HIP(launch_prep(pa, st));
     if (timed) KS_HIP(hipEventRecord(ev[1], st));
     SearchArgs sq;
@@ -365,7 +380,7 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         tune.rl = p.rl;
         tune.rl_small = p.rl_small;
         tune.s_small = ms_s_small;
-        tune.pad = 0;
+        tune.incr_pct = ms_incr_pct;
         KS_HIP(launch_search_ms(sm, (int)g, tune, p.ms_hist_words, p.maxB_ms, st));
     }
     if (timed) KS_HIP(hipEventRecord(ev[2], st));
@@ -402,6 +417,7 @@ void Context::collect_stats(const Plan& p, bool timed) {
     last.window_evals = (int64_t)c.window_evals;
     last.voxel_visits = (int64_t)c.voxel_visits;
     last.final_visits = (int64_t)c.final_visits;
+    last.swept_voxels = (int64_t)c.swept;
     for (int i = 0; i < p.nvol; ++i) last.regions += nf[i];
     if (timed) {
         float a = 0, b = 0, d = 0;
@@ -575,7 +591,7 @@ ks_status ks_context_set_profiling(ks_context* ctx, int32_t on) {
 }
 
 ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32_t quad_replicas_log2) {
-    if (!ctx || ms_replicas_log2 < 1 || ms_replicas_log2 > 6 || quad_replicas_log2 < 0 || quad_replicas_log2 > 3)
+    if (!ctx || ms_replicas_log2 < 2 || ms_replicas_log2 > 6 || quad_replicas_log2 < 0 || quad_replicas_log2 > 3)
         return KS_E_INVALID;
     ctx->ms_rl_pref = ms_replicas_log2;
     ctx->ms_rl_small_pref = ms_replicas_log2;
@@ -584,9 +600,15 @@ ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32
 }
 
 ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas_log2, int32_t s_small) {
-    if (!ctx || ms_small_replicas_log2 < 1 || ms_small_replicas_log2 > 6 || s_small < 0) return KS_E_INVALID;
+    if (!ctx || ms_small_replicas_log2 < 2 || ms_small_replicas_log2 > 6 || s_small < 0) return KS_E_INVALID;
     ctx->ms_rl_small_pref = ms_small_replicas_log2;
     ctx->ms_s_small = s_small;
+    return KS_OK;
+}
+
+ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct) {
+    if (!ctx || incremental_pct < 0 || incremental_pct > 200) return KS_E_INVALID;
+    ctx->ms_incr_pct = incremental_pct;
     return KS_OK;
 }
 
@@ -700,6 +722,7 @@ ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     PrepArgs pa;
     pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
     const VolDesc& d = p.vols[0];
     if (hipMemcpy2DAsync(out, (size_t)d.X, d.bins, (size_t)d.xp, (size_t)d.X, (size_t)d.Y * d.Z,
@@ -713,17 +736,18 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
                         int32_t kind, const int32_t range[2], int32_t n, const int32_t* xyz, const int32_t* scale,
                         void* out, void* stream) {
     if (!ctx || !out || n < 0 || (n > 0 && !xyz)) return KS_E_INVALID;
-    if (kind < KS_HIST_CUBE || kind > KS_HIST_SHELLS) return KS_E_INVALID;
+    if (kind < KS_HIST_CUBE || kind > KS_HIST_MS_INNER) return KS_E_INVALID;
     const int32_t sc[2] = {1, 1};
     ks_status s = check_request(d_volume, dtype, dims, bins, 1, sc, KS_QUADRANT, 0);
     if (s != KS_OK) return s;
-    const bool per_window = kind == KS_HIST_CUBE || kind == KS_HIST_MEANSHIFT;
+    const bool per_window = kind != KS_HIST_OCTANTS && kind != KS_HIST_SHELLS;
+    const int stride = kind == KS_HIST_MS_MOVE ? 6 : 3;
     if (per_window && n > 0 && !scale) return KS_E_INVALID;
     if (!per_window && (!range || range[0] < 0 || range[0] > range[1] || range[1] > kSmaxLimit + 1))
         return KS_E_INVALID;
     for (int i = 0; i < n; ++i) {
-        for (int a = 0; a < 3; ++a)
-            if (xyz[3 * i + a] < 0 || xyz[3 * i + a] >= dims[a]) return KS_E_INVALID;
+        for (int a = 0; a < stride; ++a)
+            if (xyz[stride * i + a] < 0 || xyz[stride * i + a] >= dims[a % 3]) return KS_E_INVALID;
         if (per_window && (scale[i] < 1 || scale[i] > kSmaxLimit)) return KS_E_INVALID;
     }
     if (n == 0) return KS_OK;
@@ -739,28 +763,31 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     PrepArgs pa;
     pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
-    const size_t in_bytes = sizeof(int32_t) * 4 * (size_t)n;
+    const size_t in_bytes = sizeof(int32_t) * (size_t)(stride + 1) * (size_t)n;
     if ((s = ctx->d_hook.ensure(in_bytes, &ctx->generation)) != KS_OK) return s;
-    std::vector<int32_t> hin((size_t)4 * n);
-    std::memcpy(hin.data(), xyz, sizeof(int32_t) * 3 * (size_t)n);
-    if (per_window) std::memcpy(hin.data() + 3 * (size_t)n, scale, sizeof(int32_t) * (size_t)n);
+    std::vector<int32_t> hin((size_t)(stride + 1) * n);
+    std::memcpy(hin.data(), xyz, sizeof(int32_t) * (size_t)stride * (size_t)n);
+    if (per_window) std::memcpy(hin.data() + (size_t)stride * n, scale, sizeof(int32_t) * (size_t)n);
     if (hipMemcpyAsync(ctx->d_hook.ptr, hin.data(), in_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
         return KS_E_DEVICE;
     const int32_t* dxyz = static_cast<const int32_t*>(ctx->d_hook.ptr);
-    const int32_t* dsc = dxyz + 3 * (size_t)n;
+    const int32_t* dsc = dxyz + (size_t)stride * n;
     const int K = per_window ? 1 : range[1] - range[0] + 1;
     size_t out_bytes;
     if (kind == KS_HIST_CUBE) out_bytes = sizeof(uint32_t) * (size_t)n * bins;
-    else if (kind == KS_HIST_MEANSHIFT) out_bytes = sizeof(int32_t) * (size_t)n * 4 * bins;
+    else if (kind == KS_HIST_MEANSHIFT || kind == KS_HIST_MS_MOVE) out_bytes = sizeof(int32_t) * (size_t)n * 4 * bins;
+    else if (kind == KS_HIST_MS_INNER) out_bytes = sizeof(uint32_t) * (size_t)n * 3 * bins;
     else if (kind == KS_HIST_OCTANTS) out_bytes = sizeof(uint32_t) * (size_t)n * 8 * K * bins;
     else out_bytes = sizeof(uint32_t) * (size_t)n * K * bins;
     if ((s = ctx->d_hook_out.ensure(out_bytes, &ctx->generation)) != KS_OK) return s;
     hipError_t e;
     if (per_window) {
         const int rl = pick_ms_rl(bins, ctx->ms_rl_pref);
-        e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), kind == KS_HIST_CUBE ? 0 : 1, n, dxyz, dsc, rl,
-                           (bins << rl) + 64, bins, ctx->d_hook_out.ptr, st);
+        const int hook_kind = kind == KS_HIST_CUBE ? 0 : kind == KS_HIST_MEANSHIFT ? 1 : kind == KS_HIST_MS_MOVE ? 2 : 3;
+        e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), hook_kind, n, dxyz, dsc, rl, (bins << rl) + 64,
+                           bins, ctx->d_hook_out.ptr, st);
     } else {
         const int rq = pick_quad_rq(K, bins, ctx->quad_rq_pref);
         const LdsQuad lay = quad_layout(K, bins, rq);

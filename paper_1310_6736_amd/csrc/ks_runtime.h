@@ -43,6 +43,7 @@ struct Plan {
     std::vector<TaskSeg> segs_q, segs_m;
     long long ntask_q = 0, ntask_m = 0;
     long long total_traj = 0, total_regions = 0, max_traj = 0, max_voxels = 0, max_words = 0;
+    int max_tx = 0, max_ty = 0, max_z = 0;  // mean-shift volumes: 64-voxel x, y tiles and Z
     unsigned long long n_pad = 2;
     int maxS_quad = 0, maxB_quad = 0, maxB_ms = 0;
     int rl = 4, rl_small = 3, rq = 0, ms_hist_words = 0;
@@ -64,6 +65,7 @@ struct Context {
     int ms_rl_pref = 4;
     int ms_rl_small_pref = 2;
     int ms_s_small = 6;
+    int ms_incr_pct = 100;  // running-window updates while cheaper than a fresh window
     int quad_rq_pref = 0;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;

@@ -18,13 +18,14 @@ LIB_PATH = os.path.join(HERE, "libks.so")
 KS_OK, KS_E_INVALID, KS_E_NOMEM, KS_E_DEVICE, KS_E_TOO_LARGE, KS_E_NOT_READY, KS_E_SHUTDOWN = 0, -1, -2, -3, -4, -5, -6
 KS_U8, KS_U16, KS_I16 = 0, 1, 2
 KS_QUADRANT, KS_MEANSHIFT = 0, 1
-KS_HIST_CUBE, KS_HIST_OCTANTS, KS_HIST_MEANSHIFT, KS_HIST_SHELLS = 0, 1, 2, 3
+KS_HIST_CUBE, KS_HIST_OCTANTS, KS_HIST_MEANSHIFT, KS_HIST_SHELLS, KS_HIST_MS_MOVE, KS_HIST_MS_INNER = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
     "ks_status_str", "ks_context_create", "ks_context_destroy", "ks_context_set_profiling", "ks_context_set_tuning",
     "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
+    "ks_context_set_ms_update",
 ]
 
 
@@ -50,7 +51,7 @@ class RunStats(C.Structure):
     _fields_ = [("trajectories", C.c_int64), ("evals", C.c_int64), ("window_evals", C.c_int64),
                 ("voxel_visits", C.c_int64), ("final_visits", C.c_int64), ("regions", C.c_int64),
                 ("ms_prep", C.c_double), ("ms_search", C.c_double), ("ms_rank", C.c_double),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("swept_voxels", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -90,6 +91,7 @@ def lib():
     L.ks_context_set_profiling.argtypes = [vp, i32]
     L.ks_context_set_tuning.argtypes = [vp, i32, i32]
     L.ks_context_set_tuning_small.argtypes = [vp, i32, i32]
+    L.ks_context_set_ms_update.argtypes = [vp, i32]
     L.ks_last_stats.argtypes = [vp, C.POINTER(RunStats)]
     L.ks_detect.argtypes = [vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p]
     L.ks_detect_device.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p, vp]
@@ -204,6 +206,10 @@ def ks_context_set_tuning(ctx: Context, ms_replicas_log2: int, quad_replicas_log
     _check(lib().ks_context_set_tuning(ctx.handle, ms_replicas_log2, quad_replicas_log2), "ks_context_set_tuning")
 
 
+def ks_context_set_ms_update(ctx: Context, incremental_pct: int = 100):
+    _check(lib().ks_context_set_ms_update(ctx.handle, incremental_pct), "ks_context_set_ms_update")
+
+
 def ks_context_set_tuning_small(ctx: Context, ms_small_replicas_log2: int, s_small: int):
     _check(lib().ks_context_set_tuning_small(ctx.handle, ms_small_replicas_log2, s_small),
            "ks_context_set_tuning_small")
@@ -258,14 +264,18 @@ def ks_bin_volume(ctx: Context, volume, bins, stream=None) -> np.ndarray:
 
 
 def ks_histograms(ctx: Context, volume, bins, kind, xyz, scale=None, scale_range=(1, 1), stream=None) -> np.ndarray:
+    """Window histograms through the search's device code.  KS_HIST_MS_MOVE takes
+    xyz as (n, 6): P then Q per window."""
     ptr, dt, dims = _volume_args(volume)
-    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 6 if kind == KS_HIST_MS_MOVE else 3)
     n = xyz.shape[0]
     K = scale_range[1] - scale_range[0] + 1
     if kind == KS_HIST_CUBE:
         out = np.zeros((n, bins), np.uint32)
-    elif kind == KS_HIST_MEANSHIFT:
+    elif kind in (KS_HIST_MEANSHIFT, KS_HIST_MS_MOVE):
         out = np.zeros((n, 4, bins), np.int32)
+    elif kind == KS_HIST_MS_INNER:
+        out = np.zeros((n, 3, bins), np.uint32)
     elif kind == KS_HIST_OCTANTS:
         out = np.zeros((n, 8, K, bins), np.uint32)
     else:

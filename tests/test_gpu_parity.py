@@ -35,6 +35,12 @@ def ctx(torch_dev):
     c.close()
 
 
+def restore_tuning(ctx):
+    """The context's default tuning (4 / 1 replicas, 4 replicas up to s = 6)."""
+    ks.ks_context_set_tuning(ctx, 4, 0)
+    ks.ks_context_set_tuning_small(ctx, 2, 6)
+
+
 def note(msg):
     print(f"[gpu-case] {msg}", flush=True)
     sys.stdout.flush()
@@ -113,12 +119,74 @@ def test_meanshift_window_stats_bit_exact(torch_dev, ctx, bins, rl):
         got = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_MEANSHIFT, pts, sc)
         cube = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_CUBE, pts, sc)
     finally:
-        ks.ks_context_set_tuning(ctx, 6, 3)
+        restore_tuning(ctx)
     for i, p in enumerate(pts):
         counts, msum, _, _ = oracle.eval_meanshift(bv, bins, p, int(sc[i]))
         assert np.array_equal(got[i, 0], counts.astype(np.int32)), (i, p, sc[i])
         assert np.array_equal(got[i, 1:].T, msum.astype(np.int32)), (i, p, sc[i])
         assert np.array_equal(cube[i], counts), (i, p, sc[i])
+
+
+def move_pairs(shape, seed):
+    """(P, Q, s) triples for the running-window update: small moves in every
+    direction, zero moves, moves across the volume border, moves longer than the
+    window, both corners, and the largest scale."""
+    z, y, x = shape
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(40):
+        s = int(rng.integers(1, 33))
+        p = [int(a) for a in rng.integers(0, (x, y, z))]
+        d = [int(a) for a in rng.integers(-s, s + 1, 3)]
+        q = [min(max(p[a] + d[a], 0), (x, y, z)[a] - 1) for a in range(3)]
+        out.append((p, q, s))
+    out += [([0, 0, 0], [1, 1, 1], 3), ([x - 1, y - 1, z - 1], [x - 2, y - 1, z - 3], 5),
+            ([5, 6, 7], [5, 6, 7], 4), ([0, y // 2, z // 2], [x - 1, y // 2, z // 2], 2),
+            ([x // 2, y // 2, z // 2], [x // 2 + 1, y // 2 - 2, z // 2], 32), ([3, 3, 3], [3, 3, 4], 1),
+            ([x // 2, 2, z - 2], [x // 2 - 9, 0, z - 1], 9)]
+    return out
+
+
+@pytest.mark.parametrize("bins", [2, 64, 256])
+@pytest.mark.parametrize("rl", [2, 4, 6])
+def test_meanshift_running_window_update_bit_exact(torch_dev, ctx, bins, rl):
+    """A window updated from P to Q (voxels leaving taken out, offsets shifted,
+    voxels entering added) equals the oracle's fresh window at Q."""
+    note(f"hist ms move B={bins} rl={rl}")
+    v = random_volume(bins * 3 + rl, (37, 41, 45), np.uint16, 0, 4095)
+    bv = oracle.bin_volume(v, bins)
+    trip = move_pairs(v.shape, bins + rl)
+    pq = np.array([p + q for p, q, _ in trip], np.int32)
+    sc = np.array([s for _, _, s in trip], np.int32)
+    ks.ks_context_set_tuning(ctx, rl, 0)
+    try:
+        got = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_MS_MOVE, pq, sc)
+    finally:
+        restore_tuning(ctx)
+    for i, (p, q, s) in enumerate(trip):
+        counts, msum, _, _ = oracle.eval_meanshift(bv, bins, q, s)
+        assert np.array_equal(got[i, 0], counts.astype(np.int32)), (i, p, q, s)
+        assert np.array_equal(got[i, 1:].T, msum.astype(np.int32)), (i, p, q, s)
+
+
+@pytest.mark.parametrize("bins", [2, 64, 256])
+def test_meanshift_inner_cube_counts_bit_exact(torch_dev, ctx, bins):
+    """The final pass's inner-cube counts, through the shell subtraction and swept
+    directly, equal the oracle's cube of half-width s-1 (s = 1: one voxel)."""
+    note(f"hist ms inner B={bins}")
+    v = random_volume(bins + 11, (29, 33, 47), np.uint8, 0, 255)
+    bv = oracle.bin_volume(v, bins)
+    pts = positions(v.shape, 20, 9)
+    rng = np.random.default_rng(bins)
+    sc = rng.integers(1, 33, len(pts)).astype(np.int32)
+    sc[:4] = [1, 32, 2, 1]
+    got = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_MS_INNER, pts, sc)
+    for i, p in enumerate(pts):
+        s = int(sc[i])
+        assert np.array_equal(got[i, 0], oracle.hist_cube(bv, bins, p, s)), (i, p, s)
+        inner = oracle.hist_cube(bv, bins, p, s - 1)
+        assert np.array_equal(got[i, 1], inner), (i, p, s, "shell")
+        assert np.array_equal(got[i, 2], inner), (i, p, s, "inner")
 
 
 @pytest.mark.parametrize("bins,rng_", [(32, (3, 8)), (64, (4, 16)), (256, (1, 5)), (13, (2, 2)), (64, (1, 32))])
@@ -132,7 +200,7 @@ def test_octant_histograms_bit_exact(torch_dev, ctx, bins, rng_, rq):
     try:
         got = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_OCTANTS, pts, scale_range=rng_)
     finally:
-        ks.ks_context_set_tuning(ctx, 6, 3)
+        restore_tuning(ctx)
     for i, p in enumerate(pts):
         for j in range(8):
             for kk, k in enumerate(range(rng_[0], rng_[1] + 1)):
@@ -181,6 +249,23 @@ def test_traces_pet_shell_full(torch_dev, ctx, method):
     got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
     want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
     compare_traces(got, want, w.name)
+
+
+@pytest.mark.parametrize("update", [0, 200], ids=["fresh", "always"])
+def test_traces_meanshift_update_settings(torch_dev, ctx, update):
+    """Mean-shift traces are the same with running-window updates off (every
+    evaluation sweeps its whole window) and with updates taken wherever the two
+    difference regions are smaller than twice the window."""
+    w = synth.pet_shell(ks.KS_MEANSHIFT)
+    note(f"traces {w.name} update={update}")
+    ks.ks_context_set_ms_update(ctx, update)
+    try:
+        got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    finally:
+        ks.ks_context_set_ms_update(ctx, 100)
+    ids = np.arange(0, len(got), 5)
+    want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, ids=ids)
+    compare_traces(got[ids], want, f"{w.name} update={update}")
 
 
 def test_traces_mr_blobs_sampled(torch_dev, ctx):
@@ -287,3 +372,25 @@ def test_stats_count_the_work(torch_dev, ctx):
     assert st["evals"] == ost["evals"]
     assert st["window_evals"] == ost["window_evals"]
     assert st["voxel_visits"] + st["final_visits"] == ost["voxel_visits"]
+    assert st["swept_voxels"] == st["voxel_visits"] + st["final_visits"]
+
+
+def test_stats_meanshift_swept_voxels(torch_dev, ctx):
+    """Window evaluations and visits count the method's work (as the oracle does);
+    the voxels swept with running-window updates are fewer, and with updates off
+    they are the visits less the final pass's saving."""
+    w = synth.pet_shell(ks.KS_MEANSHIFT)
+    note("stats meanshift")
+    t = dev(torch_dev, w.volume)
+    ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    st = ks.ks_last_stats(ctx)
+    ks.ks_context_set_ms_update(ctx, 0)
+    try:
+        ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+        fresh = ks.ks_last_stats(ctx)
+    finally:
+        ks.ks_context_set_ms_update(ctx, 100)
+    for f in ("evals", "window_evals", "voxel_visits", "final_visits", "regions"):
+        assert st[f] == fresh[f], f
+    assert fresh["voxel_visits"] < fresh["swept_voxels"] < fresh["voxel_visits"] + fresh["final_visits"]
+    assert st["swept_voxels"] < 0.7 * fresh["swept_voxels"]
