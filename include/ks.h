@@ -101,6 +101,20 @@ typedef struct {
                               of the mean-shift search, fewer than voxel_visits + final_visits */
 } ks_run_stats;
 
+/* Selection and order of the output regions.  A trajectory yields a region when
+ * its decision-precision entropy H > h_min and saliency Y > y_min (the entropy
+ * and saliency thresholds of Sec. 1 and Sec. 2.3, given no values there; default
+ * 0 with strict >).  Regions are ranked by rank_by descending: KS_RANK_SALIENCY
+ * (Y = H * W, default) or KS_RANK_PDF_CHANGE (W, the ranking of the PET
+ * experiment, Sec. 3.1), ties by (scale, z, y, x) ascending.  All zero = the
+ * defaults. */
+enum { KS_RANK_SALIENCY = 0, KS_RANK_PDF_CHANGE = 1 };
+typedef struct {
+    double h_min, y_min;
+    int32_t rank_by;
+    int32_t reserved;      /* 0 */
+} ks_options;
+
 typedef struct ks_context ks_context;
 typedef struct ks_server ks_server;
 
@@ -127,6 +141,12 @@ ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32
 /* Mean-shift windows of half-width <= s_small use 2^ms_small_replicas_log2
  * replicas (ms_small_replicas_log2 in [2,6], s_small >= 0). */
 ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas_log2, int32_t s_small);
+
+/* Options for the context's later ks_detect_device and ks_seed_traces calls
+ * (ks_detect always uses the defaults; batch and server requests carry their
+ * own).  NULL restores the defaults.  KS_E_INVALID for an unknown rank_by, a
+ * non-zero reserved field or a NaN threshold. */
+ks_status ks_context_set_options(ks_context* ctx, const ks_options* options);
 
 /* Running-window updates of the mean-shift search (Sec. 2.3 evaluates Eq. 4-6 on
  * the window at every new position; consecutive windows of a trajectory
@@ -197,6 +217,7 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
                         int32_t kind, const int32_t range[2], int32_t n, const int32_t* xyz, const int32_t* scale,
                         void* out, void* stream);
 
+
 /* One request of a batch or of the server. */
 typedef struct {
     const void* volume;    /* device pointer (ks_detect_batch) or host pointer (ks_server_submit) */
@@ -207,6 +228,7 @@ typedef struct {
     int32_t scales[2];
     int32_t method;        /* ks_method */
     int32_t max_iter;
+    ks_options options;
 } ks_request;
 
 typedef struct {

@@ -72,7 +72,7 @@ def lib():
         L.kso_run.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32,
                               C.c_double, C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(Stats)]
         L.kso_detect.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32,
-                                 C.c_double, C.c_double, C.c_void_p, C.c_int32, i32p, C.POINTER(Stats)]
+                                 C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, i32p, C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -170,7 +170,11 @@ def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_mi
     return arr, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}
 
 
-def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=None, h_min=0.0, y_min=0.0):
+RANK_SALIENCY, RANK_PDF_CHANGE = 0, 1
+
+
+def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=None, h_min=0.0, y_min=0.0,
+           rank_by=RANK_SALIENCY):
     """Full detection; returns (structured array of regions, n_found, stats dict)."""
     vol = np.ascontiguousarray(vol)
     z, y, x = vol.shape
@@ -180,6 +184,6 @@ def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=No
     nf = C.c_int32()
     st = Stats()
     lib().kso_detect(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, spacing, (C.c_int32 * 2)(*scales), method,
-                     max_iter, h_min, y_min, out, capacity, C.byref(nf), C.byref(st))
+                     max_iter, h_min, y_min, rank_by, out, capacity, C.byref(nf), C.byref(st))
     arr = np.ctypeslib.as_array(out)[:min(capacity, nf.value)].copy()
     return arr, nf.value, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}

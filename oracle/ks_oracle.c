@@ -420,8 +420,8 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
 
 /* ------------------------------------------------------------- ranking */
 
-/* Order: saliency (decision precision) descending, then scale, z, y, x, seed
- * ascending.  Equal (x,y,z,scale) records carry equal saliency, so duplicates are
+/* Order: rank key (decision precision) descending, then scale, z, y, x, seed
+ * ascending.  Equal (x,y,z,scale) records carry equal keys, so duplicates are
  * adjacent and the first one holds the smallest seed. */
 static int region_cmp(const void* pa, const void* pb) {
     const kso_region* a = (const kso_region*)pa;
@@ -437,7 +437,7 @@ static int region_cmp(const void* pa, const void* pb) {
 
 int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
                const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
-               kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
+               int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
     int64_t n = kso_num_trajectories(dims, spacing, scales, method);
     kso_traj* t = (kso_traj*)malloc(sizeof(kso_traj) * (size_t)n);
     kso_run(vol, dtype, dims, bins, spacing, scales, method, max_iter, h_min, y_min, NULL, 0, t, stats);
@@ -448,7 +448,8 @@ int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bi
         kso_region* g = r + m++;
         g->x = t[i].x; g->y = t[i].y; g->z = t[i].z; g->scale = t[i].scale;
         g->saliency = t[i].y_ref; g->entropy = t[i].h_ref; g->pdf_change = t[i].w64;
-        g->key = t[i].y64; g->seed = t[i].traj;
+        g->key = rank_by == KSO_RANK_PDF_CHANGE ? t[i].w64 : t[i].y64;
+        g->seed = t[i].traj;
     }
     qsort(r, (size_t)m, sizeof(kso_region), region_cmp);
     int64_t u = 0;

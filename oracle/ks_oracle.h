@@ -21,6 +21,8 @@ extern "C" {
 enum { KSO_U8 = 0, KSO_U16 = 1, KSO_I16 = 2 };
 enum { KSO_QUADRANT = 0, KSO_MEANSHIFT = 1 };
 enum { KSO_STOP_MAX_ITER = 0, KSO_STOP_ZERO_MOVE = 1, KSO_STOP_CLAMPED = 2, KSO_STOP_REJECTED = 3 };
+/* Rank key of the output: saliency Y = H * W (default), or the pdf change W. */
+enum { KSO_RANK_SALIENCY = 0, KSO_RANK_PDF_CHANGE = 1 };
 
 /* Outcome of one trajectory (a grid seed for the quadrant method, a
  * (grid seed, scale) pair for mean-shift). */
@@ -78,11 +80,13 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
             const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
             const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats);
 
-/* Full detection: run every trajectory, dedup and rank.  Writes min(capacity, n)
- * regions; *n_found is the total. */
+/* Full detection: run every trajectory, keep those with H > h_min and Y > y_min,
+ * dedup on (x, y, z, scale) and rank by rank_by (KSO_RANK_*) descending, ties by
+ * scale, z, y, x ascending.  Writes min(capacity, n) regions; *n_found is the
+ * total. */
 int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
                const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
-               kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats);
+               int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats);
 
 #ifdef __cplusplus
 }

@@ -43,7 +43,7 @@ struct VolDesc {
     int32_t dtype, B, sp, s_min, s_max, method, max_iter;
     int32_t gx, gy, gz, ox, oy, oz;  // seed grid
     int32_t S;              // s_max - s_min + 1
-    int32_t pad0;
+    int32_t rank_by;        // output order: 0 saliency Y, 1 pdf change W
     int64_t traj_base;      // first slot of this volume in the trajectory records
     int64_t n_traj;
     double h_min, y_min;
@@ -64,18 +64,20 @@ struct TaskSeg {
     int64_t seed_begin;     // first seed id of the run
 };
 
-// Result of one trajectory (64 bytes).
+// Result of one trajectory (80 bytes).
 struct TrajRec {
     int32_t x0, y0, z0, x, y, z;
     int32_t scale, iters, stop, keep;
     double objective;
     double y64;
+    double key64;           // rank key: y64, or W at s* in decision precision
     float h32, w32, y32;
     int32_t seed;           // trajectory id within its volume
 };
 
-// Sort record of a kept trajectory: ordered by vol, ky (= ~bits(y64): saliency
-// descending), kpos (= s<<48 | z<<32 | y<<16 | x), then seed.
+// Sort record of a kept trajectory: ordered by vol, ky (= ~bits(key64): rank key
+// descending; keys are non-negative doubles), kpos (= s<<48 | z<<32 | y<<16 | x),
+// then seed.
 struct SortRec {
     uint64_t vol;
     uint64_t ky;

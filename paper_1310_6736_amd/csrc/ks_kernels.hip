@@ -656,7 +656,7 @@ __device__ EvalOut ms_moments(const VolDesc& v, const Tables& tb, int px, int py
 
 struct Saliency {
     int scale, keep;
-    double y64;
+    double y64, w64;
     float h32, w32, y32;
 };
 
@@ -692,6 +692,7 @@ __device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int 
     Saliency r;
     r.scale = s;
     r.y64 = H64 * W64;
+    r.w64 = W64;
     r.keep = (H64 > v.h_min && r.y64 > v.y_min) ? 1 : 0;
     r.h32 = H32;
     r.w32 = ((float)(s * s) / (float)(2 * s - 1)) * ((float)A / ((float)Ns * (float)Np));
@@ -774,12 +775,13 @@ __device__ __forceinline__ TrajOut run_trajectory(const VolDesc& v, const int* p
 }
 
 __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const TrajOut& o, const Saliency& sal,
-                                          int32_t id) {
+                                          int32_t id, int rank_by) {
     TrajRec r;
     r.x0 = p0[0]; r.y0 = p0[1]; r.z0 = p0[2];
     r.x = o.p[0]; r.y = o.p[1]; r.z = o.p[2];
     r.scale = sal.scale; r.iters = o.iters; r.stop = o.stop; r.keep = sal.keep;
     r.objective = o.obj; r.y64 = sal.y64;
+    r.key64 = rank_by == 1 ? sal.w64 : sal.y64;
     r.h32 = sal.h32; r.w32 = sal.w32; r.y32 = sal.y32;
     r.seed = id;
     *dst = r;
@@ -906,7 +908,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
             o.p[0] = px; o.p[1] = py; o.p[2] = pz;
             o.iters = it; o.stop = stop; o.obj = cur.obj;
             const long long local = seed * v.S + (s - v.s_min);
-            write_rec(out + v.traj_base + local, p0, o, sal, (int32_t)local);
+            write_rec(out + v.traj_base + local, p0, o, sal, (int32_t)local, v.rank_by);
         }
     }
     if (lane == 0) {
@@ -1249,6 +1251,7 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
     const int best = uniform((int)L.res[0]);
     out.scale = best < 0 ? 0 : best;
     out.y64 = best < 0 ? 0.0 : L.res[1];
+    out.w64 = 0.0;
     out.keep = 0;
     out.h32 = out.w32 = out.y32 = 0.0f;
     if (best >= 0) {
@@ -1256,6 +1259,7 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
         const int64_t N = cube_count(v, px, py, pz, best);
         const int64_t Np = cube_count(v, px, py, pz, best - 1);
         const long long A = L.arow[r];
+        out.w64 = ((double)(best * best) / (double)(2 * best - 1)) * ((double)A / ((double)N * (double)Np));
         out.h32 = L.h32row[r];
         out.w32 = ((float)(best * best) / (float)(2 * best - 1)) * ((float)A / ((float)N * (float)Np));
         out.y32 = out.h32 * out.w32;
@@ -1267,8 +1271,10 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
 
 // --------------------------------------------------------- quadrant kernel
 
+constexpr int kQuadThreads = 256;  // threads per trajectory (one workgroup)
+
 template <int M>
-__global__ __launch_bounds__(256) void k_search_quad(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg,
+__global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg,
                                                      long long ntask, Tables tb, TrajRec* out, Counters* cnt,
                                                      int rq, LdsQuad lay) {
     extern __shared__ __align__(16) char smem[];
@@ -1276,7 +1282,7 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* __restrict__
     const int tid = threadIdx.x;
     {
         uint32_t* h = reinterpret_cast<uint32_t*>(smem + lay.hist_off);
-        for (int i = tid; i < lay.hist_words; i += 256) h[i] = 0u;
+        for (int i = tid; i < lay.hist_words; i += kQuadThreads) h[i] = 0u;
     }
     const QuadLds L = quad_lds(smem, lay);
     __syncthreads();
@@ -1294,13 +1300,13 @@ __global__ __launch_bounds__(256) void k_search_quad(const VolDesc* __restrict__
         int p0[3];
         seed_pos(v, seed, p0);
         const TrajOut o = run_trajectory(
-            v, p0, [&](int x, int y, int z) { return quad_eval<256, M>(v, tb, x, y, z, rq, L, tid); }, lc, v.s_max,
+            v, p0, [&](int x, int y, int z) { return quad_eval<kQuadThreads, M>(v, tb, x, y, z, rq, L, tid); }, lc, v.s_max,
             8 * v.S);
-        const Saliency sal = quad_saliency<256, M>(v, tb, o.p[0], o.p[1], o.p[2], rq, L, tid);
+        const Saliency sal = quad_saliency<kQuadThreads, M>(v, tb, o.p[0], o.p[1], o.p[2], rq, L, tid);
         lc.final_visits += cube_count(v, o.p[0], o.p[1], o.p[2], v.s_max + 1);
         lc.window_evals += (unsigned long long)v.S + 2ull;
         lc.swept = lc.voxel_visits + lc.final_visits;
-        if (tid == 0) write_rec(out + v.traj_base + seed, p0, o, sal, (int32_t)seed);
+        if (tid == 0) write_rec(out + v.traj_base + seed, p0, o, sal, (int32_t)seed, v.rank_by);
     }
     if (tid == 0) {
         atomicAdd(&cnt->evals, lc.evals);
@@ -1433,7 +1439,7 @@ __global__ __launch_bounds__(256) void k_compact(const VolDesc* vols, const Traj
         const unsigned long long k = atomicAdd(&cnt->n_sort, 1ull);
         SortRec o;
         o.vol = blockIdx.y;
-        o.ky = ~(uint64_t)__double_as_longlong(r.y64 + 0.0);
+        o.ky = ~(uint64_t)__double_as_longlong(r.key64 + 0.0);
         o.kpos = ((uint64_t)r.scale << 48) | ((uint64_t)r.z << 32) | ((uint64_t)r.y << 16) | (uint64_t)r.x;
         o.seed = (uint32_t)r.seed;
         o.idx = (uint32_t)(v.traj_base + i);
@@ -1661,13 +1667,13 @@ hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQu
     if (a.ntask <= 0) return hipSuccess;
     const int M = bins_per_lane_host(maxB);
     if (M == 1)
-        hipLaunchKernelGGL(k_search_quad<1>, dim3(grid), dim3(256), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
+        hipLaunchKernelGGL(k_search_quad<1>, dim3(grid), dim3(kQuadThreads), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
                            a.tb, a.rec, a.cnt, rq, lay);
     else if (M == 2)
-        hipLaunchKernelGGL(k_search_quad<2>, dim3(grid), dim3(256), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
+        hipLaunchKernelGGL(k_search_quad<2>, dim3(grid), dim3(kQuadThreads), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
                            a.tb, a.rec, a.cnt, rq, lay);
     else
-        hipLaunchKernelGGL(k_search_quad<4>, dim3(grid), dim3(256), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
+        hipLaunchKernelGGL(k_search_quad<4>, dim3(grid), dim3(kQuadThreads), lay.bytes, st, a.vols, a.segs, a.nseg, a.ntask,
                            a.tb, a.rec, a.cnt, rq, lay);
     return hipGetLastError();
 }
@@ -1741,9 +1747,9 @@ int max_blocks_ms(int hist_words, int maxB) {
 int max_blocks_quad(size_t lds_bytes, int maxB) {
     int nb = 0;
     const int M = bins_per_lane_host(maxB);
-    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<1>, 256, lds_bytes)
-                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<2>, 256, lds_bytes)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<4>, 256, lds_bytes);
+    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<1>, kQuadThreads, lds_bytes)
+                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<2>, kQuadThreads, lds_bytes)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<4>, kQuadThreads, lds_bytes);
     if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }

@@ -27,6 +27,11 @@ static bool dims_ok(const int32_t* d) {
     return (int64_t)((d[0] + 15) & ~15) * d[1] * d[2] < (int64_t(1) << 31);
 }
 
+bool options_ok(const ks_options& o) {
+    return o.h_min == o.h_min && o.y_min == o.y_min && (o.rank_by == KS_RANK_SALIENCY || o.rank_by == KS_RANK_PDF_CHANGE) &&
+           o.reserved == 0;
+}
+
 ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
                         const int32_t* scales, int32_t method, int32_t max_iter) {
     if (!vol || !dims || !scales) return KS_E_INVALID;
@@ -241,7 +246,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         v.gz = (int32_t)grid_count(v.Z, v.sp, &v.oz);
         v.traj_base = traj;
         v.n_traj = num_trajectories(r.dims, r.spacing, r.scales, r.method);
-        v.h_min = 0.0; v.y_min = 0.0;
+        v.h_min = r.opt.h_min; v.y_min = r.opt.y_min; v.rank_by = r.opt.rank_by;
         v.reg_off = regs;
         v.cap = r.capacity;
         bins_off[i] = bins_total;
@@ -488,6 +493,10 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
         key.push_back(v.dtype); key.push_back(v.dims[0]); key.push_back(v.dims[1]); key.push_back(v.dims[2]);
         key.push_back(v.bins); key.push_back(v.spacing); key.push_back(v.scales[0]); key.push_back(v.scales[1]);
         key.push_back(v.method); key.push_back(v.max_iter); key.push_back(v.capacity);
+        int64_t hb, yb;
+        std::memcpy(&hb, &v.opt.h_min, sizeof(hb));
+        std::memcpy(&yb, &v.opt.y_min, sizeof(yb));
+        key.push_back(hb); key.push_back(yb); key.push_back(v.opt.rank_by);
     }
     hipGraphExec_t exec = nullptr;
     for (const GraphEntry& g : graphs)
@@ -606,6 +615,17 @@ ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas
     return KS_OK;
 }
 
+ks_status ks_context_set_options(ks_context* ctx, const ks_options* options) {
+    if (!ctx) return KS_E_INVALID;
+    if (!options) {
+        ctx->opts = ks_options{};
+        return KS_OK;
+    }
+    if (!options_ok(*options)) return KS_E_INVALID;
+    ctx->opts = *options;
+    return KS_OK;
+}
+
 ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct) {
     if (!ctx || incremental_pct < 0 || incremental_pct > 200) return KS_E_INVALID;
     ctx->ms_incr_pct = incremental_pct;
@@ -634,6 +654,7 @@ ks_status ks_detect_device(ks_context* ctx, const void* d_volume, ks_dtype dtype
     v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
     v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
     v.max_iter = max_iter; v.capacity = capacity;
+    v.opt = ctx->opts;
     std::vector<std::vector<ks_region>> res;
     std::vector<int> nf;
     s = ctx->detect_volumes({v}, static_cast<hipStream_t>(stream), &res, &nf);
@@ -683,6 +704,7 @@ ks_status ks_seed_traces(ks_context* ctx, const void* d_volume, ks_dtype dtype, 
     v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
     v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
     v.max_iter = max_iter; v.capacity = 0;
+    v.opt = ctx->opts;
     Plan p;
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
@@ -809,10 +831,12 @@ ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks
         ks_status s = check_request(r.volume, r.dtype, r.dims, r.bins, r.seed_spacing, r.scales, r.method, r.max_iter);
         if (s != KS_OK) return s;
         if (results[i].capacity < 0 || (results[i].capacity > 0 && !results[i].regions)) return KS_E_INVALID;
+        if (!options_ok(r.options)) return KS_E_INVALID;
         VolIn& v = in[(size_t)i];
         v.raw = r.volume; v.dtype = r.dtype; std::memcpy(v.dims, r.dims, sizeof(v.dims)); v.bins = r.bins;
         v.spacing = r.seed_spacing; v.scales[0] = r.scales[0]; v.scales[1] = r.scales[1]; v.method = r.method;
         v.max_iter = r.max_iter; v.capacity = results[i].capacity;
+        v.opt = r.options;
     }
     if (n == 0) return KS_OK;
     std::vector<std::vector<ks_region>> res;

@@ -35,6 +35,7 @@ struct VolIn {
     int32_t scales[2];
     int32_t method, max_iter;
     int32_t capacity;
+    ks_options opt{};
 };
 
 struct Plan {
@@ -66,6 +67,7 @@ struct Context {
     int ms_rl_small_pref = 2;
     int ms_s_small = 6;
     int ms_incr_pct = 100;  // running-window updates while cheaper than a fresh window
+    ks_options opts{};      // selection and order for ks_detect_device / ks_seed_traces
     int quad_rq_pref = 0;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
@@ -96,6 +98,7 @@ struct Context {
                                  std::vector<std::vector<ks_region>>* out, std::vector<int>* nfound);
 };
 
+bool options_ok(const ks_options& o);  // thresholds not NaN, known rank key
 ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
                         const int32_t* scales, int32_t method, int32_t max_iter);
 int64_t num_trajectories(const int32_t* dims, int32_t spacing, const int32_t* scales, int32_t method);

@@ -300,6 +300,7 @@ ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket
     ks_status st = ks::check_request(req->volume, req->dtype, req->dims, req->bins, req->seed_spacing, req->scales,
                                      req->method, req->max_iter);
     if (st != KS_OK) return st;
+    if (!ks::options_ok(req->options)) return KS_E_INVALID;
     SrvReq r;
     r.in.raw = nullptr;
     r.in.dtype = req->dtype;
@@ -310,6 +311,7 @@ ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket
     r.in.scales[1] = req->scales[1];
     r.in.method = req->method;
     r.in.max_iter = req->max_iter;
+    r.in.opt = req->options;
     r.in.capacity = (int32_t)std::min<int64_t>(ks::num_trajectories(req->dims, req->seed_spacing, req->scales,
                                                                     req->method), 1 << 20);
     r.footprint = footprint(r.in);

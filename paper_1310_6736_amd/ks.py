@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libks.so")
 KS_OK, KS_E_INVALID, KS_E_NOMEM, KS_E_DEVICE, KS_E_TOO_LARGE, KS_E_NOT_READY, KS_E_SHUTDOWN = 0, -1, -2, -3, -4, -5, -6
 KS_U8, KS_U16, KS_I16 = 0, 1, 2
 KS_QUADRANT, KS_MEANSHIFT = 0, 1
+KS_RANK_SALIENCY, KS_RANK_PDF_CHANGE = 0, 1
 KS_HIST_CUBE, KS_HIST_OCTANTS, KS_HIST_MEANSHIFT, KS_HIST_SHELLS, KS_HIST_MS_MOVE, KS_HIST_MS_INNER = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
@@ -25,7 +26,7 @@ EXPORTS = [
     "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
-    "ks_context_set_ms_update",
+    "ks_context_set_ms_update", "ks_context_set_options",
 ]
 
 
@@ -54,10 +55,20 @@ class RunStats(C.Structure):
                 ("ms_total", C.c_double), ("swept_voxels", C.c_int64)]
 
 
+class Options(C.Structure):
+    _fields_ = [("h_min", C.c_double), ("y_min", C.c_double), ("rank_by", C.c_int32), ("reserved", C.c_int32)]
+
+
+def options(h_min=0.0, y_min=0.0, rank_by=0) -> Options:
+    o = Options()
+    o.h_min, o.y_min, o.rank_by, o.reserved = float(h_min), float(y_min), int(rank_by), 0
+    return o
+
+
 class Request(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("dtype", C.c_int32), ("dims", C.c_int32 * 3), ("bins", C.c_int32),
                 ("seed_spacing", C.c_int32), ("scales", C.c_int32 * 2), ("method", C.c_int32),
-                ("max_iter", C.c_int32)]
+                ("max_iter", C.c_int32), ("options", Options)]
 
 
 class Result(C.Structure):
@@ -92,6 +103,7 @@ def lib():
     L.ks_context_set_tuning.argtypes = [vp, i32, i32]
     L.ks_context_set_tuning_small.argtypes = [vp, i32, i32]
     L.ks_context_set_ms_update.argtypes = [vp, i32]
+    L.ks_context_set_options.argtypes = [vp, C.POINTER(Options)]
     L.ks_last_stats.argtypes = [vp, C.POINTER(RunStats)]
     L.ks_detect.argtypes = [vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p]
     L.ks_detect_device.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p, vp]
@@ -206,6 +218,13 @@ def ks_context_set_tuning(ctx: Context, ms_replicas_log2: int, quad_replicas_log
     _check(lib().ks_context_set_tuning(ctx.handle, ms_replicas_log2, quad_replicas_log2), "ks_context_set_tuning")
 
 
+def ks_context_set_options(ctx: Context, opts=None):
+    """Selection thresholds and rank key for later ks_detect_device / ks_seed_traces
+    calls on ctx (None: the defaults)."""
+    _check(lib().ks_context_set_options(ctx.handle, None if opts is None else C.byref(opts)),
+           "ks_context_set_options")
+
+
 def ks_context_set_ms_update(ctx: Context, incremental_pct: int = 100):
     _check(lib().ks_context_set_ms_update(ctx.handle, incremental_pct), "ks_context_set_ms_update")
 
@@ -287,8 +306,10 @@ def ks_histograms(ctx: Context, volume, bins, kind, xyz, scale=None, scale_range
     return out
 
 
-def make_request(volume, bins, seed_spacing, scales, method, max_iter, host=False) -> Request:
+def make_request(volume, bins, seed_spacing, scales, method, max_iter, host=False, opts=None) -> Request:
     r = Request()
+    if opts is not None:
+        r.options = opts
     if host:
         vol = np.ascontiguousarray(volume)
         z, y, x = vol.shape
@@ -339,8 +360,8 @@ class Server:
                "ks_server_create")
         self.handle = h
 
-    def submit(self, volume: np.ndarray, bins, seed_spacing, scales, method, max_iter) -> int:
-        r = make_request(volume, bins, seed_spacing, scales, method, max_iter, host=True)
+    def submit(self, volume: np.ndarray, bins, seed_spacing, scales, method, max_iter, opts=None) -> int:
+        r = make_request(volume, bins, seed_spacing, scales, method, max_iter, host=True, opts=opts)
         t = C.c_uint64()
         _check(lib().ks_server_submit(self.handle, C.byref(r), C.byref(t)), "ks_server_submit")
         return t.value

@@ -346,6 +346,47 @@ def test_detect_matches_oracle(torch_dev, ctx, which):
     assert n2 == n_want and np.array_equal(top, got[:20])
 
 
+OPTION_CASES = [("rank_w", 0.0, 0.0, 1), ("thresholds", 0.6, 0.02, 0), ("thresholds_rank_w", 1.0, 0.01, 1),
+                ("negative_y_min", -1.0, -1.0, 0)]
+
+
+@pytest.mark.parametrize("method", [ks.KS_QUADRANT, ks.KS_MEANSHIFT])
+@pytest.mark.parametrize("case", OPTION_CASES, ids=[c[0] for c in OPTION_CASES])
+def test_detect_options_match_oracle(torch_dev, ctx, method, case):
+    """Entropy / saliency thresholds and the pdf-change rank key, through the
+    context options and through a batch request, against the oracle."""
+    name, h_min, y_min, rank_by = case
+    w = synth.Workload("opt", synth.spheres_volume(11, (44, 41, 37)), 32, 5, (2, 6), method, 20)
+    note(f"detect options {name} method={method}")
+    want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=4096,
+                                    h_min=h_min, y_min=y_min, rank_by=rank_by)
+    opts = ks.options(h_min, y_min, rank_by)
+    t = dev(torch_dev, w.volume)
+    ks.ks_context_set_options(ctx, opts)
+    try:
+        got, n = ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=4096)
+    finally:
+        ks.ks_context_set_options(ctx, None)
+    compare_regions(got, n, want, n_want, name)
+    req = ks.make_request(t, w.bins, w.spacing, w.scales, w.method, w.max_iter, opts=opts)
+    plain = ks.make_request(t, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    (bg, bn), (pg, pn) = ks.ks_detect_batch(ctx, [req, plain], capacity=4096)
+    assert bn == n and np.array_equal(bg, got)
+    base, n_base, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=4096)
+    compare_regions(pg, pn, base, n_base, "defaults in the same batch")
+
+
+def test_options_are_validated(torch_dev, ctx):
+    for bad in (ks.options(rank_by=2), ks.options(h_min=float("nan"))):
+        with pytest.raises(ks.KsError) as e:
+            ks.ks_context_set_options(ctx, bad)
+        assert e.value.status == ks.KS_E_INVALID
+    bad = ks.options()
+    bad.reserved = 1
+    with pytest.raises(ks.KsError):
+        ks.ks_context_set_options(ctx, bad)
+
+
 def test_detect_host_entry_point(torch_dev):
     w = synth.spheres_64()
     note("ks_detect host volume")

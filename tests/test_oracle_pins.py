@@ -385,3 +385,48 @@ def test_seeds_overlapping_a_sphere_converge_to_it(method):
     assert near.sum() > 0
     assert np.all(np.abs(end[near]).max(1) <= np.abs(start[near]).max(1))
     assert np.mean(np.abs(end[near]).max(1)) < np.mean(d0[near])
+
+
+def _kept_keys(w):
+    """(x, y, z, scale) -> (h64, w64, y64) of every trajectory that yields a region."""
+    tr, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    out = {}
+    for t in tr[tr["keep"] == 1]:
+        out[(int(t["x"]), int(t["y"]), int(t["z"]), int(t["scale"]))] = (float(t["h64"]), float(t["w64"]),
+                                                                           float(t["y64"]))
+    return out
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_thresholds_filter_the_unthresholded_result(method):
+    """h_min and y_min drop exactly the regions whose decision-precision H or Y is
+    not above them, and keep the order of the others (thresholds are a filter)."""
+    w = synth.Workload("spheres", synth.spheres_volume(5, (40, 36, 32)), 32, 6, (2, 5), method, 20)
+    keys = _kept_keys(w)
+    full, n_full, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    assert n_full == len(keys) > 4
+    hs = sorted(v[0] for v in keys.values())
+    ys = sorted(v[2] for v in keys.values())
+    h_min, y_min = hs[len(hs) // 3], ys[len(ys) // 4]
+    got, n, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, h_min=h_min, y_min=y_min)
+    want = [r for r in full if keys[(int(r["x"]), int(r["y"]), int(r["z"]), int(r["scale"]))][0] > h_min
+            and keys[(int(r["x"]), int(r["y"]), int(r["z"]), int(r["scale"]))][2] > y_min]
+    assert 0 < n == len(want) < n_full
+    for a, b in zip(got, want):
+        assert (a["x"], a["y"], a["z"], a["scale"], a["seed"]) == (b["x"], b["y"], b["z"], b["scale"], b["seed"])
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_rank_by_pdf_change_orders_the_same_regions_by_w(method):
+    """Ranking by the pdf change W returns the same regions as ranking by Y, in
+    W-descending order with ties by (scale, z, y, x) ascending."""
+    w = synth.Workload("spheres", synth.spheres_volume(6, (38, 40, 33)), 32, 6, (2, 5), method, 20)
+    by_y, n_y, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    by_w, n_w, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter,
+                                 rank_by=oracle.RANK_PDF_CHANGE)
+    assert n_y == n_w > 4
+    key = lambda r: (int(r["x"]), int(r["y"]), int(r["z"]), int(r["scale"]), int(r["seed"]))
+    assert sorted(map(key, by_y)) == sorted(map(key, by_w))
+    order = sorted(by_w, key=lambda r: (-r["pdf_change"], r["scale"], r["z"], r["y"], r["x"]))
+    assert [key(r) for r in order] == [key(r) for r in by_w]
+    assert [key(r) for r in by_y] != [key(r) for r in by_w]
