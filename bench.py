@@ -9,10 +9,12 @@ host).  The input is in HBM before the timed region starts.
 
 Prints one JSON line.  Extra fields: volumes/s, per-method device times, the
 roofline of the dominant kernel (the mean-shift search) measured with HIP events
-on the launch stream, the CPU oracle timed on a bounded sample, the uneven
-64-volume batch (one captured launch sequence) against plain per-volume
-launches, and a Poisson serving stream against a plain one-launch-per-volume
-loop with p50/p99 latency.
+on the launch stream (against the published HBM peak and the measured copy
+peak), both searches' LDS-atomic rates against measured LDS ceilings, the
+host-to-device copy of the volume (outside the timed step), the CPU oracle timed
+on a bounded sample, the uneven 64-volume batch (one captured launch sequence)
+against plain per-volume launches, and Poisson serving streams at several rates
+against a plain one-launch-per-volume loop with p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -40,7 +42,7 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_k_search_ms_pet128x128x64.json"))
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256)
     return ap.parse_args()
 
 
@@ -77,21 +79,22 @@ def batch_section(ks, torch, ctx):
 
 
 def serving_section(ks, torch, ctx, n_req):
-    """Poisson stream of the 50/30/20 mix at native sizes: the continuous-batching
+    """Poisson streams of the 50/30/20 mix at native sizes: the continuous-batching
     server against a plain loop that serves requests one launch sequence at a
-    time in arrival order (both copy each host volume to the device)."""
-    import threading
-
+    time in arrival order (both copy each host volume to the device).  Arrival
+    rates 0.5, 0.7, 0.9 and 1.2 x the plain loop's measured capacity, a saturated
+    stream (all requests at t = 0), and the saturated stream under a budget that
+    holds one large request at a time."""
     from paper_1310_6736_amd import synth
 
     pool = {0: [synth.typed_workload(0, 2000 + i, synth.TYPE_DIMS[0]) for i in range(4)],
             1: [synth.typed_workload(1, 2100 + i, synth.TYPE_DIMS[1], method_parity=i) for i in range(4)],
             2: [synth.typed_workload(2, 2200 + i, synth.TYPE_DIMS[2]) for i in range(2)]}
     cap = 64
-    dev_buf = {k: [torch.empty(w.volume.shape, dtype={np.dtype(np.uint8): torch.uint8,
-                                                      np.dtype(np.int16): torch.int16}.get(w.volume.dtype,
-                                                                                           getattr(torch, "uint16", None)),
-                               device="cuda:0") for w in ws] for k, ws in pool.items()}
+    tdt = {np.dtype(np.uint8): torch.uint8, np.dtype(np.int16): torch.int16,
+           np.dtype(np.uint16): getattr(torch, "uint16", None)}
+    dev_buf = {k: [torch.empty(w.volume.shape, dtype=tdt[w.volume.dtype], device="cuda:0") for w in ws]
+               for k, ws in pool.items()}
 
     def plain_one(kind, j):
         w = pool[kind][j]
@@ -102,7 +105,7 @@ def serving_section(ks, torch, ctx, n_req):
     # plain capacity on the mix (saturated, arrival order)
     trace = synth.arrival_trace(1.0, n=n_req)
     order = [(k, (seed % len(pool[k]))) for _, k, seed, _ in trace]
-    for k, j in order[:6]:
+    for k, j in order[:8]:
         plain_one(k, j)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -125,9 +128,7 @@ def serving_section(ks, torch, ctx, n_req):
         return {"volumes_per_s": len(trace) / span, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(np.mean(lat))}
 
-    srv = ks.Server(0, hbm_budget=8 << 30, max_slots=4)
-
-    def run_server(trace):
+    def run_server(srv, trace):
         srv.reset_stats()
         tickets = []
         start = time.perf_counter()
@@ -142,17 +143,25 @@ def serving_section(ks, torch, ctx, n_req):
         for t in tickets:
             srv.poll(t, capacity=cap)
         return {"volumes_per_s": st["volumes_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                "mean_ms": st["mean_ms"]}
+                "mean_ms": st["mean_ms"], "refused": int(st["refused"])}
 
+    sat = [(0.0, k, seed, i) for _, k, seed, i in trace]
     out = {"workload": "%d requests, Poisson arrivals, 50/30/20 mix of the 64^3 spheres, 128x128x64 PET-like "
                        "(quadrant/mean-shift alternating) and 256x256x160 MR-like generators" % n_req,
            "plain_capacity_volumes_per_s": c_plain}
-    sat = [(0.0, k, seed, i) for _, k, seed, i in trace]
-    run_server(sat)  # warm-up: the slots' device buffers grow to the mix's sizes
-    out["saturated"] = {"server": run_server(sat), "plain": run_plain(sat)}
-    lam = 0.7 * c_plain
-    tr = synth.arrival_trace(lam, n=n_req)
-    out["rate_0.7"] = {"rate_per_s": lam, "server": run_server(tr), "plain": run_plain(tr)}
+    srv = ks.Server(0, hbm_budget=8 << 30, max_slots=4)
+    run_server(srv, sat)  # warm-up: the slots' device buffers grow to the mix's sizes
+    out["saturated"] = {"server": run_server(srv, sat), "plain": run_plain(sat)}
+    for f in (0.5, 0.7, 0.9, 1.2):
+        lam = f * c_plain
+        tr = synth.arrival_trace(lam, n=n_req)
+        out["rate_%.1f" % f] = {"rate_per_s": lam, "server": run_server(srv, tr), "plain": run_plain(tr)}
+    srv.close()
+    # a budget that holds one MR-like request (about 130 MB of device state) at a time
+    small = 160 << 20
+    srv = ks.Server(0, hbm_budget=small, max_slots=4)
+    run_server(srv, sat[:16])
+    out["small_budget"] = {"budget_bytes": small, "saturated": run_server(srv, sat)}
     srv.close()
     return out
 
@@ -178,27 +187,39 @@ def measured_traffic(path):
         return None
 
 
-def cpu_baseline(stride: int):
-    """The oracle as it stands, single-threaded, on every stride-th trajectory of the
-    same workload; window evaluations per second."""
+def _oracle_shard(job):
+    """One worker of the CPU baseline: the oracle on one interleaved share of the
+    trajectory ids of one method."""
     import oracle
     from paper_1310_6736_amd import synth
 
-    total_evals, total_s = 0, 0.0
-    sample = []
-    for method in (0, 1):
-        w = synth.pet_shell(method)
-        n = oracle.num_trajectories(w.dims, w.spacing, w.scales, w.method)
-        ids = np.arange(0, n, stride, dtype=np.int64)
-        t0 = time.perf_counter()
-        _, st = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, ids=ids)
-        total_s += time.perf_counter() - t0
-        total_evals += st["window_evals"]
-        sample.append(f"{w.name}: {len(ids)}/{n} trajectories")
-    return {"value": total_evals / total_s, "unit": "window_evals/s", "cores": 1, "kind": "oracle",
-            "sample": "%s of the PET-like volume, both methods (%s); %.1f s" %
-                      ("every trajectory" if stride == 1 else "every %d-th trajectory" % stride, "; ".join(sample),
-                       total_s)}
+    method, stride, worker, workers = job
+    w = synth.pet_shell(method)
+    n = oracle.num_trajectories(w.dims, w.spacing, w.scales, w.method)
+    ids = np.arange(0, n, stride, dtype=np.int64)[worker::workers]
+    _, st = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, ids=ids)
+    return st["window_evals"], len(ids), n
+
+
+def cpu_baseline(stride: int, workers: int):
+    """The oracle as it stands on every stride-th trajectory of the same workload,
+    sharded over `workers` processes by trajectory id; window evaluations per
+    second of wall time.  Runs before the GPU is initialised (the pool forks)."""
+    import multiprocessing as mp
+
+    jobs = [(m, stride, k, workers) for m in (0, 1) for k in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_shard, jobs, chunksize=1)
+    total_s = time.perf_counter() - t0
+    total_evals = sum(r[0] for r in res)
+    done = {m: sum(r[1] for r, j in zip(res, jobs) if j[0] == m) for m in (0, 1)}
+    of = {m: next(r[2] for r, j in zip(res, jobs) if j[0] == m) for m in (0, 1)}
+    which = "every trajectory" if stride == 1 else "every %d-th trajectory" % stride
+    return {"value": total_evals / total_s, "unit": "window_evals/s", "cores": workers, "kind": "oracle",
+            "sample": "%s of the PET-like volume, both methods (quadrant %d/%d, mean-shift %d/%d trajectories), "
+                      "ids dealt round-robin to %d processes; %.1f s wall" %
+                      (which, done[0], of[0], done[1], of[1], workers, total_s)}
 
 
 def main():
@@ -206,6 +227,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_sample_stride, max(1, min(16, os.cpu_count() or 1)))
     import torch
 
     from paper_1310_6736_amd import ks, synth
@@ -252,6 +276,26 @@ def main():
     q_bytes = q_stats[-1]["voxel_visits"] + q_stats[-1]["final_visits"]
     achieved = ms_bytes / (ms_kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.traffic_json)
+    # measured ceilings: streaming copy, conflict-free 64-bit / 32-bit LDS atomics
+    copy_gbs = ks.ks_roofline(ks.KS_ROOF_COPY) / 1e9
+    lds64 = ks.ks_roofline(ks.KS_ROOF_LDS_ADD64)
+    lds32 = ks.ks_roofline(ks.KS_ROOF_LDS_ADD32)
+    ms_ops = float(np.mean([s["lds_ops"] for s in ms_stats]))
+    q_ops = float(np.mean([s["lds_ops"] for s in q_stats]))
+    ms_swept = float(np.mean([s["swept_voxels"] for s in ms_stats]))
+    # host-to-device copy of the input volume (not part of the timed step)
+    host = torch.from_numpy(wq.volume)
+    pinned = host.pin_memory()
+    h2d = {}
+    for name, src in (("pageable", host), ("pinned", pinned)):
+        buf = torch.empty_like(vol)
+        buf.copy_(src)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(10):
+            buf.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d[name + "_ms"] = (time.perf_counter() - t1) * 100.0
 
     line = {
         "metric": "seed-scale window evals/sec",
@@ -279,14 +323,27 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_search_ms", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": int(ms_bytes),
+                     "swept_bytes_per_launch": int(ms_swept),
+                     "copy_peak_measured": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "quadrant_achieved": q_bytes / (q_kernel_ms * 1e-3) / 1e9},
+        "lds_atomic": {"unit": "lane-ops/s",
+                       "meanshift": {"kernel": "k_search_ms", "ops_per_launch": int(ms_ops),
+                                     "achieved": ms_ops / (ms_kernel_ms * 1e-3), "peak": lds64,
+                                     "peak_kind": "conflict-free 64-bit LDS add microbenchmark",
+                                     "frac": ms_ops / (ms_kernel_ms * 1e-3) / lds64},
+                       "quadrant": {"kernel": "k_search_quad", "ops_per_launch": int(q_ops),
+                                    "achieved": q_ops / (q_kernel_ms * 1e-3), "peak": lds32,
+                                    "peak_kind": "conflict-free 32-bit LDS add microbenchmark",
+                                    "frac": q_ops / (q_kernel_ms * 1e-3) / lds32}},
+        "h2d": dict(h2d, bytes=int(wq.volume.nbytes),
+                    pcie_inclusive_window_evals_per_s=window_evals / (dt / args.steps + h2d["pinned_ms"] * 1e-3)),
     }
     if not args.no_batch:
         line["batch"] = batch_section(ks, torch, ctx)
     if not args.no_serve:
         line["serving"] = serving_section(ks, torch, ctx, args.serve_requests)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     ctx.close()
     print(json.dumps(line), flush=True)
 

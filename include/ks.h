@@ -99,6 +99,8 @@ typedef struct {
     double ms_prep, ms_search, ms_rank, ms_total; /* device time per phase (only with profiling on) */
     int64_t swept_voxels;  /* voxels the searches actually swept: with running-window updates
                               of the mean-shift search, fewer than voxel_visits + final_visits */
+    int64_t lds_ops;       /* lane-level LDS atomic additions of the searches (histogram
+                              scatter, including the adds of padding bytes into spare slots) */
 } ks_run_stats;
 
 /* Selection and order of the output regions.  A trajectory yields a region when

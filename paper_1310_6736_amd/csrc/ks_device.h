@@ -91,6 +91,7 @@ struct Counters {
     unsigned long long queue_head[2];   // task queues (quadrant, mean-shift)
     unsigned long long n_sort;          // kept trajectories
     unsigned long long swept;           // voxels actually swept by the searches
+    unsigned long long lds_ops;         // lane-level LDS atomic operations of the searches
 };
 
 // Launch-time tuning of the mean-shift evaluation: replicas per wavefront,

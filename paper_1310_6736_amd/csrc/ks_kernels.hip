@@ -246,6 +246,7 @@ __global__ void k_prep_init(VolDesc* vols, int nvol, Counters* cnt, int* vol_nfo
         cnt->queue_head[0] = cnt->queue_head[1] = 0;
         cnt->n_sort = 0;
         cnt->swept = 0;
+        cnt->lds_ops = 0;
     }
 }
 
@@ -543,8 +544,8 @@ __device__ __forceinline__ int64_t boxes_volume(const VolDesc& v, const BoxSet& 
 // trash slots at trash_base, past every bin layout.  The flush budget runs across
 // the boxes.
 template <int M>
-__device__ __forceinline__ void ms_sweep(const VolDesc& v, BoxSet bs, int rl, int trash_base,
-                                         unsigned long long* hist, int lane, BinAcc<M>& acc) {
+__device__ __forceinline__ unsigned int ms_sweep(const VolDesc& v, BoxSet bs, int rl, int trash_base,
+                                                 unsigned long long* hist, int lane, BinAcc<M>& acc) {
     bs.kind = uniform(bs.kind); bs.px = uniform(bs.px); bs.py = uniform(bs.py); bs.pz = uniform(bs.pz);
     bs.qx = uniform(bs.qx); bs.qy = uniform(bs.qy); bs.qz = uniform(bs.qz); bs.s = uniform(bs.s);
     rl = uniform(rl);
@@ -569,6 +570,7 @@ __device__ __forceinline__ void ms_sweep(const VolDesc& v, BoxSet bs, int rl, in
         __syncthreads();
     };
     int used = 0;
+    unsigned int ops = 0;
     const int nb = box_count(bs);
 #pragma unroll 1
     for (int i = 0; i < nb; ++i) {
@@ -616,10 +618,12 @@ __device__ __forceinline__ void ms_sweep(const VolDesc& v, BoxSet bs, int rl, in
                     const uint32_t bin = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
                     atomicAdd(reinterpret_cast<unsigned long long*>(hb + (bin << shift) + off[k]), cp[k] + step);
                 }
+                ops += 4;
             },
             flush);
     }
     if (used > 0) flush();
+    return ops;
 }
 
 struct EvalOut {
@@ -727,6 +731,7 @@ __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? l
 
 struct LocalCounts {
     unsigned long long evals, window_evals, voxel_visits, final_visits, swept;
+    unsigned int lds_ops;   // this lane's LDS atomic operations
 };
 
 // The search loop shared by both methods: round the proposed move, stop if it is
@@ -802,7 +807,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
     const int lane = threadIdx.x;
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
     __syncthreads();
-    LocalCounts lc = {0, 0, 0, 0, 0};
+    LocalCounts lc = {0, 0, 0, 0, 0, 0u};
     const int trash_base = hist_words - 64;
     for (;;) {
         long long t = 0;
@@ -867,7 +872,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
             } else {
                 lc.swept += (unsigned long long)cube_count(v, px, py, pz, s);
             }
-            ms_sweep<M>(v, bs, rl, trash_base, hist, lane, a);
+            lc.lds_ops += ms_sweep<M>(v, bs, rl, trash_base, hist, lane, a);
             if (phase == 2) break;
             // an evaluation at W (= P0 in phase 0, Q in phase 1)
             const EvalOut e = ms_moments<M>(v, tb, wx, wy, wz, s, a);
@@ -918,6 +923,8 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         atomicAdd(&cnt->final_visits, lc.final_visits);
         atomicAdd(&cnt->swept, lc.swept);
     }
+    const unsigned long long ops = (unsigned long long)bfly_sumll((long long)lc.lds_ops);
+    if (lane == 0) atomicAdd(&cnt->lds_ops, ops);
 }
 
 // ------------------------------------------------ quadrant: bucketed scatter
@@ -927,8 +934,9 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
 // row = max(max(|x-cx|,|y-cy|,|z-cz|) - base, 0); bytes outside the box go to
 // row trash_row.
 template <int NT>
-__device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx, int cy,
-                               int cz, int base, int trash_row, int rq, uint32_t region, uint32_t* hist, int tid) {
+__device__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx,
+                                       int cy, int cz, int base, int trash_row, int rq, uint32_t region,
+                                       uint32_t* hist, int tid) {
     const Layout L = layout_x(v);
     const Sweep w = make_sweep<NT>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, tid);
     const uint32_t rowbytes = (uint32_t)row_stride(v.B) << (rq + 2);
@@ -944,6 +952,7 @@ __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb,
     }
     const int dy0 = ya + w.oy - cy, dz0 = za + w.oz - cz;
     int used = 0;
+    unsigned int ops = 0;
     run_sweep(
         L, w, used, INT_MAX,
         [&](uint32_t word, int iy0, int iz0) {
@@ -955,8 +964,10 @@ __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb,
                 const uint32_t addr = max(rx[k], RR) + (b << bshift);
                 atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(hist) + addr), 1u);
             }
+            ops += 4;
         },
         []() {});
+    return ops;
 }
 
 // One sweep over the brick P + [-R, R]^3 (clipped) for all 8 octants: a voxel
@@ -967,8 +978,8 @@ __device__ void bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb,
 // LDS add; the x-plane voxel of a lane costs one more add per step, and the rare
 // rows on the y or z plane take a separate path.
 template <int NT>
-__device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base, int trash_row, int rq,
-                               uint32_t region_bytes, uint32_t* hist, int tid) {
+__device__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base, int trash_row,
+                                       int rq, uint32_t region_bytes, uint32_t* hist, int tid) {
     const int xa = max(px - Rr, 0), xb = min(px + Rr, v.X - 1);
     const int ya = max(py - Rr, 0), yb = min(py + Rr, v.Y - 1);
     const int za = max(pz - Rr, 0), zb = min(pz + Rr, v.Z - 1);
@@ -996,6 +1007,7 @@ __device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr,
     const uint32_t ry2 = 2u * region_bytes, rz4 = 4u * region_bytes;
     char* hb = reinterpret_cast<char*>(hist);
     int used = 0;
+    unsigned int ops = 0;
     run_sweep(
         L, w, used, INT_MAX,
         [&](uint32_t word, int iy0, int iz0) {
@@ -1024,9 +1036,12 @@ __device__ void octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr,
                     if (zm) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + zm), 1u);
                     if (ym && zm) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + ym + zm), 1u);
                 }
+                ops += (xdup ? 5u : 4u) * ((ym ? 1u : 0u) + (zm ? 1u : 0u) + (ym && zm ? 1u : 0u));
             }
+            ops += xdup ? 5u : 4u;
         },
         []() {});
+    return ops;
 }
 
 // Sum the replicas of every (region, bin) and prefix over rows 0..nrows-1, in
@@ -1126,11 +1141,11 @@ __device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows
 // maximising scale, E = sum of the 8 maxima, move = sum_j eps_j k*_j sigma_j / E.
 template <int NT, int M>
 __device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq, const QuadLds& L,
-                             int tid) {
+                             int tid, unsigned int& ops) {
     px = uniform(px); py = uniform(py); pz = uniform(pz);
     const int S = v.S, B = v.B;
     const uint32_t region_bytes = (uint32_t)(S + 1) * (uint32_t)row_stride(B) << (rq + 2);
-    octant_scatter<NT>(v, px, py, pz, v.s_max, v.s_min, S, rq, region_bytes, L.hist, tid);
+    ops += octant_scatter<NT>(v, px, py, pz, v.s_max, v.s_min, S, rq, region_bytes, L.hist, tid);
     __syncthreads();
     bucket_merge<NT>(L.hist, 8, S, B, rq, tid);
     __syncthreads();
@@ -1188,14 +1203,14 @@ __device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py,
 // peak with the largest H*W (first on ties).
 template <int NT, int M>
 __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq,
-                                  const QuadLds& L, int tid) {
+                                  const QuadLds& L, int tid, unsigned int& ops) {
     px = uniform(px); py = uniform(py); pz = uniform(pz);
     const int S = v.S, B = v.B;
     const int nrows = S + 2;
     const int base = v.s_min - 1;
     const int wave = tid >> 6, lane = tid & 63;
     const int R = v.s_max + 1;
-    bucket_scatter<NT>(v, max(px - R, 0), min(px + R, v.X - 1), max(py - R, 0), min(py + R, v.Y - 1),
+    ops += bucket_scatter<NT>(v, max(px - R, 0), min(px + R, v.X - 1), max(py - R, 0), min(py + R, v.Y - 1),
                        max(pz - R, 0), min(pz + R, v.Z - 1), px, py, pz, base, nrows, rq, 0u, L.hist, tid);
     __syncthreads();
     bucket_merge<NT>(L.hist, 1, nrows, B, rq, tid);
@@ -1286,7 +1301,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __r
     }
     const QuadLds L = quad_lds(smem, lay);
     __syncthreads();
-    LocalCounts lc = {0, 0, 0, 0, 0};
+    LocalCounts lc = {0, 0, 0, 0, 0, 0u};
     for (;;) {
         if (tid == 0) s_task = (long long)atomicAdd(&cnt->queue_head[0], 1ull);
         __syncthreads();
@@ -1300,9 +1315,9 @@ __global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __r
         int p0[3];
         seed_pos(v, seed, p0);
         const TrajOut o = run_trajectory(
-            v, p0, [&](int x, int y, int z) { return quad_eval<kQuadThreads, M>(v, tb, x, y, z, rq, L, tid); }, lc, v.s_max,
+            v, p0, [&](int x, int y, int z) { return quad_eval<kQuadThreads, M>(v, tb, x, y, z, rq, L, tid, lc.lds_ops); }, lc, v.s_max,
             8 * v.S);
-        const Saliency sal = quad_saliency<kQuadThreads, M>(v, tb, o.p[0], o.p[1], o.p[2], rq, L, tid);
+        const Saliency sal = quad_saliency<kQuadThreads, M>(v, tb, o.p[0], o.p[1], o.p[2], rq, L, tid, lc.lds_ops);
         lc.final_visits += cube_count(v, o.p[0], o.p[1], o.p[2], v.s_max + 1);
         lc.window_evals += (unsigned long long)v.S + 2ull;
         lc.swept = lc.voxel_visits + lc.final_visits;
@@ -1315,6 +1330,8 @@ __global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __r
         atomicAdd(&cnt->final_visits, lc.final_visits);
         atomicAdd(&cnt->swept, lc.swept);
     }
+    const unsigned long long ops = (unsigned long long)bfly_sumll((long long)lc.lds_ops);
+    if ((tid & 63) == 0) atomicAdd(&cnt->lds_ops, ops);
 }
 
 // ------------------------------------------------------------ test hooks

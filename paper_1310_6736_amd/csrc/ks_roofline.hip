@@ -12,7 +12,7 @@
 
 #include "../../include/ks.h"
 
-namespace {
+namespace ks {
 
 constexpr int kLdsWords = 2048;  // 16 KB of u64 per workgroup
 constexpr int kIters = 4096;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ a, uint4
         b[i] = a[i];
 }
 
-}  // namespace
+}  // namespace ks
 
 extern "C" {
 
@@ -87,7 +87,7 @@ ks_status ks_roofline(int32_t device, int32_t kind, double* rate) {
             const int grid = prop.multiProcessorCount * 8;
             for (int r = 0; r < 6 && st == KS_OK; ++r) {
                 hipEventRecord(e0, 0);
-                hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, 0, (const uint4*)a, (uint4*)b, n);
+                hipLaunchKernelGGL(ks::k_copy, dim3(grid), dim3(256), 0, 0, (const uint4*)a, (uint4*)b, n);
                 hipEventRecord(e1, 0);
                 if (hipEventSynchronize(e1) != hipSuccess) st = KS_E_DEVICE;
                 float ms = 0;
@@ -107,9 +107,9 @@ ks_status ks_roofline(int32_t device, int32_t kind, double* rate) {
             for (int r = 0; r < 6 && st == KS_OK; ++r) {
                 hipEventRecord(e0, 0);
                 if (kind == KS_ROOF_LDS_ADD32)
-                    hipLaunchKernelGGL(k_lds_add32, dim3(grid), dim3(256), 0, 0, sink);
+                    hipLaunchKernelGGL(ks::k_lds_add32, dim3(grid), dim3(256), 0, 0, sink);
                 else
-                    hipLaunchKernelGGL(k_lds_add64, dim3(grid), dim3(256), 0, 0, sink,
+                    hipLaunchKernelGGL(ks::k_lds_add64, dim3(grid), dim3(256), 0, 0, sink,
                                        kind == KS_ROOF_LDS_ADD64_SHARED4 ? 1 : 0);
                 hipEventRecord(e1, 0);
                 if (hipEventSynchronize(e1) != hipSuccess) st = KS_E_DEVICE;
@@ -117,7 +117,7 @@ ks_status ks_roofline(int32_t device, int32_t kind, double* rate) {
                 hipEventElapsedTime(&ms, e0, e1);
                 if (r > 0 && ms < best_ms) best_ms = ms;
             }
-            if (st == KS_OK) *rate = (double)grid * 256.0 * kIters / (best_ms * 1e-3);
+            if (st == KS_OK) *rate = (double)grid * 256.0 * ks::kIters / (best_ms * 1e-3);
             hipFree(sink);
         }
     }

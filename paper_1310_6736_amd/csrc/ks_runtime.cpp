@@ -423,6 +423,7 @@ void Context::collect_stats(const Plan& p, bool timed) {
     last.voxel_visits = (int64_t)c.voxel_visits;
     last.final_visits = (int64_t)c.final_visits;
     last.swept_voxels = (int64_t)c.swept;
+    last.lds_ops = (int64_t)c.lds_ops;
     for (int i = 0; i < p.nvol; ++i) last.regions += nf[i];
     if (timed) {
         float a = 0, b = 0, d = 0;

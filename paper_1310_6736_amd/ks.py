@@ -52,7 +52,7 @@ class RunStats(C.Structure):
     _fields_ = [("trajectories", C.c_int64), ("evals", C.c_int64), ("window_evals", C.c_int64),
                 ("voxel_visits", C.c_int64), ("final_visits", C.c_int64), ("regions", C.c_int64),
                 ("ms_prep", C.c_double), ("ms_search", C.c_double), ("ms_rank", C.c_double),
-                ("ms_total", C.c_double), ("swept_voxels", C.c_int64)]
+                ("ms_total", C.c_double), ("swept_voxels", C.c_int64), ("lds_ops", C.c_int64)]
 
 
 class Options(C.Structure):

@@ -352,6 +352,46 @@ def test_subset_runs_equal_full_run():
     assert np.array_equal(sub, full[ids])
 
 
+def _shard(job):
+    vol, bins, spacing, scales, method, max_iter, ids = job
+    tr, st = oracle.run(vol, bins, spacing, scales, method, max_iter, ids=ids)
+    return tr, st
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_seed_sharded_runs_merge_to_the_single_run(method):
+    """Trajectories are independent: disjoint id ranges run in separate processes
+    merge to the single run's traces and counters, and ranking the merged kept
+    traces (key descending, ties by scale, z, y, x, seed ascending; first of each
+    (x, y, z, scale)) reproduces the single run's detection."""
+    import multiprocessing as mp
+
+    w = synth.Workload("spheres", synth.spheres_volume(8, (36, 33, 40)), 32, 5, (2, 5), method, 20)
+    n = oracle.num_trajectories(w.dims, w.spacing, w.scales, w.method)
+    cuts = [0, n // 5, n // 2, n]
+    jobs = [(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, np.arange(a, b, dtype=np.int64))
+            for a, b in zip(cuts[:-1], cuts[1:])]
+    with mp.get_context("fork").Pool(3) as pool:
+        parts = pool.map(_shard, jobs)
+    merged = np.concatenate([p[0] for p in parts])
+    full, st = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    assert np.array_equal(merged, full)
+    for f in ("evals", "window_evals", "voxel_visits"):
+        assert sum(p[1][f] for p in parts) == st[f]
+    kept = merged[merged["keep"] == 1]
+    order = sorted(range(len(kept)), key=lambda i: (-kept["y64"][i], kept["scale"][i], kept["z"][i], kept["y"][i],
+                                                    kept["x"][i], kept["traj"][i]))
+    seen, ranked = set(), []
+    for i in order:
+        k = (int(kept["x"][i]), int(kept["y"][i]), int(kept["z"][i]), int(kept["scale"][i]))
+        if k not in seen:
+            seen.add(k)
+            ranked.append(k + (int(kept["traj"][i]),))
+    want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    assert n_want == len(ranked)
+    assert ranked == [(int(r["x"]), int(r["y"]), int(r["z"]), int(r["scale"]), int(r["seed"])) for r in want]
+
+
 # ---------------------------------------------------------- behaviour (Sec. 2.1)
 
 def sphere_in_constant(r=7, n=48, seed=60):
