@@ -34,8 +34,11 @@ namespace ks {
 
 // ------------------------------------------------------------------ helpers
 
-constexpr int kUnroll = 4;  // window rows per group of loads
-constexpr int kDepth = 4;   // groups of loads in flight per wavefront
+// Sweep pipelines: rows per group of loads, groups of loads in flight (measured:
+// the mean-shift sweeps, many of them a few rows long, run best with a short
+// pipeline; the quadrant brick sweep with narrow groups).
+constexpr int kMsUnroll = 4, kMsDepth = 1;
+constexpr int kQuadUnroll = 2, kQuadDepth = 2;
 // Load offset past the end of every bin volume (volumes stay below 2^31 bytes):
 // the buffer range check turns such a load into 0 without a memory access.
 constexpr uint32_t kPastEnd = 0x80000000u;
@@ -174,15 +177,15 @@ __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int
     return w;
 }
 
-// Walks the sweep's steps in groups of kUnroll rows, keeping kDepth groups of
-// loads in flight: the loads of group g + kDepth are issued right after group g
+// Walks the sweep's steps in groups of U rows, keeping D groups of loads in
+// flight: the loads of group g + D are issued right after group g
 // is scattered.  Calls f(word, iy0, iz0) for every step in which the lane's row
 // lies inside the box (word: 4 voxels; iy0, iz0: the step's row and slice offset).
 // `used` counts the voxels each lane has scattered since the last flush, across
 // calls: before a group that would take it past `limit`, flush() runs
 // (uniformly) and the count restarts.  Loads for steps past the last one get an
 // offset beyond the descriptor's end: they return 0 without a memory access.
-template <typename F, typename G>
+template <int U, int D, typename F, typename G>
 __device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, int& used, int limit, F&& f,
                                           G&& flush) {
     const __amdgpu_buffer_rsrc_t rs = layout_rsrc(L);
@@ -190,14 +193,14 @@ __device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, int& 
     const int nz = uniform(w.nz);
     const int ny = uniform(w.ny), ty = uniform(w.ty), tz = uniform(w.tz), nsteps = uniform(w.nsteps);
     const int lim_y = w.ny - w.oy, lim_z = w.nz - w.oz;
-    constexpr int kGroupVoxels = kUnroll * 4;
+    constexpr int kGroupVoxels = U * 4;
     int iy0 = 0, iz0 = 0;
-    uint32_t buf[kDepth][kUnroll];
-    int by[kDepth][kUnroll], bz[kDepth][kUnroll];
+    uint32_t buf[D][U];
+    int by[D][U], bz[D][U];
 #pragma unroll
-    for (int g = 0; g < kDepth; ++g) {
+    for (int g = 0; g < D; ++g) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             by[g][u] = iy0;
             bz[g][u] = iz0;
             buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? iz0 * slice + iy0 * xp : kPastEnd, 0);
@@ -205,22 +208,22 @@ __device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, int& 
             if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
         }
     }
-    for (int t = 0; t < nsteps; t += kUnroll * kDepth) {
+    for (int t = 0; t < nsteps; t += U * D) {
 #pragma unroll
-        for (int g = 0; g < kDepth; ++g) {
-            if (t + g * kUnroll < nsteps) {
+        for (int g = 0; g < D; ++g) {
+            if (t + g * U < nsteps) {
                 if (used + kGroupVoxels > limit) {
                     used = 0;
                     flush();
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < U; ++u) {
                     if (w.on && by[g][u] < lim_y && bz[g][u] < lim_z) f(buf[g][u], by[g][u], bz[g][u]);
                 }
                 used += kGroupVoxels;
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < U; ++u) {
                 by[g][u] = iy0;
                 bz[g][u] = iz0;
                 buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? iz0 * slice + iy0 * xp : kPastEnd, 0);
@@ -609,7 +612,7 @@ __device__ __forceinline__ unsigned int ms_sweep(const VolDesc& v, BoxSet bs, in
         }
         const unsigned long long smr = (unsigned long long)((long long)sg * mr);
         const unsigned long long sms = (unsigned long long)((long long)sg * ms);
-        run_sweep(
+        run_sweep<kMsUnroll, kMsDepth>(
             L, w, used, limit,
             [&](uint32_t word, int iy0, int iz0) {
                 const unsigned long long step = (unsigned long long)(uint32_t)iy0 * smr + (unsigned long long)(uint32_t)iz0 * sms;
@@ -953,7 +956,7 @@ __device__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya,
     const int dy0 = ya + w.oy - cy, dz0 = za + w.oz - cz;
     int used = 0;
     unsigned int ops = 0;
-    run_sweep(
+    run_sweep<kQuadUnroll, kQuadDepth>(
         L, w, used, INT_MAX,
         [&](uint32_t word, int iy0, int iz0) {
             const int rr = max(max(abs(dy0 + iy0), abs(dz0 + iz0)) - base, 0);
@@ -1008,7 +1011,7 @@ __device__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz,
     char* hb = reinterpret_cast<char*>(hist);
     int used = 0;
     unsigned int ops = 0;
-    run_sweep(
+    run_sweep<kQuadUnroll, kQuadDepth>(
         L, w, used, INT_MAX,
         [&](uint32_t word, int iy0, int iz0) {
             const int dy = dy0 + iy0, dz = dz0 + iz0;
