@@ -11,7 +11,8 @@ Prints one JSON line.  Extra fields: volumes/s, per-method device times, the
 roofline of the dominant kernel (the mean-shift search) measured with HIP events
 on the launch stream (against the published HBM peak and the measured copy
 peak), both searches' LDS-atomic rates against measured LDS ceilings, the
-host-to-device copy of the volume (outside the timed step), the CPU oracle timed
+host-to-device copy of the volume (outside the timed step), the every-voxel
+saliency map against the seed-grid detection, the CPU oracle timed
 on a bounded sample, the uneven 64-volume batch (one captured launch sequence)
 against plain per-volume launches, and Poisson serving streams at several rates
 against a plain one-launch-per-volume loop with p50/p99 latency.
@@ -163,6 +164,34 @@ def serving_section(ks, torch, ctx, n_req):
     run_server(srv, sat[:16])
     out["small_budget"] = {"budget_bytes": small, "saturated": run_server(srv, sat)}
     srv.close()
+    return out
+
+
+def dense_section(ks, torch, ctx, q_detect_ms):
+    """The every-voxel Kadir-Brady map (the search the seed grid replaces) on the
+    spheres and PET-like volumes, against the seed-grid quadrant detection of the
+    same volume and scales: the seed grid's saving measured on this GPU."""
+    from paper_1310_6736_amd import synth
+
+    ks.ks_context_set_profiling(ctx, True)
+    out = {}
+    for w, det in ((synth.spheres_64(), None), (synth.pet_shell(ks.KS_QUADRANT), q_detect_ms)):
+        v = torch.from_numpy(w.volume).to("cuda:0")
+        ks.ks_saliency_map(ctx, v, w.bins, w.scales)
+        ts = []
+        for _ in range(3):
+            ks.ks_saliency_map(ctx, v, w.bins, w.scales)
+            ts.append(ks.ks_last_stats(ctx)["ms_search"])
+        if det is None:
+            dts = []
+            for _ in range(5):
+                ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=64)
+                dts.append(ks.ks_last_stats(ctx)["ms_total"])
+            det = float(np.median(dts))
+        m = float(np.median(ts))
+        out[w.name] = {"voxels": int(w.volume.size), "scales": list(w.scales), "map_ms": m,
+                       "seed_grid_detect_ms": det, "saving": m / det}
+    ks.ks_context_set_profiling(ctx, False)
     return out
 
 
@@ -338,6 +367,8 @@ def main():
         "h2d": dict(h2d, bytes=int(wq.volume.nbytes),
                     pcie_inclusive_window_evals_per_s=window_evals / (dt / args.steps + h2d["pinned_ms"] * 1e-3)),
     }
+    q_total = float(np.mean([s["ms_total"] for s in q_stats]))
+    line["dense_map"] = dense_section(ks, torch, ctx, q_total)
     if not args.no_batch:
         line["batch"] = batch_section(ks, torch, ctx)
     if not args.no_serve:

@@ -220,7 +220,20 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
                         void* out, void* stream);
 
 
-/* One request of a batch or of the server. */
+/* Dense Kadir-Brady saliency map (the every-voxel search that the seed grid
+ * replaces, Sec. 1 and Sec. 2.1): at every voxel of the device volume, the
+ * saliency step of the quadrant method with no search before it: centred cubes
+ * of half-width scales[0]-1 .. scales[1]+1, entropy peaks over scale in
+ * [scales[0], scales[1]], and the peak with the largest Y = H * W (first on
+ * ties, decisions in double as in ks_detect).  d_scale (uint8) receives s* or 0
+ * where there is no peak, d_saliency (float32) the saliency H * W at s* or 0;
+ * both are device arrays of X*Y*Z elements, x fastest, owned by the caller.
+ * Returns after the map is written.  Same validation as ks_detect with spacing
+ * 1; KS_E_INVALID for a null output. */
+ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
+                          const int32_t scales[2], float* d_saliency, uint8_t* d_scale, void* stream);
+
+/* One request of a batch or of the server. *//* One request of a batch or of the server. */
 typedef struct {
     const void* volume;    /* device pointer (ks_detect_batch) or host pointer (ks_server_submit) */
     int32_t dtype;         /* ks_dtype */

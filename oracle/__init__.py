@@ -71,6 +71,8 @@ def lib():
         L.kso_num_trajectories.restype = C.c_int64
         L.kso_run.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32,
                               C.c_double, C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(Stats)]
+        L.kso_saliency_map.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]
         L.kso_detect.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32,
                                  C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, i32p, C.POINTER(Stats)]
         _lib = L
@@ -171,6 +173,19 @@ def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_mi
 
 
 RANK_SALIENCY, RANK_PDF_CHANGE = 0, 1
+
+
+def saliency_map(vol: np.ndarray, bins, scales):
+    """Every-voxel Kadir-Brady map: (saliency float32, scale uint8, saliency64
+    float64), each shaped like vol; scale 0 and saliency 0 where there is no
+    entropy peak."""
+    vol = np.ascontiguousarray(vol)
+    sal = np.zeros(vol.shape, np.float32)
+    scl = np.zeros(vol.shape, np.uint8)
+    s64 = np.zeros(vol.shape, np.float64)
+    lib().kso_saliency_map(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, (C.c_int32 * 2)(*scales),
+                           sal.ctypes.data, scl.ctypes.data, s64.ctypes.data)
+    return sal, scl, s64
 
 
 def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=None, h_min=0.0, y_min=0.0,

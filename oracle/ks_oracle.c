@@ -418,6 +418,32 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
     return 0;
 }
 
+/* ----------------------------------------------------- dense saliency map */
+
+/* The every-voxel Kadir-Brady search (Sec. 1, Sec. 2.1): at every voxel the
+ * saliency step of the quadrant method (centred cubes of half-width
+ * s_min-1 .. s_max+1, entropy peaks, Y = H * W) with no search before it.
+ * Writes s* (0 when there is no peak) and the accurate saliency Y_ref = H_ref * W
+ * at s* (0 when there is no peak), x fastest. */
+int kso_saliency_map(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t scales[2],
+                     float* sal, uint8_t* scale, double* sal64) {
+    int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
+    uint8_t* bv = (uint8_t*)malloc((size_t)nv);
+    kso_bin_volume(vol, dtype, dims, bins, bv);
+    kso_stats st = {0, 0, 0};
+    for (int64_t i = 0; i < nv; ++i) {
+        int32_t p[3] = {(int32_t)(i % dims[0]), (int32_t)((i / dims[0]) % dims[1]),
+                        (int32_t)(i / ((int64_t)dims[0] * dims[1]))};
+        kso_traj t;
+        saliency(bv, dims, bins, p, KSO_QUADRANT, scales[0], scales[1], 0, 0.0, 0.0, &t, &st);
+        scale[i] = (uint8_t)t.scale;
+        sal[i] = (float)t.y_ref;
+        if (sal64) sal64[i] = t.y64;
+    }
+    free(bv);
+    return 0;
+}
+
 /* ------------------------------------------------------------- ranking */
 
 /* Order: rank key (decision precision) descending, then scale, z, y, x, seed

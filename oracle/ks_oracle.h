@@ -80,6 +80,12 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
             const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
             const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats);
 
+/* Dense Kadir-Brady map: at every voxel, s* of the saliency step of the quadrant
+ * method (0: no entropy peak) and the saliency at s* (sal: accurate Y_ref;
+ * sal64, if not NULL: decision-precision Y).  x fastest. */
+int kso_saliency_map(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t scales[2],
+                     float* sal, uint8_t* scale, double* sal64);
+
 /* Full detection: run every trajectory, keep those with H > h_min and Y > y_min,
  * dedup on (x, y, z, scale) and rank by rank_by (KSO_RANK_*) descending, ties by
  * scale, z, y, x ascending.  Writes min(capacity, n) regions; *n_found is the

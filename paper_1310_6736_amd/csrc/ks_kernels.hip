@@ -709,7 +709,7 @@ __device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int 
 
 // ----------------------------------------------------- task decoding, loop
 
-__device__ __forceinline__ int find_seg(const TaskSeg* segs, int nseg, long long t) {
+__device__ __forceinline__ int find_seg(const TaskSeg* __restrict__ segs, int nseg, long long t) {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -803,9 +803,10 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 // P*.  Every sweep of the kernel goes through the one ms_sweep call below, so
 // the scatter code is instantiated once.
 template <int M>
-__global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg,
-                                                  long long ntask, Tables tb, TrajRec* out, Counters* cnt,
-                                                  MsTune tune, int hist_words) {
+__global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols,
+                                                  const TaskSeg* __restrict__ segs, int nseg, long long ntask,
+                                                  Tables tb, TrajRec* out, Counters* cnt, MsTune tune,
+                                                  int hist_words) {
     extern __shared__ unsigned long long hist[];
     const int lane = threadIdx.x;
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
@@ -1292,9 +1293,10 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
 constexpr int kQuadThreads = 256;  // threads per trajectory (one workgroup)
 
 template <int M>
-__global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __restrict__ vols, const TaskSeg* segs, int nseg,
-                                                     long long ntask, Tables tb, TrajRec* out, Counters* cnt,
-                                                     int rq, LdsQuad lay) {
+__global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __restrict__ vols,
+                                                             const TaskSeg* __restrict__ segs, int nseg,
+                                                             long long ntask, Tables tb, TrajRec* out,
+                                                             Counters* cnt, int rq, LdsQuad lay) {
     extern __shared__ __align__(16) char smem[];
     __shared__ long long s_task;
     const int tid = threadIdx.x;
@@ -1335,6 +1337,155 @@ __global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __r
     }
     const unsigned long long ops = (unsigned long long)bfly_sumll((long long)lc.lds_ops);
     if ((tid & 63) == 0) atomicAdd(&cnt->lds_ops, ops);
+}
+
+// ------------------------------------------------------ dense saliency map
+//
+// The every-voxel Kadir-Brady search that the seed grid avoids (Sec. 1,
+// Sec. 2.1): at every voxel the centred cubes of half-width s_min-1 .. s_max+1,
+// their entropies, the entropy peaks over scale and Y = H * W at the best peak,
+// with the decision arithmetic of the quadrant method's final pass.  One
+// wavefront slides along an x row: it builds the cube histograms of the row's
+// first voxel, and for each next voxel takes column x - s out of and column
+// x + s + 1 into the histogram of every half-width s (a y-z square each, swept
+// along y in the y-fastest copy).
+
+// Adds delta (mod 2^32) to the u32 counter of every voxel's bin in the box, row
+// at byte offset rowoff; bytes outside the box go to the lane's trash word.
+__device__ __forceinline__ unsigned int map_box(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb,
+                                                uint32_t* hist, uint32_t rowoff, uint32_t trash, uint32_t delta,
+                                                int lane) {
+    xa = uniform(xa); xb = uniform(xb); ya = uniform(ya); yb = uniform(yb); za = uniform(za); zb = uniform(zb);
+    if (xa > xb || ya > yb || za > zb) return 0u;
+    const bool tr = xb - xa < yb - ya;
+    const Layout L = tr ? layout_t(v) : layout_x(v);
+    const Sweep w = tr ? make_sweep<64>(L, ya, yb, za, zb - za + 1, 1, xa, xb - xa + 1, 1, lane)
+                       : make_sweep<64>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, lane);
+    const int fa = tr ? ya : xa, fb = tr ? yb : xb;
+    uint32_t off[4], wid[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int f = w.x0 + k;
+        const bool ok = f >= fa && f <= fb;
+        off[k] = ok ? rowoff : trash;
+        wid[k] = ok ? 8u : 0u;
+    }
+    char* hb = reinterpret_cast<char*>(hist);
+    unsigned int ops = 0;
+    int used = 0;
+    run_sweep<kMsUnroll, kMsDepth>(
+        L, w, used, INT_MAX,
+        [&](uint32_t word, int, int) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t bin = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
+                atomicAdd(reinterpret_cast<uint32_t*>(hb + off[k] + (bin << 2)), delta);
+            }
+            ops += 4;
+        },
+        []() {});
+    return ops;
+}
+
+template <int M>
+__global__ __launch_bounds__(64) void k_saliency_map(const VolDesc* __restrict__ vols, Tables tb,
+                                                     float* __restrict__ sal, uint8_t* __restrict__ scl,
+                                                     Counters* cnt) {
+    extern __shared__ uint32_t hmap[];
+    const int lane = threadIdx.x;
+    const VolDesc& v = vols[0];
+    const int B = v.B, Bs = row_stride(B);
+    const int lo = v.s_min - 1, K = v.S + 2;  // rows: half-widths lo .. s_max + 1
+    const uint32_t trash = (uint32_t)(K * Bs + lane) << 2;
+    unsigned int ops = 0;
+    const long long rows = (long long)v.Y * v.Z;
+    for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % v.Y), z = (int)(r / v.Y);
+        for (int i = lane; i < K * Bs; i += 64) hmap[i] = 0u;
+        __syncthreads();
+        for (int i = 0; i < K; ++i) {
+            const int s = lo + i;
+            ops += map_box(v, 0, min(s, v.X - 1), max(y - s, 0), min(y + s, v.Y - 1), max(z - s, 0),
+                           min(z + s, v.Z - 1), hmap, (uint32_t)(i * Bs) << 2, trash, 1u, lane);
+        }
+        __syncthreads();
+        for (int x = 0; x < v.X; ++x) {
+            // entropies of every row, streaming: the peak test of half-width
+            // s - 1 runs once H(s) is known
+            int best = -1;
+            double bestY = 0.0;
+            double hA = 0.0, hB = 0.0;
+            long long aB = 0;
+            int64_t nA = 1, nB = 1;
+            for (int i = 0; i < K; ++i) {
+                const int s = lo + i;
+                const int64_t N = cube_count(v, x, y, z, s);
+                double cl[M];
+                long long am = 0;
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    const int b = lane * M + t;
+                    const uint32_t c = b < B ? hmap[i * Bs + b] : 0u;
+                    cl[t] = tb.cl[c];
+                    if (i > 0 && b < B) {
+                        const long long d = (long long)c * nB - (long long)hmap[(i - 1) * Bs + b] * N;
+                        am += d < 0 ? -d : d;
+                    }
+                }
+                const double H = (tb.cl[N] - bfly_sum(local_pw<M>(cl))) / (double)N;
+                const long long A = i > 0 ? bfly_sumll(am) : 0ll;
+                if (i >= 2) {
+                    const int sp = s - 1;
+                    if (hB > hA && hB > H) {
+                        const double W = ((double)(sp * sp) / (double)(2 * sp - 1)) *
+                                         ((double)aB / ((double)nB * (double)nA));
+                        const double Y = hB * W;
+                        if (best < 0 || Y > bestY) { best = sp; bestY = Y; }
+                    }
+                }
+                hA = hB; hB = H; aB = A; nA = nB; nB = N;
+            }
+            float y32 = 0.0f;
+            if (best >= 0) {
+                const int rb = best - lo;
+                const int64_t N = cube_count(v, x, y, z, best), Np = cube_count(v, x, y, z, best - 1);
+                long long am = 0;
+                float h = 0.0f;
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    const int b = lane * M + t;
+                    if (b < B) {
+                        const uint32_t c = hmap[rb * Bs + b];
+                        h += entropy_term32((int)c, N);
+                        const long long d = (long long)c * Np - (long long)hmap[(rb - 1) * Bs + b] * N;
+                        am += d < 0 ? -d : d;
+                    }
+                }
+                const float h32 = bfly_sumf(h);
+                const long long A = bfly_sumll(am);
+                const float w32 = ((float)(best * best) / (float)(2 * best - 1)) * ((float)A / ((float)N * (float)Np));
+                y32 = h32 * w32;
+            }
+            if (lane == 0) {
+                const int64_t idx = (int64_t)x + (int64_t)v.X * ((int64_t)y + (int64_t)v.Y * z);
+                sal[idx] = y32;
+                scl[idx] = (uint8_t)(best < 0 ? 0 : best);
+            }
+            __syncthreads();
+            if (x + 1 < v.X) {
+                for (int i = 0; i < K; ++i) {
+                    const int s = lo + i;
+                    const int ya = max(y - s, 0), yb = min(y + s, v.Y - 1), za = max(z - s, 0), zb = min(z + s, v.Z - 1);
+                    const uint32_t ro = (uint32_t)(i * Bs) << 2;
+                    if (x - s >= 0) ops += map_box(v, x - s, x - s, ya, yb, za, zb, hmap, ro, trash, 0xFFFFFFFFu, lane);
+                    if (x + 1 + s < v.X) ops += map_box(v, x + 1 + s, x + 1 + s, ya, yb, za, zb, hmap, ro, trash, 1u, lane);
+                }
+                __syncthreads();
+            }
+        }
+    }
+    const unsigned long long tot = (unsigned long long)bfly_sumll((long long)ops);
+    if (lane == 0) atomicAdd(&cnt->lds_ops, tot);
 }
 
 // ------------------------------------------------------------ test hooks
@@ -1751,6 +1902,27 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_emit, dim3(grid_for((long long)n_pad, 256, 4096)), dim3(256), 0, st, sorted, a.cnt, a.grank,
                        a.vol_base, a.vols, a.rec, a.regions);
     return hipGetLastError();
+}
+
+hipError_t launch_saliency_map(const VolDesc* vols, Tables tb, float* sal, uint8_t* scl, Counters* cnt, int K, int B,
+                               int grid, hipStream_t st) {
+    const size_t lds = ((size_t)K * (size_t)(B | 1) + 64) * 4;
+    const int M = bins_per_lane_host(B);
+    if (M == 1) hipLaunchKernelGGL(k_saliency_map<1>, dim3(grid), dim3(64), lds, st, vols, tb, sal, scl, cnt);
+    else if (M == 2) hipLaunchKernelGGL(k_saliency_map<2>, dim3(grid), dim3(64), lds, st, vols, tb, sal, scl, cnt);
+    else hipLaunchKernelGGL(k_saliency_map<4>, dim3(grid), dim3(64), lds, st, vols, tb, sal, scl, cnt);
+    return hipGetLastError();
+}
+
+int max_blocks_map(int K, int B) {
+    int nb = 0;
+    const size_t lds = ((size_t)K * (size_t)(B | 1) + 64) * 4;
+    const int M = bins_per_lane_host(B);
+    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_saliency_map<1>, 64, lds)
+                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_saliency_map<2>, 64, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_saliency_map<4>, 64, lds);
+    if (e != hipSuccess) return 1;
+    return nb < 1 ? 1 : nb;
 }
 
 int max_blocks_ms(int hist_words, int maxB) {

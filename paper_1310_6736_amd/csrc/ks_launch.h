@@ -66,6 +66,10 @@ hipError_t launch_search_ms(const SearchArgs& a, int grid, const MsTune& tune, i
 hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, int maxB, hipStream_t st);
 hipError_t launch_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc, int rl, int hist_words,
                           int maxB, void* out, hipStream_t st);
+// Dense Kadir-Brady map of vols[0]: K = S + 2 histogram rows of B bins per wave.
+hipError_t launch_saliency_map(const VolDesc* vols, Tables tb, float* sal, uint8_t* scl, Counters* cnt, int K, int B,
+                               int grid, hipStream_t st);
+int max_blocks_map(int K, int B);
 hipError_t launch_hook_quad(const VolDesc* vols, int kind, int lo, int hi, int n, const int* xyz, int rq,
                             const LdsQuad& lay, uint32_t* out, hipStream_t st);
 hipError_t launch_rank(const RankArgs& a, hipStream_t st);

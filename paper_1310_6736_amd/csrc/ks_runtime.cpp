@@ -755,6 +755,51 @@ ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     return KS_OK;
 }
 
+ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
+                          const int32_t scales[2], float* d_saliency, uint8_t* d_scale, void* stream) {
+    if (!ctx || !d_saliency || !d_scale) return KS_E_INVALID;
+    ks_status s = check_request(d_volume, dtype, dims, bins, 1, scales, KS_QUADRANT, 0);
+    if (s != KS_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
+    // prep as for a mean-shift volume (the map's column sweeps read the y-fast copy)
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = 1 << 20; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = KS_MEANSHIFT;
+    v.max_iter = 0; v.capacity = 0;
+    Plan p;
+    if ((s = ctx->plan({v}, p)) != KS_OK) return s;
+    if ((s = ctx->upload(p, st)) != KS_OK) return s;
+    PrepArgs pa;
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
+    if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[0], st));
+    if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
+    const int K = scales[1] - scales[0] + 3;
+    const long long rows = (long long)dims[1] * dims[2];
+    const int grid = (int)std::min<long long>(rows, (long long)max_blocks_map(K, bins) * ctx->num_cu);
+    if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[1], st));
+    if (launch_saliency_map(static_cast<VolDesc*>(ctx->d_vols.ptr), ctx->tables, d_saliency, d_scale,
+                            static_cast<Counters*>(ctx->d_cnt.ptr), K, bins, grid, st) != hipSuccess)
+        return KS_E_DEVICE;
+    if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[2], st));
+    Counters c;
+    if (hipMemcpyAsync(&c, ctx->d_cnt.ptr, sizeof(Counters), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return KS_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
+    std::memset(&ctx->last, 0, sizeof(ctx->last));
+    ctx->last.trajectories = (int64_t)dims[0] * dims[1] * dims[2];
+    ctx->last.lds_ops = (int64_t)c.lds_ops;
+    if (ctx->profiling) {
+        float a = 0, b = 0;
+        hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]);
+        hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]);
+        ctx->last.ms_prep = a; ctx->last.ms_search = b; ctx->last.ms_total = a + b;
+    }
+    return KS_OK;
+}
+
 ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
                         int32_t kind, const int32_t range[2], int32_t n, const int32_t* xyz, const int32_t* scale,
                         void* out, void* stream) {

@@ -26,7 +26,7 @@ EXPORTS = [
     "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
-    "ks_context_set_ms_update", "ks_context_set_options",
+    "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map",
 ]
 
 
@@ -104,6 +104,7 @@ def lib():
     L.ks_context_set_tuning_small.argtypes = [vp, i32, i32]
     L.ks_context_set_ms_update.argtypes = [vp, i32]
     L.ks_context_set_options.argtypes = [vp, C.POINTER(Options)]
+    L.ks_saliency_map.argtypes = [vp, vp, i32, C.POINTER(C.c_int32), i32, C.POINTER(C.c_int32), vp, vp, vp]
     L.ks_last_stats.argtypes = [vp, C.POINTER(RunStats)]
     L.ks_detect.argtypes = [vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p]
     L.ks_detect_device.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p, vp]
@@ -216,6 +217,19 @@ def ks_context_set_profiling(ctx: Context, on: bool):
 
 def ks_context_set_tuning(ctx: Context, ms_replicas_log2: int, quad_replicas_log2: int):
     _check(lib().ks_context_set_tuning(ctx.handle, ms_replicas_log2, quad_replicas_log2), "ks_context_set_tuning")
+
+
+def ks_saliency_map(ctx: Context, volume, bins, scales, stream=None):
+    """Dense Kadir-Brady map of a device volume (torch tensor (Z, Y, X)): returns
+    (saliency float32, scale uint8) device tensors of the same shape."""
+    import torch
+
+    ptr, dt, dims = _volume_args(volume)
+    sal = torch.empty(tuple(volume.shape), dtype=torch.float32, device=volume.device)
+    scl = torch.empty(tuple(volume.shape), dtype=torch.uint8, device=volume.device)
+    _check(lib().ks_saliency_map(ctx.handle, ptr, dt, dims, bins, _i2(scales), C.c_void_p(sal.data_ptr()),
+                                 C.c_void_p(scl.data_ptr()), _stream_ptr(stream)), "ks_saliency_map")
+    return sal, scl
 
 
 def ks_context_set_options(ctx: Context, opts=None):

@@ -435,3 +435,44 @@ def test_stats_meanshift_swept_voxels(torch_dev, ctx):
         assert st[f] == fresh[f], f
     assert fresh["voxel_visits"] < fresh["swept_voxels"] < fresh["voxel_visits"] + fresh["final_visits"]
     assert st["swept_voxels"] < 0.7 * fresh["swept_voxels"]
+
+
+# ---------------------------------------------------------- dense saliency map
+
+MAP_CASES = [
+    ("blocks_u8", np.uint8, (17, 21, 26), 16, (2, 4)),
+    ("blocks_u16_b64", np.uint16, (13, 19, 23), 64, (1, 3)),
+    ("thin_i16", np.int16, (3, 29, 31), 32, (2, 5)),
+    ("scale_past_volume", np.uint8, (9, 8, 11), 32, (5, 7)),
+    ("b256", np.uint8, (11, 12, 14), 256, (2, 3)),
+]
+
+
+@pytest.mark.parametrize("case", MAP_CASES, ids=[c[0] for c in MAP_CASES])
+def test_saliency_map_matches_oracle(torch_dev, ctx, case):
+    """Every voxel: s* bit-identical to the oracle's every-voxel search, float32
+    saliency within 1e-5 of the accurate value and 0 exactly where it is 0."""
+    name, dt, shape, bins, scales = case
+    note(f"saliency map {name} {shape} B={bins} s={scales}")
+    hi = 255 if dt == np.uint8 else 3000
+    v = random_volume(zlib.crc32(name.encode()) % 1000, shape, dt, 0, hi)
+    sal, scl = ks.ks_saliency_map(ctx, dev(torch_dev, v), bins, scales)
+    torch_dev.cuda.synchronize()
+    w_sal, w_scl, _ = oracle.saliency_map(v, bins, scales)
+    got_scl = scl.cpu().numpy()
+    assert np.array_equal(got_scl, w_scl), int((got_scl != w_scl).sum())
+    assert close32(sal.cpu().numpy().ravel(), w_sal.astype(np.float64).ravel())
+    assert (w_scl > 0).sum() > 0
+
+
+def test_saliency_map_spheres64(torch_dev, ctx):
+    """The 64^3 spheres volume at its scales 3..8: the whole map against the
+    oracle's whole map (about 7 s of CPU)."""
+    w = synth.spheres_64()
+    note("saliency map spheres64")
+    sal, scl = ks.ks_saliency_map(ctx, dev(torch_dev, w.volume), w.bins, w.scales)
+    torch_dev.cuda.synchronize()
+    got_scl, got_sal = scl.cpu().numpy(), sal.cpu().numpy()
+    full_sal, full_scl, _ = oracle.saliency_map(w.volume, w.bins, w.scales)
+    assert np.array_equal(got_scl, full_scl), int((got_scl != full_scl).sum())
+    assert close32(got_sal.ravel(), full_sal.astype(np.float64).ravel())

@@ -470,3 +470,33 @@ def test_rank_by_pdf_change_orders_the_same_regions_by_w(method):
     order = sorted(by_w, key=lambda r: (-r["pdf_change"], r["scale"], r["z"], r["y"], r["x"]))
     assert [key(r) for r in order] == [key(r) for r in by_w]
     assert [key(r) for r in by_y] != [key(r) for r in by_w]
+
+
+def test_saliency_map_equals_every_voxel_search():
+    """The dense map is the every-voxel search: at each voxel it equals the
+    trajectory of a spacing-1, zero-iteration quadrant run (scale, Y64), and the
+    numpy brute force (scale exactly, Y64 to 1e-12 away from near-ties)."""
+    rng = np.random.default_rng(13)
+    vol = np.clip(rng.normal(40, 4, (10, 12, 14)), 0, 255).astype(np.uint8)
+    vol[3:8, 4:9, 5:11] = rng.integers(0, 256, (5, 5, 6))
+    bins, scales = 16, (2, 4)
+    sal, scl, s64 = oracle.saliency_map(vol, bins, scales)
+    tr, _ = oracle.run(vol, bins, 1, scales, 0, 0)
+    assert np.array_equal(scl.ravel(), tr["scale"].astype(np.uint8))
+    assert np.array_equal(s64.ravel(), np.where(tr["scale"] > 0, tr["y64"], 0.0))
+    assert np.allclose(sal.ravel(), np.where(tr["scale"] > 0, tr["y_ref"], 0.0), rtol=1e-6, atol=0)
+    assert (scl > 0).sum() > 10
+    bv = oracle.bin_volume(vol, bins)
+    dense = bf.dense_kb(bv, bins, scales[0], scales[1])
+    checked = 0
+    for z in range(vol.shape[0]):
+        for y in range(vol.shape[1]):
+            for x in range(vol.shape[2]):
+                want = dense.get((x, y, z))
+                if want is None:
+                    assert scl[z, y, x] == 0
+                elif not want[4]:
+                    assert scl[z, y, x] == want[0]
+                    assert abs(s64[z, y, x] - want[3]) <= 1e-12 * max(1.0, abs(want[3]))
+                    checked += 1
+    assert checked > 10
