@@ -69,12 +69,16 @@ def lib():
                                          C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
         L.kso_num_trajectories.argtypes = [i32p, C.c_int32, i32p, C.c_int32]
         L.kso_num_trajectories.restype = C.c_int64
-        L.kso_run.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32,
-                              C.c_double, C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(Stats)]
-        L.kso_saliency_map.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_void_p, C.c_void_p,
-                                       C.c_void_p]
-        L.kso_detect.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32,
-                                 C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, i32p, C.POINTER(Stats)]
+        L.kso_run.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32,
+                              C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_int64, C.c_void_p,
+                              C.POINTER(Stats)]
+        L.kso_saliency_map.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, i32p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+        L.kso_bin_volume_window.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, C.c_int32, C.c_int32,
+                                            C.c_void_p]
+        L.kso_detect.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32,
+                                 C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, i32p,
+                                 C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -91,11 +95,21 @@ def _dims(vol: np.ndarray):
 _DT = {np.dtype(np.uint8): 0, np.dtype(np.uint16): 1, np.dtype(np.int16): 2}
 
 
-def bin_volume(vol: np.ndarray, bins: int) -> np.ndarray:
+def bin_volume(vol: np.ndarray, bins: int, window=None) -> np.ndarray:
+    """Bin volume; with window = (lo, hi) the window-level binning (voxels outside
+    get the value `bins`, ignored by every histogram)."""
     vol = np.ascontiguousarray(vol)
     out = np.empty(vol.shape, np.uint8)
-    lib().kso_bin_volume(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, out.ctypes.data)
+    if window is None:
+        lib().kso_bin_volume(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, out.ctypes.data)
+    else:
+        lib().kso_bin_volume_window(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, int(window[0]),
+                                    int(window[1]), out.ctypes.data)
     return out
+
+
+def _win(window):
+    return None if window is None else (C.c_int32 * 2)(int(window[0]), int(window[1]))
 
 
 def entropy64(counts) -> float:
@@ -153,7 +167,7 @@ def num_trajectories(dims, spacing, scales, method) -> int:
 TRAJ_FIELDS = [f[0] for f in Traj._fields_]
 
 
-def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_min=0.0, y_min=0.0):
+def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_min=0.0, y_min=0.0, window=None):
     """Run trajectories (all, or the listed ids).  Returns (structured array, stats dict)."""
     vol = np.ascontiguousarray(vol)
     z, y, x = vol.shape
@@ -166,8 +180,8 @@ def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_mi
         idp = ids.ctypes.data
     out = (Traj * max(n, 1))()
     st = Stats()
-    lib().kso_run(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, spacing, (C.c_int32 * 2)(*scales), method,
-                  max_iter, h_min, y_min, idp, n, out, C.byref(st))
+    lib().kso_run(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window), spacing,
+                  (C.c_int32 * 2)(*scales), method, max_iter, h_min, y_min, idp, n, out, C.byref(st))
     arr = np.ctypeslib.as_array(out)[:n].copy()
     return arr, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}
 
@@ -175,7 +189,7 @@ def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_mi
 RANK_SALIENCY, RANK_PDF_CHANGE = 0, 1
 
 
-def saliency_map(vol: np.ndarray, bins, scales):
+def saliency_map(vol: np.ndarray, bins, scales, window=None):
     """Every-voxel Kadir-Brady map: (saliency float32, scale uint8, saliency64
     float64), each shaped like vol; scale 0 and saliency 0 where there is no
     entropy peak."""
@@ -183,13 +197,13 @@ def saliency_map(vol: np.ndarray, bins, scales):
     sal = np.zeros(vol.shape, np.float32)
     scl = np.zeros(vol.shape, np.uint8)
     s64 = np.zeros(vol.shape, np.float64)
-    lib().kso_saliency_map(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, (C.c_int32 * 2)(*scales),
-                           sal.ctypes.data, scl.ctypes.data, s64.ctypes.data)
+    lib().kso_saliency_map(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window),
+                           (C.c_int32 * 2)(*scales), sal.ctypes.data, scl.ctypes.data, s64.ctypes.data)
     return sal, scl, s64
 
 
 def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=None, h_min=0.0, y_min=0.0,
-           rank_by=RANK_SALIENCY):
+           rank_by=RANK_SALIENCY, window=None):
     """Full detection; returns (structured array of regions, n_found, stats dict)."""
     vol = np.ascontiguousarray(vol)
     z, y, x = vol.shape
@@ -198,7 +212,8 @@ def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=No
     out = (Region * max(capacity, 1))()
     nf = C.c_int32()
     st = Stats()
-    lib().kso_detect(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, spacing, (C.c_int32 * 2)(*scales), method,
-                     max_iter, h_min, y_min, rank_by, out, capacity, C.byref(nf), C.byref(st))
+    lib().kso_detect(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window), spacing,
+                     (C.c_int32 * 2)(*scales), method, max_iter, h_min, y_min, rank_by, out, capacity, C.byref(nf),
+                     C.byref(st))
     arr = np.ctypeslib.as_array(out)[:min(capacity, nf.value)].copy()
     return arr, nf.value, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}

@@ -66,6 +66,26 @@ static double sum_octants(const double* e) { return ((e[0] + e[1]) + (e[2] + e[3
 
 /* ---------------------------------------------------------------- binning */
 
+/* Window-level binning (Sec. 3.2: entropy over the intensity range of the
+ * structure of interest): voxels in [lo, hi] get ((v - lo) * bins) / (hi - lo + 1),
+ * voxels outside get the value `bins`, which every histogram below ignores. */
+int kso_bin_volume_window(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t lo,
+                          int32_t hi, uint8_t* out) {
+    int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+    int64_t width = (int64_t)hi - lo + 1;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = read_voxel(vol, dtype, i);
+        out[i] = (v < lo || v > hi) ? (uint8_t)bins : (uint8_t)(((v - lo) * bins) / width);
+    }
+    return 0;
+}
+
+static void bin_any(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                    uint8_t* out) {
+    if (window) kso_bin_volume_window(vol, dtype, dims, bins, window[0], window[1], out);
+    else kso_bin_volume(vol, dtype, dims, bins, out);
+}
+
 int kso_bin_volume(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, uint8_t* out) {
     int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
     int32_t vmin = read_voxel(vol, dtype, 0), vmax = vmin;
@@ -120,7 +140,8 @@ double kso_entropy_ref(const uint32_t* counts, int32_t bins) { return entropy_re
 
 /* ---------------------------------------------------------------- windows */
 
-/* Counts of bins in the box [x0,x1]x[y0,y1]x[z0,z1] clipped to the volume. */
+/* Counts of bins in the box [x0,x1]x[y0,y1]x[z0,z1] clipped to the volume; voxels
+ * outside a window level (value >= bins) are not counted.  Returns the count. */
 static int64_t box_hist(const uint8_t* bv, const int32_t dims[3], int32_t bins, int32_t x0, int32_t x1, int32_t y0,
                         int32_t y1, int32_t z0, int32_t z1, uint32_t* c) {
     memset(c, 0, sizeof(uint32_t) * (size_t)bins);
@@ -132,7 +153,9 @@ static int64_t box_hist(const uint8_t* bv, const int32_t dims[3], int32_t bins, 
     for (int32_t z = z0; z <= z1; ++z)
         for (int32_t y = y0; y <= y1; ++y)
             for (int32_t x = x0; x <= x1; ++x) {
-                c[bv[vidx(dims, x, y, z)]] += 1;
+                int32_t b = bv[vidx(dims, x, y, z)];
+                if (b >= bins) continue;
+                c[b] += 1;
                 n += 1;
             }
     return n;
@@ -230,6 +253,7 @@ int kso_eval_meanshift(const uint8_t* bv, const int32_t dims[3], int32_t bins, c
             for (int32_t x = p[0] - s; x <= p[0] + s; ++x) {
                 if (x < 0 || y < 0 || z < 0 || x >= dims[0] || y >= dims[1] || z >= dims[2]) continue;
                 int32_t b = bv[vidx(dims, x, y, z)];
+                if (b >= bins) continue;
                 counts[b] += 1;
                 msum[3 * b + 0] += x - p[0];
                 msum[3 * b + 1] += y - p[1];
@@ -255,6 +279,7 @@ int kso_eval_meanshift(const uint8_t* bv, const int32_t dims[3], int32_t bins, c
 /* pdf change between scales s-1 and s: s^2/(2s-1) * sum_b |c_s/N_s - c_{s-1}/N_{s-1}|,
  * the numerator taken exactly as sum_b |c_s N_{s-1} - c_{s-1} N_s|. */
 static double pdf_change(const uint32_t* cs, int64_t Ns, const uint32_t* cp, int64_t Np, int32_t bins, int32_t s) {
+    if (Ns == 0 || Np == 0) return 0.0;  /* only with a window level: no counted voxel */
     int64_t A = 0;
     for (int32_t b = 0; b < bins; ++b) {
         int64_t d = (int64_t)cs[b] * Np - (int64_t)cp[b] * Ns;
@@ -382,12 +407,12 @@ static void run_trajectory(eval_ctx* e, int32_t max_iter, const int32_t p0[3], i
     t->objective = obj;
 }
 
-int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
-            const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+            int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
             const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats) {
     int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
     uint8_t* bv = (uint8_t*)malloc((size_t)nv);
-    kso_bin_volume(vol, dtype, dims, bins, bv);
+    bin_any(vol, dtype, dims, bins, window, bv);
     int32_t g[3], o[3];
     grid_dims(dims, spacing, g, o);
     int32_t S = scales[1] - scales[0] + 1;
@@ -425,11 +450,11 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
  * s_min-1 .. s_max+1, entropy peaks, Y = H * W) with no search before it.
  * Writes s* (0 when there is no peak) and the accurate saliency Y_ref = H_ref * W
  * at s* (0 when there is no peak), x fastest. */
-int kso_saliency_map(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t scales[2],
-                     float* sal, uint8_t* scale, double* sal64) {
+int kso_saliency_map(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                     const int32_t scales[2], float* sal, uint8_t* scale, double* sal64) {
     int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
     uint8_t* bv = (uint8_t*)malloc((size_t)nv);
-    kso_bin_volume(vol, dtype, dims, bins, bv);
+    bin_any(vol, dtype, dims, bins, window, bv);
     kso_stats st = {0, 0, 0};
     for (int64_t i = 0; i < nv; ++i) {
         int32_t p[3] = {(int32_t)(i % dims[0]), (int32_t)((i / dims[0]) % dims[1]),
@@ -461,12 +486,12 @@ static int region_cmp(const void* pa, const void* pb) {
     return 0;
 }
 
-int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
-               const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+               int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
                int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
     int64_t n = kso_num_trajectories(dims, spacing, scales, method);
     kso_traj* t = (kso_traj*)malloc(sizeof(kso_traj) * (size_t)n);
-    kso_run(vol, dtype, dims, bins, spacing, scales, method, max_iter, h_min, y_min, NULL, 0, t, stats);
+    kso_run(vol, dtype, dims, bins, window, spacing, scales, method, max_iter, h_min, y_min, NULL, 0, t, stats);
     kso_region* r = (kso_region*)malloc(sizeof(kso_region) * (size_t)(n > 0 ? n : 1));
     int64_t m = 0;
     for (int64_t i = 0; i < n; ++i) {

@@ -53,6 +53,11 @@ typedef struct {
 
 /* Step 1 of the search: intensity -> bin index (the paper's beta(s), Eq. 4). */
 int kso_bin_volume(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, uint8_t* out);
+/* Window-level binning (Sec. 3.2): voxels in [lo, hi] -> ((v - lo) * bins) /
+ * (hi - lo + 1); voxels outside -> the value `bins`, which every histogram
+ * ignores (it is not counted, and N is the count of the voxels that are). */
+int kso_bin_volume_window(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t lo,
+                          int32_t hi, uint8_t* out);
 
 /* Entropies of one count vector: decision precision (H64) and accurate (Href). */
 double kso_entropy64(const uint32_t* counts, int32_t bins);
@@ -75,23 +80,24 @@ int kso_eval_meanshift(const uint8_t* bv, const int32_t dims[3], int32_t bins, c
 /* Number of trajectories of a search. */
 int64_t kso_num_trajectories(const int32_t dims[3], int32_t spacing, const int32_t scales[2], int32_t method);
 
-/* Run the trajectories listed in ids[0..n) (all when ids == NULL, n ignored). */
-int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
-            const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+/* Run the trajectories listed in ids[0..n) (all when ids == NULL, n ignored).
+ * window: NULL, or {lo, hi} for window-level binning. */
+int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+            int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
             const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats);
 
 /* Dense Kadir-Brady map: at every voxel, s* of the saliency step of the quadrant
  * method (0: no entropy peak) and the saliency at s* (sal: accurate Y_ref;
  * sal64, if not NULL: decision-precision Y).  x fastest. */
-int kso_saliency_map(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t scales[2],
-                     float* sal, uint8_t* scale, double* sal64);
+int kso_saliency_map(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                     const int32_t scales[2], float* sal, uint8_t* scale, double* sal64);
 
 /* Full detection: run every trajectory, keep those with H > h_min and Y > y_min,
  * dedup on (x, y, z, scale) and rank by rank_by (KSO_RANK_*) descending, ties by
  * scale, z, y, x ascending.  Writes min(capacity, n) regions; *n_found is the
  * total. */
-int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, int32_t spacing,
-               const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+               int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
                int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats);
 
 #ifdef __cplusplus

@@ -21,8 +21,9 @@ def clipped(bv: np.ndarray, lo, hi):
 
 
 def cube_counts(bv, bins, p, s):
+    """Counts of bins 0..bins-1; values >= bins (outside a window level) are dropped."""
     sub, _ = clipped(bv, [p[0] - s, p[1] - s, p[2] - s], [p[0] + s, p[1] + s, p[2] + s])
-    return np.bincount(sub.ravel(), minlength=bins)
+    return np.bincount(sub.ravel(), minlength=bins + 1)[:bins]
 
 
 def octant_counts(bv, bins, p, j, k):
@@ -33,7 +34,7 @@ def octant_counts(bv, bins, p, j, k):
         else:
             lo.append(p[a] - k); hi.append(p[a])
     sub, _ = clipped(bv, lo, hi)
-    return np.bincount(sub.ravel(), minlength=bins)
+    return np.bincount(sub.ravel(), minlength=bins + 1)[:bins]
 
 
 def H(counts) -> float:
@@ -44,6 +45,8 @@ def H(counts) -> float:
 
 
 def W(c_s, c_prev, s) -> float:
+    if np.sum(c_s) == 0 or np.sum(c_prev) == 0:
+        return 0.0
     p = np.asarray(c_s, np.float64) / np.sum(c_s)
     q = np.asarray(c_prev, np.float64) / np.sum(c_prev)
     return float(s * s / (2 * s - 1) * np.abs(p - q).sum())
@@ -57,10 +60,12 @@ def meanshift_step_literal(bv, bins, p, s):
     zz, yy, xx = np.meshgrid(np.arange(sub.shape[0]) + l[2], np.arange(sub.shape[1]) + l[1],
                              np.arange(sub.shape[2]) + l[0], indexing="ij")
     b = sub.ravel()
+    keep = b < bins  # voxels outside a window level do not take part
+    b = b[keep]
     pb = np.bincount(b, minlength=bins) / b.size
     q = 1.0 / bins
     w = np.sqrt(q / pb[b])
-    pos = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1).astype(np.float64)
+    pos = np.stack([xx.ravel()[keep], yy.ravel()[keep], zz.ravel()[keep]], axis=1).astype(np.float64)
     x_new = (w[:, None] * pos).sum(axis=0) / w.sum()
     rho = float(np.sqrt(pb * q).sum())
     return x_new - np.asarray(p, np.float64), rho

@@ -500,3 +500,74 @@ def test_saliency_map_equals_every_voxel_search():
                     assert abs(s64[z, y, x] - want[3]) <= 1e-12 * max(1.0, abs(want[3]))
                     checked += 1
     assert checked > 10
+
+
+# ------------------------------------------------- window level (Sec. 3.2)
+
+def test_window_binning():
+    """Window-level binning: the window [vmin, vmax] reproduces the plain binning;
+    voxels outside a window get the value B; inside, every bin covers an
+    equal-width interval of the window."""
+    rng = np.random.default_rng(21)
+    v = rng.integers(-900, 1400, (7, 9, 11)).astype(np.int16)
+    for bins in (7, 32, 64):
+        assert np.array_equal(oracle.bin_volume(v, bins, window=(int(v.min()), int(v.max()))),
+                              oracle.bin_volume(v, bins))
+    lo, hi, bins = -100, 499, 40
+    bv = oracle.bin_volume(v, bins, window=(lo, hi))
+    inside = (v >= lo) & (v <= hi)
+    assert np.all(bv[~inside] == bins) and np.all(bv[inside] < bins)
+    vals = np.arange(lo, hi + 1, dtype=np.int16).reshape(1, 1, -1)
+    bvals = oracle.bin_volume(vals, bins, window=(lo, hi)).ravel()
+    assert np.all(np.diff(bvals.astype(int)) >= 0) and bvals[0] == 0 and bvals[-1] == bins - 1
+    widths = np.bincount(bvals, minlength=bins)
+    assert widths.min() == widths.max() == (hi - lo + 1) // bins
+
+
+def test_window_histograms_and_meanshift_ignore_voxels_outside():
+    """Histograms count only the voxels inside the window level (np.bincount of
+    the masked slice); the mean-shift move and Bhattacharyya coefficient equal
+    the literal Eq. 5/6 over those voxels; a window holding none gives H = 0 and
+    no move."""
+    rng = np.random.default_rng(22)
+    v = rng.integers(0, 4096, (12, 13, 14)).astype(np.uint16)
+    bins, win = 24, (1000, 2999)
+    bv = oracle.bin_volume(v, bins, window=win)
+    for p, s in [((3, 4, 5), 2), ((0, 0, 0), 3), ((13, 12, 11), 4), ((7, 6, 5), 1)]:
+        want = bf.cube_counts(bv, bins, p, s)
+        assert np.array_equal(oracle.hist_cube(bv, bins, p, s), want)
+        counts, msum, delta, rho = oracle.eval_meanshift(bv, bins, p, s)
+        assert np.array_equal(counts, want)
+        d_lit, rho_lit = bf.meanshift_step_literal(bv, bins, p, s)
+        assert np.allclose(delta, d_lit, atol=1e-12) and abs(rho / np.sqrt(bins) - rho_lit) < 1e-12
+    empty = np.full((5, 5, 5), 10, np.uint8)
+    bv0 = oracle.bin_volume(empty, 16, window=(100, 200))
+    counts, _, delta, rho = oracle.eval_meanshift(bv0, 16, (2, 2, 2), 2)
+    assert counts.sum() == 0 and rho == 0.0 and np.all(delta == 0.0)
+    assert oracle.entropy64(counts) == 0.0
+
+
+def test_windowed_every_voxel_search_matches_brute_force():
+    """The dense search with a window level equals the numpy brute force over the
+    masked histograms (s* exactly, Y to 1e-12 away from near-ties)."""
+    rng = np.random.default_rng(23)
+    vol = np.clip(rng.normal(60, 6, (10, 12, 13)), 0, 255).astype(np.uint8)
+    vol[2:8, 3:9, 4:10] = rng.integers(0, 256, (6, 6, 6))
+    bins, scales, win = 16, (2, 4), (40, 200)
+    sal, scl, s64 = oracle.saliency_map(vol, bins, scales, window=win)
+    bv = oracle.bin_volume(vol, bins, window=win)
+    dense = bf.dense_kb(bv, bins, scales[0], scales[1])
+    checked = 0
+    for z in range(vol.shape[0]):
+        for y in range(vol.shape[1]):
+            for x in range(vol.shape[2]):
+                want = dense.get((x, y, z))
+                if want is None:
+                    assert scl[z, y, x] == 0
+                elif not want[4]:
+                    assert scl[z, y, x] == want[0]
+                    assert abs(s64[z, y, x] - want[3]) <= 1e-12 * max(1.0, abs(want[3]))
+                    checked += 1
+    assert checked > 10
+    plain = oracle.saliency_map(vol, bins, scales)[1]
+    assert not np.array_equal(plain, scl)
