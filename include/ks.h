@@ -114,7 +114,14 @@ enum { KS_RANK_SALIENCY = 0, KS_RANK_PDF_CHANGE = 1 };
 typedef struct {
     double h_min, y_min;
     int32_t rank_by;
-    int32_t reserved;      /* 0 */
+    /* Window level (Sec. 3.2: entropy over the intensity range of the structure
+     * of interest).  window = 1: voxels with win_lo <= v <= win_hi are binned
+     * over that range, ((v - win_lo) * bins) / (win_hi - win_lo + 1); voxels
+     * outside take part in no histogram, and N is the count of those that do (a
+     * window with none has H = 0, no move and W = 0).  Needs bins <= 255.
+     * window = 0: the volume's own range (default). */
+    int32_t window;
+    int32_t win_lo, win_hi;
 } ks_options;
 
 typedef struct ks_context ks_context;
@@ -146,8 +153,10 @@ ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas
 
 /* Options for the context's later ks_detect_device and ks_seed_traces calls
  * (ks_detect always uses the defaults; batch and server requests carry their
- * own).  NULL restores the defaults.  KS_E_INVALID for an unknown rank_by, a
- * non-zero reserved field or a NaN threshold. */
+ * own); the window level also applies to the context's ks_saliency_map,
+ * ks_bin_volume and ks_histograms calls.  NULL restores the defaults.
+ * KS_E_INVALID for an unknown rank_by or window flag, win_lo > win_hi or a NaN
+ * threshold (and, at the call, a window level with bins > 255). */
 ks_status ks_context_set_options(ks_context* ctx, const ks_options* options);
 
 /* Running-window updates of the mean-shift search (Sec. 2.3 evaluates Eq. 4-6 on

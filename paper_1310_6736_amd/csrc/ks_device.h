@@ -40,6 +40,8 @@ struct VolDesc {
     int64_t slice;          // xp * Y
     int32_t yp, pad2;       // y pitch of bins_t (multiple of 16)
     int64_t slice_t;        // yp * Z
+    int32_t win;            // 1: window-level binning over [win_lo, win_hi]; voxels outside get bin B
+    int32_t win_lo, win_hi, pad3;
     int32_t dtype, B, sp, s_min, s_max, method, max_iter;
     int32_t gx, gy, gz, ox, oy, oz;  // seed grid
     int32_t S;              // s_max - s_min + 1

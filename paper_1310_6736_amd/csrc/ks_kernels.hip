@@ -93,9 +93,10 @@ __device__ __forceinline__ double local_pw(const double* v) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Row stride (in counters) of the shell-bucketed histograms: odd, so that equal
-// bins of neighbouring rows fall in different LDS banks.
-__device__ __forceinline__ int row_stride(int B) { return B | 1; }
+// Row stride (in counters) of the shell-bucketed histograms: room for bin B (the
+// voxels outside a window level, never read) and odd, so that equal bins of
+// neighbouring rows fall in different LDS banks.
+__device__ __forceinline__ int row_stride(int B) { return (B + 1) | 1; }
 
 __device__ __forceinline__ int64_t clipped_len(int c, int r, int n) {
     int lo = c - r < 0 ? 0 : c - r;
@@ -290,13 +291,16 @@ __global__ __launch_bounds__(256) void k_minmax(const VolDesc* vols) {
     }
 }
 
-// bin = floor((v - vmin) * B / (vmax - vmin + 1)); 4 voxels of a padded row per thread.
+// bin = floor((v - vmin) * B / (vmax - vmin + 1)), or over a window level (Sec.
+// 3.2) with B for the voxels outside it; 4 voxels of a padded row per thread.
 __global__ __launch_bounds__(256) void k_quantize(const VolDesc* vols) {
     const VolDesc& v = vols[blockIdx.y];
     const int qx = v.xp >> 2;
     const int64_t n = (int64_t)qx * v.Y * v.Z;
     const int vmin = v.minmax[0];
-    const uint32_t width = (uint32_t)(v.minmax[1] - vmin + 1);
+    // window level: voxels outside [win_lo, win_hi] get bin B (never counted)
+    const int lo = v.win ? v.win_lo : vmin;
+    const uint32_t width = v.win ? (uint32_t)(v.win_hi - v.win_lo + 1) : (uint32_t)(v.minmax[1] - vmin + 1);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t row = i / qx;
         int x0 = (int)(i - row * qx) * 4;
@@ -308,8 +312,10 @@ __global__ __launch_bounds__(256) void k_quantize(const VolDesc* vols) {
         for (int k = 0; k < 4; ++k) {
             int x = x0 + k;
             if (x < v.X) {
-                uint32_t d = (uint32_t)(read_raw(v.raw, v.dtype, base + x) - vmin);
-                word |= ((d * (uint32_t)v.B) / width) << (8 * k);
+                const int r = read_raw(v.raw, v.dtype, base + x);
+                const uint32_t d = (uint32_t)(r - lo);
+                const uint32_t b = (v.win && (r < v.win_lo || r > v.win_hi)) ? (uint32_t)v.B : (d * (uint32_t)v.B) / width;
+                word |= b << (8 * k);
             }
         }
         *reinterpret_cast<uint32_t*>(v.bins + row * v.xp + x0) = word;
@@ -633,6 +639,15 @@ struct EvalOut {
     double obj, dx, dy, dz;
 };
 
+// N of a window under a window level: the voxels counted in bins 0..B-1.
+template <int M>
+__device__ __forceinline__ int64_t window_total(const int* c) {
+    long long n = 0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) n += c[t];
+    return (int64_t)bfly_sumll(n);
+}
+
 // Eq. 4-6 with a flat kernel and the uniform target: move = (sum_b M_b/sqrt(c_b)) /
 // (sum_b sqrt(c_b)), objective rho~ = (sum_b sqrt(c_b)) / sqrt(N), from the
 // window totals (f = sums of d + s).
@@ -652,9 +667,9 @@ __device__ EvalOut ms_moments(const VolDesc& v, const Tables& tb, int px, int py
     const double nx = bfly_sum(local_pw<M>(tx));
     const double ny = bfly_sum(local_pw<M>(ty));
     const double nzs = bfly_sum(local_pw<M>(tz));
-    const int64_t N = cube_count(v, px, py, pz, s);
+    const int64_t N = v.win ? window_total<M>(a.c) : cube_count(v, px, py, pz, s);
     EvalOut e;
-    e.obj = D / tb.sq[N];
+    e.obj = N > 0 ? D / tb.sq[N] : 0.0;
     e.dx = D > 0.0 ? nx / D : 0.0;
     e.dy = D > 0.0 ? ny / D : 0.0;
     e.dz = D > 0.0 ? nzs / D : 0.0;
@@ -679,8 +694,8 @@ __device__ __forceinline__ float entropy_term32(int c, int64_t N) {
 template <int M>
 __device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, const int* cs,
                                 const int* cin) {
-    const int64_t Ns = cube_count(v, px, py, pz, s);
-    const int64_t Np = cube_count(v, px, py, pz, s - 1);
+    const int64_t Ns = v.win ? window_total<M>(cs) : cube_count(v, px, py, pz, s);
+    const int64_t Np = v.win ? window_total<M>(cin) : cube_count(v, px, py, pz, s - 1);
     double cl[M];
     long long am = 0;
     float h = 0.0f;
@@ -694,15 +709,17 @@ __device__ Saliency ms_saliency(const VolDesc& v, const Tables& tb, int px, int 
     const double S = bfly_sum(local_pw<M>(cl));
     const long long A = bfly_sumll(am);
     const float H32 = bfly_sumf(h);
-    const double H64 = (tb.cl[Ns] - S) / (double)Ns;
-    const double W64 = ((double)(s * s) / (double)(2 * s - 1)) * ((double)A / ((double)Ns * (double)Np));
+    // with a window level a window may count no voxel: H = 0, W = 0
+    const double H64 = Ns > 0 ? (tb.cl[Ns] - S) / (double)Ns : 0.0;
+    const bool wok = Ns > 0 && Np > 0;
+    const double W64 = wok ? ((double)(s * s) / (double)(2 * s - 1)) * ((double)A / ((double)Ns * (double)Np)) : 0.0;
     Saliency r;
     r.scale = s;
     r.y64 = H64 * W64;
     r.w64 = W64;
     r.keep = (H64 > v.h_min && r.y64 > v.y_min) ? 1 : 0;
     r.h32 = H32;
-    r.w32 = ((float)(s * s) / (float)(2 * s - 1)) * ((float)A / ((float)Ns * (float)Np));
+    r.w32 = wok ? ((float)(s * s) / (float)(2 * s - 1)) * ((float)A / ((float)Ns * (float)Np)) : 0.0f;
     r.y32 = r.h32 * r.w32;
     return r;
 }
@@ -1083,6 +1100,7 @@ struct QuadLds {
     double* eps;     // [8][S]
     double* hrow;    // [S+2]
     long long* arow; // [S+2]
+    long long* nrow; // [S+2] counted voxels of each centred cube
     float* h32row;   // [S+2]
     double* res;     // [4]
 };
@@ -1093,6 +1111,7 @@ __device__ __forceinline__ QuadLds quad_lds(char* smem, const LdsQuad& L) {
     q.eps = reinterpret_cast<double*>(smem + L.eps_off);
     q.hrow = reinterpret_cast<double*>(smem + L.hrow_off);
     q.arow = reinterpret_cast<long long*>(smem + L.arow_off);
+    q.nrow = reinterpret_cast<long long*>(smem + L.nrow_off);
     q.h32row = reinterpret_cast<float*>(smem + L.h32_off);
     q.res = reinterpret_cast<double*>(smem + L.res_off);
     return q;
@@ -1100,22 +1119,25 @@ __device__ __forceinline__ QuadLds quad_lds(char* smem, const LdsQuad& L) {
 
 // Entropy H64 = (cl[N] - sum_b cl[c_b]) / N of merged rows; wave w takes rows
 // w, w + NW, ..., kRowBatch at a time so that their table loads are in flight
-// together; N of a row from nrow(g, r).  The replica-0 counters read here are
+// together; N of a row from nrow(g, r), or (win) the row's counted voxels, and
+// H = 0 for a row that counts none.  The replica-0 counters read here are
 // cleared.
 constexpr int kRowBatch = 8;
 
 template <int NT, int M, typename NF>
 __device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows, int B, int rq, const Tables& tb,
-                                             NF&& nrow, double* out, int tid) {
+                                             NF&& nrow, bool win, double* out, int tid) {
     const int wave = tid >> 6, lane = tid & 63;
     const int rows_total = nrows + 1;
     const int nq = nreg * nrows;
     for (int q0 = wave; q0 < nq; q0 += kRowBatch * (NT / 64)) {
         double v[kRowBatch][M];
+        int cn[kRowBatch];
 #pragma unroll
         for (int i = 0; i < kRowBatch; ++i) {
             const int q = q0 + i * (NT / 64);
             const int g = q / nrows, r = q - g * nrows;
+            cn[i] = 0;
 #pragma unroll
             for (int t = 0; t < M; ++t) {
                 const int b = lane * M + t;
@@ -1126,16 +1148,18 @@ __device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows
                     hist[e] = 0u;
                 }
                 v[i][t] = tb.cl[c];
+                cn[i] += (int)c;
             }
         }
 #pragma unroll
         for (int i = 0; i < kRowBatch; ++i) {
             const int q = q0 + i * (NT / 64);
             const double S = bfly_sum(local_pw<M>(v[i]));
+            const long long wn = win ? bfly_sumll((long long)cn[i]) : 0ll;
             if (lane == 0 && q < nq) {
                 const int g = q / nrows, r = q - g * nrows;
-                const int64_t N = nrow(g, r);
-                out[q] = (tb.cl[N] - S) / (double)N;
+                const int64_t N = win ? (int64_t)wn : nrow(g, r);
+                out[q] = N > 0 ? (tb.cl[N] - S) / (double)N : 0.0;
             }
         }
     }
@@ -1161,7 +1185,7 @@ __device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py,
             const int rz = (j & 4) ? v.Z - 1 - pz : pz;
             return (int64_t)(min(k, rx) + 1) * (min(k, ry) + 1) * (min(k, rz) + 1);
         },
-        L.eps, tid);
+        v.win != 0, L.eps, tid);
     __syncthreads();
     if (tid < 64) {
         // lane j < 8 scans octant j over k (first maximum); lane 0 combines
@@ -1219,12 +1243,28 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
     __syncthreads();
     bucket_merge<NT>(L.hist, 1, nrows, B, rq, tid);
     __syncthreads();
+    // N of every centred cube: its in-volume voxels, or with a window level the
+    // voxels it counts
+    for (int r = wave; r < nrows; r += NT / 64) {
+        long long n = 0;
+        if (v.win) {
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                const int b = lane * M + t;
+                if (b < B) n += merged(L.hist, 0, nrows + 1, r, B, b, rq);
+            }
+            n = bfly_sumll(n);
+        } else {
+            n = cube_count(v, px, py, pz, base + r);
+        }
+        if (lane == 0) L.nrow[r] = n;
+    }
+    __syncthreads();
     // pdf change numerators and float entropies need the counts: read them before
     // rows_entropy clears them
     for (int r = wave; r < nrows; r += NT / 64) {
-        const int s = base + r;
-        const int64_t N = cube_count(v, px, py, pz, s);
-        const int64_t Np = r > 0 ? cube_count(v, px, py, pz, s - 1) : 1;
+        const int64_t N = L.nrow[r];
+        const int64_t Np = r > 0 ? L.nrow[r - 1] : 1;
         long long a = 0;
         float h = 0.0f;
 #pragma unroll
@@ -1248,7 +1288,7 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
     }
     __syncthreads();
     rows_entropy<NT, M>(
-        L.hist, 1, nrows, B, rq, tb, [&](int, int r) { return cube_count(v, px, py, pz, base + r); }, L.hrow, tid);
+        L.hist, 1, nrows, B, rq, tb, [&](int, int r) { return (int64_t)L.nrow[r]; }, false, L.hrow, tid);
     __syncthreads();
     if (tid == 0) {
         int best = -1;
@@ -1256,9 +1296,12 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
         for (int s = v.s_min; s <= v.s_max; ++s) {
             const int r = s - base;
             if (!(L.hrow[r] > L.hrow[r - 1] && L.hrow[r] > L.hrow[r + 1])) continue;
-            const int64_t N = cube_count(v, px, py, pz, s);
-            const int64_t Np = cube_count(v, px, py, pz, s - 1);
-            const double W = ((double)(s * s) / (double)(2 * s - 1)) * ((double)L.arow[r] / ((double)N * (double)Np));
+            const int64_t N = L.nrow[r];
+            const int64_t Np = L.nrow[r - 1];
+            // a peak has H > 0, so N > 0; with a window level the smaller cube may count none
+            const double W = Np > 0 ? ((double)(s * s) / (double)(2 * s - 1)) *
+                                          ((double)L.arow[r] / ((double)N * (double)Np))
+                                    : 0.0;
             const double Y = L.hrow[r] * W;
             if (best < 0 || Y > bestY) { best = s; bestY = Y; }
         }
@@ -1275,12 +1318,13 @@ __device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, in
     out.h32 = out.w32 = out.y32 = 0.0f;
     if (best >= 0) {
         const int r = best - base;
-        const int64_t N = cube_count(v, px, py, pz, best);
-        const int64_t Np = cube_count(v, px, py, pz, best - 1);
+        const int64_t N = L.nrow[r];
+        const int64_t Np = L.nrow[r - 1];
         const long long A = L.arow[r];
-        out.w64 = ((double)(best * best) / (double)(2 * best - 1)) * ((double)A / ((double)N * (double)Np));
+        const bool wok = N > 0 && Np > 0;
+        out.w64 = wok ? ((double)(best * best) / (double)(2 * best - 1)) * ((double)A / ((double)N * (double)Np)) : 0.0;
         out.h32 = L.h32row[r];
-        out.w32 = ((float)(best * best) / (float)(2 * best - 1)) * ((float)A / ((float)N * (float)Np));
+        out.w32 = wok ? ((float)(best * best) / (float)(2 * best - 1)) * ((float)A / ((float)N * (float)Np)) : 0.0f;
         out.y32 = out.h32 * out.w32;
         out.keep = (L.hrow[r] > v.h_min && out.y64 > v.y_min) ? 1 : 0;
     }
@@ -1419,26 +1463,36 @@ __global__ __launch_bounds__(64) void k_saliency_map(const VolDesc* __restrict__
             int64_t nA = 1, nB = 1;
             for (int i = 0; i < K; ++i) {
                 const int s = lo + i;
-                const int64_t N = cube_count(v, x, y, z, s);
+                uint32_t cc[M];
+                long long nsum = 0;
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    const int b = lane * M + t;
+                    cc[t] = b < B ? hmap[i * Bs + b] : 0u;
+                    nsum += cc[t];
+                }
+                // N: the cube's in-volume voxels, or with a window level the voxels it counts
+                const int64_t N = v.win ? (int64_t)bfly_sumll(nsum) : cube_count(v, x, y, z, s);
                 double cl[M];
                 long long am = 0;
 #pragma unroll
                 for (int t = 0; t < M; ++t) {
                     const int b = lane * M + t;
-                    const uint32_t c = b < B ? hmap[i * Bs + b] : 0u;
-                    cl[t] = tb.cl[c];
+                    cl[t] = tb.cl[cc[t]];
                     if (i > 0 && b < B) {
-                        const long long d = (long long)c * nB - (long long)hmap[(i - 1) * Bs + b] * N;
+                        const long long d = (long long)cc[t] * nB - (long long)hmap[(i - 1) * Bs + b] * N;
                         am += d < 0 ? -d : d;
                     }
                 }
-                const double H = (tb.cl[N] - bfly_sum(local_pw<M>(cl))) / (double)N;
+                const double S = bfly_sum(local_pw<M>(cl));
+                const double H = N > 0 ? (tb.cl[N] - S) / (double)N : 0.0;
                 const long long A = i > 0 ? bfly_sumll(am) : 0ll;
                 if (i >= 2) {
                     const int sp = s - 1;
                     if (hB > hA && hB > H) {
-                        const double W = ((double)(sp * sp) / (double)(2 * sp - 1)) *
-                                         ((double)aB / ((double)nB * (double)nA));
+                        const double W = nA > 0 ? ((double)(sp * sp) / (double)(2 * sp - 1)) *
+                                                      ((double)aB / ((double)nB * (double)nA))
+                                                : 0.0;
                         const double Y = hB * W;
                         if (best < 0 || Y > bestY) { best = sp; bestY = Y; }
                     }
@@ -1448,7 +1502,20 @@ __global__ __launch_bounds__(64) void k_saliency_map(const VolDesc* __restrict__
             float y32 = 0.0f;
             if (best >= 0) {
                 const int rb = best - lo;
-                const int64_t N = cube_count(v, x, y, z, best), Np = cube_count(v, x, y, z, best - 1);
+                int64_t N = cube_count(v, x, y, z, best), Np = cube_count(v, x, y, z, best - 1);
+                if (v.win) {
+                    long long n0 = 0, n1 = 0;
+#pragma unroll
+                    for (int t = 0; t < M; ++t) {
+                        const int b = lane * M + t;
+                        if (b < B) {
+                            n0 += hmap[rb * Bs + b];
+                            n1 += hmap[(rb - 1) * Bs + b];
+                        }
+                    }
+                    N = (int64_t)bfly_sumll(n0);
+                    Np = (int64_t)bfly_sumll(n1);
+                }
                 long long am = 0;
                 float h = 0.0f;
 #pragma unroll
@@ -1463,7 +1530,9 @@ __global__ __launch_bounds__(64) void k_saliency_map(const VolDesc* __restrict__
                 }
                 const float h32 = bfly_sumf(h);
                 const long long A = bfly_sumll(am);
-                const float w32 = ((float)(best * best) / (float)(2 * best - 1)) * ((float)A / ((float)N * (float)Np));
+                const float w32 = Np > 0 ? ((float)(best * best) / (float)(2 * best - 1)) *
+                                               ((float)A / ((float)N * (float)Np))
+                                         : 0.0f;
                 y32 = h32 * w32;
             }
             if (lane == 0) {

@@ -18,7 +18,7 @@ struct ks_region_dev {
 
 // Byte offsets of the quadrant kernel's dynamic LDS.
 struct LdsQuad {
-    size_t hist_off, eps_off, hrow_off, arow_off, h32_off, res_off, bytes;
+    size_t hist_off, eps_off, hrow_off, arow_off, nrow_off, h32_off, res_off, bytes;
     int hist_words;
     int pad;
 };

@@ -29,8 +29,10 @@ static bool dims_ok(const int32_t* d) {
 
 bool options_ok(const ks_options& o) {
     return o.h_min == o.h_min && o.y_min == o.y_min && (o.rank_by == KS_RANK_SALIENCY || o.rank_by == KS_RANK_PDF_CHANGE) &&
-           o.reserved == 0;
+           (o.window == 0 || (o.window == 1 && o.win_lo <= o.win_hi));
 }
+
+bool options_fit(const ks_options& o, int32_t bins) { return o.window == 0 || bins <= 255; }
 
 ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
                         const int32_t* scales, int32_t method, int32_t max_iter) {
@@ -185,7 +187,7 @@ static unsigned long long next_pow2(unsigned long long n) {
 // same-address LDS atomics; fewer, cheaper merges).
 int pick_ms_rl(int maxB, int pref) {
     int rl = pref;
-    while (rl > 2 && ((size_t)maxB * ((size_t)1 << rl) + 64) * 8 > 36 * 1024) --rl;
+    while (rl > 2 && (((size_t)maxB + 1) * ((size_t)1 << rl) + 64) * 8 > 36 * 1024) --rl;
     return rl;
 }
 
@@ -195,7 +197,7 @@ LdsQuad quad_layout(int maxS, int maxB, int rq) {
     LdsQuad L;
     size_t off = 0;
     L.hist_off = off;
-    L.hist_words = (int)(8 * ((size_t)maxS + 1) * ((size_t)maxB | 1) * ((size_t)1 << rq));
+    L.hist_words = (int)(8 * ((size_t)maxS + 1) * (((size_t)maxB + 1) | 1) * ((size_t)1 << rq));
     off += (size_t)L.hist_words * 4;
     off = (off + 15) & ~(size_t)15;
     L.eps_off = off;
@@ -203,6 +205,8 @@ LdsQuad quad_layout(int maxS, int maxB, int rq) {
     L.hrow_off = off;
     off += (size_t)(maxS + 2) * 8;
     L.arow_off = off;
+    off += (size_t)(maxS + 2) * 8;
+    L.nrow_off = off;
     off += (size_t)(maxS + 2) * 8;
     L.h32_off = off;
     off += (size_t)(maxS + 2) * 4;
@@ -247,6 +251,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         v.traj_base = traj;
         v.n_traj = num_trajectories(r.dims, r.spacing, r.scales, r.method);
         v.h_min = r.opt.h_min; v.y_min = r.opt.y_min; v.rank_by = r.opt.rank_by;
+        v.win = r.opt.window; v.win_lo = r.opt.win_lo; v.win_hi = r.opt.win_hi;
         v.reg_off = regs;
         v.cap = r.capacity;
         bins_off[i] = bins_total;
@@ -338,7 +343,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     p.rq = pick_quad_rq(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), quad_rq_pref);
     p.lay = quad_layout(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), p.rq);
     // bins of the larger layout plus one trash slot per replica
-    p.ms_hist_words = (std::max(p.maxB_ms, 2) << std::max(p.rl, p.rl_small)) + 64;
+    p.ms_hist_words = ((std::max(p.maxB_ms, 2) + 1) << std::max(p.rl, p.rl_small)) + 64;
     return KS_OK;
 }
 
@@ -656,6 +661,7 @@ ks_status ks_detect_device(ks_context* ctx, const void* d_volume, ks_dtype dtype
     v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
     v.max_iter = max_iter; v.capacity = capacity;
     v.opt = ctx->opts;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
     std::vector<std::vector<ks_region>> res;
     std::vector<int> nf;
     s = ctx->detect_volumes({v}, static_cast<hipStream_t>(stream), &res, &nf);
@@ -706,6 +712,7 @@ ks_status ks_seed_traces(ks_context* ctx, const void* d_volume, ks_dtype dtype, 
     v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
     v.max_iter = max_iter; v.capacity = 0;
     v.opt = ctx->opts;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
     Plan p;
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
@@ -739,6 +746,8 @@ ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     VolIn v;
     v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
     v.spacing = 1 << 20; v.scales[0] = 1; v.scales[1] = 1; v.method = KS_QUADRANT; v.max_iter = 0; v.capacity = 0;
+    v.opt.window = ctx->opts.window; v.opt.win_lo = ctx->opts.win_lo; v.opt.win_hi = ctx->opts.win_hi;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
     Plan p;
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
@@ -767,6 +776,8 @@ ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype,
     v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
     v.spacing = 1 << 20; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = KS_MEANSHIFT;
     v.max_iter = 0; v.capacity = 0;
+    v.opt.window = ctx->opts.window; v.opt.win_lo = ctx->opts.win_lo; v.opt.win_hi = ctx->opts.win_hi;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
     Plan p;
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
@@ -825,6 +836,8 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
     v.spacing = 1 << 20; v.scales[0] = 1; v.scales[1] = 1;
     v.method = per_window ? KS_MEANSHIFT : KS_QUADRANT; v.max_iter = 0; v.capacity = 0;
+    v.opt.window = ctx->opts.window; v.opt.win_lo = ctx->opts.win_lo; v.opt.win_hi = ctx->opts.win_hi;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
     Plan p;
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
@@ -854,8 +867,8 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if (per_window) {
         const int rl = pick_ms_rl(bins, ctx->ms_rl_pref);
         const int hook_kind = kind == KS_HIST_CUBE ? 0 : kind == KS_HIST_MEANSHIFT ? 1 : kind == KS_HIST_MS_MOVE ? 2 : 3;
-        e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), hook_kind, n, dxyz, dsc, rl, (bins << rl) + 64,
-                           bins, ctx->d_hook_out.ptr, st);
+        e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), hook_kind, n, dxyz, dsc, rl,
+                           ((bins + 1) << rl) + 64, bins, ctx->d_hook_out.ptr, st);
     } else {
         const int rq = pick_quad_rq(K, bins, ctx->quad_rq_pref);
         const LdsQuad lay = quad_layout(K, bins, rq);
@@ -877,7 +890,7 @@ ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks
         ks_status s = check_request(r.volume, r.dtype, r.dims, r.bins, r.seed_spacing, r.scales, r.method, r.max_iter);
         if (s != KS_OK) return s;
         if (results[i].capacity < 0 || (results[i].capacity > 0 && !results[i].regions)) return KS_E_INVALID;
-        if (!options_ok(r.options)) return KS_E_INVALID;
+        if (!options_ok(r.options) || !options_fit(r.options, r.bins)) return KS_E_INVALID;
         VolIn& v = in[(size_t)i];
         v.raw = r.volume; v.dtype = r.dtype; std::memcpy(v.dims, r.dims, sizeof(v.dims)); v.bins = r.bins;
         v.spacing = r.seed_spacing; v.scales[0] = r.scales[0]; v.scales[1] = r.scales[1]; v.method = r.method;

@@ -98,7 +98,8 @@ struct Context {
                                  std::vector<std::vector<ks_region>>* out, std::vector<int>* nfound);
 };
 
-bool options_ok(const ks_options& o);  // thresholds not NaN, known rank key
+bool options_ok(const ks_options& o);  // thresholds not NaN, known rank key, window lo <= hi
+bool options_fit(const ks_options& o, int32_t bins);  // a window level needs bins <= 255
 ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
                         const int32_t* scales, int32_t method, int32_t max_iter);
 int64_t num_trajectories(const int32_t* dims, int32_t spacing, const int32_t* scales, int32_t method);

@@ -300,7 +300,7 @@ ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket
     ks_status st = ks::check_request(req->volume, req->dtype, req->dims, req->bins, req->seed_spacing, req->scales,
                                      req->method, req->max_iter);
     if (st != KS_OK) return st;
-    if (!ks::options_ok(req->options)) return KS_E_INVALID;
+    if (!ks::options_ok(req->options) || !ks::options_fit(req->options, req->bins)) return KS_E_INVALID;
     SrvReq r;
     r.in.raw = nullptr;
     r.in.dtype = req->dtype;

@@ -56,12 +56,15 @@ class RunStats(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("h_min", C.c_double), ("y_min", C.c_double), ("rank_by", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("h_min", C.c_double), ("y_min", C.c_double), ("rank_by", C.c_int32), ("window", C.c_int32),
+                ("win_lo", C.c_int32), ("win_hi", C.c_int32)]
 
 
-def options(h_min=0.0, y_min=0.0, rank_by=0) -> Options:
+def options(h_min=0.0, y_min=0.0, rank_by=0, window=None) -> Options:
+    """Selection and binning options; window = (lo, hi) for a window level."""
     o = Options()
-    o.h_min, o.y_min, o.rank_by, o.reserved = float(h_min), float(y_min), int(rank_by), 0
+    o.h_min, o.y_min, o.rank_by = float(h_min), float(y_min), int(rank_by)
+    o.window, o.win_lo, o.win_hi = (0, 0, 0) if window is None else (1, int(window[0]), int(window[1]))
     return o
 
 

@@ -377,14 +377,23 @@ def test_detect_options_match_oracle(torch_dev, ctx, method, case):
 
 
 def test_options_are_validated(torch_dev, ctx):
-    for bad in (ks.options(rank_by=2), ks.options(h_min=float("nan"))):
+    for bad in (ks.options(rank_by=2), ks.options(h_min=float("nan")), ks.options(window=(10, 9))):
         with pytest.raises(ks.KsError) as e:
             ks.ks_context_set_options(ctx, bad)
         assert e.value.status == ks.KS_E_INVALID
     bad = ks.options()
-    bad.reserved = 1
+    bad.window = 2
     with pytest.raises(ks.KsError):
         ks.ks_context_set_options(ctx, bad)
+    # a window level needs bins <= 255 (bin value 255 marks the voxels outside)
+    v = dev(torch_dev, random_volume(3, (8, 9, 10), np.uint8, 0, 255))
+    ks.ks_context_set_options(ctx, ks.options(window=(10, 200)))
+    try:
+        with pytest.raises(ks.KsError) as e:
+            ks.ks_detect_device(ctx, v, 256, 3, (1, 2), ks.KS_QUADRANT, 5)
+        assert e.value.status == ks.KS_E_INVALID
+    finally:
+        ks.ks_context_set_options(ctx, None)
 
 
 def test_detect_host_entry_point(torch_dev):
@@ -476,3 +485,80 @@ def test_saliency_map_spheres64(torch_dev, ctx):
     full_sal, full_scl, _ = oracle.saliency_map(w.volume, w.bins, w.scales)
     assert np.array_equal(got_scl, full_scl), int((got_scl != full_scl).sum())
     assert close32(got_sal.ravel(), full_sal.astype(np.float64).ravel())
+
+
+# ------------------------------------------------- window level (Sec. 3.2)
+
+WINDOW_CASES = [
+    ("u16_pet_window", np.uint16, (21, 26, 31), 32, (1000, 2999)),
+    ("i16_narrow", np.int16, (13, 17, 29), 48, (-200, 199)),
+    ("u8_empty_corners", np.uint8, (19, 23, 24), 16, (100, 180)),
+]
+
+
+def windowed_volume(name, dt, shape):
+    hi = 255 if dt == np.uint8 else 3000
+    lo = -900 if dt == np.int16 else 0
+    return random_volume(zlib.crc32(name.encode()) % 1000, shape, dt, lo, hi)
+
+
+@pytest.mark.parametrize("case", WINDOW_CASES, ids=[c[0] for c in WINDOW_CASES])
+def test_window_level_binning_and_histograms(torch_dev, ctx, case):
+    name, dt, shape, bins, win = case
+    note(f"window hooks {name}")
+    v = windowed_volume(name, dt, shape)
+    bv = oracle.bin_volume(v, bins, window=win)
+    pts = positions(v.shape, 12, 5)
+    sc = np.random.default_rng(2).integers(1, 9, len(pts)).astype(np.int32)
+    ks.ks_context_set_options(ctx, ks.options(window=win))
+    try:
+        assert np.array_equal(ks.ks_bin_volume(ctx, dev(torch_dev, v), bins), bv)
+        cube = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_CUBE, pts, sc)
+        ms = ks.ks_histograms(ctx, dev(torch_dev, v), bins, ks.KS_HIST_MEANSHIFT, pts, sc)
+    finally:
+        ks.ks_context_set_options(ctx, None)
+    for i, p in enumerate(pts):
+        counts, msum, _, _ = oracle.eval_meanshift(bv, bins, p, int(sc[i]))
+        assert np.array_equal(cube[i], counts), (i, p)
+        assert np.array_equal(ms[i, 0], counts.astype(np.int32)), (i, p)
+        assert np.array_equal(ms[i, 1:].T, msum.astype(np.int32)), (i, p)
+
+
+@pytest.mark.parametrize("method", [ks.KS_QUADRANT, ks.KS_MEANSHIFT])
+@pytest.mark.parametrize("case", WINDOW_CASES, ids=[c[0] for c in WINDOW_CASES])
+def test_window_level_traces_and_detection(torch_dev, ctx, case, method):
+    """Traces and ranked detections with a window level equal the oracle's."""
+    name, dt, shape, bins, win = case
+    note(f"window traces {name} method={method}")
+    v = windowed_volume(name, dt, shape)
+    sp, scales, iters = 4, (2, 5), 20
+    t = dev(torch_dev, v)
+    ks.ks_context_set_options(ctx, ks.options(window=win))
+    try:
+        got = ks.ks_seed_traces(ctx, t, bins, sp, scales, method, iters)
+        regs, n = ks.ks_detect_device(ctx, t, bins, sp, scales, method, iters, capacity=4096)
+    finally:
+        ks.ks_context_set_options(ctx, None)
+    want, _ = oracle.run(v, bins, sp, scales, method, iters, window=win)
+    compare_traces(got, want, f"{name} window")
+    wreg, wn, _ = oracle.detect(v, bins, sp, scales, method, iters, capacity=4096, window=win)
+    compare_regions(regs, n, wreg, wn, f"{name} window")
+    req = ks.make_request(t, bins, sp, scales, method, iters, opts=ks.options(window=win))
+    (bg, bn), = ks.ks_detect_batch(ctx, [req], capacity=4096)
+    assert bn == n and np.array_equal(bg, regs)
+
+
+@pytest.mark.parametrize("case", WINDOW_CASES, ids=[c[0] for c in WINDOW_CASES])
+def test_window_level_saliency_map(torch_dev, ctx, case):
+    name, dt, shape, bins, win = case
+    note(f"window map {name}")
+    v = windowed_volume(name, dt, shape)
+    ks.ks_context_set_options(ctx, ks.options(window=win))
+    try:
+        sal, scl = ks.ks_saliency_map(ctx, dev(torch_dev, v), bins, (2, 4))
+        torch_dev.cuda.synchronize()
+    finally:
+        ks.ks_context_set_options(ctx, None)
+    w_sal, w_scl, _ = oracle.saliency_map(v, bins, (2, 4), window=win)
+    assert np.array_equal(scl.cpu().numpy(), w_scl)
+    assert close32(sal.cpu().numpy().ravel(), w_sal.astype(np.float64).ravel())
