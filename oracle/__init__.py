@@ -79,6 +79,11 @@ def lib():
         L.kso_detect.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32,
                                  C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, i32p,
                                  C.POINTER(Stats)]
+        L.kso_run_seeded.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_void_p, C.c_int64, i32p,
+                                     C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_void_p, C.POINTER(Stats)]
+        L.kso_detect_seeded.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_void_p, C.c_int64, i32p,
+                                        C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_void_p,
+                                        C.c_int32, i32p, C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -167,10 +172,30 @@ def num_trajectories(dims, spacing, scales, method) -> int:
 TRAJ_FIELDS = [f[0] for f in Traj._fields_]
 
 
-def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_min=0.0, y_min=0.0, window=None):
-    """Run trajectories (all, or the listed ids).  Returns (structured array, stats dict)."""
+def _seeds(seeds):
+    a = np.ascontiguousarray(np.asarray(seeds, dtype=np.int32).reshape(-1, 3))
+    return a, a.shape[0]
+
+
+def run(vol: np.ndarray, bins, spacing, scales, method, max_iter, ids=None, h_min=0.0, y_min=0.0, window=None,
+        seeds=None):
+    """Run trajectories (all, or the listed ids), from the seed grid or, with
+    seeds = [(x, y, z), ...], from those positions.  Returns (structured array,
+    stats dict)."""
     vol = np.ascontiguousarray(vol)
     z, y, x = vol.shape
+    if seeds is not None:
+        if ids is not None:
+            raise ValueError("ids and seeds are exclusive")
+        sa, ns = _seeds(seeds)
+        n = ns * (scales[1] - scales[0] + 1 if method == MEANSHIFT else 1)
+        out = (Traj * max(n, 1))()
+        st = Stats()
+        if lib().kso_run_seeded(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window), sa.ctypes.data, ns,
+                                (C.c_int32 * 2)(*scales), method, max_iter, h_min, y_min, out, C.byref(st)) != 0:
+            raise ValueError("seed outside the volume")
+        arr = np.ctypeslib.as_array(out)[:n].copy()
+        return arr, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}
     if ids is None:
         n = num_trajectories((x, y, z), spacing, scales, method)
         idp = None
@@ -203,17 +228,30 @@ def saliency_map(vol: np.ndarray, bins, scales, window=None):
 
 
 def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=None, h_min=0.0, y_min=0.0,
-           rank_by=RANK_SALIENCY, window=None):
-    """Full detection; returns (structured array of regions, n_found, stats dict)."""
+           rank_by=RANK_SALIENCY, window=None, seeds=None):
+    """Full detection from the seed grid or, with seeds = [(x, y, z), ...], from
+    those positions; returns (structured array of regions, n_found, stats dict)."""
     vol = np.ascontiguousarray(vol)
     z, y, x = vol.shape
+    if seeds is not None:
+        sa, ns = _seeds(seeds)
+        ntraj = ns * (scales[1] - scales[0] + 1 if method == MEANSHIFT else 1)
+    else:
+        ntraj = num_trajectories((x, y, z), spacing, scales, method)
     if capacity is None:
-        capacity = max(1, num_trajectories((x, y, z), spacing, scales, method))
+        capacity = max(1, ntraj)
     out = (Region * max(capacity, 1))()
     nf = C.c_int32()
     st = Stats()
-    lib().kso_detect(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window), spacing,
-                     (C.c_int32 * 2)(*scales), method, max_iter, h_min, y_min, rank_by, out, capacity, C.byref(nf),
-                     C.byref(st))
+    if seeds is not None:
+        rc = lib().kso_detect_seeded(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window), sa.ctypes.data,
+                                     ns, (C.c_int32 * 2)(*scales), method, max_iter, h_min, y_min, rank_by, out,
+                                     capacity, C.byref(nf), C.byref(st))
+        if rc != 0:
+            raise ValueError("seed outside the volume")
+    else:
+        lib().kso_detect(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window), spacing,
+                         (C.c_int32 * 2)(*scales), method, max_iter, h_min, y_min, rank_by, out, capacity,
+                         C.byref(nf), C.byref(st))
     arr = np.ctypeslib.as_array(out)[:min(capacity, nf.value)].copy()
     return arr, nf.value, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}

@@ -407,16 +407,29 @@ static void run_trajectory(eval_ctx* e, int32_t max_iter, const int32_t p0[3], i
     t->objective = obj;
 }
 
-int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
-            int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
-            const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats) {
+/* Trajectories start at the seed grid, or (seeds != NULL) at the n_seeds listed
+ * positions (x, y, z): a tracking warm start from earlier detections (Sec. 4). */
+static int seeds_ok(const int32_t dims[3], const int32_t* seeds, int64_t n_seeds) {
+    if (n_seeds < 0) return 0;
+    for (int64_t i = 0; seeds && i < n_seeds; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (seeds[3 * i + a] < 0 || seeds[3 * i + a] >= dims[a]) return 0;
+    return 1;
+}
+
+static int run_impl(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                    int32_t spacing, const int32_t* seeds, int64_t n_seeds, const int32_t scales[2], int32_t method,
+                    int32_t max_iter, double h_min, double y_min, const int64_t* ids, int64_t n, kso_traj* out,
+                    kso_stats* stats) {
+    if (!seeds_ok(dims, seeds, n_seeds)) return -1;
     int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
     uint8_t* bv = (uint8_t*)malloc((size_t)nv);
     bin_any(vol, dtype, dims, bins, window, bv);
     int32_t g[3], o[3];
     grid_dims(dims, spacing, g, o);
     int32_t S = scales[1] - scales[0] + 1;
-    int64_t ntraj = kso_num_trajectories(dims, spacing, scales, method);
+    int64_t ntraj = seeds ? n_seeds * (method == KSO_MEANSHIFT ? S : 1)
+                          : kso_num_trajectories(dims, spacing, scales, method);
     if (ids == NULL) n = ntraj;
     eval_ctx e;
     e.bv = bv; e.dims = dims; e.bins = bins; e.method = method; e.s_min = scales[0]; e.s_max = scales[1];
@@ -432,6 +445,9 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
         int32_t gy = (int32_t)((seed / g[0]) % g[1]);
         int32_t gz = (int32_t)(seed / ((int64_t)g[0] * g[1]));
         int32_t p0[3] = {o[0] + gx * spacing, o[1] + gy * spacing, o[2] + gz * spacing};
+        if (seeds) {
+            p0[0] = seeds[3 * seed]; p0[1] = seeds[3 * seed + 1]; p0[2] = seeds[3 * seed + 2];
+        }
         kso_traj* t = out + i;
         t->traj = id;
         run_trajectory(&e, max_iter, p0, s, t, &st);
@@ -441,6 +457,20 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
     if (stats) *stats = st;
     free(e.eps); free(e.counts); free(e.msum); free(bv);
     return 0;
+}
+
+int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+            int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+            const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats) {
+    return run_impl(vol, dtype, dims, bins, window, spacing, NULL, 0, scales, method, max_iter, h_min, y_min, ids, n,
+                    out, stats);
+}
+
+int kso_run_seeded(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                   const int32_t* seeds, int64_t n_seeds, const int32_t scales[2], int32_t method, int32_t max_iter,
+                   double h_min, double y_min, kso_traj* out, kso_stats* stats) {
+    return run_impl(vol, dtype, dims, bins, window, 1, seeds, n_seeds, scales, method, max_iter, h_min, y_min, NULL,
+                    0, out, stats);
 }
 
 /* ----------------------------------------------------- dense saliency map */
@@ -486,12 +516,16 @@ static int region_cmp(const void* pa, const void* pb) {
     return 0;
 }
 
-int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
-               int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
-               int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
-    int64_t n = kso_num_trajectories(dims, spacing, scales, method);
-    kso_traj* t = (kso_traj*)malloc(sizeof(kso_traj) * (size_t)n);
-    kso_run(vol, dtype, dims, bins, window, spacing, scales, method, max_iter, h_min, y_min, NULL, 0, t, stats);
+static int detect_impl(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                       int32_t spacing, const int32_t* seeds, int64_t n_seeds, const int32_t scales[2],
+                       int32_t method, int32_t max_iter, double h_min, double y_min, int32_t rank_by,
+                       kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
+    if (!seeds_ok(dims, seeds, n_seeds)) return -1;
+    int64_t n = seeds ? n_seeds * (method == KSO_MEANSHIFT ? scales[1] - scales[0] + 1 : 1)
+                      : kso_num_trajectories(dims, spacing, scales, method);
+    kso_traj* t = (kso_traj*)malloc(sizeof(kso_traj) * (size_t)(n > 0 ? n : 1));
+    run_impl(vol, dtype, dims, bins, window, spacing, seeds, n_seeds, scales, method, max_iter, h_min, y_min, NULL, 0,
+             t, stats);
     kso_region* r = (kso_region*)malloc(sizeof(kso_region) * (size_t)(n > 0 ? n : 1));
     int64_t m = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -515,4 +549,19 @@ int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bi
     *n_found = (int32_t)u;
     free(r); free(t);
     return 0;
+}
+
+int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+               int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
+               int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
+    return detect_impl(vol, dtype, dims, bins, window, spacing, NULL, 0, scales, method, max_iter, h_min, y_min,
+                       rank_by, out, capacity, n_found, stats);
+}
+
+int kso_detect_seeded(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                      const int32_t* seeds, int64_t n_seeds, const int32_t scales[2], int32_t method,
+                      int32_t max_iter, double h_min, double y_min, int32_t rank_by, kso_region* out,
+                      int32_t capacity, int32_t* n_found, kso_stats* stats) {
+    return detect_impl(vol, dtype, dims, bins, window, 1, seeds, n_seeds, scales, method, max_iter, h_min, y_min,
+                       rank_by, out, capacity, n_found, stats);
 }

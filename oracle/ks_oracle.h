@@ -86,6 +86,18 @@ int kso_run(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins,
             int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
             const int64_t* ids, int64_t n, kso_traj* out, kso_stats* stats);
 
+/* As kso_run / kso_detect with the trajectories starting at n_seeds given
+ * positions (x, y, z) instead of the seed grid (trajectory id = seed index, times
+ * S plus the scale index for mean-shift): a tracking warm start from earlier
+ * detections (Sec. 4). */
+int kso_run_seeded(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                   const int32_t* seeds, int64_t n_seeds, const int32_t scales[2], int32_t method, int32_t max_iter,
+                   double h_min, double y_min, kso_traj* out, kso_stats* stats);
+int kso_detect_seeded(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                      const int32_t* seeds, int64_t n_seeds, const int32_t scales[2], int32_t method,
+                      int32_t max_iter, double h_min, double y_min, int32_t rank_by, kso_region* out,
+                      int32_t capacity, int32_t* n_found, kso_stats* stats);
+
 /* Dense Kadir-Brady map: at every voxel, s* of the saliency step of the quadrant
  * method (0: no entropy peak) and the saliency at s* (sal: accurate Y_ref;
  * sal64, if not NULL: decision-precision Y).  x fastest. */

@@ -352,6 +352,71 @@ def test_subset_runs_equal_full_run():
     assert np.array_equal(sub, full[ids])
 
 
+# ------------------------------------------------- explicit seeds (warm start)
+
+def _grid_positions(dims, sp):
+    axes = []
+    for d in dims:
+        o = sp // 2 if sp // 2 < d else (d - 1) // 2
+        axes.append(list(range(o, d, sp)))
+    return [(x, y, z) for z in axes[2] for y in axes[1] for x in axes[0]]
+
+
+@pytest.mark.parametrize("method", [oracle.QUADRANT, oracle.MEANSHIFT])
+def test_explicit_grid_seeds_reproduce_the_grid_run(method):
+    w = synth.spheres_64()
+    grid, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, method, w.max_iter)
+    seeds = _grid_positions(w.dims, w.spacing)
+    got, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, method, w.max_iter, seeds=seeds)
+    assert np.array_equal(got, grid)
+    reg, n, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, method, w.max_iter)
+    reg2, n2, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, method, w.max_iter, seeds=seeds)
+    assert n == n2 and np.array_equal(reg, reg2)
+
+
+@pytest.mark.parametrize("method", [oracle.QUADRANT, oracle.MEANSHIFT])
+def test_warm_start_from_a_converged_position_stays_there(method):
+    # A search that stopped for any reason other than the iteration cap sits at
+    # a fixed point of its update (Alg. 1, Eq. 6 with the objective test), so a
+    # trajectory started there takes no step and reports the same region.
+    rng = np.random.default_rng(50)
+    vol = np.clip(np.rint(rng.normal(40, 6, (24, 28, 32))), 0, 255).astype(np.uint8)
+    vol[6:16, 8:18, 10:22] = rng.integers(0, 256, (10, 10, 12))
+    bins, sp, scales = 32, 5, (2, 5)
+    S = scales[1] - scales[0] + 1
+    tr, _ = oracle.run(vol, bins, sp, scales, method, 30)
+    done = tr[tr["stop"] != 0]
+    assert done.size > 20
+    seeds = np.stack([done["x"], done["y"], done["z"]], 1)
+    warm, _ = oracle.run(vol, bins, sp, scales, method, 30, seeds=seeds)
+    if method == oracle.MEANSHIFT:
+        warm = warm[np.arange(done.size) * S + done["traj"] % S]
+    assert np.all(warm["iters"] == 0)
+    for f in ("x", "y", "z", "stop", "objective", "scale", "keep", "h64", "w64", "y64", "h_ref", "y_ref"):
+        assert np.array_equal(warm[f], done[f]), f
+    assert np.array_equal(warm["x0"], done["x"])
+
+
+def test_seed_list_edge_cases():
+    w = synth.spheres_64()
+    for method in (oracle.QUADRANT, oracle.MEANSHIFT):
+        tr, st = oracle.run(w.volume, w.bins, w.spacing, w.scales, method, 5, seeds=np.zeros((0, 3)))
+        assert tr.size == 0 and st["evals"] == 0
+        reg, n, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, method, 5, seeds=np.zeros((0, 3)))
+        assert n == 0
+        X, Y, Z = w.dims
+        for bad in ((X, 0, 0), (0, -1, 0), (0, 0, Z)):
+            with pytest.raises(ValueError):
+                oracle.run(w.volume, w.bins, w.spacing, w.scales, method, 5, seeds=[bad])
+            with pytest.raises(ValueError):
+                oracle.detect(w.volume, w.bins, w.spacing, w.scales, method, 5, seeds=[bad])
+        corner = [(0, 0, 0), (X - 1, Y - 1, Z - 1), (X - 1, 0, Z - 1)]
+        tr, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, method, 5, seeds=corner)
+        k = 1 if method == oracle.QUADRANT else w.scales[1] - w.scales[0] + 1
+        assert tr.size == 3 * k
+        assert np.array_equal(tr["x0"][::k], [0, X - 1, X - 1])
+
+
 def _shard(job):
     vol, bins, spacing, scales, method, max_iter, ids = job
     tr, st = oracle.run(vol, bins, spacing, scales, method, max_iter, ids=ids)
