@@ -169,6 +169,18 @@ ks_status ks_context_set_options(ks_context* ctx, const ks_options* options);
  * integers, so results do not depend on the value. */
 ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct);
 
+/* Explicit start positions for the context's later ks_detect_device and
+ * ks_seed_traces calls, in place of the seed grid (whose spacing is then only
+ * validated): a warm start from earlier detections, as when tracking a region
+ * from frame to frame with the converged regions of the previous frame (Sec. 4).
+ * seeds: host array of 3 * n_seeds int32 (x, y, z), copied by the call; every
+ * seed starts one quadrant trajectory, or one mean-shift trajectory per scale
+ * (trajectory id = seed index * S + scale - scales[0]), and a region's `seed`
+ * field is that id.  NULL restores the grid.  KS_E_INVALID for n_seeds < 0 or a
+ * null list with n_seeds > 0; at the call, for a seed outside the volume or more
+ * than 2^31 - 1 trajectories.  An empty list finds no region. */
+ks_status ks_context_set_seeds(ks_context* ctx, const int32_t* seeds, int64_t n_seeds);
+
 /* Counters and times of the last detect/batch call on this context. */
 ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out);
 
@@ -242,7 +254,7 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
 ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
                           const int32_t scales[2], float* d_saliency, uint8_t* d_scale, void* stream);
 
-/* One request of a batch or of the server. *//* One request of a batch or of the server. */
+/* One request of a batch or of the server. */
 typedef struct {
     const void* volume;    /* device pointer (ks_detect_batch) or host pointer (ks_server_submit) */
     int32_t dtype;         /* ks_dtype */
@@ -253,6 +265,11 @@ typedef struct {
     int32_t method;        /* ks_method */
     int32_t max_iter;
     ks_options options;
+    /* Start positions in place of the seed grid (see ks_context_set_seeds): host
+     * array of 3 * n_seeds int32 (x, y, z), read during the call (the server
+     * copies it at submit); NULL: the grid of seed_spacing. */
+    const int32_t* seeds;
+    int64_t n_seeds;
 } ks_request;
 
 typedef struct {
@@ -301,6 +318,16 @@ ks_status ks_server_create(int32_t device, size_t hbm_budget, int32_t max_slots,
 ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket);
 /* KS_E_NOT_READY until the request is done; then writes its regions once. */
 ks_status ks_server_poll(ks_server* s, uint64_t ticket, ks_region* out, int32_t capacity, int32_t* n_found);
+/* A request of a tracked sequence (Sec. 4: tracking seeded from the converged
+ * regions of the previous frame).  Frames of one track (any int64 id) are run in
+ * submission order, each only after the one before it has completed; other
+ * requests may pass a waiting frame.  A frame starts from the positions of the
+ * first max_seeds regions, in rank order and with repeated positions taken once,
+ * of the track's last completed frame; the track's first frame, and a frame
+ * after one that found no region or failed, uses the request's own seeds or
+ * grid.  max_seeds >= 1.  Results are polled like any other request. */
+ks_status ks_server_submit_tracked(ks_server* s, const ks_request* req, int64_t track, int32_t max_seeds,
+                                   uint64_t* ticket);
 /* Blocks until every submitted request is done. */
 ks_status ks_server_drain(ks_server* s);
 ks_status ks_server_stats(ks_server* s, ks_server_stats_t* out);

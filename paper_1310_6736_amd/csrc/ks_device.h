@@ -53,6 +53,7 @@ struct VolDesc {
     int64_t reg_off;        // first slot of this volume in the region output
     int32_t cap;            // region capacity of this volume
     int32_t pad1;
+    const int32_t* seeds;   // explicit start positions (x, y, z) x gx, or null: the seed grid
 };
 
 // A run of tasks with the same window size: tasks [task_begin, task_begin + count)

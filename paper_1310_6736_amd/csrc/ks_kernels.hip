@@ -737,6 +737,12 @@ __device__ __forceinline__ int find_seg(const TaskSeg* __restrict__ segs, int ns
 }
 
 __device__ __forceinline__ void seed_pos(const VolDesc& v, long long seed, int* p) {
+    if (v.seeds) {
+        p[0] = v.seeds[3 * seed];
+        p[1] = v.seeds[3 * seed + 1];
+        p[2] = v.seeds[3 * seed + 2];
+        return;
+    }
     const long long gxy = (long long)v.gx * v.gy;
     const int gz = (int)(seed / gxy);
     const long long r = seed - (long long)gz * gxy;

@@ -60,6 +60,21 @@ int64_t num_trajectories(const int32_t* dims, int32_t spacing, const int32_t* sc
     return method == KS_MEANSHIFT ? n * (scales[1] - scales[0] + 1) : n;
 }
 
+int64_t num_trajectories(const VolIn& v) {
+    if (!v.seeds) return num_trajectories(v.dims, v.spacing, v.scales, v.method);
+    return v.method == KS_MEANSHIFT ? v.n_seeds * (v.scales[1] - v.scales[0] + 1) : v.n_seeds;
+}
+
+ks_status check_seeds(const int32_t* dims, const int32_t* scales, int32_t method, const int32_t* seeds, int64_t n) {
+    if (n < 0 || (n > 0 && !seeds)) return KS_E_INVALID;
+    const int64_t per = method == KS_MEANSHIFT ? scales[1] - scales[0] + 1 : 1;
+    if (n > (int64_t)INT32_MAX / per) return KS_E_INVALID;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (seeds[3 * i + a] < 0 || seeds[3 * i + a] >= dims[a]) return KS_E_INVALID;
+    return KS_OK;
+}
+
 // Bin volume x fastest (rows padded to 16 bytes), then the y-fastest copy.
 static size_t bins_x_bytes(const int32_t* dims) {
     const size_t xp = ((size_t)dims[0] + 15) & ~(size_t)15;
@@ -248,8 +263,14 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         v.gx = (int32_t)grid_count(v.X, v.sp, &v.ox);
         v.gy = (int32_t)grid_count(v.Y, v.sp, &v.oy);
         v.gz = (int32_t)grid_count(v.Z, v.sp, &v.oz);
+        p.seed_off.push_back(p.seed_ints);
+        if (r.seeds) {  // a list of n_seeds positions in place of the grid
+            v.gx = (int32_t)r.n_seeds; v.gy = 1; v.gz = 1;
+            v.ox = v.oy = v.oz = 0;
+            p.seed_ints += 3 * (size_t)r.n_seeds;
+        }
         v.traj_base = traj;
-        v.n_traj = num_trajectories(r.dims, r.spacing, r.scales, r.method);
+        v.n_traj = num_trajectories(r);
         v.h_min = r.opt.h_min; v.y_min = r.opt.y_min; v.rank_by = r.opt.rank_by;
         v.win = r.opt.window; v.win_lo = r.opt.win_lo; v.win_hi = r.opt.win_hi;
         v.reg_off = regs;
@@ -282,6 +303,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     for (int i = 0; i < nvol; ++i) {
         const VolDesc& v = p.vols[i];
         const int64_t seeds = (int64_t)v.gx * v.gy * v.gz;
+        if (seeds == 0) continue;
         if (v.method == KS_QUADRANT) {
             Run r;
             r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = 0; r.s.seed_begin = 0;
@@ -315,6 +337,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     if ((st = d_vols.ensure(vol_bytes, &generation)) != KS_OK) return st;
     if ((st = d_segs.ensure(seg_bytes, &generation)) != KS_OK) return st;
+    if ((st = d_seeds.ensure(std::max<size_t>(sizeof(int32_t) * p.seed_ints, 256), &generation)) != KS_OK) return st;
     if ((st = d_bins.ensure(std::max<size_t>(bins_total, 256), &generation)) != KS_OK) return st;
     if ((st = d_rec.ensure(sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1), &generation)) != KS_OK) return st;
     if ((st = d_sr.ensure(2 * sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
@@ -329,11 +352,14 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         p.vols[i].bins = static_cast<uint8_t*>(d_bins.ptr) + bins_off[i];
         p.vols[i].bins_t = p.vols[i].bins + bins_x_bytes(in[i].dims);
         p.vols[i].minmax = volint + 2 * i;
+        p.vols[i].seeds = in[i].seeds ? static_cast<const int32_t*>(d_seeds.ptr) + p.seed_off[i] : nullptr;
     }
+    p.seed_src.resize(nvol);
+    for (int i = 0; i < nvol; ++i) p.seed_src[i] = in[i].seeds;
     p.vol_nfound = volint + 2 * nvol;
     p.vol_base = volint + 3 * nvol;
-    // Host staging: vols, segs.
-    const size_t stage_bytes = vol_bytes + seg_bytes;
+    // Host staging: vols, segs, seed lists.
+    const size_t stage_bytes = vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints;
     if ((st = h_stage.ensure(stage_bytes)) != KS_OK) return st;
     const size_t out_bytes = sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 1) + sizeof(int) * nvol +
                              sizeof(Counters);
@@ -358,6 +384,13 @@ ks_status Context::upload(const Plan& p, hipStream_t st) {
     for (const TaskSeg& s : p.segs_m) hs[ns++] = s;
     KS_HIP(hipMemcpyAsync(d_vols.ptr, h, vol_bytes, hipMemcpyHostToDevice, st));
     if (ns) KS_HIP(hipMemcpyAsync(d_segs.ptr, hs, sizeof(TaskSeg) * ns, hipMemcpyHostToDevice, st));
+    if (p.seed_ints) {
+        int32_t* hseed = reinterpret_cast<int32_t*>(h + vol_bytes + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1));
+        for (int i = 0; i < p.nvol; ++i)
+            if (p.seed_src[i])
+                std::memcpy(hseed + p.seed_off[i], p.seed_src[i], sizeof(int32_t) * 3 * (size_t)p.vols[i].gx);
+        KS_HIP(hipMemcpyAsync(d_seeds.ptr, hseed, sizeof(int32_t) * p.seed_ints, hipMemcpyHostToDevice, st));
+    }
     return KS_OK;
 }
 
@@ -503,6 +536,7 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
         std::memcpy(&hb, &v.opt.h_min, sizeof(hb));
         std::memcpy(&yb, &v.opt.y_min, sizeof(yb));
         key.push_back(hb); key.push_back(yb); key.push_back(v.opt.rank_by);
+        key.push_back(v.seeds ? v.n_seeds : -1);
     }
     hipGraphExec_t exec = nullptr;
     for (const GraphEntry& g : graphs)
@@ -638,6 +672,30 @@ ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct) {
     return KS_OK;
 }
 
+ks_status ks_context_set_seeds(ks_context* ctx, const int32_t* seeds, int64_t n_seeds) {
+    if (!ctx) return KS_E_INVALID;
+    if (!seeds) {
+        ctx->use_seeds = false;
+        ctx->seeds.clear();
+        return KS_OK;
+    }
+    if (n_seeds < 0 || n_seeds > (int64_t)INT32_MAX) return KS_E_INVALID;
+    ctx->seeds.assign(seeds, seeds + 3 * n_seeds);
+    ctx->use_seeds = true;
+    return KS_OK;
+}
+
+// The context's seed list on a request, validated against its volume.
+static ks_status apply_ctx_seeds(const ks_context* ctx, VolIn& v) {
+    if (!ctx->use_seeds) return KS_OK;
+    const int64_t n = (int64_t)ctx->seeds.size() / 3;
+    // a non-null pointer even for an empty list
+    static const int32_t kNone[3] = {0, 0, 0};
+    v.seeds = n ? ctx->seeds.data() : kNone;
+    v.n_seeds = n;
+    return check_seeds(v.dims, v.scales, v.method, v.seeds, n);
+}
+
 ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out) {
     if (!ctx || !out) return KS_E_INVALID;
     *out = ctx->last;
@@ -662,6 +720,7 @@ ks_status ks_detect_device(ks_context* ctx, const void* d_volume, ks_dtype dtype
     v.max_iter = max_iter; v.capacity = capacity;
     v.opt = ctx->opts;
     if (!options_fit(v.opt, bins)) return KS_E_INVALID;
+    if ((s = apply_ctx_seeds(ctx, v)) != KS_OK) return s;
     std::vector<std::vector<ks_region>> res;
     std::vector<int> nf;
     s = ctx->detect_volumes({v}, static_cast<hipStream_t>(stream), &res, &nf);
@@ -701,25 +760,26 @@ ks_status ks_seed_traces(ks_context* ctx, const void* d_volume, ks_dtype dtype, 
     ks_status s = check_request(d_volume, dtype, dims, bins, seed_spacing, scales, method, max_iter);
     if (s != KS_OK) return s;
     if (!n || capacity < 0 || (capacity > 0 && !out)) return KS_E_INVALID;
-    if (capacity == 0) {  // count only
-        *n = (int32_t)num_trajectories(dims, seed_spacing, scales, method);
-        return KS_OK;
-    }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
     VolIn v;
     v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
     v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
     v.max_iter = max_iter; v.capacity = 0;
     v.opt = ctx->opts;
     if (!options_fit(v.opt, bins)) return KS_E_INVALID;
+    if ((s = apply_ctx_seeds(ctx, v)) != KS_OK) return s;
+    if (capacity == 0) {  // count only
+        *n = (int32_t)num_trajectories(v);
+        return KS_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
     Plan p;
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     if ((s = ctx->enqueue_search(p, st, false, false)) != KS_OK) return s;
     std::vector<TrajRec> rec((size_t)p.total_traj);
-    if (hipMemcpyAsync(rec.data(), ctx->d_rec.ptr, sizeof(TrajRec) * rec.size(), hipMemcpyDeviceToHost, st) !=
-        hipSuccess)
+    if (!rec.empty() && hipMemcpyAsync(rec.data(), ctx->d_rec.ptr, sizeof(TrajRec) * rec.size(),
+                                       hipMemcpyDeviceToHost, st) != hipSuccess)
         return KS_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
     const int64_t w = std::min<int64_t>(capacity, p.total_traj);
@@ -896,6 +956,11 @@ ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks
         v.spacing = r.seed_spacing; v.scales[0] = r.scales[0]; v.scales[1] = r.scales[1]; v.method = r.method;
         v.max_iter = r.max_iter; v.capacity = results[i].capacity;
         v.opt = r.options;
+        if (r.seeds || r.n_seeds) {
+            if ((s = check_seeds(r.dims, r.scales, r.method, r.seeds, r.n_seeds)) != KS_OK) return s;
+            v.seeds = r.seeds;
+            v.n_seeds = r.n_seeds;
+        }
     }
     if (n == 0) return KS_OK;
     std::vector<std::vector<ks_region>> res;

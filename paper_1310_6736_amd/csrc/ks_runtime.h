@@ -36,6 +36,8 @@ struct VolIn {
     int32_t method, max_iter;
     int32_t capacity;
     ks_options opt{};
+    const int32_t* seeds = nullptr;  // host (x, y, z) start positions, or null: the seed grid
+    int64_t n_seeds = 0;
 };
 
 struct Plan {
@@ -51,6 +53,9 @@ struct Plan {
     LdsQuad lay{};
     int* vol_nfound = nullptr;
     int* vol_base = nullptr;
+    std::vector<size_t> seed_off;   // per volume: int offset of its seed list in d_seeds
+    std::vector<const int32_t*> seed_src;  // per volume: the caller's host list, or null
+    size_t seed_ints = 0;
 };
 
 struct GraphEntry {
@@ -68,11 +73,13 @@ struct Context {
     int ms_s_small = 6;
     int ms_incr_pct = 100;  // running-window updates while cheaper than a fresh window
     ks_options opts{};      // selection and order for ks_detect_device / ks_seed_traces
+    bool use_seeds = false; // explicit start positions for ks_detect_device / ks_seed_traces
+    std::vector<int32_t> seeds;
     int quad_rq_pref = 0;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
     Tables tables{};
-    Buffer tables_buf, d_vols, d_segs, d_bins, d_rec, d_sr, d_bsum, d_grank, d_volint, d_regions, d_cnt, d_hook,
+    Buffer tables_buf, d_vols, d_segs, d_seeds, d_bins, d_rec, d_sr, d_bsum, d_grank, d_volint, d_regions, d_cnt, d_hook,
         d_hook_out, d_raw;
     PinnedBuffer h_stage, h_out;
     hipStream_t aux = nullptr;
@@ -102,7 +109,10 @@ bool options_ok(const ks_options& o);  // thresholds not NaN, known rank key, wi
 bool options_fit(const ks_options& o, int32_t bins);  // a window level needs bins <= 255
 ks_status check_request(const void* vol, int32_t dtype, const int32_t* dims, int32_t bins, int32_t spacing,
                         const int32_t* scales, int32_t method, int32_t max_iter);
+// Start positions inside the volume, n >= 0, and at most 2^31 - 1 trajectories.
+ks_status check_seeds(const int32_t* dims, const int32_t* scales, int32_t method, const int32_t* seeds, int64_t n);
 int64_t num_trajectories(const int32_t* dims, int32_t spacing, const int32_t* scales, int32_t method);
+int64_t num_trajectories(const VolIn& v);  // of the grid or of the seed list
 size_t bins_bytes(const int32_t* dims);
 int pick_ms_rl(int maxB, int pref);
 int pick_quad_rq(int maxS, int maxB, int pref);

@@ -41,6 +41,17 @@ struct SrvReq {
     int status = KS_E_NOT_READY;
     std::vector<ks_region> regions;
     int n_found = 0;
+    std::vector<int32_t> seeds;    // own start positions, or those handed over by the track
+    bool own_seeds = false;
+    int64_t track = -1;            // tracked sequence, or -1
+    int32_t max_seeds = 0;
+};
+
+// A tracked sequence: whether a frame is admitted and not yet complete, and the
+// start positions its next frame takes (empty: the frame's own seeds or grid).
+struct Track {
+    bool busy = false;
+    std::vector<int32_t> seeds;
 };
 
 struct Slot {
@@ -71,6 +82,7 @@ struct ks_server {
     uint64_t next_ticket = 1;
     std::deque<uint64_t> pending;
     std::map<uint64_t, SrvReq> reqs;
+    std::map<int64_t, Track> tracks;
     std::vector<Slot*> slots;
     size_t in_use = 0;
     int64_t submitted = 0, admitted = 0, completed = 0, refused = 0, in_flight = 0;
@@ -81,18 +93,19 @@ struct ks_server {
 
     void run();
     bool tick();
+    ks_status submit(const ks_request* req, int64_t track, int32_t max_seeds, uint64_t* ticket);
 };
 
 // Device bytes a request holds while admitted: its volume, bin volume, trajectory
 // and sort records.
-static size_t footprint(const ks::VolIn& v) {
+static size_t footprint(const ks::VolIn& v, int64_t ntraj) {
     const size_t esz = v.dtype == KS_U8 ? 1 : 2;
     const size_t raw = esz * (size_t)v.dims[0] * v.dims[1] * v.dims[2];
-    const size_t n = (size_t)ks::num_trajectories(v.dims, v.spacing, v.scales, v.method);
+    const size_t n = (size_t)ntraj;
     size_t pad = 2;
     while (pad < n) pad <<= 1;
-    return raw + ks::bins_bytes(v.dims) + n * sizeof(ks::TrajRec) + pad * (2 * sizeof(ks::SortRec) + 2 * sizeof(int)) +
-           (size_t)v.capacity * sizeof(ks_region) + (1 << 16);
+    return raw + ks::bins_bytes(v.dims) + n * (sizeof(ks::TrajRec) + 12) +
+           pad * (2 * sizeof(ks::SortRec) + 2 * sizeof(int)) + (size_t)v.capacity * sizeof(ks_region) + (1 << 16);
 }
 
 static double percentile(std::vector<double> v, double q) {
@@ -108,8 +121,8 @@ static double percentile(std::vector<double> v, double q) {
 // evaluation round x a typical evaluation count per trajectory.  Used only to
 // bound a batch's work so that results come back in pieces of a few ms of device
 // time instead of one long launch.
-static double work_estimate(const ks::VolIn& v) {
-    const double seeds = (double)ks::num_trajectories(v.dims, v.spacing, v.scales, KS_QUADRANT);
+static double work_estimate(const ks::VolIn& v, int64_t n_seeds) {
+    const double seeds = (double)n_seeds;
     double win = 0;
     if (v.method == KS_QUADRANT) {
         const double w = 2.0 * v.scales[1] + 1.0;
@@ -122,6 +135,22 @@ static double work_estimate(const ks::VolIn& v) {
     }
     const double vox = (double)v.dims[0] * v.dims[1] * v.dims[2];
     return seeds * std::min(win, 64.0 * vox);
+}
+
+// Completes a tracked frame: the next frame of its track starts from the first
+// max_seeds distinct positions of its regions in rank order (none: its own seeds
+// or grid).
+static void hand_over(Track& tr, const SrvReq& r) {
+    tr.busy = false;
+    tr.seeds.clear();
+    if (r.status != KS_OK) return;
+    for (const ks_region& g : r.regions) {
+        if ((int32_t)(tr.seeds.size() / 3) >= r.max_seeds) break;
+        bool seen = false;
+        for (size_t k = 0; k < tr.seeds.size() && !seen; k += 3)
+            seen = tr.seeds[k] == g.x && tr.seeds[k + 1] == g.y && tr.seeds[k + 2] == g.z;
+        if (!seen) tr.seeds.insert(tr.seeds.end(), {g.x, g.y, g.z});
+    }
 }
 
 // Work of one batch: about 10 ms of device time at the measured visit rates.
@@ -152,6 +181,7 @@ bool ks_server::tick() {
                 r.status = KS_E_DEVICE;
                 fatal = KS_E_DEVICE;
             }
+            if (r.track >= 0) hand_over(tracks[r.track], r);
             r.t_done = t;
             r.host.clear();
             r.host.shrink_to_fit();
@@ -176,14 +206,33 @@ bool ks_server::tick() {
     {
         std::lock_guard<std::mutex> lk(mu);
         double work = 0;
-        while (!pending.empty()) {
-            SrvReq& r = reqs[pending.front()];
+        for (auto it = pending.begin(); it != pending.end();) {
+            SrvReq& r = reqs[*it];
+            // a tracked frame waits for the frame before it; others pass it
+            if (r.track >= 0 && tracks[r.track].busy) {
+                ++it;
+                continue;
+            }
             if (in_use + bytes + r.footprint > budget) break;   // oldest first: no overtaking
             if (!take.empty() && work + r.work > kBatchWork) break;
             work += r.work;
             bytes += r.footprint;
-            take.push_back(pending.front());
-            pending.pop_front();
+            bool listed = r.own_seeds;
+            if (r.track >= 0) {
+                Track& tr = tracks[r.track];
+                tr.busy = true;
+                if (!tr.seeds.empty()) {
+                    r.seeds = tr.seeds;
+                    listed = true;
+                }
+            }
+            if (listed) {
+                static const int32_t kNone[3] = {0, 0, 0};  // an empty list is not the grid
+                r.in.seeds = r.seeds.empty() ? kNone : r.seeds.data();
+                r.in.n_seeds = (int64_t)r.seeds.size() / 3;
+            }
+            take.push_back(*it);
+            it = pending.erase(it);
         }
         in_use += bytes;
         admitted += (int64_t)take.size();
@@ -229,6 +278,7 @@ bool ks_server::tick() {
             r.t_done = now_ms();
             completed += 1;
             in_flight -= 1;
+            if (r.track >= 0) hand_over(tracks[r.track], r);
         }
         in_use -= bytes;
         sl->busy = false;
@@ -295,12 +345,17 @@ ks_status ks_server_create(int32_t device, size_t hbm_budget, int32_t max_slots,
     return KS_OK;
 }
 
-ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket) {
-    if (!s || !req || !ticket) return KS_E_INVALID;
+}  // extern "C"
+
+ks_status ks_server::submit(const ks_request* req, int64_t track, int32_t max_seeds, uint64_t* ticket) {
+    ks_server* s = this;
     ks_status st = ks::check_request(req->volume, req->dtype, req->dims, req->bins, req->seed_spacing, req->scales,
                                      req->method, req->max_iter);
     if (st != KS_OK) return st;
     if (!ks::options_ok(req->options) || !ks::options_fit(req->options, req->bins)) return KS_E_INVALID;
+    const bool own = req->seeds || req->n_seeds;
+    if (own && (st = ks::check_seeds(req->dims, req->scales, req->method, req->seeds, req->n_seeds)) != KS_OK)
+        return st;
     SrvReq r;
     r.in.raw = nullptr;
     r.in.dtype = req->dtype;
@@ -312,10 +367,18 @@ ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket
     r.in.method = req->method;
     r.in.max_iter = req->max_iter;
     r.in.opt = req->options;
-    r.in.capacity = (int32_t)std::min<int64_t>(ks::num_trajectories(req->dims, req->seed_spacing, req->scales,
-                                                                    req->method), 1 << 20);
-    r.footprint = footprint(r.in);
-    r.work = work_estimate(r.in);
+    r.track = track;
+    r.max_seeds = max_seeds;
+    r.own_seeds = own;
+    if (own) r.seeds.assign(req->seeds, req->seeds + 3 * req->n_seeds);
+    // trajectories of the largest start set the request may run with
+    const int64_t per = req->method == KS_MEANSHIFT ? req->scales[1] - req->scales[0] + 1 : 1;
+    int64_t n_start = own ? req->n_seeds
+                          : ks::num_trajectories(req->dims, req->seed_spacing, req->scales, KS_QUADRANT);
+    if (track >= 0) n_start = std::max<int64_t>(n_start, max_seeds);
+    r.in.capacity = (int32_t)std::min<int64_t>(std::max<int64_t>(n_start * per, 1), 1 << 20);
+    r.footprint = footprint(r.in, n_start * per);
+    r.work = work_estimate(r.in, n_start);
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->stop) return KS_E_SHUTDOWN;
     if (s->fatal != KS_OK) return s->fatal;
@@ -338,6 +401,21 @@ ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket
     lk.unlock();
     s->cv.notify_all();
     return KS_OK;
+}
+
+extern "C" {
+
+ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket) {
+    if (!s || !req || !ticket) return KS_E_INVALID;
+    return s->submit(req, -1, 0, ticket);
+}
+
+ks_status ks_server_submit_tracked(ks_server* s, const ks_request* req, int64_t track, int32_t max_seeds,
+                                   uint64_t* ticket) {
+    if (!s || !req || !ticket || track < 0 || max_seeds < 1) return KS_E_INVALID;
+    const int64_t per = req->method == KS_MEANSHIFT ? (int64_t)req->scales[1] - req->scales[0] + 1 : 1;
+    if (per < 1 || max_seeds > (int64_t)INT32_MAX / per) return KS_E_INVALID;
+    return s->submit(req, track, max_seeds, ticket);
 }
 
 ks_status ks_server_poll(ks_server* s, uint64_t ticket, ks_region* out, int32_t capacity, int32_t* n_found) {

@@ -26,7 +26,8 @@ EXPORTS = [
     "ks_last_stats", "ks_detect", "ks_detect_device", "ks_seed_traces", "ks_bin_volume", "ks_histograms",
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
-    "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map",
+    "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
+    "ks_server_submit_tracked",
 ]
 
 
@@ -71,7 +72,8 @@ def options(h_min=0.0, y_min=0.0, rank_by=0, window=None) -> Options:
 class Request(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("dtype", C.c_int32), ("dims", C.c_int32 * 3), ("bins", C.c_int32),
                 ("seed_spacing", C.c_int32), ("scales", C.c_int32 * 2), ("method", C.c_int32),
-                ("max_iter", C.c_int32), ("options", Options)]
+                ("max_iter", C.c_int32), ("options", Options), ("seeds", C.POINTER(C.c_int32)),
+                ("n_seeds", C.c_int64)]
 
 
 class Result(C.Structure):
@@ -117,6 +119,8 @@ def lib():
     L.ks_detect_batch.argtypes = [vp, i32, C.POINTER(Request), C.POINTER(Result), vp]
     L.ks_server_create.argtypes = [i32, C.c_size_t, i32, C.POINTER(vp)]
     L.ks_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+    L.ks_server_submit_tracked.argtypes = [vp, C.POINTER(Request), C.c_int64, i32, C.POINTER(C.c_uint64)]
+    L.ks_context_set_seeds.argtypes = [vp, i32p, C.c_int64]
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
     L.ks_server_drain.argtypes = [vp]
     L.ks_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
@@ -242,6 +246,22 @@ def ks_context_set_options(ctx: Context, opts=None):
            "ks_context_set_options")
 
 
+def _seed_array(seeds):
+    a = np.ascontiguousarray(np.asarray(seeds, dtype=np.int32).reshape(-1, 3))
+    return a, a.shape[0]
+
+
+def ks_context_set_seeds(ctx: Context, seeds=None):
+    """Start positions [(x, y, z), ...] for later ks_detect_device / ks_seed_traces
+    calls on ctx, in place of the seed grid (None: the grid)."""
+    if seeds is None:
+        _check(lib().ks_context_set_seeds(ctx.handle, None, 0), "ks_context_set_seeds")
+        return
+    a, n = _seed_array(seeds)
+    _check(lib().ks_context_set_seeds(ctx.handle, a.ctypes.data_as(C.POINTER(C.c_int32)), n),
+           "ks_context_set_seeds")
+
+
 def ks_context_set_ms_update(ctx: Context, incremental_pct: int = 100):
     _check(lib().ks_context_set_ms_update(ctx.handle, incremental_pct), "ks_context_set_ms_update")
 
@@ -323,10 +343,18 @@ def ks_histograms(ctx: Context, volume, bins, kind, xyz, scale=None, scale_range
     return out
 
 
-def make_request(volume, bins, seed_spacing, scales, method, max_iter, host=False, opts=None) -> Request:
+def make_request(volume, bins, seed_spacing, scales, method, max_iter, host=False, opts=None,
+                 seeds=None) -> Request:
+    """One batch or server request; seeds = [(x, y, z), ...] replaces the grid (the
+    request keeps the array alive)."""
     r = Request()
     if opts is not None:
         r.options = opts
+    if seeds is not None:
+        a, n = _seed_array(seeds)
+        r._seed_keep = a
+        r.seeds = a.ctypes.data_as(C.POINTER(C.c_int32))
+        r.n_seeds = n
     if host:
         vol = np.ascontiguousarray(volume)
         z, y, x = vol.shape
@@ -377,10 +405,17 @@ class Server:
                "ks_server_create")
         self.handle = h
 
-    def submit(self, volume: np.ndarray, bins, seed_spacing, scales, method, max_iter, opts=None) -> int:
-        r = make_request(volume, bins, seed_spacing, scales, method, max_iter, host=True, opts=opts)
+    def submit(self, volume: np.ndarray, bins, seed_spacing, scales, method, max_iter, opts=None, seeds=None,
+               track=None, max_seeds=32) -> int:
+        """Queues a host volume; with track = an int id the request is a frame of
+        that tracked sequence (started from the previous frame's regions)."""
+        r = make_request(volume, bins, seed_spacing, scales, method, max_iter, host=True, opts=opts, seeds=seeds)
         t = C.c_uint64()
-        _check(lib().ks_server_submit(self.handle, C.byref(r), C.byref(t)), "ks_server_submit")
+        if track is None:
+            _check(lib().ks_server_submit(self.handle, C.byref(r), C.byref(t)), "ks_server_submit")
+        else:
+            _check(lib().ks_server_submit_tracked(self.handle, C.byref(r), int(track), int(max_seeds), C.byref(t)),
+                   "ks_server_submit_tracked")
         return t.value
 
     def poll(self, ticket: int, capacity=1024):

@@ -174,3 +174,64 @@ def test_server_small_budget_queues_and_refuses(torch_dev, ctx):
         assert srv.stats()["refused"] == 1
     finally:
         srv.close()
+
+
+def moving_frames(n, seed, shape=(36, 40, 44)):
+    """A textured sphere in noise moving 2 voxels per frame along x and 1 along y."""
+    Z, Y, X = shape
+    rng = np.random.default_rng(seed)
+    zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    frames = []
+    for f in range(n):
+        v = np.clip(np.rint(rng.normal(50, 4, shape)), 0, 255).astype(np.uint8)
+        c = (12 + 2 * f, 14 + f, 18)
+        m = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2 <= 36
+        v[m] = rng.integers(0, 256, int(m.sum()))
+        frames.append(v)
+    return frames
+
+
+def handed_over(regions, max_seeds):
+    """Start positions of the next frame: the first max_seeds distinct positions
+    of the frame's regions in rank order."""
+    out = []
+    for r in regions:
+        p = (int(r["x"]), int(r["y"]), int(r["z"]))
+        if p not in out:
+            out.append(p)
+        if len(out) == max_seeds:
+            break
+    return out
+
+
+def test_server_tracked_frames_start_from_the_previous_regions(torch_dev):
+    frames = moving_frames(4, 900)
+    bins, sp, max_iter, max_seeds = 32, 6, 30, 6
+    tracks = {7: (ks.KS_QUADRANT, (3, 7)), 8: (ks.KS_MEANSHIFT, (3, 6))}
+    note("server: two tracked sequences and untracked requests")
+    srv = ks.Server(0, hbm_budget=1 << 30, max_slots=4)
+    try:
+        tickets = []
+        for f, v in enumerate(frames):
+            for tid, (method, scales) in tracks.items():
+                t = srv.submit(v, bins, sp, scales, method, max_iter, track=tid, max_seeds=max_seeds)
+                tickets.append((tid, f, t))
+            tickets.append((None, f, srv.submit(v, bins, sp, (3, 7), ks.KS_QUADRANT, max_iter)))
+        srv.drain()
+        got = {(tid, f): srv.poll(t, capacity=100000) for tid, f, t in tickets}
+    finally:
+        srv.close()
+    for tid, (method, scales) in list(tracks.items()) + [(None, (ks.KS_QUADRANT, (3, 7)))]:
+        seeds = None
+        for f, v in enumerate(frames):
+            want, wn, _ = oracle.detect(v, bins, sp, scales, method, max_iter, seeds=seeds)
+            regs, n = got[(tid, f)]
+            assert n == wn, (tid, f)
+            for fld in ("x", "y", "z", "scale", "seed"):
+                assert np.array_equal(regs[fld], want[fld]), (tid, f, fld)
+            assert np.allclose(regs["saliency"], want["saliency"], rtol=1e-5, atol=0), (tid, f)
+            if tid is not None:
+                nxt = handed_over(want, max_seeds)
+                seeds = nxt if nxt else None
+    # a warm-started frame runs max_seeds trajectories per scale, not the grid
+    assert got[(7, 3)][1] <= max_seeds

@@ -6,6 +6,7 @@ decision values (objective, saliency used for ranking) must be equal; the
 float32 reported entropy / pdf change / saliency must be within 1e-5 relative of
 the oracle's accurate double values, and exactly zero where those are zero.
 """
+import ctypes
 import sys
 import zlib
 
@@ -562,3 +563,79 @@ def test_window_level_saliency_map(torch_dev, ctx, case):
     w_sal, w_scl, _ = oracle.saliency_map(v, bins, (2, 4), window=win)
     assert np.array_equal(scl.cpu().numpy(), w_scl)
     assert close32(sal.cpu().numpy().ravel(), w_sal.astype(np.float64).ravel())
+
+
+# ------------------------------------------------- explicit seeds (warm start)
+
+def seed_list(shape, n, seed):
+    """Random in-volume positions plus the eight corners and a repeated seed."""
+    Z, Y, X = shape
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.integers(0, X, n), rng.integers(0, Y, n), rng.integers(0, Z, n)], 1)
+    corners = np.array([(x, y, z) for z in (0, Z - 1) for y in (0, Y - 1) for x in (0, X - 1)])
+    return np.concatenate([pts, corners, pts[:1]]).astype(np.int32)
+
+
+@pytest.mark.parametrize("method", [ks.KS_QUADRANT, ks.KS_MEANSHIFT])
+def test_seeded_traces_and_detection_match_oracle(torch_dev, ctx, method):
+    w = synth.pet_shell(method)
+    seeds = seed_list(w.volume.shape, 150, 71 + method)
+    note(f"seeded traces/detect {w.name} n_seeds={len(seeds)}")
+    ks.ks_context_set_seeds(ctx, seeds)
+    try:
+        got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+        regs, n = ks.ks_detect_device(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method,
+                                      w.max_iter, capacity=100000)
+    finally:
+        ks.ks_context_set_seeds(ctx, None)
+    want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, seeds=seeds)
+    compare_traces(got, want, f"{w.name} seeded")
+    wreg, wn, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, seeds=seeds)
+    compare_regions(regs, n, wreg, wn, f"{w.name} seeded")
+    # the grid again once the list is cleared
+    grid = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    assert len(grid) == oracle.num_trajectories(w.dims, w.spacing, w.scales, w.method)
+
+
+def test_seeded_edge_cases(torch_dev, ctx):
+    v = random_volume(88, (9, 14, 23), np.uint16, 0, 4000)
+    Z, Y, X = v.shape
+    for method in (ks.KS_QUADRANT, ks.KS_MEANSHIFT):
+        note(f"seeded edge cases method={method}")
+        try:
+            ks.ks_context_set_seeds(ctx, np.zeros((0, 3), np.int32))
+            tr = ks.ks_seed_traces(ctx, dev(torch_dev, v), 32, 4, (1, 5), method, 10)
+            regs, n = ks.ks_detect_device(ctx, dev(torch_dev, v), 32, 4, (1, 5), method, 10)
+            assert len(tr) == 0 and n == 0
+            one = np.array([[X - 1, 0, Z // 2]], np.int32)
+            ks.ks_context_set_seeds(ctx, one)
+            tr = ks.ks_seed_traces(ctx, dev(torch_dev, v), 32, 4, (1, 5), method, 10)
+            want, _ = oracle.run(v, 32, 4, (1, 5), method, 10, seeds=one)
+            compare_traces(tr, want, f"one seed method={method}")
+            for bad in ([X, 0, 0], [0, Y, 0], [0, 0, -1]):
+                ks.ks_context_set_seeds(ctx, np.array([bad], np.int32))
+                with pytest.raises(ks.KsError):
+                    ks.ks_seed_traces(ctx, dev(torch_dev, v), 32, 4, (1, 5), method, 10)
+                with pytest.raises(ks.KsError):
+                    ks.ks_detect_device(ctx, dev(torch_dev, v), 32, 4, (1, 5), method, 10)
+        finally:
+            ks.ks_context_set_seeds(ctx, None)
+    three = (ctypes.c_int32 * 3)()
+    assert ks.lib().ks_context_set_seeds(ctx.handle, three, -1) != 0
+    assert ks.lib().ks_context_set_seeds(ctx.handle, None, 5) == 0  # NULL: the grid, count ignored
+
+
+def test_batch_with_seed_lists(torch_dev, ctx):
+    ws = [synth.pet_shell(ks.KS_QUADRANT), synth.pet_shell(ks.KS_MEANSHIFT), synth.spheres_64()]
+    vols = [dev(torch_dev, w.volume) for w in ws]
+    lists = [seed_list(ws[0].volume.shape, 60, 5), None, np.zeros((0, 3), np.int32), seed_list(ws[1].volume.shape,
+                                                                                                 40, 6)]
+    order = [0, 1, 2, 1]
+    reqs = [ks.make_request(vols[k], ws[k].bins, ws[k].spacing, ws[k].scales, ws[k].method, ws[k].max_iter,
+                            seeds=lists[i]) for i, k in enumerate(order)]
+    note("batch with seed lists")
+    out = ks.ks_detect_batch(ctx, reqs, capacity=100000)
+    for i, k in enumerate(order):
+        w = ws[k]
+        want, wn, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, seeds=lists[i])
+        compare_regions(out[i][0], out[i][1], want, wn, f"batch {i} {w.name}")
