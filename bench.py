@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the timed step and the roofline microbenchmarks (for profiling runs)")
     return ap.parse_args()
 
 
@@ -193,6 +195,89 @@ def dense_section(ks, torch, ctx, q_detect_ms):
                        "seed_grid_detect_ms": det, "saving": m / det}
     ks.ks_context_set_profiling(ctx, False)
     return out
+
+
+def window_level_section(ks, torch, ctx):
+    """Constrained-range entropy (window level) on the MR-like volume: the
+    mean-shift detection binned over the lesion window only, against the same
+    detection over the full dynamic range."""
+    from paper_1310_6736_amd import synth
+
+    w = synth.mr_blobs()
+    v = torch.from_numpy(w.volume).to("cuda:0")
+    out = {"workload": w.name, "window": [1201, 3000]}
+    ks.ks_context_set_profiling(ctx, True)
+    try:
+        for name, opt in (("full_range", None), ("window", ks.options(window=(1201, 3000)))):
+            ks.ks_context_set_options(ctx, opt)
+            ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=64)
+            ts, n, st = [], 0, None
+            for _ in range(3):
+                _, n = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=64)
+                st = ks.ks_last_stats(ctx)
+                ts.append(st["ms_total"])
+            m = float(np.median(ts))
+            out[name] = {"device_ms": m, "regions": int(n), "window_evals": int(st["window_evals"]),
+                         "window_evals_per_s": st["window_evals"] / (m * 1e-3)}
+    finally:
+        ks.ks_context_set_options(ctx, None)
+        ks.ks_context_set_profiling(ctx, False)
+    return out
+
+
+def tracking_section(ks, torch, ctx, n_frames=5, max_seeds=20):
+    """Warm start from the previous frame's regions: PET-like frames in which the
+    volume moves one voxel along x per frame.  Every frame runs the seed grid, and
+    every frame after the first also runs a warm start from the first max_seeds
+    distinct positions of the previous frame's warm (frame 0: grid) regions."""
+    from paper_1310_6736_amd import synth
+
+    w = synth.pet_shell(ks.KS_QUADRANT)
+    frames = [torch.from_numpy(np.ascontiguousarray(np.roll(w.volume, f, axis=2))).to("cuda:0")
+              for f in range(n_frames)]
+
+    def run(v, seeds):
+        ks.ks_context_set_seeds(ctx, seeds)
+        regs, n = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=4096)
+        return regs, n, ks.ks_last_stats(ctx)
+
+    def top(regs, n):
+        return [int(regs[f][0]) for f in ("x", "y", "z", "scale")] + [float(regs["saliency"][0])] if n else None
+
+    ks.ks_context_set_profiling(ctx, True)
+    grid_ms, warm_ms, warm_traj, grid_top, warm_top = [], [], [], [], []
+    try:
+        for rep in range(2):
+            prev = None
+            for f, v in enumerate(frames):
+                g, gn, gst = run(v, None)
+                regs, n = g, gn
+                if f > 0:
+                    pts = []
+                    for r in prev:
+                        p = (int(r["x"]), int(r["y"]), int(r["z"]))
+                        if p not in pts:
+                            pts.append(p)
+                        if len(pts) == max_seeds:
+                            break
+                    regs, n, st = run(v, np.array(pts, np.int32) if pts else None)
+                    if rep == 1:
+                        warm_ms.append(st["ms_total"])
+                        warm_traj.append(int(st["trajectories"]))
+                        warm_top.append(top(regs, n))
+                if rep == 1:
+                    grid_ms.append(gst["ms_total"])
+                    grid_top.append(top(g, gn))
+                prev = regs
+    finally:
+        ks.ks_context_set_seeds(ctx, None)
+        ks.ks_context_set_profiling(ctx, False)
+    gm, wm = float(np.median(grid_ms)), float(np.median(warm_ms))
+    return {"workload": w.name + " moved 1 voxel/frame along x", "frames": n_frames, "max_seeds": max_seeds,
+            "grid_frame_ms": gm, "warm_frame_ms": wm, "speedup": gm / wm, "warm_trajectories": warm_traj,
+            "grid_top_region": grid_top, "warm_top_region": warm_top[:],
+            "warm_top_saliency_over_grid_top": [a[4] / b[4] if a and b else None
+                                                for a, b in zip(warm_top, grid_top[1:])]}
 
 
 def measured_traffic(path):
@@ -368,10 +453,13 @@ def main():
                     pcie_inclusive_window_evals_per_s=window_evals / (dt / args.steps + h2d["pinned_ms"] * 1e-3)),
     }
     q_total = float(np.mean([s["ms_total"] for s in q_stats]))
-    line["dense_map"] = dense_section(ks, torch, ctx, q_total)
-    if not args.no_batch:
+    if not args.main_only:
+        line["dense_map"] = dense_section(ks, torch, ctx, q_total)
+        line["window_level"] = window_level_section(ks, torch, ctx)
+        line["tracking"] = tracking_section(ks, torch, ctx)
+    if not (args.no_batch or args.main_only):
         line["batch"] = batch_section(ks, torch, ctx)
-    if not args.no_serve:
+    if not (args.no_serve or args.main_only):
         line["serving"] = serving_section(ks, torch, ctx, args.serve_requests)
     if cpu is not None:
         line["cpu_baseline"] = cpu
