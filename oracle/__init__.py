@@ -42,6 +42,16 @@ class Region(C.Structure):
                 ("key", C.c_double), ("seed", C.c_int64)]
 
 
+class Ellipsoid(C.Structure):
+    _fields_ = [("id", C.c_int64), ("x0", C.c_int32), ("y0", C.c_int32), ("z0", C.c_int32), ("radius", C.c_int32),
+                ("x", C.c_double * 3), ("h", C.c_double * 6), ("rho", C.c_double), ("entropy", C.c_double),
+                ("iters", C.c_int32), ("stop", C.c_int32)]
+
+
+ABM_STOP = {"max_iter": 0, "converged": 1, "deteriorated": 2, "empty": 3, "degenerate": 4}
+ABM_TOL = 0.01
+
+
 class Stats(C.Structure):
     _fields_ = [("evals", C.c_int64), ("window_evals", C.c_int64), ("voxel_visits", C.c_int64)]
 
@@ -84,6 +94,8 @@ def lib():
         L.kso_detect_seeded.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_void_p, C.c_int64, i32p,
                                         C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_void_p,
                                         C.c_int32, i32p, C.POINTER(Stats)]
+        L.kso_abmsod.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32, C.c_void_p, C.c_int64,
+                                 i32p, C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -255,3 +267,31 @@ def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=No
                          C.byref(nf), C.byref(st))
     arr = np.ctypeslib.as_array(out)[:min(capacity, nf.value)].copy()
     return arr, nf.value, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}
+
+
+def abmsod(vol: np.ndarray, bins, spacing, radii, max_iter, threshold=0.0, seeds=None, ids=None, window=None):
+    """ABMSOD candidates (grid or seed list x radii, or the listed ids).  Returns
+    (structured array with fields id, x0, y0, z0, radius, x[3], h[6], rho,
+    entropy, iters, stop; stats dict)."""
+    vol = np.ascontiguousarray(vol)
+    z, y, x = vol.shape
+    R = radii[1] - radii[0] + 1
+    if seeds is not None:
+        sa, ns = _seeds(seeds)
+        sp_, nstart = sa.ctypes.data, ns
+    else:
+        sa, sp_, ns = None, None, 0
+        nstart = num_trajectories((x, y, z), spacing, (1, 1), QUADRANT)
+    if ids is None:
+        n, idp = nstart * R, None
+    else:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        n, idp = ids.size, ids.ctypes.data
+    out = (Ellipsoid * max(n, 1))()
+    st = Stats()
+    rc = lib().kso_abmsod(vol.ctypes.data, _DT[vol.dtype], _dims(vol), bins, _win(window), spacing, sp_, ns,
+                          (C.c_int32 * 2)(*radii), max_iter, float(threshold), idp, n, out, C.byref(st))
+    if rc != 0:
+        raise ValueError("seed outside the volume or bad radii")
+    arr = np.ctypeslib.as_array(out)[:n].copy()
+    return arr, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}

@@ -565,3 +565,216 @@ int kso_detect_seeded(const void* vol, int32_t dtype, const int32_t dims[3], int
     return detect_impl(vol, dtype, dims, bins, window, 1, seeds, n_seeds, scales, method, max_iter, h_min, y_min,
                        rank_by, out, capacity, n_found, stats);
 }
+
+/* ------------------------------------------------ ABMSOD (Sec. 2.3, Alg. 2) */
+
+/* Symmetric 3x3 matrices are stored as {xx, yy, zz, xy, xz, yz}. */
+
+/* Inverse by cofactors; 0 unless the matrix is positive definite (leading
+ * minors and determinant > 0). */
+static int sym3_inverse(const double h[6], double inv[6]) {
+    double a = h[0], d = h[1], f = h[2], b = h[3], c = h[4], e = h[5];
+    double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+    double det = a * c00 + b * c01 + c * c02;
+    if (!(a > 0.0) || !(a * d - b * b > 0.0) || !(det > 0.0)) return 0;
+    inv[0] = c00 / det;
+    inv[1] = (a * f - c * c) / det;
+    inv[2] = (a * d - b * b) / det;
+    inv[3] = c01 / det;
+    inv[4] = c02 / det;
+    inv[5] = (b * c - a * e) / det;
+    return 1;
+}
+
+/* Squared Mahalanobis distance u^T H^-1 u. */
+static double mahal(const double inv[6], const double u[3]) {
+    return inv[0] * u[0] * u[0] + inv[1] * u[1] * u[1] + inv[2] * u[2] * u[2] +
+           2.0 * (inv[3] * u[0] * u[1] + inv[4] * u[0] * u[2] + inv[5] * u[1] * u[2]);
+}
+
+/* The window of bandwidth H at x: the voxels v of the volume with
+ * (v - x)^T H^-1 (v - x) <= 5, the solid ellipsoid whose uniform second moment
+ * is H.  Its bounding box has half-extent sqrt(5 H_aa) along axis a. */
+typedef struct {
+    const uint8_t* bv;
+    const int32_t* dims;
+    int32_t bins;
+    int64_t visits;
+} abm_ctx;
+
+enum { ABM_HIST = 0, ABM_MEAN = 1, ABM_COV = 2 };
+
+/* One pass over the window at x with inverse bandwidth inv:
+ *   ABM_HIST: G[b] += exp(-d/2) (the Gaussian profile of Alg. 2, unnormalised p_b)
+ *   ABM_MEAN: acc[0] += g w, acc[1..3] += g w v      (Eq. 5; -K' of the Gaussian is g/2)
+ *   ABM_COV:  acc[0] += w,   acc[1..6] += w (x - v)(x - v)^T   (Eq. 7)
+ * with w = w_of_bin[bin(v)]; voxels of the sentinel bin (window level) are skipped. */
+static void abm_pass(abm_ctx* c, int kind, const double x[3], const double h[6], const double inv[6],
+                     const double* w_of_bin, double* G, double* acc) {
+    int32_t lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        double e = sqrt(5.0 * h[a]);
+        double l = ceil(x[a] - e), u = floor(x[a] + e);
+        lo[a] = l < 0 ? 0 : (int32_t)l;
+        hi[a] = u > c->dims[a] - 1 ? c->dims[a] - 1 : (int32_t)u;
+    }
+    for (int32_t z = lo[2]; z <= hi[2]; ++z)
+        for (int32_t y = lo[1]; y <= hi[1]; ++y)
+            for (int32_t vx = lo[0]; vx <= hi[0]; ++vx) {
+                double u[3] = {vx - x[0], y - x[1], z - x[2]};
+                double d = mahal(inv, u);
+                if (!(d <= 5.0)) continue;
+                c->visits += 1;
+                int32_t b = c->bv[vidx(c->dims, vx, y, z)];
+                if (b >= c->bins) continue;
+                if (kind == ABM_HIST) {
+                    G[b] += exp(-d / 2.0);
+                } else if (kind == ABM_MEAN) {
+                    double gw = exp(-d / 2.0) * w_of_bin[b];
+                    acc[0] += gw;
+                    acc[1] += gw * vx;
+                    acc[2] += gw * y;
+                    acc[3] += gw * z;
+                } else {
+                    double w = w_of_bin[b];
+                    acc[0] += w;
+                    acc[1] += w * u[0] * u[0];
+                    acc[2] += w * u[1] * u[1];
+                    acc[3] += w * u[2] * u[2];
+                    acc[4] += w * u[0] * u[1];
+                    acc[5] += w * u[0] * u[2];
+                    acc[6] += w * u[1] * u[2];
+                }
+            }
+}
+
+/* Weights of Eq. 5 for the uniform target q_b = 1/B: w_b = sqrt(q_b / p_b),
+ * p_b = G_b / sum G.  Returns sum G (0: empty window). */
+static double abm_weights(const double* G, int32_t bins, double* w) {
+    double tot = 0.0;
+    for (int32_t b = 0; b < bins; ++b) tot += G[b];
+    for (int32_t b = 0; b < bins; ++b) w[b] = G[b] > 0.0 ? sqrt((1.0 / bins) / (G[b] / tot)) : 0.0;
+    return tot;
+}
+
+static void abm_trajectory(abm_ctx* c, const int32_t p0[3], int32_t r, int32_t r_cap, int32_t max_iter,
+                           double threshold, kso_ellipsoid* t, kso_stats* st) {
+    const int32_t B = c->bins;
+    double* G = (double*)calloc((size_t)B, sizeof(double));
+    double* w = (double*)calloc((size_t)B, sizeof(double));
+    double x[3] = {p0[0], p0[1], p0[2]};
+    /* the ball of radius r + 1/2: its boundary passes through no lattice point */
+    const double h0 = (r + 0.5) * (r + 0.5) / 5.0;
+    double h[6] = {h0, h0, h0, 0.0, 0.0, 0.0};
+    double inv[6];
+    double best = 0.0;
+    t->x[0] = x[0]; t->x[1] = x[1]; t->x[2] = x[2];
+    memcpy(t->h, h, sizeof(h));
+    t->rho = 0.0;
+    t->entropy = 0.0;
+    int32_t it = 0, stop = KSO_ABM_MAX_ITER;
+    while (it < max_iter) {
+        sym3_inverse(h, inv);
+        /* position step (Eq. 4, 5) at x */
+        memset(G, 0, sizeof(double) * (size_t)B);
+        abm_pass(c, ABM_HIST, x, h, inv, NULL, G, NULL);
+        st->evals += 1;
+        if (abm_weights(G, B, w) == 0.0) { stop = KSO_ABM_EMPTY; break; }
+        double m[4] = {0, 0, 0, 0};
+        abm_pass(c, ABM_MEAN, x, h, inv, w, NULL, m);
+        double xn[3];
+        for (int a = 0; a < 3; ++a) {
+            xn[a] = m[a + 1] / m[0];
+            if (xn[a] < 0.0) xn[a] = 0.0;
+            if (xn[a] > c->dims[a] - 1) xn[a] = c->dims[a] - 1;
+        }
+        /* bandwidth step (Eq. 7) and coefficient at x_new with the same H */
+        memset(G, 0, sizeof(double) * (size_t)B);
+        abm_pass(c, ABM_HIST, xn, h, inv, NULL, G, NULL);
+        st->evals += 1;
+        double tot = abm_weights(G, B, w);
+        if (tot == 0.0) { stop = KSO_ABM_EMPTY; break; }
+        double rho = 0.0, ent = 0.0;
+        for (int32_t b = 0; b < B; ++b) {
+            if (G[b] <= 0.0) continue;
+            double p = G[b] / tot;
+            rho += sqrt(p * (1.0 / B));
+            ent -= p * log(p);
+        }
+        double s[7] = {0, 0, 0, 0, 0, 0, 0};
+        abm_pass(c, ABM_COV, xn, h, inv, w, NULL, s);
+        double hn[6], tmp[6];
+        for (int k = 0; k < 6; ++k) hn[k] = s[k + 1] / s[0];
+        if (!sym3_inverse(hn, tmp)) { stop = KSO_ABM_DEGENERATE; break; }
+        /* keep the window within the largest start window: half-extent r_cap + 1/2 */
+        double hmax = hn[0] > hn[1] ? hn[0] : hn[1];
+        if (hn[2] > hmax) hmax = hn[2];
+        const double cap2 = (r_cap + 0.5) * (r_cap + 0.5);
+        if (5.0 * hmax > cap2) {
+            double f = cap2 / (5.0 * hmax);
+            for (int k = 0; k < 6; ++k) hn[k] *= f;
+        }
+        /* best-so-far tracking and the termination test of Alg. 2 */
+        double delta = best - rho;
+        if (rho > best) {
+            best = rho;
+            memcpy(t->x, xn, sizeof(xn));
+            memcpy(t->h, hn, sizeof(hn));
+            t->rho = rho;
+            t->entropy = ent;
+        }
+        it += 1;
+        double dx = 0.0, dh = 0.0, hd = h[0];
+        for (int a = 0; a < 3; ++a) dx = fmax(dx, fabs(xn[a] - x[a]));
+        for (int k = 0; k < 6; ++k) dh = fmax(dh, fabs(hn[k] - h[k]));
+        hd = fmax(hd, fmax(h[1], h[2]));
+        memcpy(x, xn, sizeof(xn));
+        memcpy(h, hn, sizeof(hn));
+        if (delta > threshold) { stop = KSO_ABM_DETERIORATED; break; }
+        if (dx < KSO_ABM_TOL && dh < KSO_ABM_TOL * hd) { stop = KSO_ABM_CONVERGED; break; }
+    }
+    t->iters = it;
+    t->stop = stop;
+    free(G);
+    free(w);
+}
+
+int kso_abmsod(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+               int32_t spacing, const int32_t* seeds, int64_t n_seeds, const int32_t radii[2], int32_t max_iter,
+               double threshold, const int64_t* ids, int64_t n, kso_ellipsoid* out, kso_stats* stats) {
+    if (!seeds_ok(dims, seeds, n_seeds)) return -1;
+    if (radii[0] < 1 || radii[0] > radii[1]) return -1;
+    int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
+    uint8_t* bv = (uint8_t*)malloc((size_t)nv);
+    bin_any(vol, dtype, dims, bins, window, bv);
+    int32_t g[3], o[3];
+    grid_dims(dims, spacing, g, o);
+    int32_t R = radii[1] - radii[0] + 1;
+    int64_t n_start = seeds ? n_seeds : (int64_t)g[0] * g[1] * g[2];
+    if (ids == NULL) n = n_start * R;
+    abm_ctx c = {bv, dims, bins, 0};
+    kso_stats st = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t id = ids ? ids[i] : i;
+        int64_t seed = id / R;
+        int32_t r = radii[0] + (int32_t)(id % R);
+        int32_t p0[3];
+        if (seeds) {
+            p0[0] = seeds[3 * seed]; p0[1] = seeds[3 * seed + 1]; p0[2] = seeds[3 * seed + 2];
+        } else {
+            p0[0] = o[0] + (int32_t)(seed % g[0]) * spacing;
+            p0[1] = o[1] + (int32_t)((seed / g[0]) % g[1]) * spacing;
+            p0[2] = o[2] + (int32_t)(seed / ((int64_t)g[0] * g[1])) * spacing;
+        }
+        kso_ellipsoid* t = out + i;
+        t->id = id;
+        t->x0 = p0[0]; t->y0 = p0[1]; t->z0 = p0[2];
+        t->radius = r;
+        abm_trajectory(&c, p0, r, radii[1], max_iter, threshold, t, &st);
+    }
+    st.window_evals = st.evals;
+    st.voxel_visits = c.visits;
+    if (stats) *stats = st;
+    free(bv);
+    return 0;
+}

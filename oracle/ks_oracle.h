@@ -98,6 +98,45 @@ int kso_detect_seeded(const void* vol, int32_t dtype, const int32_t dims[3], int
                       int32_t max_iter, double h_min, double y_min, int32_t rank_by, kso_region* out,
                       int32_t capacity, int32_t* n_found, kso_stats* stats);
 
+/* ABMSOD (Sec. 2.3, Eq. 4, 5, 7, Alg. 2) with the uniform target pmf: a
+ * candidate is a centre x (real) and a bandwidth H (symmetric positive definite
+ * 3x3); its window is the voxels v with (v-x)^T H^-1 (v-x) <= 5, weighted by
+ * the Gaussian profile g = exp(-d/2).  One iteration moves x to the g*w-weighted
+ * mean of the window (Eq. 5, w = sqrt(q_b/p_b) of the voxel's bin), then, at the
+ * new centre with the same H, measures the Bhattacharyya coefficient rho to the
+ * uniform pmf and re-estimates H by Eq. 7 (w-weighted second moment about the
+ * new centre).  The best rho so far and its (x, H) are kept; the search stops
+ * when rho falls more than `threshold` below the best (Alg. 2), after max_iter
+ * iterations, when x moves less than KSO_ABM_TOL voxel and H less than
+ * KSO_ABM_TOL of its largest diagonal entry, when a window holds no counted
+ * voxel, or when the new H is not positive definite.  A new H whose bounding
+ * half-extent sqrt(5 H_aa) exceeds that of the largest start window (r + 1/2 for
+ * the largest radius r) is scaled down to it.
+ * Candidates: every start position (grid or seed list) x every radius r in
+ * [radii[0], radii[1]] (id = seed * R + r - radii[0]), starting from
+ * H = (r + 1/2)^2/5 I, the ball of radius r + 1/2 (whose boundary passes through
+ * no lattice point, so that rounding cannot move a voxel in or out). */
+enum { KSO_ABM_MAX_ITER = 0, KSO_ABM_CONVERGED = 1, KSO_ABM_DETERIORATED = 2, KSO_ABM_EMPTY = 3,
+       KSO_ABM_DEGENERATE = 4 };
+#define KSO_ABM_TOL 0.01
+typedef struct {
+    int64_t id;
+    int32_t x0, y0, z0, radius;  /* start position and radius */
+    double x[3];                 /* best centre */
+    double h[6];                 /* its bandwidth: xx, yy, zz, xy, xz, yz */
+    double rho;                  /* best Bhattacharyya coefficient (0: none) */
+    double entropy;              /* entropy (nats) of the weighted pmf behind it */
+    int32_t iters, stop;         /* iterations done, KSO_ABM_* */
+} kso_ellipsoid;
+/* seeds: NULL for the grid of `spacing`, else n_seeds positions (x, y, z);
+ * ids: NULL for every candidate, else the n candidate ids to run.  Stats:
+ * evals = window histograms (two per iteration), voxel_visits = window voxels
+ * of all four passes of every iteration.  -1 for a seed outside the volume or
+ * bad radii. */
+int kso_abmsod(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+               int32_t spacing, const int32_t* seeds, int64_t n_seeds, const int32_t radii[2], int32_t max_iter,
+               double threshold, const int64_t* ids, int64_t n, kso_ellipsoid* out, kso_stats* stats);
+
 /* Dense Kadir-Brady map: at every voxel, s* of the saliency step of the quadrant
  * method (0: no entropy peak) and the saliency at s* (sal: accurate Y_ref;
  * sal64, if not NULL: decision-precision Y).  x fastest. */

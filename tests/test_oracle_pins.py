@@ -636,3 +636,170 @@ def test_windowed_every_voxel_search_matches_brute_force():
     assert checked > 10
     plain = oracle.saliency_map(vol, bins, scales)[1]
     assert not np.array_equal(plain, scl)
+
+
+# ------------------------------------------------------ ABMSOD (Alg. 2, Eq. 7)
+
+def _sym(h):
+    return np.array([[h[0], h[3], h[4]], [h[3], h[1], h[5]], [h[4], h[5], h[2]]])
+
+
+def _oblique_blob(seed=3, shape=(40, 48, 48), centre=(24, 24, 20), semi=(10, 3.5, 3.5)):
+    """Constant background, textured ellipsoid whose long axis is the x-y diagonal."""
+    Z, Y, X = shape
+    rng = np.random.default_rng(seed)
+    v = np.full(shape, 40, np.uint8)
+    zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    axes = np.array([[1, 1, 0], [-1, 1, 0], [0, 0, np.sqrt(2)]]) / np.sqrt(2)
+    u = np.stack([xx - centre[0], yy - centre[1], zz - centre[2]], -1)
+    q = sum((u @ axes[k] / semi[k]) ** 2 for k in range(3))
+    m = q <= 1
+    v[m] = rng.integers(0, 256, int(m.sum()))
+    return v, axes[0]
+
+
+def test_abmsod_flat_volume_window_is_the_lattice_ball():
+    # One bin everywhere: the pmf is a point mass (rho = 1/sqrt(B), entropy 0),
+    # every weight is equal, so the mean stays at the centre and Eq. 7 gives the
+    # second moment of the window's lattice points: for H = (r + 1/2)^2/5 I the
+    # lattice points of the ball of radius r + 1/2.
+    v = np.full((31, 31, 31), 9, np.uint8)
+    B = 32
+    tr, st = oracle.abmsod(v, B, 1, (2, 12), 1, threshold=1e9, seeds=[(15, 15, 15)])
+    visits = 0
+    for t in tr:
+        r = int(t["radius"])
+        g = np.indices((2 * r + 1,) * 3).reshape(3, -1).T - r
+        ball = g[(g ** 2).sum(1) <= r * r + r]
+        visits += 4 * len(ball)
+        m2 = (ball[:, :, None] * ball[:, None, :]).mean(0)
+        if r == 12:  # the largest start window bounds the bandwidth
+            assert 5 * m2[0, 0] > 12.5 ** 2
+            m2 = m2 * 12.5 ** 2 / (5 * m2[0, 0])
+        assert np.allclose(t["x"], 15.0, atol=1e-9, rtol=0)
+        assert np.allclose(_sym(t["h"]), m2, atol=1e-9, rtol=0), r
+        assert abs(t["rho"] - 1 / math.sqrt(B)) < 1e-15 and t["entropy"] == 0.0
+        assert t["iters"] == 1
+        # the lattice ball's moment is within a few percent of the continuum's
+        assert abs(m2[0, 0] / ((r + 0.5) ** 2 / 5.0) - 1) < (0.15 if r < 3 else 0.04) or r == 12
+    assert st["voxel_visits"] == visits and st["evals"] == 2 * len(tr)
+
+
+def test_abmsod_coefficient_and_entropy_bounds():
+    v = random_u8(31, (22, 26, 30))
+    B = 24
+    tr, _ = oracle.abmsod(v, B, 5, (2, 6), 12)
+    ok = tr["rho"] > 0
+    assert ok.all()
+    # sum_b sqrt(p_b / B) lies in [1/sqrt(B), 1] for any pmf (Cauchy-Schwarz)
+    assert np.all(tr["rho"] >= 1 / math.sqrt(B) - 1e-12) and np.all(tr["rho"] <= 1 + 1e-12)
+    assert np.all(tr["entropy"] >= 0) and np.all(tr["entropy"] <= math.log(B) + 1e-12)
+    assert np.all((tr["iters"] <= 12) & (tr["iters"] >= 1))
+    for t in tr:
+        assert np.all(np.linalg.eigvalsh(_sym(t["h"])) > 0)
+        assert np.all((t["x"] >= 0) & (t["x"] <= np.array([29, 25, 21])))
+
+
+def random_u8(seed, shape):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 256, shape).astype(np.uint8)
+
+
+def test_abmsod_is_translation_equivariant():
+    v, _ = _oblique_blob()
+    seeds = np.array([(24, 24, 20), (20, 21, 19), (28, 26, 21), (22, 27, 18)])
+    t = np.array([3, -2, 1])
+    moved = np.roll(v, (t[2], t[1], t[0]), axis=(0, 1, 2))
+    a, _ = oracle.abmsod(v, 32, 1, (3, 7), 25, seeds=seeds)
+    b, _ = oracle.abmsod(moved, 32, 1, (3, 7), 25, seeds=seeds + t)
+    assert np.array_equal(a["iters"], b["iters"]) and np.array_equal(a["stop"], b["stop"])
+    assert np.allclose(b["x"], a["x"] + t, atol=1e-9, rtol=0)
+    assert np.allclose(b["h"], a["h"], atol=1e-9, rtol=0)
+    assert np.allclose(b["rho"], a["rho"], atol=1e-12, rtol=0)
+
+
+def test_abmsod_is_equivariant_under_an_axis_swap():
+    v, _ = _oblique_blob(seed=4, shape=(40, 44, 48), centre=(22, 23, 20))
+    seeds = np.array([(22, 23, 20), (19, 20, 18), (26, 25, 21)])
+    a, _ = oracle.abmsod(v, 32, 1, (3, 7), 25, seeds=seeds)
+    swapped = np.ascontiguousarray(v.transpose(2, 1, 0))   # x <-> z
+    b, _ = oracle.abmsod(swapped, 32, 1, (3, 7), 25, seeds=seeds[:, ::-1])
+    assert np.array_equal(a["iters"], b["iters"]) and np.array_equal(a["stop"], b["stop"])
+    assert np.allclose(b["x"], a["x"][:, ::-1], atol=1e-9, rtol=0)
+    perm = [2, 1, 0, 5, 4, 3]     # xx, yy, zz, xy, xz, yz under x <-> z
+    assert np.allclose(b["h"], a["h"][:, perm], atol=1e-9, rtol=0)
+
+
+def test_abmsod_aligns_with_an_oblique_blob():
+    # The reason for the adaptive bandwidth (Sec. 2.3): a window started as a
+    # ball inside an oblique, elongated structure turns and stretches along it.
+    v, axis = _oblique_blob()
+    tr, _ = oracle.abmsod(v, 32, 1, (5, 8), 40, seeds=[(24, 24, 20), (21, 21, 20), (27, 27, 20)])
+    for t in tr:
+        w, V = np.linalg.eigh(_sym(t["h"]))
+        angle = math.degrees(math.acos(min(1.0, abs(V[:, -1] @ axis))))
+        assert angle < 5.0, (t["radius"], angle)
+        assert math.sqrt(w[-1]) > 1.6 * math.sqrt(w[1]), t["radius"]
+        u = np.asarray(t["x"]) - [24, 24, 20]     # the centre stays inside the structure
+        assert (u @ axis / 10) ** 2 + (u[0] - u[1]) ** 2 / 2 / 3.5 ** 2 + (u[2] / 3.5) ** 2 < 1
+
+
+def test_abmsod_best_tracking_and_stops():
+    v = random_u8(32, (20, 24, 26))
+    prev = None
+    for k in range(1, 7):
+        tr, _ = oracle.abmsod(v, 16, 6, (2, 5), k, threshold=1e9)
+        if prev is not None:
+            assert np.all(tr["rho"] >= prev["rho"])
+            same = prev["stop"] != oracle.ABM_STOP["max_iter"]
+            assert np.array_equal(tr[same], prev[same])
+        prev = tr
+    # a negative threshold ends every search after its first iteration
+    tr, _ = oracle.abmsod(v, 16, 6, (2, 5), 10, threshold=-1.0)
+    assert np.all(tr["iters"] == 1) and np.all(tr["stop"] == oracle.ABM_STOP["deteriorated"])
+
+
+def test_abmsod_edge_cases():
+    v = random_u8(33, (12, 14, 16))
+    tr, st = oracle.abmsod(v, 16, 4, (2, 4), 0)
+    assert np.all(tr["iters"] == 0) and np.all(tr["stop"] == 0) and st["evals"] == 0
+    assert np.array_equal(tr["x"][:, 0], tr["x0"]) and np.all(tr["rho"] == 0)
+    r2 = (tr["radius"] + 0.5) ** 2 / 5
+    assert np.array_equal(tr["h"][:, 0], r2) and np.all(tr["h"][:, 3:] == 0)
+    # a window level that holds no voxel: every window is empty
+    tr, _ = oracle.abmsod(v, 16, 4, (2, 4), 5, window=(300, 400))
+    assert np.all(tr["stop"] == oracle.ABM_STOP["empty"]) and np.all(tr["iters"] == 0)
+    corners = [(0, 0, 0), (15, 13, 11)]
+    tr, _ = oracle.abmsod(v, 16, 4, (1, 3), 8, seeds=corners)
+    assert len(tr) == 6 and np.all(tr["x"] >= 0) and np.all(tr["x"] <= [15, 13, 11])
+    with pytest.raises(ValueError):
+        oracle.abmsod(v, 16, 4, (1, 3), 8, seeds=[(16, 0, 0)])
+    with pytest.raises(ValueError):
+        oracle.abmsod(v, 16, 4, (3, 2), 8)
+
+
+def test_abmsod_first_step_on_a_radial_two_bin_volume_by_brute_force():
+    # Bins depend only on |v - c|, so the mean stays at c and the first
+    # iteration's pmf, coefficient and bandwidth follow from the lattice points
+    # of the start ball alone: Gaussian profile exp(-d/2) with d = 5|u|^2/(r+1/2)^2
+    # (Alg. 2), weights sqrt(q_b/p_b) (Eq. 5), w-weighted second moment (Eq. 7).
+    c, B = 12, 8
+    zz, yy, xx = np.meshgrid(*(np.arange(25),) * 3, indexing="ij")
+    rr = (xx - c) ** 2 + (yy - c) ** 2 + (zz - c) ** 2
+    v = np.where(rr <= 6, 255, 0).astype(np.uint8)   # bins 7 (inner) and 0
+    for r in (3, 5):
+        tr, _ = oracle.abmsod(v, B, 1, (r, r + 4), 1, threshold=1e9, seeds=[(c, c, c)])
+        t = tr[0]   # radius r; the bandwidth cap (r + 4.5) does not bind
+        g = np.indices((2 * r + 1,) * 3).reshape(3, -1).T - r
+        u2 = (g ** 2).sum(1)
+        ball, u2 = g[u2 <= r * r + r], u2[u2 <= r * r + r]
+        kern = np.exp(-0.5 * 5.0 * u2 / (r + 0.5) ** 2)
+        inner = u2 <= 6
+        p = np.array([kern[~inner].sum(), kern[inner].sum()]) / kern.sum()
+        w = np.sqrt((1.0 / B) / p)
+        wv = np.where(inner, w[1], w[0])
+        h = (wv[:, None, None] * ball[:, :, None] * ball[:, None, :]).sum(0) / wv.sum()
+        assert np.allclose(t["x"], c, atol=1e-9, rtol=0)
+        assert abs(t["entropy"] + (p * np.log(p)).sum()) < 1e-12
+        assert abs(t["rho"] - np.sqrt(p / B).sum()) < 1e-12
+        assert np.allclose(_sym(t["h"]), h, atol=1e-9, rtol=0)
