@@ -254,6 +254,53 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
 ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
                           const int32_t scales[2], float* d_saliency, uint8_t* d_scale, void* stream);
 
+/* ------------------------------------------------------------------ ABMSOD */
+
+/* One ABMSOD candidate (Sec. 2.3, Alg. 2): an ellipsoidal window of centre x and
+ * bandwidth H, the voxels v with (v - x)^T H^-1 (v - x) <= 5 (the solid ellipsoid
+ * whose uniform second moment is H). */
+typedef struct {
+    int32_t x0, y0, z0;    /* start position */
+    int32_t radius;        /* start radius r: H = (r + 1/2)^2 / 5 I */
+    double x[3];           /* centre of the best iteration */
+    double h[6];           /* its bandwidth H: xx, yy, zz, xy, xz, yz */
+    double rho;            /* best Bhattacharyya coefficient to the uniform pmf (0: none) */
+    double entropy;        /* entropy (nats) of the Gaussian-weighted pmf behind it */
+    int32_t iters;         /* iterations done */
+    int32_t stop;          /* ks_abm_stop */
+} ks_ellipsoid;
+
+typedef enum {
+    KS_ABM_MAX_ITER = 0,      /* max_iter iterations */
+    KS_ABM_CONVERGED = 1,     /* centre moved < 0.01 voxel and H < 0.01 of its largest diagonal entry */
+    KS_ABM_DETERIORATED = 2,  /* coefficient fell more than `threshold` below the best (Alg. 2) */
+    KS_ABM_EMPTY = 3,         /* a window held no counted voxel */
+    KS_ABM_DEGENERATE = 4     /* the new H was not positive definite */
+} ks_abm_stop;
+
+/* ABMSOD search with the uniform target pmf (Sec. 2.3: Eq. 4 with the Gaussian
+ * profile exp(-d/2) of Alg. 2, the move of Eq. 5, the bandwidth of Eq. 7) from
+ * every start position (the seed grid of seed_spacing, or the context's seed
+ * list) and every start radius r in [radii[0], radii[1]]: candidate id =
+ * seed * R + r - radii[0], R = radii[1] - radii[0] + 1.  One iteration moves the
+ * centre to the Gaussian- and weight-weighted mean of its window (weights
+ * sqrt(q_b / p_b) of the voxel's bin, q_b = 1/B), then, at the new centre with
+ * the same H, measures the coefficient rho = sum_b sqrt(p_b q_b) and re-estimates
+ * H as the weight-weighted second moment of the window about the new centre; a
+ * new H whose half-extent sqrt(5 H_aa) exceeds radii[1] + 1/2 is scaled down to
+ * it, and new centres are clamped to the volume.  The best coefficient so far
+ * and its (centre, H) are kept (Alg. 2); see ks_abm_stop for the ends.  The
+ * binning, including a window level, follows the context's options.  Sums of
+ * the Gaussian profile are taken in 2^-40 fixed point (order-independent);
+ * everything else is IEEE double.
+ * out: host array of capacity candidates in id order; *n = number of candidates
+ * (capacity 0: count only).  KS_E_INVALID as for ks_seed_traces, or for radii
+ * outside 1..32, max_iter < 0, or a NaN threshold.  Returns when out is
+ * written. */
+ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
+                    int32_t seed_spacing, const int32_t radii[2], int32_t max_iter, double threshold,
+                    ks_ellipsoid* out, int32_t capacity, int32_t* n, void* stream);
+
 /* One request of a batch or of the server. */
 typedef struct {
     const void* volume;    /* device pointer (ks_detect_batch) or host pointer (ks_server_submit) */

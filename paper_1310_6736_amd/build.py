@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libks.so")
-SOURCES = ["ks_kernels.hip", "ks_runtime.cpp", "ks_server.cpp", "ks_roofline.hip"]
+SOURCES = ["ks_kernels.hip", "ks_abmsod.hip", "ks_runtime.cpp", "ks_server.cpp", "ks_roofline.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

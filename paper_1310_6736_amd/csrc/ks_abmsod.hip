@@ -1,0 +1,291 @@
+// ABMSOD search with the uniform target pmf (Sec. 2.3: Eq. 4 with the Gaussian
+// profile of Alg. 2, the move of Eq. 5, the bandwidth estimate of Eq. 7, and the
+// best-coefficient tracking and termination of Alg. 2).
+//
+// One wavefront per candidate (start position, start radius), persistent: a
+// wave pops candidates, largest radius first, from a device counter.  An
+// iteration makes four sweeps of the ellipsoid's bounding box, a voxel per lane
+// per step:
+//   1. Gaussian-weighted histogram at x            (LDS, 64-bit fixed point)
+//   2. weighted mean of the window at x (Eq. 5)    (registers, wave sum)
+//   3. Gaussian-weighted histogram at x_new         (LDS)
+//   4. weighted second moment at x_new (Eq. 7)     (registers, wave sum)
+// Window membership is (v-x)^T H^-1 (v-x) <= 5, evaluated per voxel.  The
+// histogram adds exp(-d/2) rounded to 2^-40 with 64-bit integer LDS atomics into
+// four replicas per wave, so its totals do not depend on the order of the
+// additions; the register sums are reduced by a fixed butterfly, which leaves
+// the same bits in every lane, so every lane takes the same decisions.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "../../include/ks.h"
+#include "ks_abmsod.h"
+#include "ks_device.h"
+
+namespace ks {
+namespace {
+
+constexpr int kAbmReplicas = 4;
+constexpr double kFix = 1099511627776.0;         // 2^40
+constexpr double kUnfix = 1.0 / 1099511627776.0;
+constexpr double kTol = 0.01;
+constexpr int kBlocksPerCu = 12;
+
+enum { kHist = 0, kMean = 1, kCov = 2 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Inverse of a symmetric 3x3 matrix {xx, yy, zz, xy, xz, yz} by cofactors;
+// false unless positive definite.
+__device__ __forceinline__ bool sym3_inv(const double h[6], double inv[6]) {
+    const double a = h[0], d = h[1], f = h[2], b = h[3], c = h[4], e = h[5];
+    const double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+    const double det = a * c00 + b * c01 + c * c02;
+    if (!(a > 0.0) || !(a * d - b * b > 0.0) || !(det > 0.0)) return false;
+    inv[0] = c00 / det;
+    inv[1] = (a * f - c * c) / det;
+    inv[2] = (a * d - b * b) / det;
+    inv[3] = c01 / det;
+    inv[4] = c02 / det;
+    inv[5] = (b * c - a * e) / det;
+    return true;
+}
+
+// Bounding box of the window, one voxel wider than sqrt(5 H_aa) on each side,
+// clipped to the volume (membership is decided per voxel).
+struct WinBox {
+    int x0, y0, z0, bx, by, bz;
+};
+
+__device__ __forceinline__ WinBox window_box(const VolDesc& v, const double x[3], const double h[6]) {
+    const int dims[3] = {v.X, v.Y, v.Z};
+    int lo[3], n[3];
+    for (int a = 0; a < 3; ++a) {
+        const double e = sqrt(5.0 * h[a]);
+        int l = (int)ceil(x[a] - e) - 1, u = (int)floor(x[a] + e) + 1;
+        l = l < 0 ? 0 : l;
+        u = u > dims[a] - 1 ? dims[a] - 1 : u;
+        lo[a] = l;
+        n[a] = u - l + 1;
+    }
+    return {lo[0], lo[1], lo[2], n[0], n[1], n[2]};
+}
+
+// One sweep of the window at x; returns the lane's count of window voxels.
+//   kHist: hist[bin] += round(exp(-d/2) 2^40)                (this lane's replica)
+//   kMean: acc[0] += g w, acc[1..3] += g w (v - x)            (Eq. 5)
+//   kCov:  acc[0] += w,   acc[1..6] += w (v - x)(v - x)^T     (Eq. 7)
+template <int KIND>
+__device__ __forceinline__ unsigned abm_sweep(const VolDesc& v, const double x[3], const double inv[6],
+                                              const WinBox& w, unsigned long long* hist, const double* wtab,
+                                              double* acc, int lane) {
+    const uint8_t* __restrict__ bins = v.bins;
+    const int q = 64 / w.bx, rem = 64 % w.bx;
+    int cx = lane % w.bx;
+    int cy = lane / w.bx;
+    int cz = 0;
+    while (cy >= w.by) { cy -= w.by; ++cz; }
+    unsigned visits = 0;
+    while (cz < w.bz) {
+        const int vx = w.x0 + cx, vy = w.y0 + cy, vz = w.z0 + cz;
+        const double u0 = vx - x[0], u1 = vy - x[1], u2 = vz - x[2];
+        const double d = inv[0] * u0 * u0 + inv[1] * u1 * u1 + inv[2] * u2 * u2 +
+                         2.0 * (inv[3] * u0 * u1 + inv[4] * u0 * u2 + inv[5] * u1 * u2);
+        if (d <= 5.0) {
+            ++visits;
+            const int b = bins[(int64_t)vz * v.slice + (int64_t)vy * v.xp + vx];
+            if (b < v.B) {
+                if (KIND == kHist) {
+                    const double g = exp(-d / 2.0);
+                    atomicAdd(&hist[b], (unsigned long long)__double2ull_rn(g * kFix));
+                } else if (KIND == kMean) {
+                    const double gw = exp(-d / 2.0) * wtab[b];
+                    acc[0] += gw;
+                    acc[1] += gw * u0;
+                    acc[2] += gw * u1;
+                    acc[3] += gw * u2;
+                } else {
+                    const double wb = wtab[b];
+                    acc[0] += wb;
+                    acc[1] += wb * u0 * u0;
+                    acc[2] += wb * u1 * u1;
+                    acc[3] += wb * u2 * u2;
+                    acc[4] += wb * u0 * u1;
+                    acc[5] += wb * u0 * u2;
+                    acc[6] += wb * u1 * u2;
+                }
+            }
+        }
+        cx += rem;
+        cy += q;
+        if (cx >= w.bx) { cx -= w.bx; ++cy; }
+        while (cy >= w.by) { cy -= w.by; ++cz; }
+    }
+    return visits;
+}
+
+// Folds the replicas into per-bin totals, clears them, writes the Eq. 5 weights
+// sqrt(q_b / p_b) (q_b = 1/B) into wtab and returns the total (fixed point).
+// rho and ent receive sum_b sqrt(p_b q_b) and -sum_b p_b ln p_b.
+__device__ __forceinline__ unsigned long long abm_fold(unsigned long long* hist, double* wtab, int B, int lane,
+                                                       double& rho, double& ent) {
+    __syncthreads();
+    unsigned long long part = 0;
+    for (int b = lane; b < B; b += 64) {
+        unsigned long long s = 0;
+        for (int r = 0; r < kAbmReplicas; ++r) {
+            s += hist[r * B + b];
+            hist[r * B + b] = 0;
+        }
+        part += s;
+        wtab[b] = (double)s;    // raw total until the sum over bins is known
+    }
+    const unsigned long long tot = wave_sum_u64(part);
+    const double totd = (double)tot * kUnfix;
+    double r0 = 0.0, e0 = 0.0;
+    for (int b = lane; b < B; b += 64) {
+        const double g = wtab[b] * kUnfix;
+        double wb = 0.0;
+        if (g > 0.0) {
+            const double p = g / totd;
+            wb = sqrt((1.0 / B) / p);
+            r0 += sqrt(p * (1.0 / B));
+            e0 -= p * log(p);
+        }
+        wtab[b] = wb;
+    }
+    rho = wave_sum(r0);
+    ent = wave_sum(e0);
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, ks_ellipsoid* out, Counters* cnt) {
+    extern __shared__ unsigned long long smem[];
+    const VolDesc& v = vols[0];
+    const int lane = threadIdx.x;
+    const int B = v.B;
+    unsigned long long* hist_all = smem;
+    double* wtab = reinterpret_cast<double*>(smem + kAbmReplicas * B);
+    unsigned long long* hist = hist_all;    // replica of this lane, offset by its index below
+    for (int i = lane; i < kAbmReplicas * B; i += 64) hist_all[i] = 0;
+    __syncthreads();
+    const int rep = lane & (kAbmReplicas - 1);
+    hist = hist_all + rep * B;
+    const long long ntask = a.n_start * a.R;
+    const double cap2 = (a.r_max + 0.5) * (a.r_max + 0.5);
+    for (;;) {
+        unsigned long long t0 = 0;
+        if (lane == 0) t0 = atomicAdd(&cnt->queue_head[1], 1ull);
+        const long long t = (long long)__shfl((long long)t0, 0, 64);
+        if (t >= ntask) break;
+        const int ridx = a.R - 1 - (int)(t / a.n_start);
+        const long long seed = t % a.n_start;
+        const long long id = seed * a.R + ridx;
+        const int r = a.r_min + ridx;
+        int p0[3];
+        seed_pos(v, seed, p0);
+        double x[3] = {(double)p0[0], (double)p0[1], (double)p0[2]};
+        const double h0 = (r + 0.5) * (r + 0.5) / 5.0;
+        double h[6] = {h0, h0, h0, 0.0, 0.0, 0.0};
+        double inv[6];
+        double best = 0.0, xo[3] = {x[0], x[1], x[2]}, ho[6], rho_o = 0.0, ent_o = 0.0;
+        for (int k = 0; k < 6; ++k) ho[k] = h[k];
+        int it = 0, stop = KS_ABM_MAX_ITER;
+        unsigned visits = 0;
+        int evals = 0;
+        while (it < a.max_iter) {
+            sym3_inv(h, inv);
+            // Eq. 4 and 5 at x
+            WinBox w = window_box(v, x, h);
+            visits += abm_sweep<kHist>(v, x, inv, w, hist, wtab, nullptr, lane);
+            ++evals;
+            double rho, ent;
+            if (abm_fold(hist_all, wtab, B, lane, rho, ent) == 0) { stop = KS_ABM_EMPTY; break; }
+            double m[4] = {0.0, 0.0, 0.0, 0.0};
+            visits += abm_sweep<kMean>(v, x, inv, w, hist, wtab, m, lane);
+            for (int k = 0; k < 4; ++k) m[k] = wave_sum(m[k]);
+            const double dims[3] = {(double)(v.X - 1), (double)(v.Y - 1), (double)(v.Z - 1)};
+            double xn[3];
+            for (int k = 0; k < 3; ++k) {
+                xn[k] = x[k] + m[k + 1] / m[0];
+                xn[k] = xn[k] < 0.0 ? 0.0 : (xn[k] > dims[k] ? dims[k] : xn[k]);
+            }
+            // coefficient and Eq. 7 at x_new with the same H
+            __syncthreads();
+            w = window_box(v, xn, h);
+            visits += abm_sweep<kHist>(v, xn, inv, w, hist, wtab, nullptr, lane);
+            ++evals;
+            if (abm_fold(hist_all, wtab, B, lane, rho, ent) == 0) { stop = KS_ABM_EMPTY; break; }
+            double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            visits += abm_sweep<kCov>(v, xn, inv, w, hist, wtab, s, lane);
+            for (int k = 0; k < 7; ++k) s[k] = wave_sum(s[k]);
+            __syncthreads();
+            double hn[6], tmp[6];
+            for (int k = 0; k < 6; ++k) hn[k] = s[k + 1] / s[0];
+            if (!sym3_inv(hn, tmp)) { stop = KS_ABM_DEGENERATE; break; }
+            double hmax = hn[0] > hn[1] ? hn[0] : hn[1];
+            if (hn[2] > hmax) hmax = hn[2];
+            if (5.0 * hmax > cap2) {
+                const double f = cap2 / (5.0 * hmax);
+                for (int k = 0; k < 6; ++k) hn[k] *= f;
+            }
+            // best-so-far tracking and the termination test of Alg. 2
+            const double delta = best - rho;
+            if (rho > best) {
+                best = rho;
+                for (int k = 0; k < 3; ++k) xo[k] = xn[k];
+                for (int k = 0; k < 6; ++k) ho[k] = hn[k];
+                rho_o = rho;
+                ent_o = ent;
+            }
+            ++it;
+            double dx = 0.0, dh = 0.0, hd = h[0];
+            for (int k = 0; k < 3; ++k) dx = fmax(dx, fabs(xn[k] - x[k]));
+            for (int k = 0; k < 6; ++k) dh = fmax(dh, fabs(hn[k] - h[k]));
+            hd = fmax(hd, fmax(h[1], h[2]));
+            for (int k = 0; k < 3; ++k) x[k] = xn[k];
+            for (int k = 0; k < 6; ++k) h[k] = hn[k];
+            if (delta > a.threshold) { stop = KS_ABM_DETERIORATED; break; }
+            if (dx < kTol && dh < kTol * hd) { stop = KS_ABM_CONVERGED; break; }
+        }
+        const unsigned long long nv = wave_sum_u64((unsigned long long)visits);
+        if (lane == 0) {
+            ks_ellipsoid e;
+            e.x0 = p0[0]; e.y0 = p0[1]; e.z0 = p0[2];
+            e.radius = r;
+            for (int k = 0; k < 3; ++k) e.x[k] = xo[k];
+            for (int k = 0; k < 6; ++k) e.h[k] = ho[k];
+            e.rho = rho_o;
+            e.entropy = ent_o;
+            e.iters = it;
+            e.stop = stop;
+            out[id] = e;
+            atomicAdd(&cnt->evals, (unsigned long long)evals);
+            atomicAdd(&cnt->voxel_visits, nv);
+        }
+    }
+}
+
+}  // namespace
+
+size_t abmsod_lds_bytes(int B) { return (size_t)kAbmReplicas * B * 8 + (size_t)B * 8; }
+
+int abmsod_blocks_per_cu() { return kBlocksPerCu; }
+
+hipError_t launch_abmsod(const VolDesc* vols, const AbmArgs& a, int B, int grid, ks_ellipsoid* out, Counters* cnt,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_abmsod, dim3(grid), dim3(64), abmsod_lds_bytes(B), st, vols, a, out, cnt);
+    return hipGetLastError();
+}
+
+}  // namespace ks

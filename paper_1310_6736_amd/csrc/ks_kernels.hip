@@ -736,23 +736,6 @@ __device__ __forceinline__ int find_seg(const TaskSeg* __restrict__ segs, int ns
     return lo;
 }
 
-__device__ __forceinline__ void seed_pos(const VolDesc& v, long long seed, int* p) {
-    if (v.seeds) {
-        p[0] = v.seeds[3 * seed];
-        p[1] = v.seeds[3 * seed + 1];
-        p[2] = v.seeds[3 * seed + 2];
-        return;
-    }
-    const long long gxy = (long long)v.gx * v.gy;
-    const int gz = (int)(seed / gxy);
-    const long long r = seed - (long long)gz * gxy;
-    const int gy = (int)(r / v.gx);
-    const int gx = (int)(r - (long long)gy * v.gx);
-    p[0] = v.ox + gx * v.sp;
-    p[1] = v.oy + gy * v.sp;
-    p[2] = v.oz + gz * v.sp;
-}
-
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
 struct LocalCounts {

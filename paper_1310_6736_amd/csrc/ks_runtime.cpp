@@ -14,6 +14,7 @@
 #include "ks_device.h"
 #include "ks_launch.h"
 #include "ks_runtime.h"
+#include "ks_abmsod.h"
 
 namespace ks {
 
@@ -177,8 +178,8 @@ void Context::destroy() {
     for (auto& g : graphs)
         if (g.exec) hipGraphExecDestroy(g.exec);
     graphs.clear();
-    Buffer* bufs[] = {&tables_buf, &d_vols, &d_segs, &d_bins, &d_rec, &d_sr, &d_bsum, &d_grank, &d_volint,
-                      &d_regions, &d_cnt, &d_hook, &d_hook_out, &d_raw};
+    Buffer* bufs[] = {&tables_buf, &d_vols, &d_segs, &d_seeds, &d_abm, &d_bins, &d_rec, &d_sr, &d_bsum,
+                      &d_grank, &d_volint, &d_regions, &d_cnt, &d_hook, &d_hook_out, &d_raw};
     for (Buffer* b : bufs) b->release();
     h_stage.release();
     h_out.release();
@@ -868,6 +869,76 @@ ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype,
         hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]);
         ctx->last.ms_prep = a; ctx->last.ms_search = b; ctx->last.ms_total = a + b;
     }
+    return KS_OK;
+}
+
+ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3], int32_t bins,
+                    int32_t seed_spacing, const int32_t radii[2], int32_t max_iter, double threshold,
+                    ks_ellipsoid* out, int32_t capacity, int32_t* n, void* stream) {
+    if (!ctx || !n || capacity < 0 || (capacity > 0 && !out) || threshold != threshold) return KS_E_INVALID;
+    ks_status s = check_request(d_volume, dtype, dims, bins, seed_spacing, radii, KS_MEANSHIFT, max_iter);
+    if (s != KS_OK) return s;
+    // prep as a quadrant volume (no y-fast copy); one start per seed
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = seed_spacing; v.scales[0] = radii[0]; v.scales[1] = radii[1]; v.method = KS_QUADRANT;
+    v.max_iter = 0; v.capacity = 0;
+    v.opt.window = ctx->opts.window; v.opt.win_lo = ctx->opts.win_lo; v.opt.win_hi = ctx->opts.win_hi;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
+    if ((s = apply_ctx_seeds(ctx, v)) != KS_OK) return s;
+    const int R = radii[1] - radii[0] + 1;
+    const int64_t n_start = num_trajectories(v);
+    if (n_start * R > (int64_t)INT32_MAX) return KS_E_INVALID;
+    const int64_t total = n_start * R;
+    if (capacity == 0) {  // count only
+        *n = (int32_t)total;
+        return KS_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
+    Plan p;
+    if ((s = ctx->plan({v}, p)) != KS_OK) return s;
+    if ((s = ctx->d_abm.ensure(sizeof(ks_ellipsoid) * (size_t)std::max<int64_t>(total, 1), &ctx->generation)) != KS_OK)
+        return s;
+    if ((s = ctx->upload(p, st)) != KS_OK) return s;
+    PrepArgs pa;
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
+    pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
+    if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[0], st));
+    if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
+    if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[1], st));
+    if (total > 0) {
+        AbmArgs a;
+        a.n_start = n_start; a.R = R; a.r_min = radii[0]; a.r_max = radii[1]; a.max_iter = max_iter;
+        a.threshold = threshold;
+        const int grid = (int)std::min<int64_t>(total, (int64_t)abmsod_blocks_per_cu() * ctx->num_cu);
+        if (launch_abmsod(static_cast<VolDesc*>(ctx->d_vols.ptr), a, bins, grid,
+                          static_cast<ks_ellipsoid*>(ctx->d_abm.ptr), static_cast<Counters*>(ctx->d_cnt.ptr),
+                          st) != hipSuccess)
+            return KS_E_DEVICE;
+    }
+    if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[2], st));
+    const int64_t w = std::min<int64_t>(capacity, total);
+    if (w > 0 && hipMemcpyAsync(out, ctx->d_abm.ptr, sizeof(ks_ellipsoid) * (size_t)w, hipMemcpyDeviceToHost, st) !=
+                     hipSuccess)
+        return KS_E_DEVICE;
+    Counters c;
+    if (hipMemcpyAsync(&c, ctx->d_cnt.ptr, sizeof(Counters), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return KS_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
+    std::memset(&ctx->last, 0, sizeof(ctx->last));
+    ctx->last.trajectories = total;
+    ctx->last.evals = (int64_t)c.evals;
+    ctx->last.window_evals = (int64_t)c.evals;
+    ctx->last.voxel_visits = (int64_t)c.voxel_visits;
+    if (ctx->profiling) {
+        float a0 = 0, b0 = 0;
+        hipEventElapsedTime(&a0, ctx->ev[0], ctx->ev[1]);
+        hipEventElapsedTime(&b0, ctx->ev[1], ctx->ev[2]);
+        ctx->last.ms_prep = a0; ctx->last.ms_search = b0; ctx->last.ms_total = a0 + b0;
+    }
+    *n = (int32_t)total;
     return KS_OK;
 }
 

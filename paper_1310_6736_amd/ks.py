@@ -27,7 +27,7 @@ EXPORTS = [
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
-    "ks_server_submit_tracked",
+    "ks_server_submit_tracked", "ks_abmsod",
 ]
 
 
@@ -67,6 +67,15 @@ def options(h_min=0.0, y_min=0.0, rank_by=0, window=None) -> Options:
     o.h_min, o.y_min, o.rank_by = float(h_min), float(y_min), int(rank_by)
     o.window, o.win_lo, o.win_hi = (0, 0, 0) if window is None else (1, int(window[0]), int(window[1]))
     return o
+
+
+class Ellipsoid(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("z0", C.c_int32), ("radius", C.c_int32),
+                ("x", C.c_double * 3), ("h", C.c_double * 6), ("rho", C.c_double), ("entropy", C.c_double),
+                ("iters", C.c_int32), ("stop", C.c_int32)]
+
+
+KS_ABM_MAX_ITER, KS_ABM_CONVERGED, KS_ABM_DETERIORATED, KS_ABM_EMPTY, KS_ABM_DEGENERATE = 0, 1, 2, 3, 4
 
 
 class Request(C.Structure):
@@ -121,6 +130,7 @@ def lib():
     L.ks_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
     L.ks_server_submit_tracked.argtypes = [vp, C.POINTER(Request), C.c_int64, i32, C.POINTER(C.c_uint64)]
     L.ks_context_set_seeds.argtypes = [vp, i32p, C.c_int64]
+    L.ks_abmsod.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, C.c_double, vp, i32, i32p, vp]
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
     L.ks_server_drain.argtypes = [vp]
     L.ks_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
@@ -308,6 +318,20 @@ def ks_seed_traces(ctx: Context, volume, bins, seed_spacing, scales, method, max
     n = C.c_int32()
     _check(lib().ks_seed_traces(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter, out,
                                 n_est.value, C.byref(n), _stream_ptr(stream)), "ks_seed_traces")
+    return np.ctypeslib.as_array(out)[:n.value].copy()
+
+
+def ks_abmsod(ctx: Context, volume, bins, seed_spacing, radii, max_iter, threshold=0.0, stream=None):
+    """ABMSOD candidates of a device volume (every start x every radius, in id
+    order) as a structured array."""
+    ptr, dt, dims = _volume_args(volume)
+    n_est = C.c_int32()
+    _check(lib().ks_abmsod(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(radii), max_iter, float(threshold),
+                           None, 0, C.byref(n_est), _stream_ptr(stream)), "ks_abmsod")
+    out = (Ellipsoid * max(n_est.value, 1))()
+    n = C.c_int32()
+    _check(lib().ks_abmsod(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(radii), max_iter, float(threshold),
+                           out, n_est.value, C.byref(n), _stream_ptr(stream)), "ks_abmsod")
     return np.ctypeslib.as_array(out)[:n.value].copy()
 
 

@@ -639,3 +639,88 @@ def test_batch_with_seed_lists(torch_dev, ctx):
         w = ws[k]
         want, wn, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, seeds=lists[i])
         compare_regions(out[i][0], out[i][1], want, wn, f"batch {i} {w.name}")
+
+
+# ------------------------------------------------------------------- ABMSOD
+
+def compare_ellipsoids(got, want, label, atol=1e-8):
+    """Starts, radii, iterations and stop reasons equal; centres (voxels),
+    bandwidths (voxel^2), coefficients and entropies within atol (the GPU sums
+    the Gaussian profile in 2^-40 fixed point, the oracle in double)."""
+    assert len(got) == len(want), label
+    for f in ("x0", "y0", "z0", "radius", "iters", "stop"):
+        bad = np.nonzero(got[f] != want[f])[0]
+        assert bad.size == 0, f"{label}: {f} differs at {bad[:10]}: got {got[f][bad[:5]]} want {want[f][bad[:5]]}"
+    for f in ("x", "h", "rho", "entropy"):
+        err = np.abs(np.asarray(got[f], np.float64) - np.asarray(want[f], np.float64))
+        assert err.max() <= atol, f"{label}: {f} max error {err.max():.3e}"
+
+
+def oblique_volume():
+    Z, Y, X = 40, 48, 52
+    rng = np.random.default_rng(61)
+    v = np.clip(np.rint(rng.normal(60, 3, (Z, Y, X))), 0, 255).astype(np.uint8)
+    zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    ax = np.array([1.0, 1.0, 0.5]) / 1.5
+    u = np.stack([xx - 26, yy - 24, zz - 20], -1).astype(float)
+    along = u @ ax
+    perp = np.linalg.norm(u - along[..., None] * ax, axis=-1)
+    m = (along / 11) ** 2 + (perp / 3.5) ** 2 <= 1
+    v[m] = rng.integers(0, 256, int(m.sum()))
+    return v
+
+
+def test_abmsod_oblique_structure_matches_oracle(torch_dev, ctx):
+    v = oblique_volume()
+    note("abmsod oblique 52x48x40 spacing 6 radii 3..7")
+    ks.ks_context_set_profiling(ctx, True)
+    try:
+        got = ks.ks_abmsod(ctx, dev(torch_dev, v), 32, 6, (3, 7), 30)
+        st = ks.ks_last_stats(ctx)
+    finally:
+        ks.ks_context_set_profiling(ctx, False)
+    want, wst = oracle.abmsod(v, 32, 6, (3, 7), 30)
+    compare_ellipsoids(got, want, "oblique")
+    assert st["evals"] == wst["evals"] and st["voxel_visits"] == wst["voxel_visits"]
+    assert st["trajectories"] == len(want)
+    assert np.any(want["stop"] == oracle.ABM_STOP["converged"])
+
+
+def test_abmsod_window_level_seeds_and_edges(torch_dev, ctx):
+    v = random_volume(62, (17, 21, 26), np.uint16, 0, 3000)
+    Z, Y, X = v.shape
+    seeds = np.array([(0, 0, 0), (X - 1, Y - 1, Z - 1), (13, 10, 8), (2, 19, 15), (13, 10, 8)], np.int32)
+    note("abmsod window level, seed list, corners")
+    ks.ks_context_set_options(ctx, ks.options(window=(500, 2200)))
+    ks.ks_context_set_seeds(ctx, seeds)
+    try:
+        got = ks.ks_abmsod(ctx, dev(torch_dev, v), 24, 3, (1, 5), 15, threshold=0.002)
+        got0 = ks.ks_abmsod(ctx, dev(torch_dev, v), 24, 3, (1, 5), 0)
+        ks.ks_context_set_options(ctx, ks.options(window=(3100, 3200)))   # holds no voxel
+        empty = ks.ks_abmsod(ctx, dev(torch_dev, v), 24, 3, (1, 5), 15)
+    finally:
+        ks.ks_context_set_options(ctx, None)
+        ks.ks_context_set_seeds(ctx, None)
+    want, _ = oracle.abmsod(v, 24, 3, (1, 5), 15, threshold=0.002, seeds=seeds, window=(500, 2200))
+    compare_ellipsoids(got, want, "window+seeds")
+    want0, _ = oracle.abmsod(v, 24, 3, (1, 5), 0, seeds=seeds, window=(500, 2200))
+    compare_ellipsoids(got0, want0, "max_iter 0", atol=0.0)
+    assert np.all(empty["stop"] == ks.KS_ABM_EMPTY) and np.all(empty["iters"] == 0)
+
+
+def test_abmsod_pet_sampled(torch_dev, ctx):
+    w = synth.pet_shell(ks.KS_QUADRANT)
+    radii, max_iter = (4, 16), 20
+    note(f"abmsod {w.name} radii {radii} (full GPU run, sampled oracle)")
+    got = ks.ks_abmsod(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, radii, max_iter)
+    ids = np.arange(0, len(got), 211)
+    want, _ = oracle.abmsod(w.volume, w.bins, w.spacing, radii, max_iter, ids=ids)
+    compare_ellipsoids(got[ids], want, w.name)
+
+
+def test_abmsod_validation(torch_dev, ctx):
+    v = dev(torch_dev, random_volume(63, (8, 9, 10), np.uint8, 0, 255))
+    for radii, it, thr in (((0, 3), 5, 0.0), ((4, 3), 5, 0.0), ((1, 33), 5, 0.0), ((1, 3), -1, 0.0),
+                           ((1, 3), 5, float("nan"))):
+        with pytest.raises(ks.KsError):
+            ks.ks_abmsod(ctx, v, 16, 3, radii, it, threshold=thr)
