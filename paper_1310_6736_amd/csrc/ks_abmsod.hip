@@ -4,8 +4,7 @@
 //
 // One wavefront per candidate (start position, start radius), persistent: a
 // wave pops candidates, largest radius first, from a device counter.  An
-// iteration makes four sweeps of the ellipsoid's bounding box, a voxel per lane
-// per step:
+// iteration makes four sweeps of the ellipsoid, a row interval per lane:
 //   1. Gaussian-weighted histogram at x            (LDS, 64-bit fixed point)
 //   2. weighted mean of the window at x (Eq. 5)    (registers, wave sum)
 //   3. Gaussian-weighted histogram at x_new         (LDS)
@@ -60,75 +59,85 @@ __device__ __forceinline__ bool sym3_inv(const double h[6], double inv[6]) {
     return true;
 }
 
-// Bounding box of the window, one voxel wider than sqrt(5 H_aa) on each side,
-// clipped to the volume (membership is decided per voxel).
-struct WinBox {
-    int x0, y0, z0, bx, by, bz;
-};
-
-__device__ __forceinline__ WinBox window_box(const VolDesc& v, const double x[3], const double h[6]) {
-    const int dims[3] = {v.X, v.Y, v.Z};
-    int lo[3], n[3];
-    for (int a = 0; a < 3; ++a) {
-        const double e = sqrt(5.0 * h[a]);
-        int l = (int)ceil(x[a] - e) - 1, u = (int)floor(x[a] + e) + 1;
-        l = l < 0 ? 0 : l;
-        u = u > dims[a] - 1 ? dims[a] - 1 : u;
-        lo[a] = l;
-        n[a] = u - l + 1;
-    }
-    return {lo[0], lo[1], lo[2], n[0], n[1], n[2]};
-}
-
-// One sweep of the window at x; returns the lane's count of window voxels.
+// One voxel of a sweep: the membership test (v-x)^T H^-1 (v-x) <= 5 and the
+// sweep's accumulation.
 //   kHist: hist[bin] += round(exp(-d/2) 2^40)                (this lane's replica)
 //   kMean: acc[0] += g w, acc[1..3] += g w (v - x)            (Eq. 5)
 //   kCov:  acc[0] += w,   acc[1..6] += w (v - x)(v - x)^T     (Eq. 7)
 template <int KIND>
-__device__ __forceinline__ unsigned abm_sweep(const VolDesc& v, const double x[3], const double inv[6],
-                                              const WinBox& w, unsigned long long* hist, const double* wtab,
+__device__ __forceinline__ void abm_voxel(const VolDesc& v, int vx, int vy, int vz, int b, const double x[3],
+                                          const double inv[6], unsigned long long* hist, const double* wtab,
+                                          double* acc, unsigned& visits) {
+    const double u0 = vx - x[0], u1 = vy - x[1], u2 = vz - x[2];
+    const double d = inv[0] * u0 * u0 + inv[1] * u1 * u1 + inv[2] * u2 * u2 +
+                     2.0 * (inv[3] * u0 * u1 + inv[4] * u0 * u2 + inv[5] * u1 * u2);
+    if (!(d <= 5.0)) return;
+    ++visits;
+    if (b >= v.B) return;
+    if (KIND == kHist) {
+        const double g = exp(-d / 2.0);
+        atomicAdd(&hist[b], (unsigned long long)__double2ull_rn(g * kFix));
+    } else if (KIND == kMean) {
+        const double gw = exp(-d / 2.0) * wtab[b];
+        acc[0] += gw;
+        acc[1] += gw * u0;
+        acc[2] += gw * u1;
+        acc[3] += gw * u2;
+    } else {
+        const double wb = wtab[b];
+        acc[0] += wb;
+        acc[1] += wb * u0 * u0;
+        acc[2] += wb * u1 * u1;
+        acc[3] += wb * u2 * u2;
+        acc[4] += wb * u0 * u1;
+        acc[5] += wb * u0 * u2;
+        acc[6] += wb * u1 * u2;
+    }
+}
+
+__device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+// One sweep of the window of bandwidth h at x, a row (y, z) per lane.  The
+// slice of the ellipsoid at z = x_z + c is the ellipse of the Schur complement
+// Hc = H_xy,xy - H_xy,z H_z,xy / H_zz, centred at x_xy + c H_xy,z / H_zz, of
+// squared radius 5 - c^2 / H_zz in the metric of Hc, and its row at y has a
+// closed-form x interval; the lane walks that interval widened by one voxel at
+// each end (the exact test decides membership), four voxels per dword load.
+// Returns the lane's count of window voxels.
+template <int KIND>
+__device__ __forceinline__ unsigned abm_sweep(const VolDesc& v, const double x[3], const double h[6],
+                                              const double inv[6], unsigned long long* hist, const double* wtab,
                                               double* acc, int lane) {
-    const uint8_t* __restrict__ bins = v.bins;
-    const int q = 64 / w.bx, rem = 64 % w.bx;
-    int cx = lane % w.bx;
-    int cy = lane / w.bx;
-    int cz = 0;
-    while (cy >= w.by) { cy -= w.by; ++cz; }
     unsigned visits = 0;
-    while (cz < w.bz) {
-        const int vx = w.x0 + cx, vy = w.y0 + cy, vz = w.z0 + cz;
-        const double u0 = vx - x[0], u1 = vy - x[1], u2 = vz - x[2];
-        const double d = inv[0] * u0 * u0 + inv[1] * u1 * u1 + inv[2] * u2 * u2 +
-                         2.0 * (inv[3] * u0 * u1 + inv[4] * u0 * u2 + inv[5] * u1 * u2);
-        if (d <= 5.0) {
-            ++visits;
-            const int b = bins[(int64_t)vz * v.slice + (int64_t)vy * v.xp + vx];
-            if (b < v.B) {
-                if (KIND == kHist) {
-                    const double g = exp(-d / 2.0);
-                    atomicAdd(&hist[b], (unsigned long long)__double2ull_rn(g * kFix));
-                } else if (KIND == kMean) {
-                    const double gw = exp(-d / 2.0) * wtab[b];
-                    acc[0] += gw;
-                    acc[1] += gw * u0;
-                    acc[2] += gw * u1;
-                    acc[3] += gw * u2;
-                } else {
-                    const double wb = wtab[b];
-                    acc[0] += wb;
-                    acc[1] += wb * u0 * u0;
-                    acc[2] += wb * u1 * u1;
-                    acc[3] += wb * u2 * u2;
-                    acc[4] += wb * u0 * u1;
-                    acc[5] += wb * u0 * u2;
-                    acc[6] += wb * u1 * u2;
-                }
+    const double h22 = h[2];
+    const double ey = sqrt(5.0 * h[1]), ez = sqrt(5.0 * h22);
+    const int ylo = clampi((int)ceil(x[1] - ey) - 1, 0, v.Y - 1), yhi = clampi((int)floor(x[1] + ey) + 1, 0, v.Y - 1);
+    const int zlo = clampi((int)ceil(x[2] - ez) - 1, 0, v.Z - 1), zhi = clampi((int)floor(x[2] + ez) + 1, 0, v.Z - 1);
+    const int ny = yhi - ylo + 1, nrow = ny * (zhi - zlo + 1);
+    const double k0 = h[4] / h22, k1 = h[5] / h22;
+    const double c00 = h[0] - h[4] * k0, c11 = h[1] - h[5] * k1, c01 = h[3] - h[4] * k1;
+    const double qy = c01 / c11, c00r = c00 - c01 * qy;
+    for (int row = lane; row < nrow; row += 64) {
+        const int zr = row / ny;
+        const int vz = zlo + zr, vy = ylo + (row - zr * ny);
+        const double c = vz - x[2];
+        const double rr = 5.0 - c * c / h22;
+        const double t = vy - (x[1] + c * k1);
+        const double rx = rr - t * t / c11;
+        if (rx < -1.0) continue;    // at least a voxel from the ellipse
+        const double mx = x[0] + c * k0 + qy * t, ex = sqrt(rx > 0.0 ? rx * c00r : 0.0);
+        const int xa = clampi((int)ceil(mx - ex) - 1, 0, v.X - 1);
+        const int xb = clampi((int)floor(mx + ex) + 1, 0, v.X - 1);
+        const uint8_t* rowp = v.bins + (int64_t)vz * v.slice + (int64_t)vy * v.xp;
+        for (int x4 = xa & ~3; x4 <= xb; x4 += 4) {
+            const uint32_t word = *reinterpret_cast<const uint32_t*>(rowp + x4);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int vx = x4 + k;
+                if (vx < xa || vx > xb) continue;
+                abm_voxel<KIND>(v, vx, vy, vz, (word >> (8 * k)) & 0xFFu, x, inv, hist, wtab, acc, visits);
             }
         }
-        cx += rem;
-        cy += q;
-        if (cx >= w.bx) { cx -= w.bx; ++cy; }
-        while (cy >= w.by) { cy -= w.by; ++cz; }
     }
     return visits;
 }
@@ -206,13 +215,12 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
         while (it < a.max_iter) {
             sym3_inv(h, inv);
             // Eq. 4 and 5 at x
-            WinBox w = window_box(v, x, h);
-            visits += abm_sweep<kHist>(v, x, inv, w, hist, wtab, nullptr, lane);
+            visits += abm_sweep<kHist>(v, x, h, inv, hist, wtab, nullptr, lane);
             ++evals;
             double rho, ent;
             if (abm_fold(hist_all, wtab, B, lane, rho, ent) == 0) { stop = KS_ABM_EMPTY; break; }
             double m[4] = {0.0, 0.0, 0.0, 0.0};
-            visits += abm_sweep<kMean>(v, x, inv, w, hist, wtab, m, lane);
+            visits += abm_sweep<kMean>(v, x, h, inv, hist, wtab, m, lane);
             for (int k = 0; k < 4; ++k) m[k] = wave_sum(m[k]);
             const double dims[3] = {(double)(v.X - 1), (double)(v.Y - 1), (double)(v.Z - 1)};
             double xn[3];
@@ -222,12 +230,11 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
             }
             // coefficient and Eq. 7 at x_new with the same H
             __syncthreads();
-            w = window_box(v, xn, h);
-            visits += abm_sweep<kHist>(v, xn, inv, w, hist, wtab, nullptr, lane);
+            visits += abm_sweep<kHist>(v, xn, h, inv, hist, wtab, nullptr, lane);
             ++evals;
             if (abm_fold(hist_all, wtab, B, lane, rho, ent) == 0) { stop = KS_ABM_EMPTY; break; }
             double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            visits += abm_sweep<kCov>(v, xn, inv, w, hist, wtab, s, lane);
+            visits += abm_sweep<kCov>(v, xn, h, inv, hist, wtab, s, lane);
             for (int k = 0; k < 7; ++k) s[k] = wave_sum(s[k]);
             __syncthreads();
             double hn[6], tmp[6];
