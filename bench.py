@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6  # MI355X fp64 vector, published
 
 
 def parse():
@@ -41,6 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-stride", type=int, default=1)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_k_search_ms_pet128x128x64.json"))
+    ap.add_argument("--abmsod-ops-json", default=os.path.join(ROOT, "profiles", "alu_k_abmsod_pet128x128x64.json"))
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -280,10 +282,46 @@ def tracking_section(ks, torch, ctx, n_frames=5, max_seeds=20):
                                                 for a, b in zip(warm_top, grid_top[1:])]}
 
 
-def measured_traffic(path):
-    """HBM bytes per launch of the mean-shift search from the committed counter
-    summary, or None when the kernel sources have changed since the counters were
-    taken (the summary records a SHA-256 of the files that define the kernel)."""
+def abmsod_section(ks, torch, ctx, ops_json):
+    """ABMSOD (ellipsoidal Gaussian-weighted windows with bandwidth updates) on the
+    PET-like volume: every grid seed x every start radius 4..16, 20 iterations.
+    Bound by fp64 arithmetic: the fp64 operations per window voxel come from the
+    committed counter summary (None once the kernel sources have changed)."""
+    from paper_1310_6736_amd import synth
+
+    w = synth.pet_shell(ks.KS_QUADRANT)
+    radii, max_iter = (4, 16), 20
+    v = torch.from_numpy(w.volume).to("cuda:0")
+    ks.ks_context_set_profiling(ctx, True)
+    try:
+        out = ks.ks_abmsod(ctx, v, w.bins, w.spacing, radii, max_iter)
+        ts, st = [], None
+        for _ in range(3):
+            out = ks.ks_abmsod(ctx, v, w.bins, w.spacing, radii, max_iter)
+            st = ks.ks_last_stats(ctx)
+            ts.append(st["ms_search"])
+    finally:
+        ks.ks_context_set_profiling(ctx, False)
+    m = float(np.median(ts))
+    visits_per_s = st["voxel_visits"] / (m * 1e-3)
+    ops = measured_record(ops_json, "fp64_ops_per_visit")
+    line = {"workload": w.name + ", radii 4..16, 20 iterations, threshold 0", "kernel": "k_abmsod",
+            "candidates": int(len(out)), "device_ms": m, "window_histograms": int(st["evals"]),
+            "window_voxel_visits": int(st["voxel_visits"]), "visits_per_s": visits_per_s,
+            "mean_iterations": float(out["iters"].mean()),
+            "stops": {k: int(n) for k, n in zip(("max_iter", "converged", "deteriorated", "empty", "degenerate"),
+                                                np.bincount(out["stop"], minlength=5))}}
+    achieved = None if ops is None else ops * visits_per_s / 1e12
+    line["roofline"] = {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS, "achieved": achieved,
+                        "frac": None if achieved is None else achieved / FP64_PEAK_TFLOPS,
+                        "fp64_ops_per_visit": ops}
+    return line
+
+
+def measured_record(path, field):
+    """A field of a committed counter summary, or None when the kernel sources
+    have changed since the counters were taken (the summary records a SHA-256 of
+    the files that define the kernel)."""
     import hashlib
 
     if not os.path.exists(path):
@@ -296,9 +334,15 @@ def measured_traffic(path):
                 h.update(fh.read())
         if h.hexdigest() != rec["source_sha256"]:
             return None
-        return rec["bytes_per_launch"]
+        return rec[field]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic(path):
+    """HBM bytes per launch of the mean-shift search from the committed counter
+    summary, or None when the kernel sources have changed since then."""
+    return measured_record(path, "bytes_per_launch")
 
 
 def _oracle_shard(job):
@@ -457,6 +501,7 @@ def main():
         line["dense_map"] = dense_section(ks, torch, ctx, q_total)
         line["window_level"] = window_level_section(ks, torch, ctx)
         line["tracking"] = tracking_section(ks, torch, ctx)
+        line["abmsod"] = abmsod_section(ks, torch, ctx, args.abmsod_ops_json)
     if not (args.no_batch or args.main_only):
         line["batch"] = batch_section(ks, torch, ctx)
     if not (args.no_serve or args.main_only):
