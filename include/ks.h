@@ -101,6 +101,8 @@ typedef struct {
                               of the mean-shift search, fewer than voxel_visits + final_visits */
     int64_t lds_ops;       /* lane-level LDS atomic additions of the searches (histogram
                               scatter, including the adds of padding bytes into spare slots) */
+    double ms_search_quad, ms_search_ms; /* device time of each search launch (profiling on;
+                              0 for a method the call does not run) */
 } ks_run_stats;
 
 /* Selection and order of the output regions.  A trajectory yields a region when
@@ -181,7 +183,15 @@ ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct);
  * than 2^31 - 1 trajectories.  An empty list finds no region. */
 ks_status ks_context_set_seeds(ks_context* ctx, const int32_t* seeds, int64_t n_seeds);
 
-/* Counters and times of the last detect/batch call on this context. */
+/* Runs the quadrant and mean-shift searches of one call (a batch holding both
+ * methods) concurrently on two streams, so that the blocks of each fill the
+ * other's tail (on = 1, the default), or one after the other (0).  Results do
+ * not depend on it. */
+ks_status ks_context_set_overlap(ks_context* ctx, int32_t on);
+
+/* Counters and times of the last detect/batch call on this context.  With
+ * profiling on, ks_detect_batch runs its launch sequence directly instead of
+ * through a captured graph, so that the phases can be timed. */
 ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out);
 
 /* Detection on a host volume (synchronous).  Uses a library-owned context on

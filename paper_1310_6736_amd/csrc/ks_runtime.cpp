@@ -412,10 +412,20 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
     sq.rec = rec; sq.cnt = dc;
     SearchArgs sm = sq;
     sm.segs = ds + p.segs_q.size(); sm.nseg = (int)p.segs_m.size(); sm.ntask = p.ntask_m;
+    // with both methods and overlap on, the mean-shift search runs on the aux stream
+    // beside the quadrant search, so that each fills the other's tail
+    const bool fork = p.ntask_q > 0 && p.ntask_m > 0 && overlap;
+    hipStream_t sm_st = fork ? aux : st;
+    if (fork) {
+        KS_HIP(hipEventRecord(fork_ev, st));
+        KS_HIP(hipStreamWaitEvent(aux, fork_ev, 0));
+    }
     if (p.ntask_q > 0) {
         const int per_cu = max_blocks_quad(p.lay.bytes, p.maxB_quad);
         const long long g = std::min<long long>(p.ntask_q, std::max<long long>(1, (long long)per_cu * num_cu * grid_pct / 100));
+        if (timed) KS_HIP(hipEventRecord(ev[6], st));
         KS_HIP(launch_search_quad(sq, (int)g, p.rq, p.lay, p.maxB_quad, st));
+        if (timed) KS_HIP(hipEventRecord(ev[7], st));
     }
     if (p.ntask_m > 0) {
         const int per_cu = max_blocks_ms(p.ms_hist_words, p.maxB_ms);
@@ -425,7 +435,13 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         tune.rl_small = p.rl_small;
         tune.s_small = ms_s_small;
         tune.incr_pct = ms_incr_pct;
-        KS_HIP(launch_search_ms(sm, (int)g, tune, p.ms_hist_words, p.maxB_ms, st));
+        if (timed) KS_HIP(hipEventRecord(ev[4], sm_st));
+        KS_HIP(launch_search_ms(sm, (int)g, tune, p.ms_hist_words, p.maxB_ms, sm_st));
+        if (timed) KS_HIP(hipEventRecord(ev[5], sm_st));
+    }
+    if (fork) {
+        KS_HIP(hipEventRecord(join_ev, aux));
+        KS_HIP(hipStreamWaitEvent(st, join_ev, 0));
     }
     if (timed) KS_HIP(hipEventRecord(ev[2], st));
     if (with_rank) {
@@ -470,6 +486,10 @@ void Context::collect_stats(const Plan& p, bool timed) {
         hipEventElapsedTime(&b, ev[1], ev[2]);
         hipEventElapsedTime(&d, ev[2], ev[3]);
         last.ms_prep = a; last.ms_search = b; last.ms_rank = d; last.ms_total = a + b + d;
+        float m = 0, q = 0;
+        if (p.ntask_m > 0) hipEventElapsedTime(&m, ev[4], ev[5]);
+        if (p.ntask_q > 0) hipEventElapsedTime(&q, ev[6], ev[7]);
+        last.ms_search_ms = m; last.ms_search_quad = q;
     }
 }
 
@@ -528,6 +548,7 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     key.push_back(ms_rl_small_pref);
     key.push_back(ms_s_small);
     key.push_back(quad_rq_pref);
+    key.push_back(overlap ? 1 : 0);
     for (const VolIn& v : in) {
         key.push_back((int64_t)(intptr_t)v.raw);
         key.push_back(v.dtype); key.push_back(v.dims[0]); key.push_back(v.dims[1]); key.push_back(v.dims[2]);
@@ -670,6 +691,12 @@ ks_status ks_context_set_options(ks_context* ctx, const ks_options* options) {
 ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct) {
     if (!ctx || incremental_pct < 0 || incremental_pct > 200) return KS_E_INVALID;
     ctx->ms_incr_pct = incremental_pct;
+    return KS_OK;
+}
+
+ks_status ks_context_set_overlap(ks_context* ctx, int32_t on) {
+    if (!ctx || (on != 0 && on != 1)) return KS_E_INVALID;
+    ctx->overlap = on != 0;
     return KS_OK;
 }
 
@@ -1036,7 +1063,9 @@ ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks
     if (n == 0) return KS_OK;
     std::vector<std::vector<ks_region>> res;
     std::vector<int> nf;
-    ks_status s = ctx->detect_batch_graph(in, static_cast<hipStream_t>(stream), &res, &nf);
+    // with profiling on, the direct launch sequence (per-phase and per-search events)
+    ks_status s = ctx->profiling ? ctx->detect_volumes(in, static_cast<hipStream_t>(stream), &res, &nf)
+                                 : ctx->detect_batch_graph(in, static_cast<hipStream_t>(stream), &res, &nf);
     if (s != KS_OK) return s;
     for (int i = 0; i < n; ++i) {
         if (!res[(size_t)i].empty())

@@ -64,7 +64,7 @@ struct GraphEntry {
 };
 
 struct Context {
-    static constexpr int kEvents = 4;
+    static constexpr int kEvents = 8;   // phases 0..3, then mean-shift and quadrant search begin/end
     int device = 0;
     int num_cu = 256;
     bool profiling = false;
@@ -72,6 +72,7 @@ struct Context {
     int ms_rl_small_pref = 2;
     int ms_s_small = 6;
     int ms_incr_pct = 100;  // running-window updates while cheaper than a fresh window
+    bool overlap = true;    // quadrant and mean-shift searches of one call on two streams
     ks_options opts{};      // selection and order for ks_detect_device / ks_seed_traces
     bool use_seeds = false; // explicit start positions for ks_detect_device / ks_seed_traces
     std::vector<int32_t> seeds;

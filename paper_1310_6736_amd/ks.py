@@ -27,7 +27,7 @@ EXPORTS = [
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
-    "ks_server_submit_tracked", "ks_abmsod",
+    "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap",
 ]
 
 
@@ -53,7 +53,8 @@ class RunStats(C.Structure):
     _fields_ = [("trajectories", C.c_int64), ("evals", C.c_int64), ("window_evals", C.c_int64),
                 ("voxel_visits", C.c_int64), ("final_visits", C.c_int64), ("regions", C.c_int64),
                 ("ms_prep", C.c_double), ("ms_search", C.c_double), ("ms_rank", C.c_double),
-                ("ms_total", C.c_double), ("swept_voxels", C.c_int64), ("lds_ops", C.c_int64)]
+                ("ms_total", C.c_double), ("swept_voxels", C.c_int64), ("lds_ops", C.c_int64),
+                ("ms_search_quad", C.c_double), ("ms_search_ms", C.c_double)]
 
 
 class Options(C.Structure):
@@ -130,6 +131,7 @@ def lib():
     L.ks_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
     L.ks_server_submit_tracked.argtypes = [vp, C.POINTER(Request), C.c_int64, i32, C.POINTER(C.c_uint64)]
     L.ks_context_set_seeds.argtypes = [vp, i32p, C.c_int64]
+    L.ks_context_set_overlap.argtypes = [vp, i32]
     L.ks_abmsod.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, C.c_double, vp, i32, i32p, vp]
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
     L.ks_server_drain.argtypes = [vp]
@@ -270,6 +272,10 @@ def ks_context_set_seeds(ctx: Context, seeds=None):
     a, n = _seed_array(seeds)
     _check(lib().ks_context_set_seeds(ctx.handle, a.ctypes.data_as(C.POINTER(C.c_int32)), n),
            "ks_context_set_seeds")
+
+
+def ks_context_set_overlap(ctx: Context, on: bool):
+    _check(lib().ks_context_set_overlap(ctx.handle, int(bool(on))), "ks_context_set_overlap")
 
 
 def ks_context_set_ms_update(ctx: Context, incremental_pct: int = 100):

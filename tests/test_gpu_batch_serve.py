@@ -235,3 +235,30 @@ def test_server_tracked_frames_start_from_the_previous_regions(torch_dev):
                 seeds = nxt if nxt else None
     # a warm-started frame runs max_seeds trajectories per scale, not the grid
     assert got[(7, 3)][1] <= max_seeds
+
+
+def test_batch_overlapped_searches_equal_sequential(torch_dev, ctx):
+    """The quadrant and mean-shift searches of a batch run concurrently on two
+    streams by default; results equal the sequential launch order, through the
+    captured graph and through the direct (profiled) launch sequence."""
+    ws = small_mix()
+    vols = [torch_dev.from_numpy(w.volume).to("cuda:0") for w in ws]
+    reqs = [ks.make_request(v, w.bins, w.spacing, w.scales, w.method, w.max_iter) for v, w in zip(vols, ws)]
+    note("batch: overlapped vs sequential searches")
+    out = {}
+    try:
+        for ov in (0, 1):
+            ks.ks_context_set_overlap(ctx, ov)
+            for prof in (0, 1):
+                ks.ks_context_set_profiling(ctx, prof)
+                out[(ov, prof)] = ks.ks_detect_batch(ctx, reqs, capacity=4096)
+                if prof:
+                    st = ks.ks_last_stats(ctx)
+                    assert st["ms_search_quad"] > 0 and st["ms_search_ms"] > 0
+    finally:
+        ks.ks_context_set_overlap(ctx, 1)
+        ks.ks_context_set_profiling(ctx, 0)
+    ref = out[(0, 0)]
+    for key, res in out.items():
+        for i in range(len(ws)):
+            assert res[i][1] == ref[i][1] and np.array_equal(res[i][0], ref[i][0]), (key, i)
