@@ -140,7 +140,10 @@ ks_status ks_context_destroy(ks_context* ctx);
 /* Turn per-phase device timing (HIP events) on or off; off by default. */
 ks_status ks_context_set_profiling(ks_context* ctx, int32_t on);
 
-/* Tuning of the scatter kernels (the values the built-in tuner picks by default).
+/* Tuning of the scatter kernels (defaults: 2^4 replicas per wave for mean-shift
+ * windows of half-width > 6 and 2^2 up to 6, one octant histogram per quadrant
+ * workgroup, measured on the PET-like and MR-like workloads;
+ * ks_context_autotune picks them for a given workload).
  * ms_replicas_log2 in [2,6]: packed LDS histogram replicas per wavefront of the
  * mean-shift scatter, 2^value (also sets the small-window value);
  * quad_replicas_log2 in [0,3]: replicas per workgroup of the octant scatter.
@@ -152,6 +155,20 @@ ks_status ks_context_set_tuning(ks_context* ctx, int32_t ms_replicas_log2, int32
 /* Mean-shift windows of half-width <= s_small use 2^ms_small_replicas_log2
  * replicas (ms_small_replicas_log2 in [2,6], s_small >= 0). */
 ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas_log2, int32_t s_small);
+
+/* Autotuning by window-size class: runs the search of one request (device
+ * volume, ks_detect_device parameters) under a set of candidate tunings and
+ * keeps, in the context, the fastest by device time of the search launch:
+ * mean-shift, the replicas per wave of large windows (2^3..2^5), then the
+ * replicas and the half-width bound of the small-window class (2^2..2^3 up to
+ * s_small in {4, 6, 8}); quadrant, the replicas per workgroup (2^0..2^2, as the
+ * LDS budget allows).  Each candidate is timed `reps` times (1..16) after one
+ * warm-up and scored by its fastest run.  Results of later calls do not depend
+ * on the tuning.  Leaves profiling as it was; out: NULL or the chosen
+ * {ms_replicas_log2, ms_small_replicas_log2, s_small, quad_replicas_log2}. */
+ks_status ks_context_autotune(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                              int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                              int32_t max_iter, int32_t reps, int32_t out[4], void* stream);
 
 /* Options for the context's later ks_detect_device and ks_seed_traces calls
  * (ks_detect always uses the defaults; batch and server requests carry their

@@ -677,6 +677,75 @@ ks_status ks_context_set_tuning_small(ks_context* ctx, int32_t ms_small_replicas
     return KS_OK;
 }
 
+static ks_status apply_ctx_seeds(const ks_context* ctx, VolIn& v);
+
+ks_status ks_context_autotune(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                              int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                              int32_t max_iter, int32_t reps, int32_t out[4], void* stream) {
+    if (!ctx || reps < 1 || reps > 16) return KS_E_INVALID;
+    ks_status s = check_request(d_volume, dtype, dims, bins, seed_spacing, scales, method, max_iter);
+    if (s != KS_OK) return s;
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
+    v.max_iter = max_iter; v.capacity = 1;
+    v.opt = ctx->opts;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
+    if ((s = apply_ctx_seeds(ctx, v)) != KS_OK) return s;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool prof = ctx->profiling;
+    ctx->profiling = true;
+    // device time of the search launch under the context's current tuning: the
+    // fastest of reps runs after a warm-up
+    auto measure = [&](double* best) -> ks_status {
+        std::vector<std::vector<ks_region>> res;
+        std::vector<int> nf;
+        *best = 1e30;
+        for (int r = 0; r <= reps; ++r) {
+            ks_status e = ctx->detect_volumes({v}, st, &res, &nf);
+            if (e != KS_OK) return e;
+            const double t = method == KS_MEANSHIFT ? ctx->last.ms_search_ms : ctx->last.ms_search_quad;
+            if (r > 0 && t < *best) *best = t;
+        }
+        return KS_OK;
+    };
+    double t;
+    if (method == KS_MEANSHIFT) {
+        // large-window class first (the small class at its current setting), then the small class
+        int best_rl = ctx->ms_rl_pref;
+        double best_t = 1e30;
+        for (int rl = 3; rl <= 5 && s == KS_OK; ++rl) {
+            ctx->ms_rl_pref = rl;
+            if ((s = measure(&t)) == KS_OK && t < best_t) { best_t = t; best_rl = rl; }
+        }
+        ctx->ms_rl_pref = best_rl;
+        int best_rls = ctx->ms_rl_small_pref, best_ss = ctx->ms_s_small;
+        for (int rls = 2; rls <= 3 && s == KS_OK; ++rls)
+            for (int ss = 4; ss <= 8 && s == KS_OK; ss += 2) {
+                ctx->ms_rl_small_pref = rls;
+                ctx->ms_s_small = ss;
+                if ((s = measure(&t)) == KS_OK && t < best_t) { best_t = t; best_rls = rls; best_ss = ss; }
+            }
+        ctx->ms_rl_small_pref = best_rls;
+        ctx->ms_s_small = best_ss;
+    } else {
+        int best_rq = ctx->quad_rq_pref;
+        double best_t = 1e30;
+        for (int rq = 0; rq <= 2 && s == KS_OK; ++rq) {
+            if (pick_quad_rq(scales[1] - scales[0] + 1, bins, rq) != rq) break;  // beyond the LDS budget
+            ctx->quad_rq_pref = rq;
+            if ((s = measure(&t)) == KS_OK && t < best_t) { best_t = t; best_rq = rq; }
+        }
+        ctx->quad_rq_pref = best_rq;
+    }
+    ctx->profiling = prof;
+    if (s != KS_OK) return s;
+    if (out) {
+        out[0] = ctx->ms_rl_pref; out[1] = ctx->ms_rl_small_pref; out[2] = ctx->ms_s_small; out[3] = ctx->quad_rq_pref;
+    }
+    return KS_OK;
+}
+
 ks_status ks_context_set_options(ks_context* ctx, const ks_options* options) {
     if (!ctx) return KS_E_INVALID;
     if (!options) {

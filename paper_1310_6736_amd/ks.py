@@ -27,7 +27,7 @@ EXPORTS = [
     "ks_detect_batch", "ks_server_create", "ks_server_submit", "ks_server_poll", "ks_server_drain",
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
-    "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap",
+    "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap", "ks_context_autotune",
 ]
 
 
@@ -132,6 +132,7 @@ def lib():
     L.ks_server_submit_tracked.argtypes = [vp, C.POINTER(Request), C.c_int64, i32, C.POINTER(C.c_uint64)]
     L.ks_context_set_seeds.argtypes = [vp, i32p, C.c_int64]
     L.ks_context_set_overlap.argtypes = [vp, i32]
+    L.ks_context_autotune.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, i32, i32p, vp]
     L.ks_abmsod.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, C.c_double, vp, i32, i32p, vp]
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
     L.ks_server_drain.argtypes = [vp]
@@ -272,6 +273,17 @@ def ks_context_set_seeds(ctx: Context, seeds=None):
     a, n = _seed_array(seeds)
     _check(lib().ks_context_set_seeds(ctx.handle, a.ctypes.data_as(C.POINTER(C.c_int32)), n),
            "ks_context_set_seeds")
+
+
+def ks_context_autotune(ctx: Context, volume, bins, seed_spacing, scales, method, max_iter, reps=2, stream=None):
+    """Times the search of this request under candidate tunings and keeps the
+    fastest in ctx; returns (ms_replicas_log2, ms_small_replicas_log2, s_small,
+    quad_replicas_log2)."""
+    ptr, dt, dims = _volume_args(volume)
+    out = (C.c_int32 * 4)()
+    _check(lib().ks_context_autotune(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter,
+                                     int(reps), out, _stream_ptr(stream)), "ks_context_autotune")
+    return tuple(out)
 
 
 def ks_context_set_overlap(ctx: Context, on: bool):

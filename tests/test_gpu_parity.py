@@ -724,3 +724,20 @@ def test_abmsod_validation(torch_dev, ctx):
                            ((1, 3), 5, float("nan"))):
         with pytest.raises(ks.KsError):
             ks.ks_abmsod(ctx, v, 16, 3, radii, it, threshold=thr)
+
+
+def test_autotune_picks_a_tuning_and_keeps_results(torch_dev, ctx):
+    note("autotune on the PET-like volume, both methods")
+    try:
+        for method in (ks.KS_MEANSHIFT, ks.KS_QUADRANT):
+            w = synth.pet_shell(method)
+            v = dev(torch_dev, w.volume)
+            before = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=100000)
+            t = ks.ks_context_autotune(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, reps=1)
+            assert 3 <= t[0] <= 5 and 2 <= t[1] <= 3 and t[2] in (4, 6, 8) and 0 <= t[3] <= 2, t
+            after = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=100000)
+            assert after[1] == before[1] and np.array_equal(after[0], before[0])
+        with pytest.raises(ks.KsError):
+            ks.ks_context_autotune(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, reps=0)
+    finally:
+        restore_tuning(ctx)
