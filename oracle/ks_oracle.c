@@ -21,7 +21,15 @@
  *    the objective strictly increases (best-so-far idea of Alg. 2), otherwise the
  *    search stops at the last accepted position;
  *  - saliency (Sec. 1, Sec. 2.1): entropy peaks over scale, pdf change
- *    W(s) = s^2/(2s-1) * sum_b |p_s(b) - p_{s-1}(b)|, Y = H * W.
+ *    W(s) = s^2/(2s-1) * sum_b |p_s(b) - p_{s-1}(b)|, Y = H * W;
+ *  - window level (Sec. 3.2): voxels in [lo, hi] are binned over that range,
+ *    the others take part in no histogram and N counts the voxels inside;
+ *  - tracking (Sec. 4): a run may start from a list of positions instead of
+ *    the grid (every scale per position for mean-shift);
+ *  - ABMSOD (Sec. 2.3, Eq. 5, 7, Alg. 2): the ellipsoid (v-x)^T H^-1 (v-x) <= 5
+ *    (uniform second moment H), Gaussian profile exp(-d/2), start H = (r+1/2)^2/5 I,
+ *    Eq. 7 weighted by w alone about the new centre, best coefficient kept; see
+ *    kso_abmsod in the header for the stops.
  *
  * Fixed summation order shared by definition (not by code) with the GPU path:
  * every sum over bins is a pairwise halving tree over Bp terms, where Bp is the
