@@ -103,3 +103,21 @@ def test_context_without_gpu_reports_device_error():
     L = _lib()
     h = C.c_void_p()
     assert L.ks_context_create(0, C.byref(h)) == ks.KS_E_DEVICE
+
+
+def build_consumer(out_dir):
+    """Compiles tests/abi_consumer.c as strict C99 against include/ks.h and links
+    it to libks.so (host compiler only)."""
+    import subprocess
+    _lib()
+    exe = os.path.join(out_dir, "abi_consumer")
+    libdir = os.path.dirname(ks.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+                    "-o", exe, os.path.join(ROOT, "tests", "abi_consumer.c"), "-L", libdir, "-lks",
+                    "-Wl,-rpath," + libdir], check=True)
+    return exe
+
+
+def test_header_is_c99_and_links(tmp_path):
+    exe = build_consumer(str(tmp_path))
+    assert os.path.exists(exe)

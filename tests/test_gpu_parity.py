@@ -7,6 +7,7 @@ float32 reported entropy / pdf change / saliency must be within 1e-5 relative of
 the oracle's accurate double values, and exactly zero where those are zero.
 """
 import ctypes
+import os
 import sys
 import zlib
 
@@ -741,3 +742,30 @@ def test_autotune_picks_a_tuning_and_keeps_results(torch_dev, ctx):
             ks.ks_context_autotune(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, reps=0)
     finally:
         restore_tuning(ctx)
+
+
+def test_plain_c_consumer_matches_oracle(torch_dev, tmp_path):
+    """A C99 program linked against libks.so (no Python, no torch) runs ks_detect
+    on a host volume; its regions equal the oracle's."""
+    import subprocess
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_abi_host import build_consumer
+    exe = build_consumer(str(tmp_path))
+    for method, scales in ((ks.KS_QUADRANT, (3, 6)), (ks.KS_MEANSHIFT, (2, 5))):
+        v = random_volume(91 + method, (26, 30, 34), np.uint16, 0, 3000)
+        raw = tmp_path / f"vol{method}.raw"
+        v.tofile(raw)
+        Z, Y, X = v.shape
+        note(f"C consumer method={method}")
+        r = subprocess.run([exe, str(raw), "1", str(X), str(Y), str(Z), "32", "5", str(scales[0]), str(scales[1]),
+                            str(method), "20", "100000"], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        lines = r.stdout.split("\n")
+        n = int(lines[0].split()[1])
+        rows = [l.split() for l in lines[1:] if l.strip()]
+        want, n_want, _ = oracle.detect(v, 32, 5, scales, method, 20, capacity=100000)
+        assert n == n_want and len(rows) == len(want)
+        got = np.array([[int(a) for a in row[:5]] for row in rows])
+        for k, f in enumerate(("x", "y", "z", "scale", "seed")):
+            assert np.array_equal(got[:, k], want[f]), f
+        assert close32([float(row[5]) for row in rows], want["saliency"])
