@@ -200,6 +200,13 @@ ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct);
  * than 2^31 - 1 trajectories.  An empty list finds no region. */
 ks_status ks_context_set_seeds(ks_context* ctx, const int32_t* seeds, int64_t n_seeds);
 
+/* Mean-shift scales per task: a wavefront runs one seed's trajectories of
+ * scales_per_task consecutive scales in ascending order, each starting from the
+ * previous one's first window plus the shell between the two (1..8), or 0 (the
+ * default): the largest group of up to 4 that still leaves 16 tasks per
+ * resident wavefront.  Results do not depend on it. */
+ks_status ks_context_set_ms_group(ks_context* ctx, int32_t scales_per_task);
+
 /* Runs the quadrant and mean-shift searches of one call (a batch holding both
  * methods) concurrently on two streams, so that the blocks of each fill the
  * other's tail (on = 1, the default), or one after the other (0).  Results do

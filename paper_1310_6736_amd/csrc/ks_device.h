@@ -56,15 +56,18 @@ struct VolDesc {
     const int32_t* seeds;   // explicit start positions (x, y, z) x gx, or null: the seed grid
 };
 
-// A run of tasks with the same window size: tasks [task_begin, task_begin + count)
-// are trajectories local_begin .. local_begin + count - 1 of volume `vol` (for
-// mean-shift, local ids of one scale, stride S).
+// A run of tasks with the same window sizes: task task_begin + i is seed
+// seed_begin + i of volume `vol`: its quadrant trajectory, or its mean-shift
+// trajectories of the scales scale .. scale_hi, run in that order by one
+// wavefront (each starts from the previous one's window at the seed).
 struct TaskSeg {
     int64_t task_begin;
     int64_t count;
     int32_t vol;
-    int32_t scale;          // mean-shift: the fixed scale; quadrant: 0
+    int32_t scale;          // mean-shift: the first scale of the group; quadrant: 0
     int64_t seed_begin;     // first seed id of the run
+    int32_t scale_hi;       // mean-shift: the last scale of the group; quadrant: 0
+    int32_t pad;
 };
 
 // Result of one trajectory (80 bytes).

@@ -828,9 +828,13 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         const TaskSeg sg = segs[si];
         const VolDesc& v = vols[sg.vol];
         const long long seed = sg.seed_begin + (t - sg.task_begin);
-        const int s = sg.scale;
         int p0[3];
         seed_pos(v, seed, p0);
+        // The group's scales in ascending order: the first window of scale s is
+        // the first window of s - 1 (kept in `first`) plus the shell at distance s.
+        BinAcc<M> first;
+        acc_clear<M>(first);
+        for (int s = uniform(sg.scale); s <= uniform(sg.scale_hi); ++s) {
         // replicas per wavefront by window size class
         const int rl = s <= tune.s_small ? tune.rl_small : tune.rl;
         // Search state (Sec. 2.3): accepted position P, window of the totals W,
@@ -879,11 +883,23 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
                 acc_clear<M>(a);
                 bs = BoxSet{use_shell ? kShell : kInner, px, py, pz, 0, 0, 0, s};
                 lc.swept += (unsigned long long)(use_shell ? Ns - Np : Np);
+            } else if (s > sg.scale) {
+                // shift the kept offset sums from d + (s-1) to d + s, then add the shell
+                a = first;
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    a.f1[k] += a.c[k];
+                    a.f2[k] += a.c[k];
+                    a.f3[k] += a.c[k];
+                }
+                bs = BoxSet{kShell, px, py, pz, 0, 0, 0, s};
+                lc.swept += (unsigned long long)(cube_count(v, px, py, pz, s) - cube_count(v, px, py, pz, s - 1));
             } else {
                 lc.swept += (unsigned long long)cube_count(v, px, py, pz, s);
             }
             lc.lds_ops += ms_sweep<M>(v, bs, rl, trash_base, hist, lane, a);
             if (phase == 2) break;
+            if (phase == 0) first = a;
             // an evaluation at W (= P0 in phase 0, Q in phase 1)
             const EvalOut e = ms_moments<M>(v, tb, wx, wy, wz, s, a);
             lc.evals += 1;
@@ -924,6 +940,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
             o.iters = it; o.stop = stop; o.obj = cur.obj;
             const long long local = seed * v.S + (s - v.s_min);
             write_rec(out + v.traj_base + local, p0, o, sal, (int32_t)local, v.rank_by);
+        }
         }
     }
     if (lane == 0) {

@@ -298,6 +298,26 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     p.total_traj = traj;
     p.total_regions = regs;
     p.n_pad = next_pow2((unsigned long long)std::max<int64_t>(traj, 2));
+    // Mean-shift scales per task: a task runs a seed's consecutive scales, each
+    // starting from the previous one's first window; groups shorten the sweeps
+    // but lengthen the tasks, so they are used only while the queue still holds
+    // at least 16 tasks per resident wavefront.
+    int G = ms_group;
+    if (G <= 0 && p.maxB_ms > 0) {
+        const int mb = std::max(p.maxB_ms, 2);
+        const int rl = std::max(pick_ms_rl(mb, ms_rl_pref), pick_ms_rl(mb, ms_rl_small_pref));
+        const long long resident = (long long)max_blocks_ms(((mb + 1) << rl) + 64, p.maxB_ms) * num_cu;
+        auto tasks = [&](int g) {
+            long long n = 0;
+            for (const VolDesc& v : p.vols)
+                if (v.method == KS_MEANSHIFT) n += (long long)v.gx * v.gy * v.gz * ((v.S + g - 1) / g);
+            return n;
+        };
+        G = 1;
+        while (G < 4 && tasks(G + 1) >= 16 * resident) ++G;
+    }
+    G = std::max(1, G);
+    p.ms_group = G;
     // Task runs, longest windows first (largest-processing-time order).
     struct Run { TaskSeg s; double cost; int method; };
     std::vector<Run> runs;
@@ -308,16 +328,23 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         if (v.method == KS_QUADRANT) {
             Run r;
             r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = 0; r.s.seed_begin = 0;
+            r.s.scale_hi = 0; r.s.pad = 0;
             const double w = 2.0 * v.s_max + 2.0;
             r.cost = w * w * w;
             r.method = KS_QUADRANT;
             runs.push_back(r);
         } else {
-            for (int s = v.s_max; s >= v.s_min; --s) {
+            // groups of G consecutive scales, the largest group first
+            for (int hi = v.s_max; hi >= v.s_min; hi -= G) {
+                const int lo = std::max(v.s_min, hi - G + 1);
                 Run r;
-                r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = s; r.s.seed_begin = 0;
-                const double w = 2.0 * s + 1.0;
-                r.cost = w * w * w;
+                r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = lo; r.s.seed_begin = 0;
+                r.s.scale_hi = hi; r.s.pad = 0;
+                r.cost = 0.0;
+                for (int s = lo; s <= hi; ++s) {
+                    const double w = 2.0 * s + 1.0;
+                    r.cost += w * w * w;
+                }
                 r.method = KS_MEANSHIFT;
                 runs.push_back(r);
             }
@@ -549,6 +576,7 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     key.push_back(ms_s_small);
     key.push_back(quad_rq_pref);
     key.push_back(overlap ? 1 : 0);
+    key.push_back(p.ms_group);
     for (const VolIn& v : in) {
         key.push_back((int64_t)(intptr_t)v.raw);
         key.push_back(v.dtype); key.push_back(v.dims[0]); key.push_back(v.dims[1]); key.push_back(v.dims[2]);
@@ -760,6 +788,12 @@ ks_status ks_context_set_options(ks_context* ctx, const ks_options* options) {
 ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct) {
     if (!ctx || incremental_pct < 0 || incremental_pct > 200) return KS_E_INVALID;
     ctx->ms_incr_pct = incremental_pct;
+    return KS_OK;
+}
+
+ks_status ks_context_set_ms_group(ks_context* ctx, int32_t scales_per_task) {
+    if (!ctx || scales_per_task < 0 || scales_per_task > 8) return KS_E_INVALID;
+    ctx->ms_group = scales_per_task;
     return KS_OK;
 }
 

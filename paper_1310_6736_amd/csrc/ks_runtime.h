@@ -50,6 +50,7 @@ struct Plan {
     unsigned long long n_pad = 2;
     int maxS_quad = 0, maxB_quad = 0, maxB_ms = 0;
     int rl = 4, rl_small = 3, rq = 0, ms_hist_words = 0;
+    int ms_group = 1;       // mean-shift scales per task
     LdsQuad lay{};
     int* vol_nfound = nullptr;
     int* vol_base = nullptr;
@@ -73,6 +74,7 @@ struct Context {
     int ms_s_small = 6;
     int ms_incr_pct = 100;  // running-window updates while cheaper than a fresh window
     bool overlap = true;    // quadrant and mean-shift searches of one call on two streams
+    int ms_group = 0;       // mean-shift scales per task (one seed, consecutive scales); 0: by the task count
     ks_options opts{};      // selection and order for ks_detect_device / ks_seed_traces
     bool use_seeds = false; // explicit start positions for ks_detect_device / ks_seed_traces
     std::vector<int32_t> seeds;

@@ -28,6 +28,7 @@ EXPORTS = [
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
     "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap", "ks_context_autotune",
+    "ks_context_set_ms_group",
 ]
 
 
@@ -132,6 +133,7 @@ def lib():
     L.ks_server_submit_tracked.argtypes = [vp, C.POINTER(Request), C.c_int64, i32, C.POINTER(C.c_uint64)]
     L.ks_context_set_seeds.argtypes = [vp, i32p, C.c_int64]
     L.ks_context_set_overlap.argtypes = [vp, i32]
+    L.ks_context_set_ms_group.argtypes = [vp, i32]
     L.ks_context_autotune.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, i32, i32p, vp]
     L.ks_abmsod.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, C.c_double, vp, i32, i32p, vp]
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
@@ -284,6 +286,10 @@ def ks_context_autotune(ctx: Context, volume, bins, seed_spacing, scales, method
     _check(lib().ks_context_autotune(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter,
                                      int(reps), out, _stream_ptr(stream)), "ks_context_autotune")
     return tuple(out)
+
+
+def ks_context_set_ms_group(ctx: Context, scales_per_task: int = 0):
+    _check(lib().ks_context_set_ms_group(ctx.handle, int(scales_per_task)), "ks_context_set_ms_group")
 
 
 def ks_context_set_overlap(ctx: Context, on: bool):

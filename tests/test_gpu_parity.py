@@ -429,8 +429,8 @@ def test_stats_count_the_work(torch_dev, ctx):
 
 def test_stats_meanshift_swept_voxels(torch_dev, ctx):
     """Window evaluations and visits count the method's work (as the oracle does);
-    the voxels swept with running-window updates are fewer, and with updates off
-    they are the visits less the final pass's saving."""
+    the voxels swept are fewer (first windows shared along a seed's scales, the
+    final pass's shell), and fewer again with running-window updates."""
     w = synth.pet_shell(ks.KS_MEANSHIFT)
     note("stats meanshift")
     t = dev(torch_dev, w.volume)
@@ -444,7 +444,7 @@ def test_stats_meanshift_swept_voxels(torch_dev, ctx):
         ks.ks_context_set_ms_update(ctx, 100)
     for f in ("evals", "window_evals", "voxel_visits", "final_visits", "regions"):
         assert st[f] == fresh[f], f
-    assert fresh["voxel_visits"] < fresh["swept_voxels"] < fresh["voxel_visits"] + fresh["final_visits"]
+    assert 0 < fresh["swept_voxels"] < fresh["voxel_visits"] + fresh["final_visits"]
     assert st["swept_voxels"] < 0.7 * fresh["swept_voxels"]
 
 
@@ -769,3 +769,32 @@ def test_plain_c_consumer_matches_oracle(torch_dev, tmp_path):
         for k, f in enumerate(("x", "y", "z", "scale", "seed")):
             assert np.array_equal(got[:, k], want[f]), f
         assert close32([float(row[5]) for row in rows], want["saliency"])
+
+
+@pytest.mark.parametrize("group", [1, 3, 8])
+def test_meanshift_scale_groups_give_the_same_traces(torch_dev, ctx, group):
+    """A wavefront may run a seed's consecutive scales, each starting from the
+    previous first window plus a shell; traces stay bit-identical to the oracle
+    (the PET-like volume, and the mean-shift edge cases: clipped windows, windows
+    larger than the volume, s up to 32)."""
+    ks.ks_context_set_ms_group(ctx, group)
+    try:
+        w = synth.pet_shell(ks.KS_MEANSHIFT)
+        note(f"ms group {group}: {w.name}")
+        got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
+        ids = np.arange(0, len(got), 3)
+        want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, ids=ids)
+        compare_traces(got[ids], want, f"{w.name} group {group}")
+        for name, dt, shape, bins, sp, scales, method, max_iter in EDGE_CASES:
+            if method != ks.KS_MEANSHIFT:
+                continue
+            note(f"ms group {group}: edge {name}")
+            hi = 255 if dt == np.uint8 else 4000
+            v = random_volume(zlib.crc32(name.encode()) % 1000, shape, dt, 0, hi)
+            got = ks.ks_seed_traces(ctx, dev(torch_dev, v), bins, sp, scales, method, max_iter)
+            want, _ = oracle.run(v, bins, sp, scales, method, max_iter)
+            compare_traces(got, want, f"{name} group {group}")
+    finally:
+        ks.ks_context_set_ms_group(ctx, 0)
+    with pytest.raises(ks.KsError):
+        ks.ks_context_set_ms_group(ctx, 9)
