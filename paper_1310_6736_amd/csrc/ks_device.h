@@ -104,9 +104,10 @@ struct Counters {
 // 1 << rl for windows of half-width > s_small and 1 << rl_small otherwise; a
 // later evaluation of a trajectory updates its running window when the voxels
 // that leave and enter it are fewer than incr_pct percent of the window (0:
-// never).
+// never); group: scales per task of the launch's task runs.
 struct MsTune {
     int32_t rl, rl_small, s_small, incr_pct;
+    int32_t group, pad;
 };
 
 // Start position of seed `seed` of a volume: the listed position, or grid point

@@ -808,7 +808,7 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 // are the smaller sweep), and the final pass reuses the counts of the window at
 // P*.  Every sweep of the kernel goes through the one ms_sweep call below, so
 // the scatter code is instantiated once.
-template <int M>
+template <int M, bool GROUPED>
 __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols,
                                                   const TaskSeg* __restrict__ segs, int nseg, long long ntask,
                                                   Tables tb, TrajRec* out, Counters* cnt, MsTune tune,
@@ -834,7 +834,8 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         // the first window of s - 1 (kept in `first`) plus the shell at distance s.
         BinAcc<M> first;
         acc_clear<M>(first);
-        for (int s = uniform(sg.scale); s <= uniform(sg.scale_hi); ++s) {
+        const int s_last = GROUPED ? uniform(sg.scale_hi) : uniform(sg.scale);
+        for (int s = uniform(sg.scale); s <= s_last; ++s) {
         // replicas per wavefront by window size class
         const int rl = s <= tune.s_small ? tune.rl_small : tune.rl;
         // Search state (Sec. 2.3): accepted position P, window of the totals W,
@@ -883,7 +884,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
                 acc_clear<M>(a);
                 bs = BoxSet{use_shell ? kShell : kInner, px, py, pz, 0, 0, 0, s};
                 lc.swept += (unsigned long long)(use_shell ? Ns - Np : Np);
-            } else if (s > sg.scale) {
+            } else if (GROUPED && s > sg.scale) {
                 // shift the kept offset sums from d + (s-1) to d + s, then add the shell
                 a = first;
 #pragma unroll
@@ -899,7 +900,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
             }
             lc.lds_ops += ms_sweep<M>(v, bs, rl, trash_base, hist, lane, a);
             if (phase == 2) break;
-            if (phase == 0) first = a;
+            if (GROUPED && phase == 0) first = a;
             // an evaluation at W (= P0 in phase 0, Q in phase 1)
             const EvalOut e = ms_moments<M>(v, tb, wx, wy, wz, s, a);
             lc.evals += 1;
@@ -1897,15 +1898,15 @@ hipError_t launch_search_ms(const SearchArgs& a, int grid, const MsTune& tune, i
     if (a.ntask <= 0) return hipSuccess;
     const size_t lds = (size_t)hist_words * 8;
     const int M = bins_per_lane_host(maxB);
-    if (M == 1)
-        hipLaunchKernelGGL(k_search_ms<1>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
-                           a.rec, a.cnt, tune, hist_words);
-    else if (M == 2)
-        hipLaunchKernelGGL(k_search_ms<2>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
-                           a.rec, a.cnt, tune, hist_words);
-    else
-        hipLaunchKernelGGL(k_search_ms<4>, dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, a.tb,
-                           a.rec, a.cnt, tune, hist_words);
+    // one scale per task: the kernel without the group bookkeeping (fewer registers)
+#define KS_LAUNCH_MS(MM, GG)                                                                                   \
+    hipLaunchKernelGGL((k_search_ms<MM, GG>), dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, \
+                       a.tb, a.rec, a.cnt, tune, hist_words)
+    const bool g = tune.group > 1;
+    if (M == 1) { if (g) KS_LAUNCH_MS(1, true); else KS_LAUNCH_MS(1, false); }
+    else if (M == 2) { if (g) KS_LAUNCH_MS(2, true); else KS_LAUNCH_MS(2, false); }
+    else { if (g) KS_LAUNCH_MS(4, true); else KS_LAUNCH_MS(4, false); }
+#undef KS_LAUNCH_MS
     return hipGetLastError();
 }
 
@@ -2004,9 +2005,9 @@ int max_blocks_ms(int hist_words, int maxB) {
     int nb = 0;
     const int M = bins_per_lane_host(maxB);
     const size_t lds = (size_t)hist_words * 8;
-    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<1>, 64, lds)
-                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<2>, 64, lds)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<4>, 64, lds);
+    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<1, false>, 64, lds)
+                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<2, false>, 64, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<4, false>, 64, lds);
     if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }

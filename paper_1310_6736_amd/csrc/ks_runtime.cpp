@@ -462,6 +462,8 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         tune.rl_small = p.rl_small;
         tune.s_small = ms_s_small;
         tune.incr_pct = ms_incr_pct;
+        tune.group = p.ms_group;
+        tune.pad = 0;
         if (timed) KS_HIP(hipEventRecord(ev[4], sm_st));
         KS_HIP(launch_search_ms(sm, (int)g, tune, p.ms_hist_words, p.maxB_ms, sm_st));
         if (timed) KS_HIP(hipEventRecord(ev[5], sm_st));
