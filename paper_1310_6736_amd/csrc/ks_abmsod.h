@@ -15,9 +15,11 @@ namespace ks {
 struct AbmArgs {
     long long n_start;
     int R, r_min, r_max, max_iter;
+    int replicas;           // histogram replicas per wave (abmsod_replicas)
     double threshold;
 };
 
+int abmsod_replicas(int B);
 size_t abmsod_lds_bytes(int B);
 int abmsod_blocks_per_cu();
 // One search over vols[0] (bins prepared); out: device array of n_start * R

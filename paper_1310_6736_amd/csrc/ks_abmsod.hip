@@ -4,16 +4,18 @@
 //
 // One wavefront per candidate (start position, start radius), persistent: a
 // wave pops candidates, largest radius first, from a device counter.  An
-// iteration makes four sweeps of the ellipsoid, a row interval per lane:
-//   1. Gaussian-weighted histogram at x            (LDS, 64-bit fixed point)
-//   2. weighted mean of the window at x (Eq. 5)    (registers, wave sum)
-//   3. Gaussian-weighted histogram at x_new         (LDS)
-//   4. weighted second moment at x_new (Eq. 7)     (registers, wave sum)
+// iteration makes three sweeps of the ellipsoid, a row interval per lane:
+//   1. Gaussian-weighted histogram and per-bin first moments at x, from which
+//      the weighted mean of Eq. 5 follows (the weights depend on the bin only)
+//                                                   (LDS, 64-bit fixed point)
+//   2. Gaussian-weighted histogram at x_new         (LDS)
+//   3. weighted second moment at x_new (Eq. 7)     (registers, wave sum)
 // Window membership is (v-x)^T H^-1 (v-x) <= 5, evaluated per voxel.  The
-// histogram adds exp(-d/2) rounded to 2^-40 with 64-bit integer LDS atomics into
-// four replicas per wave, so its totals do not depend on the order of the
-// additions; the register sums are reduced by a fixed butterfly, which leaves
-// the same bits in every lane, so every lane takes the same decisions.
+// histograms add exp(-d/2) rounded to 2^-40 (the moments exp(-d/2) (v - x) to
+// 2^-32) with 64-bit integer LDS atomics into replicas per wave, so their totals
+// do not depend on the order of the additions; the register sums are reduced
+// by a fixed butterfly, which leaves the same bits in every lane, so every lane
+// takes the same decisions.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -25,13 +27,14 @@
 namespace ks {
 namespace {
 
-constexpr int kAbmReplicas = 4;
 constexpr double kFix = 1099511627776.0;         // 2^40
 constexpr double kUnfix = 1.0 / 1099511627776.0;
+constexpr double kFixM = 4294967296.0;           // 2^32
+constexpr double kUnfixM = 1.0 / 4294967296.0;
 constexpr double kTol = 0.01;
 constexpr int kBlocksPerCu = 12;
 
-enum { kHist = 0, kMean = 1, kCov = 2 };
+enum { kHist = 0, kHistMean = 1, kCov = 2 };
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -61,9 +64,9 @@ __device__ __forceinline__ bool sym3_inv(const double h[6], double inv[6]) {
 
 // One voxel of a sweep: the membership test (v-x)^T H^-1 (v-x) <= 5 and the
 // sweep's accumulation.
-//   kHist: hist[bin] += round(exp(-d/2) 2^40)                (this lane's replica)
-//   kMean: acc[0] += g w, acc[1..3] += g w (v - x)            (Eq. 5)
-//   kCov:  acc[0] += w,   acc[1..6] += w (v - x)(v - x)^T     (Eq. 7)
+//   kHist:     hist[bin] += round(g 2^40), g = exp(-d/2)      (this lane's replica)
+//   kHistMean: as kHist, and hist[(1..3) B + bin] += round(g (v - x)_a 2^32)
+//   kCov:      acc[0] += w, acc[1..6] += w (v - x)(v - x)^T   (Eq. 7)
 template <int KIND>
 __device__ __forceinline__ void abm_voxel(const VolDesc& v, int vx, int vy, int vz, int b, const double x[3],
                                           const double inv[6], unsigned long long* hist, const double* wtab,
@@ -74,15 +77,15 @@ __device__ __forceinline__ void abm_voxel(const VolDesc& v, int vx, int vy, int 
     if (!(d <= 5.0)) return;
     ++visits;
     if (b >= v.B) return;
-    if (KIND == kHist) {
+    if (KIND == kHist || KIND == kHistMean) {
         const double g = exp(-d / 2.0);
         atomicAdd(&hist[b], (unsigned long long)__double2ull_rn(g * kFix));
-    } else if (KIND == kMean) {
-        const double gw = exp(-d / 2.0) * wtab[b];
-        acc[0] += gw;
-        acc[1] += gw * u0;
-        acc[2] += gw * u1;
-        acc[3] += gw * u2;
+        if (KIND == kHistMean) {
+            const int B = v.B;
+            atomicAdd(&hist[B + b], (unsigned long long)__double2ll_rn(g * u0 * kFixM));
+            atomicAdd(&hist[2 * B + b], (unsigned long long)__double2ll_rn(g * u1 * kFixM));
+            atomicAdd(&hist[3 * B + b], (unsigned long long)__double2ll_rn(g * u2 * kFixM));
+        }
     } else {
         const double wb = wtab[b];
         acc[0] += wb;
@@ -142,26 +145,41 @@ __device__ __forceinline__ unsigned abm_sweep(const VolDesc& v, const double x[3
     return visits;
 }
 
-// Folds the replicas into per-bin totals, clears them, writes the Eq. 5 weights
+// Folds the R replicas (stride 4 B words each: totals, then the three moment
+// rows) into per-bin totals and clears them, writes the Eq. 5 weights
 // sqrt(q_b / p_b) (q_b = 1/B) into wtab and returns the total (fixed point).
-// rho and ent receive sum_b sqrt(p_b q_b) and -sum_b p_b ln p_b.
-__device__ __forceinline__ unsigned long long abm_fold(unsigned long long* hist, double* wtab, int B, int lane,
-                                                       double& rho, double& ent) {
+// rho and ent receive sum_b sqrt(p_b q_b) and -sum_b p_b ln p_b.  With moments,
+// shift receives the Eq. 5 move sum_b w_b M_b / sum_b w_b G_b.
+__device__ __forceinline__ unsigned long long abm_fold(unsigned long long* hist, double* wtab, int B, int R,
+                                                       int lane, bool moments, double& rho, double& ent,
+                                                       double shift[3]) {
     __syncthreads();
     unsigned long long part = 0;
-    for (int b = lane; b < B; b += 64) {
+    long long mom[4][3];   // per-lane moments of up to 4 bins (B <= 256)
+    for (int b = lane, i = 0; b < B; b += 64, ++i) {
         unsigned long long s = 0;
-        for (int r = 0; r < kAbmReplicas; ++r) {
-            s += hist[r * B + b];
-            hist[r * B + b] = 0;
+        long long m0 = 0, m1 = 0, m2 = 0;
+        for (int r = 0; r < R; ++r) {
+            unsigned long long* h = hist + r * 4 * B;
+            s += h[b];
+            h[b] = 0;
+            if (moments) {
+                m0 += (long long)h[B + b];
+                m1 += (long long)h[2 * B + b];
+                m2 += (long long)h[3 * B + b];
+                h[B + b] = 0;
+                h[2 * B + b] = 0;
+                h[3 * B + b] = 0;
+            }
         }
+        mom[i][0] = m0; mom[i][1] = m1; mom[i][2] = m2;
         part += s;
         wtab[b] = (double)s;    // raw total until the sum over bins is known
     }
     const unsigned long long tot = wave_sum_u64(part);
     const double totd = (double)tot * kUnfix;
-    double r0 = 0.0, e0 = 0.0;
-    for (int b = lane; b < B; b += 64) {
+    double r0 = 0.0, e0 = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0, dn = 0.0;
+    for (int b = lane, i = 0; b < B; b += 64, ++i) {
         const double g = wtab[b] * kUnfix;
         double wb = 0.0;
         if (g > 0.0) {
@@ -169,11 +187,23 @@ __device__ __forceinline__ unsigned long long abm_fold(unsigned long long* hist,
             wb = sqrt((1.0 / B) / p);
             r0 += sqrt(p * (1.0 / B));
             e0 -= p * log(p);
+            if (moments) {
+                dn += wb * g;
+                n0 += wb * ((double)mom[i][0] * kUnfixM);
+                n1 += wb * ((double)mom[i][1] * kUnfixM);
+                n2 += wb * ((double)mom[i][2] * kUnfixM);
+            }
         }
         wtab[b] = wb;
     }
     rho = wave_sum(r0);
     ent = wave_sum(e0);
+    if (moments) {
+        const double den = wave_sum(dn);
+        shift[0] = wave_sum(n0) / den;
+        shift[1] = wave_sum(n1) / den;
+        shift[2] = wave_sum(n2) / den;
+    }
     __syncthreads();
     return tot;
 }
@@ -183,13 +213,12 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
     const VolDesc& v = vols[0];
     const int lane = threadIdx.x;
     const int B = v.B;
+    const int R = a.replicas;
     unsigned long long* hist_all = smem;
-    double* wtab = reinterpret_cast<double*>(smem + kAbmReplicas * B);
-    unsigned long long* hist = hist_all;    // replica of this lane, offset by its index below
-    for (int i = lane; i < kAbmReplicas * B; i += 64) hist_all[i] = 0;
+    double* wtab = reinterpret_cast<double*>(smem + 4 * R * B);
+    for (int i = lane; i < 4 * R * B; i += 64) hist_all[i] = 0;
     __syncthreads();
-    const int rep = lane & (kAbmReplicas - 1);
-    hist = hist_all + rep * B;
+    unsigned long long* hist = hist_all + (lane & (R - 1)) * 4 * B;    // this lane's replica
     const long long ntask = a.n_start * a.R;
     const double cap2 = (a.r_max + 0.5) * (a.r_max + 0.5);
     for (;;) {
@@ -214,25 +243,22 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
         int evals = 0;
         while (it < a.max_iter) {
             sym3_inv(h, inv);
-            // Eq. 4 and 5 at x
-            visits += abm_sweep<kHist>(v, x, h, inv, hist, wtab, nullptr, lane);
+            // Eq. 4 and 5 at x: one pass gives the histogram and the per-bin moments
+            // (window voxels counted for the histogram and the mean, as two passes)
+            visits += 2 * abm_sweep<kHistMean>(v, x, h, inv, hist, wtab, nullptr, lane);
             ++evals;
-            double rho, ent;
-            if (abm_fold(hist_all, wtab, B, lane, rho, ent) == 0) { stop = KS_ABM_EMPTY; break; }
-            double m[4] = {0.0, 0.0, 0.0, 0.0};
-            visits += abm_sweep<kMean>(v, x, h, inv, hist, wtab, m, lane);
-            for (int k = 0; k < 4; ++k) m[k] = wave_sum(m[k]);
+            double rho, ent, m[3];
+            if (abm_fold(hist_all, wtab, B, R, lane, true, rho, ent, m) == 0) { stop = KS_ABM_EMPTY; break; }
             const double dims[3] = {(double)(v.X - 1), (double)(v.Y - 1), (double)(v.Z - 1)};
             double xn[3];
             for (int k = 0; k < 3; ++k) {
-                xn[k] = x[k] + m[k + 1] / m[0];
+                xn[k] = x[k] + m[k];
                 xn[k] = xn[k] < 0.0 ? 0.0 : (xn[k] > dims[k] ? dims[k] : xn[k]);
             }
             // coefficient and Eq. 7 at x_new with the same H
-            __syncthreads();
             visits += abm_sweep<kHist>(v, xn, h, inv, hist, wtab, nullptr, lane);
             ++evals;
-            if (abm_fold(hist_all, wtab, B, lane, rho, ent) == 0) { stop = KS_ABM_EMPTY; break; }
+            if (abm_fold(hist_all, wtab, B, R, lane, false, rho, ent, m) == 0) { stop = KS_ABM_EMPTY; break; }
             double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             visits += abm_sweep<kCov>(v, xn, h, inv, hist, wtab, s, lane);
             for (int k = 0; k < 7; ++k) s[k] = wave_sum(s[k]);
@@ -285,7 +311,9 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
 
 }  // namespace
 
-size_t abmsod_lds_bytes(int B) { return (size_t)kAbmReplicas * B * 8 + (size_t)B * 8; }
+int abmsod_replicas(int B) { return B <= 128 ? 4 : 2; }
+
+size_t abmsod_lds_bytes(int B) { return (size_t)abmsod_replicas(B) * 4 * B * 8 + (size_t)B * 8; }
 
 int abmsod_blocks_per_cu() { return kBlocksPerCu; }
 

@@ -1043,6 +1043,7 @@ ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const
     if (total > 0) {
         AbmArgs a;
         a.n_start = n_start; a.R = R; a.r_min = radii[0]; a.r_max = radii[1]; a.max_iter = max_iter;
+        a.replicas = abmsod_replicas(bins);
         a.threshold = threshold;
         const int grid = (int)std::min<int64_t>(total, (int64_t)abmsod_blocks_per_cu() * ctx->num_cu);
         if (launch_abmsod(static_cast<VolDesc*>(ctx->d_vols.ptr), a, bins, grid,
