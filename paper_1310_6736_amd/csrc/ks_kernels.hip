@@ -650,15 +650,19 @@ __device__ __forceinline__ int64_t window_total(const int* c) {
 
 // Eq. 4-6 with a flat kernel and the uniform target: move = (sum_b M_b/sqrt(c_b)) /
 // (sum_b sqrt(c_b)), objective rho~ = (sum_b sqrt(c_b)) / sqrt(N), from the
-// window totals (f = sums of d + s).
+// window totals (f = sums of d + s).  sqrt and 1/sqrt of the integer counts are
+// computed here rather than loaded: the device's double sqrt and division are
+// correctly rounded, as the host's are, so the values equal the host-built
+// tables bit for bit (the mean-shift traces compare the objective with ==).
 template <int M>
 __device__ EvalOut ms_moments(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, const BinAcc<M>& a) {
     double sq[M], tx[M], ty[M], tz[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) {
         const bool nz = a.c[t] > 0;
-        const double rs = nz ? tb.rsq[a.c[t]] : 0.0;
-        sq[t] = nz ? tb.sq[a.c[t]] : 0.0;
+        const double sc = sqrt((double)a.c[t]);
+        const double rs = nz ? 1.0 / sc : 0.0;
+        sq[t] = nz ? sc : 0.0;
         tx[t] = nz ? (double)(a.f1[t] - a.c[t] * s) * rs : 0.0;
         ty[t] = nz ? (double)(a.f2[t] - a.c[t] * s) * rs : 0.0;
         tz[t] = nz ? (double)(a.f3[t] - a.c[t] * s) * rs : 0.0;
@@ -669,7 +673,7 @@ __device__ EvalOut ms_moments(const VolDesc& v, const Tables& tb, int px, int py
     const double nzs = bfly_sum(local_pw<M>(tz));
     const int64_t N = v.win ? window_total<M>(a.c) : cube_count(v, px, py, pz, s);
     EvalOut e;
-    e.obj = N > 0 ? D / tb.sq[N] : 0.0;
+    e.obj = N > 0 ? D / sqrt((double)N) : 0.0;
     e.dx = D > 0.0 ? nx / D : 0.0;
     e.dy = D > 0.0 ? ny / D : 0.0;
     e.dz = D > 0.0 ? nzs / D : 0.0;
