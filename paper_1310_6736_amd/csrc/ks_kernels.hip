@@ -417,6 +417,9 @@ __device__ __forceinline__ void ms_flush(unsigned long long* hist, int rl, int B
             }
         }
     }
+    // the window level's sentinel bin B is never read, but is cleared too: a
+    // later sweep with more replicas per bin would see its words as bins below B
+    for (int r = lane; r < (1 << rl); r += 64) hist[((size_t)B << rl) + r] = 0ull;
 }
 
 // --------------------------------------------------- mean-shift box sets

@@ -794,6 +794,16 @@ def test_meanshift_scale_groups_give_the_same_traces(torch_dev, ctx, group):
             got = ks.ks_seed_traces(ctx, dev(torch_dev, v), bins, sp, scales, method, max_iter)
             want, _ = oracle.run(v, bins, sp, scales, method, max_iter)
             compare_traces(got, want, f"{name} group {group}")
+        # a window level with groups that cross the replica change at s = 6 -> 7
+        v = windowed_volume("group_window", np.uint16, (24, 27, 30))
+        note(f"ms group {group}: window level, scales 4..9")
+        ks.ks_context_set_options(ctx, ks.options(window=(1000, 2200)))
+        try:
+            got = ks.ks_seed_traces(ctx, dev(torch_dev, v), 32, 5, (4, 9), ks.KS_MEANSHIFT, 20)
+        finally:
+            ks.ks_context_set_options(ctx, None)
+        want, _ = oracle.run(v, 32, 5, (4, 9), ks.KS_MEANSHIFT, 20, window=(1000, 2200))
+        compare_traces(got, want, f"window level group {group}")
     finally:
         ks.ks_context_set_ms_group(ctx, 0)
     with pytest.raises(ks.KsError):
