@@ -417,9 +417,6 @@ __device__ __forceinline__ void ms_flush(unsigned long long* hist, int rl, int B
             }
         }
     }
-    // the window level's sentinel bin B is never read, but is cleared too: a
-    // later sweep with more replicas per bin would see its words as bins below B
-    for (int r = lane; r < (1 << rl); r += 64) hist[((size_t)B << rl) + r] = 0ull;
 }
 
 // --------------------------------------------------- mean-shift box sets
@@ -826,6 +823,10 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
     __syncthreads();
     LocalCounts lc = {0, 0, 0, 0, 0, 0u};
     const int trash_base = hist_words - 64;
+    // A window level's sentinel bin B is scattered into but never read or
+    // cleared; its words, at B << rl, hold counts until the replica layout
+    // changes, where they would be read as bins below B: cleared then.
+    int dirty = -1, dirty_len = 0;
     for (;;) {
         long long t = 0;
         if (lane == 0) t = (long long)atomicAdd(&cnt->queue_head[1], 1ull);
@@ -845,6 +846,13 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         for (int s = uniform(sg.scale); s <= s_last; ++s) {
         // replicas per wavefront by window size class
         const int rl = s <= tune.s_small ? tune.rl_small : tune.rl;
+        const int sentinel = v.win ? (v.B << rl) : -1;
+        if (dirty >= 0 && (dirty != sentinel || dirty_len != (1 << rl))) {
+            for (int i = lane; i < dirty_len; i += 64) hist[dirty + i] = 0ull;
+            __syncthreads();
+        }
+        dirty = sentinel;
+        dirty_len = 1 << rl;
         // Search state (Sec. 2.3): accepted position P, window of the totals W,
         // candidate Q; phase 0 evaluates P0, 1 a candidate, 2 the final pass.
         int px = p0[0], py = p0[1], pz = p0[2];
