@@ -262,3 +262,35 @@ def test_batch_overlapped_searches_equal_sequential(torch_dev, ctx):
     for key, res in out.items():
         for i in range(len(ws)):
             assert res[i][1] == ref[i][1] and np.array_equal(res[i][0], ref[i][0]), (key, i)
+
+
+def test_batch_window_levels_and_scale_groups_match_oracle(torch_dev, ctx):
+    """Mean-shift volumes with and without window levels, different bin counts
+    and scale ranges in one batch, scale groups forced to 3 (groups cross the
+    replica change at s = 6 -> 7, and a wave moves between volumes' layouts):
+    every volume equals the oracle."""
+    specs = [("w32", np.uint16, (22, 25, 28), 32, (4, 9), (900, 2100)),
+             ("w64", np.int16, (20, 23, 26), 64, (3, 10), (-300, 600)),
+             ("full", np.uint16, (21, 24, 27), 48, (5, 8), None)]
+    vols, reqs = [], []
+    for i, (name, dt, shape, bins, scales, win) in enumerate(specs):
+        rng = np.random.default_rng(700 + i)
+        lo, hi = (-900, 2000) if dt == np.int16 else (0, 3000)
+        v = rng.integers(lo, hi + 1, shape).astype(dt)
+        vols.append(v)
+        t = torch_dev.from_numpy(v).to("cuda:0")
+        reqs.append(ks.make_request(t, bins, 4, scales, ks.KS_MEANSHIFT, 20,
+                                    opts=ks.options(window=win) if win else None))
+        reqs[-1]._keep = t
+    note("batch: window levels with scale groups")
+    ks.ks_context_set_ms_group(ctx, 3)
+    try:
+        out = ks.ks_detect_batch(ctx, reqs, capacity=100000)
+    finally:
+        ks.ks_context_set_ms_group(ctx, 0)
+    for (name, dt, shape, bins, scales, win), v, (got, n) in zip(specs, vols, out):
+        want, n_want, _ = oracle.detect(v, bins, 4, scales, ks.KS_MEANSHIFT, 20, capacity=100000, window=win)
+        assert n == n_want, name
+        for f in ("x", "y", "z", "scale", "seed"):
+            assert np.array_equal(got[f], want[f]), (name, f)
+        assert np.allclose(got["saliency"], want["saliency"], rtol=1e-5, atol=0), name
