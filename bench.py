@@ -34,6 +34,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6  # MI355X fp64 vector, published
 
 
+SECTIONS = ("dense_map", "window_level", "tracking", "abmsod")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +51,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed step and the roofline microbenchmarks (for profiling runs)")
+    ap.add_argument("--section", choices=SECTIONS,
+                    help="run only this one extra section and print its record (for profiling runs)")
     return ap.parse_args()
 
 
@@ -380,11 +385,34 @@ def cpu_baseline(stride: int, workers: int):
                       (which, done[0], of[0], done[1], of[1], workers, total_s)}
 
 
+def section_only(name):
+    """One extra section alone, on a fresh context: the workload of a kernel-trace
+    profile of that section."""
+    import torch
+
+    from paper_1310_6736_amd import ks
+
+    ctx = ks.Context(0)
+    if name == "dense_map":
+        rec = dense_section(ks, torch, ctx, None)
+    elif name == "window_level":
+        rec = window_level_section(ks, torch, ctx)
+    elif name == "tracking":
+        rec = tracking_section(ks, torch, ctx)
+    else:
+        rec = abmsod_section(ks, torch, ctx, os.path.join(ROOT, "profiles", "alu_k_abmsod_pet128x128x64.json"))
+    ctx.close()
+    print(json.dumps({"section": name, name: rec}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.section:
+        section_only(args.section)
+        return
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_sample_stride, max(1, min(16, os.cpu_count() or 1)))
