@@ -15,7 +15,7 @@
 //                  entropies in one pass
 //   both kernels end each trajectory with the Kadir-Brady saliency pass at the
 //   converged position and write one TrajRec
-//   k_compact / bitonic / dedup / emit    rank on the device
+//   k_compact / bitonic / merge / dedup   rank on the device
 //
 // Voxel bricks are read with buffer loads: the lane part of the address is fixed
 // for a whole window and each step adds one scalar offset, with several steps'
@@ -1691,31 +1691,43 @@ __device__ __forceinline__ bool rec_less(const SortRec& a, const SortRec& b) {
     return a.seed < b.seed;
 }
 
+// Kept trajectories into sort records; one counter atomic per block and pass of
+// the loop (the records' order is irrelevant: the sort keys are distinct).
 __global__ __launch_bounds__(256) void k_compact(const VolDesc* vols, const TrajRec* rec, SortRec* sr,
                                                  Counters* cnt) {
+    __shared__ unsigned int wn[4];
+    __shared__ unsigned long long bbase;
     const VolDesc& v = vols[blockIdx.y];
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < v.n_traj;
-         i += (long long)gridDim.x * blockDim.x) {
-        const TrajRec r = rec[v.traj_base + i];
-        if (!r.keep) continue;
-        const unsigned long long k = atomicAdd(&cnt->n_sort, 1ull);
-        SortRec o;
-        o.vol = blockIdx.y;
-        o.ky = ~(uint64_t)__double_as_longlong(r.key64 + 0.0);
-        o.kpos = ((uint64_t)r.scale << 48) | ((uint64_t)r.z << 32) | ((uint64_t)r.y << 16) | (uint64_t)r.x;
-        o.seed = (uint32_t)r.seed;
-        o.idx = (uint32_t)(v.traj_base + i);
-        sr[k] = o;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_sort_fill(SortRec* sr, unsigned long long n_pad, const Counters* cnt) {
-    const unsigned long long count = cnt->n_sort;
-    for (unsigned long long i = count + (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
-        SortRec o;
-        o.vol = ~0ull; o.ky = ~0ull; o.kpos = ~0ull; o.seed = ~0u; o.idx = ~0u;
-        sr[i] = o;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (long long b = (long long)blockIdx.x * blockDim.x; b < v.n_traj; b += (long long)gridDim.x * blockDim.x) {
+        const long long i = b + threadIdx.x;
+        TrajRec r;
+        bool keep = false;
+        if (i < v.n_traj) {
+            r = rec[v.traj_base + i];
+            keep = r.keep != 0;
+        }
+        const unsigned long long m = __ballot(keep);
+        if (lane == 0) wn[wave] = (unsigned int)__popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned int t = wn[0] + wn[1] + wn[2] + wn[3];
+            bbase = t ? atomicAdd(&cnt->n_sort, (unsigned long long)t) : 0ull;
+        }
+        __syncthreads();
+        unsigned long long k = bbase;
+        for (int w = 0; w < wave; ++w) k += wn[w];
+        k += (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+        if (keep) {
+            SortRec o;
+            o.vol = blockIdx.y;
+            o.ky = ~(uint64_t)__double_as_longlong(r.key64 + 0.0);
+            o.kpos = ((uint64_t)r.scale << 48) | ((uint64_t)r.z << 32) | ((uint64_t)r.y << 16) | (uint64_t)r.x;
+            o.seed = (uint32_t)r.seed;
+            o.idx = (uint32_t)(v.traj_base + i);
+            sr[k] = o;
+        }
+        __syncthreads();
     }
 }
 
@@ -1727,13 +1739,22 @@ __device__ __forceinline__ void cswap(SortRec* a, unsigned i, unsigned j) {
 // Sorts each block of L records (L = 2 * blockDim) in LDS with a bitonic network
 // whose every stage leaves its blocks ascending (first step compares i with its
 // mirror in the block, the rest are half-cleaners).  Blocks past the real records
-// are skipped; padding records sort to the end of the last real block.
+// are skipped; the last real block is filled up with all-ones padding records,
+// which sort to its end.
 __global__ __launch_bounds__(1024) void k_sort_local(SortRec* sr, unsigned L, const Counters* cnt) {
     extern __shared__ SortRec lsr[];
     const unsigned long long count = cnt->n_sort;
     const unsigned long long start = (unsigned long long)blockIdx.x * L;
     if (start >= count) return;
-    for (unsigned i = threadIdx.x; i < L; i += blockDim.x) lsr[i] = sr[start + i];
+    for (unsigned i = threadIdx.x; i < L; i += blockDim.x) {
+        if (start + i < count) {
+            lsr[i] = sr[start + i];
+        } else {
+            SortRec o;
+            o.vol = ~0ull; o.ky = ~0ull; o.kpos = ~0ull; o.seed = ~0u; o.idx = ~0u;
+            lsr[i] = o;
+        }
+    }
     __syncthreads();
     for (unsigned k = 2; k <= L; k <<= 1) {
         for (unsigned p = threadIdx.x; p < L / 2; p += blockDim.x) {
@@ -1752,31 +1773,77 @@ __global__ __launch_bounds__(1024) void k_sort_local(SortRec* sr, unsigned L, co
     for (unsigned i = threadIdx.x; i < L; i += blockDim.x) sr[start + i] = lsr[i];
 }
 
-// One merge level: src holds sorted runs of `width` records (keys distinct);
-// run pairs are merged into dst.  Each record's output position is its index in
-// its own run plus the number of records of the partner run ordered before it
-// (binary search).  Only the first `count` records are real; padding is skipped.
+// One merge level: src holds sorted runs of `width` records (keys distinct,
+// 2 * width a multiple of kMergeTile); run pairs are merged into dst.  A block
+// writes kMergeTile consecutive outputs of one pair (merge-path tiles): wave 0
+// finds how many records of the first run precede the tile's first output,
+// wave 1 the same for the tile's end, the block stages the two sub-runs between
+// in LDS, and a record's place in the tile is its index in its sub-run plus the
+// number of the other sub-run's records ordered before it.  Only the first
+// `count` records are real.
+constexpr int kMergeTile = 512;
+
+// Records of A among the first d outputs of merge(A, B): the first i in
+// [max(0, d - lb), min(d, la)] with i = min(d, la) or B[d-1-i] < A[i] (monotone
+// in i).  A 64-ary search, one candidate per lane and one ballot per round; the
+// whole wave gets the result.
+__device__ long long merge_split(const SortRec* A, long long la, const SortRec* B, long long lb, long long d,
+                                 int lane) {
+    long long lo = d > lb ? d - lb : 0;
+    long long hi = d < la ? d : la;
+    while (hi > lo) {
+        const long long stride = (hi - lo + 63) / 64;
+        const long long c = lo + lane * stride;
+        const bool t = c >= hi || rec_less(B[d - 1 - c], A[c]);
+        const unsigned long long m = __ballot(t);
+        if (m == 0ull) {
+            lo += 63 * stride + 1;
+        } else {
+            const int k = __ffsll((long long)m) - 1;
+            if (k == 0) break;
+            const long long top = lo + k * stride;
+            lo += (k - 1) * stride + 1;
+            hi = top < hi ? top : hi;
+        }
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(256) void k_merge(const SortRec* src, SortRec* dst, unsigned long long width,
                                                const Counters* cnt) {
+    __shared__ SortRec tile[kMergeTile];
+    __shared__ long long split[2];
     const unsigned long long count = cnt->n_sort;
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
-        const unsigned long long pair = i / (2 * width);
-        const unsigned long long a0 = pair * 2 * width, b0 = a0 + width;
-        const bool in_a = i < b0;
-        const unsigned long long o0 = in_a ? b0 : a0;   // partner run
-        unsigned long long olen = 0;
-        if (count > o0) olen = count - o0 < width ? count - o0 : width;
-        const SortRec x = src[i];
-        // number of partner records ordered before x
-        unsigned long long lo = 0, hi = olen;
+    const unsigned long long g0 = (unsigned long long)blockIdx.x * kMergeTile;
+    if (g0 >= count) return;
+    const unsigned long long a0 = g0 / (2 * width) * (2 * width), b0 = a0 + width;
+    const long long la = (long long)(count - a0 < width ? count - a0 : width);
+    const long long lb = count > b0 ? (long long)(count - b0 < width ? count - b0 : width) : 0;
+    const long long d0 = (long long)(g0 - a0);
+    const long long d1 = d0 + kMergeTile < la + lb ? d0 + kMergeTile : la + lb;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave < 2) {
+        const long long sp = merge_split(src + a0, la, src + b0, lb, wave ? d1 : d0, lane);
+        if (lane == 0) split[wave] = sp;
+    }
+    __syncthreads();
+    const long long i0 = split[0], i1 = split[1];
+    const int na = (int)(i1 - i0), n = (int)(d1 - d0), nb = n - na;
+    const SortRec* sa = src + a0 + i0;
+    const SortRec* sb = src + b0 + (d0 - i0);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) tile[k] = k < na ? sa[k] : sb[k - na];
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const SortRec x = tile[k];
+        const bool in_a = k < na;
+        const SortRec* other = in_a ? tile + na : tile;
+        int lo = 0, hi = in_a ? nb : na;
         while (lo < hi) {
-            const unsigned long long mid = (lo + hi) >> 1;
-            if (rec_less(src[o0 + mid], x)) lo = mid + 1;
+            const int mid = (lo + hi) >> 1;
+            if (rec_less(other[mid], x)) lo = mid + 1;
             else hi = mid;
         }
-        const unsigned long long own = i - (in_a ? a0 : b0);
-        dst[a0 + own + lo] = x;
+        dst[g0 + (in_a ? k : k - na) + lo] = x;
     }
 }
 
@@ -1787,46 +1854,62 @@ __device__ __forceinline__ bool first_of_region(const SortRec* sr, unsigned long
     return a.vol != b.vol || a.kpos != b.kpos;
 }
 
-// Per 1024-element block: number of distinct regions; per volume: regions found
-// (one atomic per wavefront and volume).
+// Per 1024-element block: number of distinct regions; per volume: regions found.
+// Each wavefront counts the regions of the first volume among its lanes; the
+// block adds the counts of consecutive wavefronts with the same volume (the
+// records are sorted by volume) in one atomic, and a lane of a later volume
+// within a wavefront (a volume boundary) adds its own.
 __global__ __launch_bounds__(1024) void k_dedup_count(const SortRec* sr, const Counters* cnt, int* bsum,
                                                       int* vol_nfound) {
-    __shared__ int wsum[16];
+    __shared__ int wsum[16], wvol[16], wcnt[16];
     const unsigned long long count = cnt->n_sort;
     const unsigned long long i = (unsigned long long)blockIdx.x * 1024 + threadIdx.x;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int f = (i < count && first_of_region(sr, i)) ? 1 : 0;
     const int vol = i < count ? (int)sr[i].vol : -1;
     const unsigned long long fmask = __ballot(f);
+    int lv = -1, lc = 0;
     if (fmask) {
         const int lead = __ffsll((long long)fmask) - 1;
-        const int lv = __shfl(vol, lead, 64);
+        lv = __shfl(vol, lead, 64);
         const bool same = f && vol == lv;
-        const unsigned long long smask = __ballot(same);
-        if (lane == lead) atomicAdd(&vol_nfound[lv], (int)__popcll(smask));
+        lc = (int)__popcll(__ballot(same));
         if (f && !same) atomicAdd(&vol_nfound[vol], 1);
     }
     int s = f;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0) wsum[threadIdx.x >> 6] = s;
+    if (lane == 0) {
+        wsum[wave] = s;
+        wvol[wave] = lv;
+        wcnt[wave] = lc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < 16; ++w) t += wsum[w];
+        int t = 0, rv = -1, rc = 0;
+        for (int w = 0; w < 16; ++w) {
+            t += wsum[w];
+            if (wcnt[w] == 0) continue;
+            if (wvol[w] != rv) {
+                if (rc) atomicAdd(&vol_nfound[rv], rc);
+                rv = wvol[w];
+                rc = 0;
+            }
+            rc += wcnt[w];
+        }
+        if (rc) atomicAdd(&vol_nfound[rv], rc);
         bsum[blockIdx.x] = t;
     }
 }
 
-// Exclusive scan of the block sums (one block, sequential chunks).
-__global__ __launch_bounds__(1024) void k_scan_bsum(int* bsum, int nblk) {
-    __shared__ int buf[1024];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
+// Exclusive scan of n ints from in to out (one 1024-thread block, sequential
+// chunks; in == out allowed).
+__device__ void block_exclusive_scan(const int* in, int* out, int n, int* buf, int* carry) {
+    if (threadIdx.x == 0) *carry = 0;
     __syncthreads();
-    for (int base = 0; base < nblk; base += 1024) {
+    for (int base = 0; base < n; base += 1024) {
         const int i = base + threadIdx.x;
-        const int x = i < nblk ? bsum[i] : 0;
+        const int x = i < n ? in[i] : 0;
         buf[threadIdx.x] = x;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
@@ -1835,16 +1918,28 @@ __global__ __launch_bounds__(1024) void k_scan_bsum(int* bsum, int nblk) {
             buf[threadIdx.x] += t;
             __syncthreads();
         }
-        if (i < nblk) bsum[i] = carry + buf[threadIdx.x] - x;
+        if (i < n) out[i] = *carry + buf[threadIdx.x] - x;
         __syncthreads();
-        if (threadIdx.x == 1023) carry += buf[1023];
+        if (threadIdx.x == 1023) *carry += buf[1023];
         __syncthreads();
     }
 }
 
-// Global region rank g of every first-of-region element; volume base ranks.
+// Exclusive scans of the block sums (in place) and of the per-volume region
+// counts (the volumes' first global ranks: records are sorted by volume).
+__global__ __launch_bounds__(1024) void k_scan_bsum(int* bsum, int nblk, const int* vol_nfound, int* vol_base,
+                                                    int nvol) {
+    __shared__ int buf[1024];
+    __shared__ int carry;
+    block_exclusive_scan(bsum, bsum, nblk, buf, &carry);
+    block_exclusive_scan(vol_nfound, vol_base, nvol, buf, &carry);
+}
+
+// Global region rank g of every first-of-region record, and its region written
+// at g - (its volume's first rank) when that is below the volume's capacity.
 __global__ __launch_bounds__(1024) void k_dedup_rank(const SortRec* sr, const Counters* cnt, const int* bsum,
-                                                     int* grank, int* vol_base) {
+                                                     const int* vol_base, const VolDesc* vols, const TrajRec* rec,
+                                                     ks_region_dev* regions) {
     __shared__ int buf[1024];
     const unsigned long long count = cnt->n_sort;
     const unsigned long long i = (unsigned long long)blockIdx.x * 1024 + threadIdx.x;
@@ -1859,28 +1954,17 @@ __global__ __launch_bounds__(1024) void k_dedup_rank(const SortRec* sr, const Co
     }
     if (f) {
         const int g = bsum[blockIdx.x] + buf[threadIdx.x] - 1;
-        grank[i] = g;
-        if (i == 0 || sr[i].vol != sr[i - 1].vol) vol_base[sr[i].vol] = g;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_emit(const SortRec* sr, const Counters* cnt, const int* grank,
-                                              const int* vol_base, const VolDesc* vols, const TrajRec* rec,
-                                              ks_region_dev* regions) {
-    const unsigned long long count = cnt->n_sort;
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
-        if (!first_of_region(sr, i)) continue;
         const int vol = (int)sr[i].vol;
-        const int pos = grank[i] - vol_base[vol];
+        const int pos = g - vol_base[vol];
         const VolDesc& v = vols[vol];
-        if (pos >= v.cap) continue;
-        const TrajRec r = rec[sr[i].idx];
-        ks_region_dev o;
-        o.x = r.x; o.y = r.y; o.z = r.z; o.scale = r.scale;
-        o.saliency = r.y32; o.entropy = r.h32; o.pdf_change = r.w32;
-        o.seed = r.seed;
-        regions[v.reg_off + pos] = o;
+        if (pos < v.cap) {
+            const TrajRec r = rec[sr[i].idx];
+            ks_region_dev o;
+            o.x = r.x; o.y = r.y; o.z = r.z; o.scale = r.scale;
+            o.saliency = r.y32; o.entropy = r.h32; o.pdf_change = r.w32;
+            o.seed = r.seed;
+            regions[v.reg_off + pos] = o;
+        }
     }
 }
 
@@ -1967,8 +2051,6 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_compact, dim3(grid_for(a.max_traj, 256, 1024), a.nvol), dim3(256), 0, st, a.vols, a.rec,
                        a.sr, a.cnt);
     const unsigned long long n_pad = a.n_pad;
-    hipLaunchKernelGGL(k_sort_fill, dim3(grid_for((long long)n_pad, 256, 4096)), dim3(256), 0, st, a.sr, n_pad,
-                       a.cnt);
     // sorted runs of L records in LDS, then merge levels ping-ponging between the
     // two halves of the sort buffer
     const unsigned L = n_pad < 512 ? (unsigned)n_pad : 512u;
@@ -1979,8 +2061,9 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     SortRec* src = a.sr;
     SortRec* dst = a.sr + n_pad;
     for (unsigned long long width = L; width < n_pad; width <<= 1) {
-        hipLaunchKernelGGL(k_merge, dim3(grid_for((long long)n_pad, 256, 8192)), dim3(256), 0, st, src, dst, width,
-                           a.cnt);
+        if ((2 * width) % kMergeTile != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_merge, dim3((unsigned)((n_pad + kMergeTile - 1) / kMergeTile)), dim3(256), 0, st, src,
+                           dst, width, a.cnt);
         SortRec* t = src;
         src = dst;
         dst = t;
@@ -1988,10 +2071,9 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     const SortRec* sorted = src;
     const int nblk = (int)((n_pad + 1023) / 1024);
     hipLaunchKernelGGL(k_dedup_count, dim3(nblk), dim3(1024), 0, st, sorted, a.cnt, a.bsum, a.vol_nfound);
-    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, a.bsum, nblk);
-    hipLaunchKernelGGL(k_dedup_rank, dim3(nblk), dim3(1024), 0, st, sorted, a.cnt, a.bsum, a.grank, a.vol_base);
-    hipLaunchKernelGGL(k_emit, dim3(grid_for((long long)n_pad, 256, 4096)), dim3(256), 0, st, sorted, a.cnt, a.grank,
-                       a.vol_base, a.vols, a.rec, a.regions);
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, a.bsum, nblk, a.vol_nfound, a.vol_base, a.nvol);
+    hipLaunchKernelGGL(k_dedup_rank, dim3(nblk), dim3(1024), 0, st, sorted, a.cnt, a.bsum, a.vol_base, a.vols, a.rec,
+                       a.regions);
     return hipGetLastError();
 }
 

@@ -54,7 +54,6 @@ struct RankArgs {
     unsigned long long n_pad;   // power of two >= total trajectories, >= 2
     long long max_traj;         // largest per-volume trajectory count
     int* bsum;                  // n_pad/1024 + 1 ints
-    int* grank;                 // n_pad ints
     int* vol_base;
     int* vol_nfound;
     ks_region_dev* regions;

@@ -179,7 +179,7 @@ void Context::destroy() {
         if (g.exec) hipGraphExecDestroy(g.exec);
     graphs.clear();
     Buffer* bufs[] = {&tables_buf, &d_vols, &d_segs, &d_seeds, &d_abm, &d_bins, &d_rec, &d_sr, &d_bsum,
-                      &d_grank, &d_volint, &d_regions, &d_cnt, &d_hook, &d_hook_out, &d_raw};
+                      &d_volint, &d_regions, &d_cnt, &d_hook, &d_hook_out, &d_raw};
     for (Buffer* b : bufs) b->release();
     h_stage.release();
     h_out.release();
@@ -370,7 +370,6 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     if ((st = d_rec.ensure(sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1), &generation)) != KS_OK) return st;
     if ((st = d_sr.ensure(2 * sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
     if ((st = d_bsum.ensure(sizeof(int) * (p.n_pad / 1024 + 2), &generation)) != KS_OK) return st;
-    if ((st = d_grank.ensure(sizeof(int) * p.n_pad, &generation)) != KS_OK) return st;
     if ((st = d_volint.ensure(sizeof(int) * 4 * (size_t)nvol, &generation)) != KS_OK) return st;
     if ((st = d_regions.ensure(sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 1), &generation)) != KS_OK)
         return st;
@@ -477,7 +476,7 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         RankArgs ra;
         ra.vols = dv; ra.nvol = p.nvol; ra.rec = rec; ra.sr = static_cast<SortRec*>(d_sr.ptr); ra.cnt = dc;
         ra.n_pad = p.n_pad; ra.max_traj = p.max_traj; ra.bsum = static_cast<int*>(d_bsum.ptr);
-        ra.grank = static_cast<int*>(d_grank.ptr); ra.vol_base = p.vol_base; ra.vol_nfound = p.vol_nfound;
+        ra.vol_base = p.vol_base; ra.vol_nfound = p.vol_nfound;
         ra.regions = static_cast<ks_region_dev*>(d_regions.ptr);
         KS_HIP(launch_rank(ra, st));
     }

@@ -82,7 +82,7 @@ struct Context {
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
     Tables tables{};
-    Buffer tables_buf, d_vols, d_segs, d_seeds, d_abm, d_bins, d_rec, d_sr, d_bsum, d_grank, d_volint, d_regions, d_cnt, d_hook,
+    Buffer tables_buf, d_vols, d_segs, d_seeds, d_abm, d_bins, d_rec, d_sr, d_bsum, d_volint, d_regions, d_cnt, d_hook,
         d_hook_out, d_raw;
     PinnedBuffer h_stage, h_out;
     hipStream_t aux = nullptr;

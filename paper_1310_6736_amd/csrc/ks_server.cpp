@@ -105,7 +105,7 @@ static size_t footprint(const ks::VolIn& v, int64_t ntraj) {
     size_t pad = 2;
     while (pad < n) pad <<= 1;
     return raw + ks::bins_bytes(v.dims) + n * (sizeof(ks::TrajRec) + 12) +
-           pad * (2 * sizeof(ks::SortRec) + 2 * sizeof(int)) + (size_t)v.capacity * sizeof(ks_region) + (1 << 16);
+           pad * (2 * sizeof(ks::SortRec) + sizeof(int)) + (size_t)v.capacity * sizeof(ks_region) + (1 << 16);
 }
 
 static double percentile(std::vector<double> v, double q) {
