@@ -27,6 +27,10 @@
 // butterfly below produces exactly that tree.
 #include <limits.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "ks_device.h"
 #include "ks_launch.h"
 
@@ -260,14 +264,40 @@ __device__ __forceinline__ int read_raw(const void* raw, int dtype, int64_t i) {
     return static_cast<const int16_t*>(raw)[i];
 }
 
-// Range scan: per-thread, per-wave and per-block reduction, one atomic pair per block.
+// Range scan: per-thread, per-wave and per-block reduction, one atomic pair per
+// block.  A 16-byte aligned volume is read in 16-byte words (the voxels of a
+// whole number of words), the rest voxel by voxel.
 __global__ __launch_bounds__(256) void k_minmax(const VolDesc* vols) {
     __shared__ int slo[4], shi[4];
     const VolDesc& v = vols[blockIdx.y];
     const int64_t n = (int64_t)v.X * v.Y * v.Z;
+    const int per_word = v.dtype == 0 ? 16 : 8;
+    const int64_t nw = (reinterpret_cast<uintptr_t>(v.raw) & 15) == 0 ? n / per_word : 0;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
     int lo = INT_MAX, hi = INT_MIN;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int a = read_raw(v.raw, v.dtype, i);
+    const uint4* words = static_cast<const uint4*>(v.raw);
+    for (int64_t w = gid; w < nw; w += stride) {
+        const uint4 q = words[w];
+        const uint32_t d[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (v.dtype == 0) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int a = (int)((d[k] >> (8 * b)) & 0xffu);
+                    lo = min(lo, a);
+                    hi = max(hi, a);
+                }
+            } else {
+                const int a0 = v.dtype == 1 ? (int)(d[k] & 0xffffu) : (int)(int16_t)(d[k] & 0xffffu);
+                const int a1 = v.dtype == 1 ? (int)(d[k] >> 16) : (int)(int16_t)(d[k] >> 16);
+                lo = min(lo, min(a0, a1));
+                hi = max(hi, max(a0, a1));
+            }
+        }
+    }
+    for (int64_t i = nw * per_word + gid; i < n; i += stride) {
+        const int a = read_raw(v.raw, v.dtype, i);
         lo = min(lo, a);
         hi = max(hi, a);
     }
@@ -1980,7 +2010,7 @@ static int grid_for(long long n, int threads, int cap) {
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_prep_init, dim3((a.nvol + 255) / 256), dim3(256), 0, st, a.vols, a.nvol, a.cnt,
                        a.vol_nfound, a.vol_base);
-    const int gx = grid_for(a.max_voxels, 256 * 16, 512);
+    const int gx = grid_for(a.max_voxels, 256 * 32, 512);
     hipLaunchKernelGGL(k_minmax, dim3(gx, a.nvol), dim3(256), 0, st, a.vols);
     const int gq = grid_for(a.max_words, 256, 4096);
     hipLaunchKernelGGL(k_quantize, dim3(gq, a.nvol), dim3(256), 0, st, a.vols);
@@ -2098,10 +2128,27 @@ int max_blocks_map(int K, int B) {
     return nb < 1 ? 1 : nb;
 }
 
-int max_blocks_ms(int hist_words, int maxB) {
+// Resident blocks per CU from the occupancy calculator, cached per device and
+// launch shape (the query costs host time on every detection otherwise).
+static int cached_occupancy(int kind, int M, size_t lds, int (*query)(int M, size_t lds)) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return query(M, lds);
+    const auto key = std::make_tuple(dev, kind, M, lds);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int nb = query(M, lds);
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = nb;
+    return nb;
+}
+
+static int query_ms(int M, size_t lds) {
     int nb = 0;
-    const int M = bins_per_lane_host(maxB);
-    const size_t lds = (size_t)hist_words * 8;
     hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<1, false>, 64, lds)
                  : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<2, false>, 64, lds)
                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_ms<4, false>, 64, lds);
@@ -2109,14 +2156,21 @@ int max_blocks_ms(int hist_words, int maxB) {
     return nb < 1 ? 1 : nb;
 }
 
-int max_blocks_quad(size_t lds_bytes, int maxB) {
+static int query_quad(int M, size_t lds) {
     int nb = 0;
-    const int M = bins_per_lane_host(maxB);
-    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<1>, kQuadThreads, lds_bytes)
-                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<2>, kQuadThreads, lds_bytes)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<4>, kQuadThreads, lds_bytes);
+    hipError_t e = M == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<1>, kQuadThreads, lds)
+                 : M == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<2>, kQuadThreads, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search_quad<4>, kQuadThreads, lds);
     if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
+}
+
+int max_blocks_ms(int hist_words, int maxB) {
+    return cached_occupancy(0, bins_per_lane_host(maxB), (size_t)hist_words * 8, query_ms);
+}
+
+int max_blocks_quad(size_t lds_bytes, int maxB) {
+    return cached_occupancy(1, bins_per_lane_host(maxB), lds_bytes, query_quad);
 }
 
 }  // namespace ks

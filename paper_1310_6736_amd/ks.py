@@ -203,8 +203,22 @@ def _volume_args(t):
     return C.c_void_p(t.data_ptr()), _torch_dtype_code(t), _i3((x, y, z))
 
 
-def regions_to_numpy(arr, n):
-    return np.ctypeslib.as_array(arr)[:n].copy() if n > 0 else np.zeros(0, dtype=np.ctypeslib.as_array(arr).dtype)
+# ks_region as a numpy record (the same fields, offsets and size as Region)
+REGION_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("z", "<i4"), ("scale", "<i4"), ("saliency", "<f4"),
+                         ("entropy", "<f4"), ("pdf_change", "<f4"), ("seed", "<i4")])
+assert REGION_DTYPE.itemsize == C.sizeof(Region)
+
+
+def _region_buffer(capacity):
+    """A numpy array of capacity ks_region records and its address for the library
+    to fill (numpy-owned: converting a ctypes array costs far more per call)."""
+    a = np.empty(max(int(capacity), 1), REGION_DTYPE)
+    return a, C.c_void_p(a.ctypes.data)
+
+
+def _regions(buf, n_found, capacity):
+    # a view of the written records (a structured copy costs tens of microseconds)
+    return buf[:max(0, min(int(n_found), int(capacity)))]
 
 
 class Context:
@@ -315,20 +329,20 @@ def ks_detect(volume: np.ndarray, bins, seed_spacing, scales, method, max_iter, 
     """Host volume (Z, Y, X) numpy array -> (regions, n_found)."""
     vol = np.ascontiguousarray(volume)
     z, y, x = vol.shape
-    out = (Region * max(int(capacity), 1))()
+    buf, out = _region_buffer(capacity)
     nf = C.c_int32()
     _check(lib().ks_detect(C.c_void_p(vol.ctypes.data), _NP_DTYPE[vol.dtype], _i3((x, y, z)), bins, seed_spacing,
                            _i2(scales), method, max_iter, out, int(capacity), C.byref(nf)), "ks_detect")
-    return regions_to_numpy(out, min(nf.value, int(capacity))), nf.value
+    return _regions(buf, nf.value, capacity), nf.value
 
 
 def ks_detect_device(ctx: Context, volume, bins, seed_spacing, scales, method, max_iter, capacity=1024, stream=None):
     ptr, dt, dims = _volume_args(volume)
-    out = (Region * max(int(capacity), 1))()
+    buf, out = _region_buffer(capacity)
     nf = C.c_int32()
     _check(lib().ks_detect_device(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter, out,
                                   int(capacity), C.byref(nf), _stream_ptr(stream)), "ks_detect_device")
-    return regions_to_numpy(out, min(nf.value, int(capacity))), nf.value
+    return _regions(buf, nf.value, capacity), nf.value
 
 
 def ks_seed_traces(ctx: Context, volume, bins, seed_spacing, scales, method, max_iter, stream=None):
@@ -424,14 +438,14 @@ def ks_detect_batch(ctx: Context, requests, capacity=1024, stream=None):
     """requests: list of Request (device volumes).  Returns a list of (regions, n_found)."""
     n = len(requests)
     reqs = (Request * max(n, 1))(*requests)
-    bufs = [(Region * max(int(capacity), 1))() for _ in range(n)]
+    bufs = [_region_buffer(capacity) for _ in range(n)]
     res = (Result * max(n, 1))()
     for i in range(n):
-        res[i].regions = C.cast(bufs[i], C.POINTER(Region))
+        res[i].regions = C.cast(bufs[i][1], C.POINTER(Region))
         res[i].capacity = int(capacity)
     _check(lib().ks_detect_batch(ctx.handle, n, reqs, res, _stream_ptr(stream) if stream is not None else None),
            "ks_detect_batch")
-    return [(regions_to_numpy(bufs[i], min(res[i].n_found, int(capacity))), res[i].n_found) for i in range(n)]
+    return [(_regions(bufs[i][0], res[i].n_found, capacity), res[i].n_found) for i in range(n)]
 
 
 KS_ROOF_COPY, KS_ROOF_LDS_ADD64, KS_ROOF_LDS_ADD32, KS_ROOF_LDS_ADD64_SHARED4 = 0, 1, 2, 3
@@ -467,13 +481,13 @@ class Server:
         return t.value
 
     def poll(self, ticket: int, capacity=1024):
-        out = (Region * max(int(capacity), 1))()
+        buf, out = _region_buffer(capacity)
         nf = C.c_int32()
         st = lib().ks_server_poll(self.handle, C.c_uint64(ticket), out, int(capacity), C.byref(nf))
         if st == KS_E_NOT_READY:
             return None
         _check(st, "ks_server_poll")
-        return regions_to_numpy(out, min(nf.value, int(capacity))), nf.value
+        return _regions(buf, nf.value, capacity), nf.value
 
     def drain(self):
         _check(lib().ks_server_drain(self.handle), "ks_server_drain")
