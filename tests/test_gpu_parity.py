@@ -89,6 +89,31 @@ def test_bin_volume_bit_exact(torch_dev, ctx, case):
     assert np.array_equal(got, oracle.bin_volume(v, bins))
 
 
+@pytest.mark.parametrize("case", [
+    ("u8", np.uint8, (13, 17, 23), 0, 255, 32),
+    ("u16", np.uint16, (9, 31, 37), 0, 4095, 64),
+    ("i16", np.int16, (11, 7, 65), -900, 1400, 7),
+])
+def test_bin_volume_unaligned_volume(torch_dev, ctx, case):
+    """A volume that starts one element into its allocation (not 16-byte aligned:
+    the range scan takes its voxel-by-voxel path), and one that starts 16 bytes in."""
+    name, dt, shape, lo, hi, bins = case
+    v = random_volume(2, shape, dt, lo, hi)
+    want = oracle.bin_volume(v, bins)
+    flat = np.ascontiguousarray(v).reshape(-1)
+    esize = np.dtype(dt).itemsize
+    for skip in (1, 16 // esize):
+        note(f"bin_volume {name} {shape} B={bins}, {skip} element(s) into the buffer")
+        # bytes placed in a uint8 buffer, then viewed as the voxel type
+        off = skip * esize
+        buf = torch_dev.zeros(flat.nbytes + 64, dtype=torch_dev.uint8, device="cuda:0")
+        buf[off:off + flat.nbytes] = torch_dev.from_numpy(flat.view(np.uint8)).to("cuda:0")
+        view = buf[off:off + flat.nbytes].view(dev(torch_dev, flat[:1]).dtype).view(*shape)
+        assert view.is_contiguous() and (view.data_ptr() % 16 != 0) == (skip * esize % 16 != 0)
+        got = ks.ks_bin_volume(ctx, view, bins)
+        assert np.array_equal(got, want), (name, skip)
+
+
 def test_bin_volume_full_size_workloads(torch_dev, ctx):
     for w in (synth.pet_shell(ks.KS_QUADRANT), synth.mr_blobs()):
         note(f"bin_volume {w.name}")
