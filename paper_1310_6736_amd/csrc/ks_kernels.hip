@@ -1761,46 +1761,54 @@ __global__ __launch_bounds__(256) void k_compact(const VolDesc* vols, const Traj
     }
 }
 
-__device__ __forceinline__ void cswap(SortRec* a, unsigned i, unsigned j) {
-    const SortRec x = a[i], y = a[j];
-    if (rec_less(y, x)) { a[i] = y; a[j] = x; }
+// A record of the lane `lane ^ m` of the same wavefront (m < 64).
+__device__ __forceinline__ SortRec shfl_xor_rec(const SortRec& r, unsigned m) {
+    uint32_t w[8];
+    static_assert(sizeof(SortRec) == sizeof(w), "SortRec is 8 dwords");
+    __builtin_memcpy(w, &r, sizeof(w));
+#pragma unroll
+    for (int t = 0; t < 8; ++t) w[t] = (uint32_t)__shfl_xor((int)w[t], (int)m, 64);
+    SortRec o;
+    __builtin_memcpy(&o, w, sizeof(w));
+    return o;
 }
 
-// Sorts each block of L records (L = 2 * blockDim) in LDS with a bitonic network
-// whose every stage leaves its blocks ascending (first step compares i with its
-// mirror in the block, the rest are half-cleaners).  Blocks past the real records
-// are skipped; the last real block is filled up with all-ones padding records,
-// which sort to its end.
-__global__ __launch_bounds__(1024) void k_sort_local(SortRec* sr, unsigned L, const Counters* cnt) {
+// Sorts each block of L records (L = blockDim, a power of two) with a bitonic
+// network whose every stage leaves its blocks ascending: in the stage for
+// blocks of k, each record is first compared with its mirror i ^ (k - 1), then
+// with i ^ j for j = k/4 .. 1 (half-cleaners); the lower index keeps the
+// smaller record.  One record per thread, in registers: partners within the
+// wavefront (distance < 64) come by lane shuffles, the others through LDS.
+// Blocks past the real records are skipped; the last real block is filled up
+// with all-ones padding records, which sort to its end.
+__global__ __launch_bounds__(512) void k_sort_local(SortRec* sr, unsigned L, const Counters* cnt) {
     extern __shared__ SortRec lsr[];
     const unsigned long long count = cnt->n_sort;
     const unsigned long long start = (unsigned long long)blockIdx.x * L;
     if (start >= count) return;
-    for (unsigned i = threadIdx.x; i < L; i += blockDim.x) {
-        if (start + i < count) {
-            lsr[i] = sr[start + i];
-        } else {
-            SortRec o;
-            o.vol = ~0ull; o.ky = ~0ull; o.kpos = ~0ull; o.seed = ~0u; o.idx = ~0u;
-            lsr[i] = o;
-        }
+    const unsigned i = threadIdx.x;
+    SortRec r;
+    if (start + i < count) {
+        r = sr[start + i];
+    } else {
+        r.vol = ~0ull; r.ky = ~0ull; r.kpos = ~0ull; r.seed = ~0u; r.idx = ~0u;
     }
-    __syncthreads();
     for (unsigned k = 2; k <= L; k <<= 1) {
-        for (unsigned p = threadIdx.x; p < L / 2; p += blockDim.x) {
-            const unsigned i = (p / (k / 2)) * k + (p % (k / 2));
-            cswap(lsr, i, i ^ (k - 1));
-        }
-        __syncthreads();
-        for (unsigned j = k / 4; j >= 1; j >>= 1) {
-            for (unsigned p = threadIdx.x; p < L / 2; p += blockDim.x) {
-                const unsigned i = (p / j) * 2 * j + (p % j);
-                cswap(lsr, i, i + j);
+        for (unsigned j = k / 2; j >= 1; j >>= 1) {
+            const unsigned m = j == k / 2 ? k - 1 : j;
+            SortRec o;
+            if (m < 64) {
+                o = shfl_xor_rec(r, m);
+            } else {
+                lsr[i] = r;
+                __syncthreads();
+                o = lsr[i ^ m];
+                __syncthreads();
             }
-            __syncthreads();
+            if ((i < (i ^ m)) == rec_less(o, r)) r = o;
         }
     }
-    for (unsigned i = threadIdx.x; i < L; i += blockDim.x) sr[start + i] = lsr[i];
+    sr[start + i] = r;
 }
 
 // One merge level: src holds sorted runs of `width` records (keys distinct,
@@ -2086,7 +2094,7 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     const unsigned L = n_pad < 512 ? (unsigned)n_pad : 512u;
     const unsigned nblk_local = (unsigned)(n_pad / L);
     const size_t lds = (size_t)L * sizeof(SortRec);
-    const unsigned threads = L / 2;
+    const unsigned threads = L;
     hipLaunchKernelGGL(k_sort_local, dim3(nblk_local), dim3(threads), lds, st, a.sr, L, a.cnt);
     SortRec* src = a.sr;
     SortRec* dst = a.sr + n_pad;
