@@ -178,7 +178,7 @@ void Context::destroy() {
     for (auto& g : graphs)
         if (g.exec) hipGraphExecDestroy(g.exec);
     graphs.clear();
-    Buffer* bufs[] = {&tables_buf, &d_vols, &d_segs, &d_seeds, &d_abm, &d_bins, &d_rec, &d_sr, &d_bsum,
+    Buffer* bufs[] = {&tables_buf, &d_vols, &d_abm, &d_bins, &d_rec, &d_sr, &d_bsum,
                       &d_volint, &d_regions, &d_cnt, &d_hook, &d_hook_out, &d_raw};
     for (Buffer* b : bufs) b->release();
     h_stage.release();
@@ -363,9 +363,10 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     ks_status st;
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)nvol;
     const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
-    if ((st = d_vols.ensure(vol_bytes, &generation)) != KS_OK) return st;
-    if ((st = d_segs.ensure(seg_bytes, &generation)) != KS_OK) return st;
-    if ((st = d_seeds.ensure(std::max<size_t>(sizeof(int32_t) * p.seed_ints, 256), &generation)) != KS_OK) return st;
+    const size_t stage_bytes = vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints;
+    // descriptors, task segments and seed lists in one allocation laid out as the
+    // host staging area, so that one copy uploads them
+    if ((st = d_vols.ensure(std::max<size_t>(stage_bytes, 256), &generation)) != KS_OK) return st;
     if ((st = d_bins.ensure(std::max<size_t>(bins_total, 256), &generation)) != KS_OK) return st;
     if ((st = d_rec.ensure(sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1), &generation)) != KS_OK) return st;
     if ((st = d_sr.ensure(2 * sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
@@ -379,14 +380,15 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         p.vols[i].bins = static_cast<uint8_t*>(d_bins.ptr) + bins_off[i];
         p.vols[i].bins_t = p.vols[i].bins + bins_x_bytes(in[i].dims);
         p.vols[i].minmax = volint + 2 * i;
-        p.vols[i].seeds = in[i].seeds ? static_cast<const int32_t*>(d_seeds.ptr) + p.seed_off[i] : nullptr;
+        p.vols[i].seeds = in[i].seeds ? reinterpret_cast<const int32_t*>(static_cast<char*>(d_vols.ptr) + vol_bytes +
+                                                                          seg_bytes) + p.seed_off[i]
+                                      : nullptr;
     }
     p.seed_src.resize(nvol);
     for (int i = 0; i < nvol; ++i) p.seed_src[i] = in[i].seeds;
     p.vol_nfound = volint + 2 * nvol;
     p.vol_base = volint + 3 * nvol;
     // Host staging: vols, segs, seed lists.
-    const size_t stage_bytes = vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints;
     if ((st = h_stage.ensure(stage_bytes)) != KS_OK) return st;
     const size_t out_bytes = sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 1) + sizeof(int) * nvol +
                              sizeof(Counters);
@@ -404,26 +406,25 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
 ks_status Context::upload(const Plan& p, hipStream_t st) {
     char* h = static_cast<char*>(h_stage.ptr);
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)p.nvol;
+    const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     std::memcpy(h, p.vols.data(), vol_bytes);
     TaskSeg* hs = reinterpret_cast<TaskSeg*>(h + vol_bytes);
     size_t ns = 0;
     for (const TaskSeg& s : p.segs_q) hs[ns++] = s;
     for (const TaskSeg& s : p.segs_m) hs[ns++] = s;
-    KS_HIP(hipMemcpyAsync(d_vols.ptr, h, vol_bytes, hipMemcpyHostToDevice, st));
-    if (ns) KS_HIP(hipMemcpyAsync(d_segs.ptr, hs, sizeof(TaskSeg) * ns, hipMemcpyHostToDevice, st));
-    if (p.seed_ints) {
-        int32_t* hseed = reinterpret_cast<int32_t*>(h + vol_bytes + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1));
-        for (int i = 0; i < p.nvol; ++i)
-            if (p.seed_src[i])
-                std::memcpy(hseed + p.seed_off[i], p.seed_src[i], sizeof(int32_t) * 3 * (size_t)p.vols[i].gx);
-        KS_HIP(hipMemcpyAsync(d_seeds.ptr, hseed, sizeof(int32_t) * p.seed_ints, hipMemcpyHostToDevice, st));
-    }
+    std::memset(hs + ns, 0, sizeof(TaskSeg));
+    int32_t* hseed = reinterpret_cast<int32_t*>(h + vol_bytes + seg_bytes);
+    for (int i = 0; i < p.nvol; ++i)
+        if (p.seed_src[i])
+            std::memcpy(hseed + p.seed_off[i], p.seed_src[i], sizeof(int32_t) * 3 * (size_t)p.vols[i].gx);
+    KS_HIP(hipMemcpyAsync(d_vols.ptr, h, vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints,
+                          hipMemcpyHostToDevice, st));
     return KS_OK;
 }
 
 ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed) {
     VolDesc* dv = static_cast<VolDesc*>(d_vols.ptr);
-    TaskSeg* ds = static_cast<TaskSeg*>(d_segs.ptr);
+    TaskSeg* ds = reinterpret_cast<TaskSeg*>(static_cast<char*>(d_vols.ptr) + sizeof(VolDesc) * (size_t)p.nvol);
     Counters* dc = static_cast<Counters*>(d_cnt.ptr);
     TrajRec* rec = static_cast<TrajRec*>(d_rec.ptr);
     if (timed) KS_HIP(hipEventRecord(ev[0], st));

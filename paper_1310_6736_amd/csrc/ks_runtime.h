@@ -54,7 +54,7 @@ struct Plan {
     LdsQuad lay{};
     int* vol_nfound = nullptr;
     int* vol_base = nullptr;
-    std::vector<size_t> seed_off;   // per volume: int offset of its seed list in d_seeds
+    std::vector<size_t> seed_off;   // per volume: int offset of its seed list after the segments
     std::vector<const int32_t*> seed_src;  // per volume: the caller's host list, or null
     size_t seed_ints = 0;
 };
@@ -82,7 +82,7 @@ struct Context {
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
     Tables tables{};
-    Buffer tables_buf, d_vols, d_segs, d_seeds, d_abm, d_bins, d_rec, d_sr, d_bsum, d_volint, d_regions, d_cnt, d_hook,
+    Buffer tables_buf, d_vols, d_abm, d_bins, d_rec, d_sr, d_bsum, d_volint, d_regions, d_cnt, d_hook,
         d_hook_out, d_raw;
     PinnedBuffer h_stage, h_out;
     hipStream_t aux = nullptr;
