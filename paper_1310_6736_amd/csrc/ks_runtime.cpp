@@ -179,7 +179,7 @@ void Context::destroy() {
         if (g.exec) hipGraphExecDestroy(g.exec);
     graphs.clear();
     Buffer* bufs[] = {&tables_buf, &d_vols, &d_abm, &d_bins, &d_rec, &d_sr, &d_bsum,
-                      &d_volint, &d_regions, &d_cnt, &d_hook, &d_hook_out, &d_raw};
+                      &d_volint, &d_regions, &d_hook, &d_hook_out, &d_raw};
     for (Buffer* b : bufs) b->release();
     h_stage.release();
     h_out.release();
@@ -371,10 +371,14 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     if ((st = d_rec.ensure(sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1), &generation)) != KS_OK) return st;
     if ((st = d_sr.ensure(2 * sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
     if ((st = d_bsum.ensure(sizeof(int) * (p.n_pad / 1024 + 2), &generation)) != KS_OK) return st;
-    if ((st = d_volint.ensure(sizeof(int) * 4 * (size_t)nvol, &generation)) != KS_OK) return st;
-    if ((st = d_regions.ensure(sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 1), &generation)) != KS_OK)
-        return st;
-    if ((st = d_cnt.ensure(sizeof(Counters), &generation)) != KS_OK) return st;
+    if ((st = d_volint.ensure(sizeof(int) * 3 * (size_t)nvol, &generation)) != KS_OK) return st;
+    // results in one allocation laid out as the host copy, so that one copy
+    // downloads them: regions, per-volume region counts, the counter block
+    p.out_nf_off = sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 0);
+    p.out_cnt_off = (p.out_nf_off + sizeof(int) * (size_t)nvol + 63) & ~(size_t)63;
+    p.out_bytes = p.out_cnt_off + sizeof(Counters);
+    if ((st = d_regions.ensure(p.out_bytes, &generation)) != KS_OK) return st;
+    p.cnt = reinterpret_cast<Counters*>(static_cast<char*>(d_regions.ptr) + p.out_cnt_off);
     int* volint = static_cast<int*>(d_volint.ptr);
     for (int i = 0; i < nvol; ++i) {
         p.vols[i].bins = static_cast<uint8_t*>(d_bins.ptr) + bins_off[i];
@@ -386,13 +390,11 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     }
     p.seed_src.resize(nvol);
     for (int i = 0; i < nvol; ++i) p.seed_src[i] = in[i].seeds;
-    p.vol_nfound = volint + 2 * nvol;
-    p.vol_base = volint + 3 * nvol;
+    p.vol_nfound = reinterpret_cast<int*>(static_cast<char*>(d_regions.ptr) + p.out_nf_off);
+    p.vol_base = volint + 2 * nvol;
     // Host staging: vols, segs, seed lists.
     if ((st = h_stage.ensure(stage_bytes)) != KS_OK) return st;
-    const size_t out_bytes = sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 1) + sizeof(int) * nvol +
-                             sizeof(Counters);
-    if ((st = h_out.ensure(out_bytes)) != KS_OK) return st;
+    if ((st = h_out.ensure(p.out_bytes)) != KS_OK) return st;
     p.rl = pick_ms_rl(std::max(p.maxB_ms, 2), ms_rl_pref);
     p.rl_small = pick_ms_rl(std::max(p.maxB_ms, 2), ms_rl_small_pref);
     p.rq = pick_quad_rq(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), quad_rq_pref);
@@ -425,7 +427,7 @@ ks_status Context::upload(const Plan& p, hipStream_t st) {
 ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed) {
     VolDesc* dv = static_cast<VolDesc*>(d_vols.ptr);
     TaskSeg* ds = reinterpret_cast<TaskSeg*>(static_cast<char*>(d_vols.ptr) + sizeof(VolDesc) * (size_t)p.nvol);
-    Counters* dc = static_cast<Counters*>(d_cnt.ptr);
+    Counters* dc = p.cnt;
     TrajRec* rec = static_cast<TrajRec*>(d_rec.ptr);
     if (timed) KS_HIP(hipEventRecord(ev[0], st));
     PrepArgs pa;
@@ -486,20 +488,15 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
 }
 
 ks_status Context::download(const Plan& p, hipStream_t st) {
-    char* h = static_cast<char*>(h_out.ptr);
-    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
-    if (rb) KS_HIP(hipMemcpyAsync(h, d_regions.ptr, rb, hipMemcpyDeviceToHost, st));
-    KS_HIP(hipMemcpyAsync(h + rb, p.vol_nfound, sizeof(int) * p.nvol, hipMemcpyDeviceToHost, st));
-    KS_HIP(hipMemcpyAsync(h + rb + sizeof(int) * p.nvol, d_cnt.ptr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    KS_HIP(hipMemcpyAsync(h_out.ptr, d_regions.ptr, p.out_bytes, hipMemcpyDeviceToHost, st));
     return KS_OK;
 }
 
 void Context::collect_stats(const Plan& p, bool timed) {
     const char* h = static_cast<const char*>(h_out.ptr);
-    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
-    const int* nf = reinterpret_cast<const int*>(h + rb);
+    const int* nf = reinterpret_cast<const int*>(h + p.out_nf_off);
     Counters c;
-    std::memcpy(&c, h + rb + sizeof(int) * p.nvol, sizeof(Counters));
+    std::memcpy(&c, h + p.out_cnt_off, sizeof(Counters));
     std::memset(&last, 0, sizeof(last));
     last.trajectories = p.total_traj;
     last.evals = (int64_t)c.evals;
@@ -536,8 +533,7 @@ void Context::end_detect(const std::vector<VolIn>& in, const Plan& p, std::vecto
     collect_stats(p, profiling);
     const char* h = static_cast<const char*>(h_out.ptr);
     const ks_region* regs = reinterpret_cast<const ks_region*>(h);
-    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
-    const int* nf = reinterpret_cast<const int*>(h + rb);
+    const int* nf = reinterpret_cast<const int*>(h + p.out_nf_off);
     out->assign(in.size(), {});
     nfound->assign(in.size(), 0);
     for (size_t i = 0; i < in.size(); ++i) {
@@ -629,8 +625,7 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     }
     const char* h = static_cast<const char*>(h_out.ptr);
     const ks_region* regs = reinterpret_cast<const ks_region*>(h);
-    const size_t rb = sizeof(ks_region) * (size_t)std::max<int64_t>(p.total_regions, 0);
-    const int* nf = reinterpret_cast<const int*>(h + rb);
+    const int* nf = reinterpret_cast<const int*>(h + p.out_nf_off);
     out->assign(in.size(), {});
     nfound->assign(in.size(), 0);
     for (size_t i = 0; i < in.size(); ++i) {
@@ -945,7 +940,7 @@ ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
@@ -975,7 +970,7 @@ ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype,
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[0], st));
@@ -985,11 +980,11 @@ ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype,
     const int grid = (int)std::min<long long>(rows, (long long)max_blocks_map(K, bins) * ctx->num_cu);
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[1], st));
     if (launch_saliency_map(static_cast<VolDesc*>(ctx->d_vols.ptr), ctx->tables, d_saliency, d_scale,
-                            static_cast<Counters*>(ctx->d_cnt.ptr), K, bins, grid, st) != hipSuccess)
+                            p.cnt, K, bins, grid, st) != hipSuccess)
         return KS_E_DEVICE;
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[2], st));
     Counters c;
-    if (hipMemcpyAsync(&c, ctx->d_cnt.ptr, sizeof(Counters), hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (hipMemcpyAsync(&c, p.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st) != hipSuccess)
         return KS_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
     std::memset(&ctx->last, 0, sizeof(ctx->last));
@@ -1034,7 +1029,7 @@ ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const
         return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[0], st));
@@ -1047,7 +1042,7 @@ ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const
         a.threshold = threshold;
         const int grid = (int)std::min<int64_t>(total, (int64_t)abmsod_blocks_per_cu() * ctx->num_cu);
         if (launch_abmsod(static_cast<VolDesc*>(ctx->d_vols.ptr), a, bins, grid,
-                          static_cast<ks_ellipsoid*>(ctx->d_abm.ptr), static_cast<Counters*>(ctx->d_cnt.ptr),
+                          static_cast<ks_ellipsoid*>(ctx->d_abm.ptr), p.cnt,
                           st) != hipSuccess)
             return KS_E_DEVICE;
     }
@@ -1057,7 +1052,7 @@ ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const
                      hipSuccess)
         return KS_E_DEVICE;
     Counters c;
-    if (hipMemcpyAsync(&c, ctx->d_cnt.ptr, sizeof(Counters), hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (hipMemcpyAsync(&c, p.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st) != hipSuccess)
         return KS_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
     std::memset(&ctx->last, 0, sizeof(ctx->last));
@@ -1106,7 +1101,7 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = static_cast<Counters*>(ctx->d_cnt.ptr);
+    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;

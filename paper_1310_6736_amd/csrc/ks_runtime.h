@@ -54,6 +54,8 @@ struct Plan {
     LdsQuad lay{};
     int* vol_nfound = nullptr;
     int* vol_base = nullptr;
+    Counters* cnt = nullptr;        // the counter block, inside the result allocation
+    size_t out_nf_off = 0, out_cnt_off = 0, out_bytes = 0;  // result layout (device and host copy)
     std::vector<size_t> seed_off;   // per volume: int offset of its seed list after the segments
     std::vector<const int32_t*> seed_src;  // per volume: the caller's host list, or null
     size_t seed_ints = 0;
@@ -82,7 +84,7 @@ struct Context {
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
     int generation = 0;
     Tables tables{};
-    Buffer tables_buf, d_vols, d_abm, d_bins, d_rec, d_sr, d_bsum, d_volint, d_regions, d_cnt, d_hook,
+    Buffer tables_buf, d_vols, d_abm, d_bins, d_rec, d_sr, d_bsum, d_volint, d_regions, d_hook,
         d_hook_out, d_raw;
     PinnedBuffer h_stage, h_out;
     hipStream_t aux = nullptr;
