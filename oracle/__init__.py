@@ -96,6 +96,7 @@ def lib():
                                         C.c_int32, i32p, C.POINTER(Stats)]
         L.kso_abmsod.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32, C.c_void_p, C.c_int64,
                                  i32p, C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(Stats)]
+        L.kso_rank.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int32, i32p]
         _lib = L
     return _lib
 
@@ -267,6 +268,20 @@ def detect(vol: np.ndarray, bins, spacing, scales, method, max_iter, capacity=No
                          C.byref(nf), C.byref(st))
     arr = np.ctypeslib.as_array(out)[:min(capacity, nf.value)].copy()
     return arr, nf.value, {"evals": st.evals, "window_evals": st.window_evals, "voxel_visits": st.voxel_visits}
+
+
+def rank(traj: np.ndarray, rank_by=RANK_SALIENCY, capacity=None):
+    """Step 8 alone on trajectory records of `run` (one run, or its shards
+    concatenated in any order): (structured array of regions, n_found)."""
+    t = np.ascontiguousarray(traj, dtype=np.dtype(Traj))
+    n = t.shape[0]
+    if capacity is None:
+        capacity = max(1, n)
+    out = (Region * max(capacity, 1))()
+    nf = C.c_int32()
+    if lib().kso_rank(t.ctypes.data, n, rank_by, out, capacity, C.byref(nf)) != 0:
+        raise MemoryError("kso_rank")
+    return np.ctypeslib.as_array(out)[:min(capacity, nf.value)].copy(), nf.value
 
 
 def abmsod(vol: np.ndarray, bins, spacing, radii, max_iter, threshold=0.0, seeds=None, ids=None, window=None):

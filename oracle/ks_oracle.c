@@ -524,17 +524,12 @@ static int region_cmp(const void* pa, const void* pb) {
     return 0;
 }
 
-static int detect_impl(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
-                       int32_t spacing, const int32_t* seeds, int64_t n_seeds, const int32_t scales[2],
-                       int32_t method, int32_t max_iter, double h_min, double y_min, int32_t rank_by,
-                       kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
-    if (!seeds_ok(dims, seeds, n_seeds)) return -1;
-    int64_t n = seeds ? n_seeds * (method == KSO_MEANSHIFT ? scales[1] - scales[0] + 1 : 1)
-                      : kso_num_trajectories(dims, spacing, scales, method);
-    kso_traj* t = (kso_traj*)malloc(sizeof(kso_traj) * (size_t)(n > 0 ? n : 1));
-    run_impl(vol, dtype, dims, bins, window, spacing, seeds, n_seeds, scales, method, max_iter, h_min, y_min, NULL, 0,
-             t, stats);
+/* Step 8: the kept trajectories' regions, deduplicated on (x, y, z, scale)
+ * (smallest trajectory id kept) and ranked; the order does not depend on the
+ * order of the input records. */
+int kso_rank(const kso_traj* t, int64_t n, int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found) {
     kso_region* r = (kso_region*)malloc(sizeof(kso_region) * (size_t)(n > 0 ? n : 1));
+    if (!r) return -1;
     int64_t m = 0;
     for (int64_t i = 0; i < n; ++i) {
         if (!t[i].keep) continue;
@@ -555,8 +550,23 @@ static int detect_impl(const void* vol, int32_t dtype, const int32_t dims[3], in
     }
     for (int64_t i = 0; i < u && i < capacity; ++i) out[i] = r[i];
     *n_found = (int32_t)u;
-    free(r); free(t);
+    free(r);
     return 0;
+}
+
+static int detect_impl(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,
+                       int32_t spacing, const int32_t* seeds, int64_t n_seeds, const int32_t scales[2],
+                       int32_t method, int32_t max_iter, double h_min, double y_min, int32_t rank_by,
+                       kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats) {
+    if (!seeds_ok(dims, seeds, n_seeds)) return -1;
+    int64_t n = seeds ? n_seeds * (method == KSO_MEANSHIFT ? scales[1] - scales[0] + 1 : 1)
+                      : kso_num_trajectories(dims, spacing, scales, method);
+    kso_traj* t = (kso_traj*)malloc(sizeof(kso_traj) * (size_t)(n > 0 ? n : 1));
+    run_impl(vol, dtype, dims, bins, window, spacing, seeds, n_seeds, scales, method, max_iter, h_min, y_min, NULL, 0,
+             t, stats);
+    const int rc = kso_rank(t, n, rank_by, out, capacity, n_found);
+    free(t);
+    return rc;
 }
 
 int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bins, const int32_t* window,

@@ -151,6 +151,10 @@ int kso_detect(const void* vol, int32_t dtype, const int32_t dims[3], int32_t bi
                int32_t spacing, const int32_t scales[2], int32_t method, int32_t max_iter, double h_min, double y_min,
                int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found, kso_stats* stats);
 
+/* Step 8 alone, on the records of kso_run (any subset order; shards of one run
+ * concatenated give the same result as kso_detect on the whole run). */
+int kso_rank(const kso_traj* t, int64_t n, int32_t rank_by, kso_region* out, int32_t capacity, int32_t* n_found);
+
 #ifdef __cplusplus
 }
 #endif

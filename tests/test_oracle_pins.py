@@ -455,6 +455,16 @@ def test_seed_sharded_runs_merge_to_the_single_run(method):
     want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)
     assert n_want == len(ranked)
     assert ranked == [(int(r["x"]), int(r["y"]), int(r["z"]), int(r["scale"]), int(r["seed"])) for r in want]
+    # the oracle's own ranking step on the shards, concatenated in reverse order
+    got, n_got = oracle.rank(np.concatenate([p[0] for p in parts[::-1]]))
+    assert n_got == n_want and np.array_equal(got, want)
+    for cap in (0, 1, n_want // 2):
+        got, n_got = oracle.rank(merged[::-1], capacity=cap)
+        assert n_got == n_want and np.array_equal(got, want[:cap])
+    got_w, _ = oracle.rank(merged, rank_by=oracle.RANK_PDF_CHANGE)
+    want_w, _, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter,
+                                 rank_by=oracle.RANK_PDF_CHANGE)
+    assert np.array_equal(got_w, want_w)
 
 
 # ---------------------------------------------------------- behaviour (Sec. 2.1)
@@ -803,3 +813,82 @@ def test_abmsod_first_step_on_a_radial_two_bin_volume_by_brute_force():
         assert abs(t["entropy"] + (p * np.log(p)).sum()) < 1e-12
         assert abs(t["rho"] - np.sqrt(p / B).sum()) < 1e-12
         assert np.allclose(_sym(t["h"]), h, atol=1e-9, rtol=0)
+
+
+def _abm_one_iteration(bv, B, x0, r, r_cap):
+    """One ABMSOD iteration written out over every voxel of the volume (Sec. 2.3):
+    at x0 with H0 = (r + 1/2)^2/5 I, the window {v : (v-x)^T H^-1 (v-x) <= 5}; its
+    Gaussian-profile pmf p_b (Alg. 2: exp(-d/2) per voxel); the Eq. 5 weights
+    w_b = sqrt(q_b / p_b) for the uniform target q_b = 1/B; the new centre as
+    the exp(-d/2) w-weighted mean of the window's voxel positions (the
+    derivative of the Gaussian profile is proportional to the profile); then
+    at the new centre, with the same H, the pmf again, the Bhattacharyya
+    coefficient sum_b sqrt(p_b q_b), the entropy, and the Eq. 7 bandwidth: the
+    w-weighted second moment of the window's voxels about the new centre,
+    scaled down if its half-extent sqrt(5 H_aa) passes r_cap + 1/2."""
+    Z, Y, X = bv.shape
+    zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    pos = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1).astype(np.float64)
+    bins = bv.ravel().astype(np.int64)
+    H = np.eye(3) * (r + 0.5) ** 2 / 5.0
+
+    def window(x, Hm):
+        u = pos - x
+        d = np.einsum("ia,ab,ib->i", u, np.linalg.inv(Hm), u)
+        m = (d <= 5.0) & (bins < B)
+        return m, d[m], u[m]
+
+    m, d, _ = window(np.asarray(x0, np.float64), H)
+    g = np.exp(-d / 2.0)
+    p = np.bincount(bins[m], g, B) / g.sum()
+    w = np.where(p > 0, np.sqrt((1.0 / B) / np.where(p > 0, p, 1.0)), 0.0)
+    gw = g * w[bins[m]]
+    xn = (gw[:, None] * pos[m]).sum(0) / gw.sum()
+    xn = np.clip(xn, 0, [X - 1, Y - 1, Z - 1])
+    m2, d2, u2 = window(xn, H)
+    g2 = np.exp(-d2 / 2.0)
+    p2 = np.bincount(bins[m2], g2, B) / g2.sum()
+    nz = p2 > 0
+    rho = np.sqrt(p2[nz] / B).sum()
+    ent = -(p2[nz] * np.log(p2[nz])).sum()
+    w2 = np.where(nz, np.sqrt((1.0 / B) / np.where(nz, p2, 1.0)), 0.0)[bins[m2]]
+    Hn = (w2[:, None, None] * u2[:, :, None] * u2[:, None, :]).sum(0) / w2.sum()
+    top = 5.0 * Hn.diagonal().max()
+    if top > (r_cap + 0.5) ** 2:
+        Hn = Hn * (r_cap + 0.5) ** 2 / top
+    return xn, Hn, rho, ent
+
+
+@pytest.mark.parametrize("case", ["half_space", "texture", "gradient_window_level"])
+def test_abmsod_off_centre_first_iteration_by_brute_force(case):
+    """One ABMSOD iteration from a start whose window is not symmetric about it
+    (the centre moves): the oracle equals the brute force above.  The two-bin
+    half-space places the start 3 voxels from the plane, so the Eq. 5 weights of
+    the two sides differ and pull the centre across; the texture and gradient
+    cases have uneven pmfs over many bins."""
+    rng = np.random.default_rng(77)
+    window = None
+    if case == "half_space":
+        v = np.zeros((22, 24, 26), np.uint8)
+        v[:, :, 13:] = 255
+        B, starts, radii = 8, [(10, 11, 12), (15, 12, 10)], (5, 6)
+    elif case == "texture":
+        v = rng.integers(0, 256, (20, 23, 25)).astype(np.uint8)
+        v[:, :11, :] //= 4          # a darker half: an uneven pmf
+        B, starts, radii = 16, [(9, 8, 10), (12, 11, 10)], (4, 5)
+    else:
+        zz, yy, xx = np.meshgrid(np.arange(21), np.arange(22), np.arange(24), indexing="ij")
+        v = (40 * xx + 25 * yy + rng.integers(0, 300, xx.shape)).astype(np.uint16)
+        B, starts, radii, window = 12, [(12, 10, 9), (5, 8, 10)], (4, 6), (300, 1100)
+    bv = oracle.bin_volume(v, B, window=window)
+    for x0 in starts:
+        tr, _ = oracle.abmsod(v, B, 1, radii, 1, threshold=1e9, seeds=[x0], window=window)
+        for t in tr:
+            r = int(t["radius"])
+            xn, Hn, rho, ent = _abm_one_iteration(bv, B, x0, r, radii[1])
+            assert np.abs(xn - np.asarray(x0)).max() > 0.05, (case, x0, r)   # the centre moved
+            assert t["iters"] == 1
+            assert np.allclose(t["x"], xn, atol=1e-9, rtol=0), (case, x0, r, t["x"], xn)
+            assert np.allclose(_sym(t["h"]), Hn, atol=1e-9, rtol=0), (case, x0, r)
+            assert abs(t["rho"] - rho) < 1e-12, (case, x0, r)
+            assert abs(t["entropy"] - ent) < 1e-9, (case, x0, r)
