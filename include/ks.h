@@ -274,6 +274,14 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
                         int32_t kind, const int32_t range[2], int32_t n, const int32_t* xyz, const int32_t* scale,
                         void* out, void* stream);
 
+/* Test hook: the square roots of window counts that the mean-shift decisions
+ * take on the device (Sec. 2.3: the bin weights of Eq. 5 and the coefficient
+ * of Eq. 4 with the uniform target), computed by the search's own device code:
+ * sq[c] = sqrt(c) and rsq[c] = 1/sqrt(c) (rsq[0] = 0) for every count c in
+ * 0..n-1.  sq, rsq: host arrays of n doubles, owned by the caller.  KS_E_INVALID
+ * for n < 1, n > 2^24 or a null pointer.  Returns when both are written. */
+ks_status ks_count_roots(ks_context* ctx, int32_t n, double* sq, double* rsq, void* stream);
+
 
 /* Dense Kadir-Brady saliency map (the every-voxel search that the seed grid
  * replaces, Sec. 1 and Sec. 2.1): at every voxel of the device volume, the
@@ -364,7 +372,10 @@ typedef struct {
 /* Batched detection of n device-resident volumes of any sizes and methods in
  * one captured launch sequence: per-volume range scan and binning, one
  * persistent search over every trajectory of every volume, one ranking pass.
- * Each volume's result equals ks_detect_device on it alone. */
+ * Each volume's result equals ks_detect_device on it alone.  The work is queued
+ * on `stream`; a NULL stream (which cannot be captured) means the context's own
+ * stream, ordered after everything queued on the null stream before the call.
+ * Returns when the results are in `results`. */
 ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks_result* results, void* stream);
 
 /* ------------------------------------------------------------- measurement */
@@ -382,20 +393,26 @@ ks_status ks_roofline(int32_t device, int32_t kind, double* rate);
 
 typedef struct {
     int64_t submitted, admitted, completed, refused, queued_now, in_flight;
-    int64_t bytes_in_use, budget_bytes;
+    int64_t bytes_in_use, budget_bytes;  /* device bytes the slots hold for requests now; the budget */
     double p50_ms, p99_ms, mean_ms;      /* submit -> result ready, completed requests */
     double volumes_per_s;                /* completed / (last completion - first submit) */
+    int64_t bytes_peak;                  /* largest bytes_in_use since the server started */
 } ks_server_stats_t;
 
 /* A server owns max_slots contexts on `device`, each with its own stream, and a
- * budget of device memory for admitted requests (hbm_budget bytes).  Pending
- * requests are admitted oldest first while their footprint fits the budget,
+ * budget of device memory for requests (hbm_budget bytes): the device memory
+ * its slots hold for them (volume copies, bin volumes, trajectory and sort
+ * records, results) never exceeds it.  Pending requests are admitted oldest
+ * first while the busy slots' memory plus the batch's own fits the budget,
  * grouped into batches of about ten milliseconds of estimated device work, one
- * batch per free slot; a batch that arrives while others run is launched at
- * once on its own stream and its work overlaps theirs on the device. */
+ * batch per free slot; a slot's buffers grow to exactly what its batches need,
+ * and idle slots give theirs back when a new batch would not fit beside them.
+ * A batch that arrives while others run is launched at once on its own stream
+ * and its work overlaps theirs on the device.  Outside the budget, each slot
+ * holds the fixed decision tables (7.2 MB) from creation to destruction. */
 ks_status ks_server_create(int32_t device, size_t hbm_budget, int32_t max_slots, ks_server** out);
-/* Copies the host volume; returns a ticket.  KS_E_TOO_LARGE if the request can
- * never fit the budget. */
+/* Copies the host volume; returns a ticket.  KS_E_TOO_LARGE if the request
+ * alone would need more device memory than the budget. */
 ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket);
 /* KS_E_NOT_READY until the request is done; then writes its regions once. */
 ks_status ks_server_poll(ks_server* s, uint64_t ticket, ks_region* out, int32_t capacity, int32_t* n_found);

@@ -684,14 +684,22 @@ __device__ __forceinline__ int64_t window_total(const int* c) {
 // computed here rather than loaded: the device's double sqrt and division are
 // correctly rounded, as the host's are, so the values equal the host-built
 // tables bit for bit (the mean-shift traces compare the objective with ==).
+// sqrt(c) and 1/sqrt(c) of a count c >= 0 (1/sqrt(0) taken as 0): IEEE double
+// square root and division, both correctly rounded.
+__device__ __forceinline__ void count_roots(int c, double& sq, double& rs) {
+    const double sc = sqrt((double)c);
+    sq = sc;
+    rs = c > 0 ? 1.0 / sc : 0.0;
+}
+
 template <int M>
 __device__ EvalOut ms_moments(const VolDesc& v, const Tables& tb, int px, int py, int pz, int s, const BinAcc<M>& a) {
     double sq[M], tx[M], ty[M], tz[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) {
         const bool nz = a.c[t] > 0;
-        const double sc = sqrt((double)a.c[t]);
-        const double rs = nz ? 1.0 / sc : 0.0;
+        double sc, rs;
+        count_roots(a.c[t], sc, rs);
         sq[t] = nz ? sc : 0.0;
         tx[t] = nz ? (double)(a.f1[t] - a.c[t] * s) * rs : 0.0;
         ty[t] = nz ? (double)(a.f2[t] - a.c[t] * s) * rs : 0.0;
@@ -2082,6 +2090,21 @@ hipError_t launch_hook_quad(const VolDesc* vols, int kind, int lo, int hi, int n
                             const LdsQuad& lay, uint32_t* out, hipStream_t st) {
     hipLaunchKernelGGL(k_hook_quad, dim3(grid_for(n, 1, 4096)), dim3(256), lay.bytes, st, vols, kind, lo, hi, n, xyz,
                        rq, lay, out);
+    return hipGetLastError();
+}
+
+// The mean-shift decisions' roots of every count 0..n-1 (test hook).
+__global__ __launch_bounds__(256) void k_count_roots(int n, double* sq, double* rs) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        double a, b;
+        count_roots(c, a, b);
+        sq[c] = a;
+        rs[c] = b;
+    }
+}
+
+hipError_t launch_count_roots(int n, double* sq, double* rs, hipStream_t st) {
+    hipLaunchKernelGGL(k_count_roots, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, sq, rs);
     return hipGetLastError();
 }
 

@@ -72,6 +72,8 @@ int max_blocks_map(int K, int B);
 hipError_t launch_hook_quad(const VolDesc* vols, int kind, int lo, int hi, int n, const int* xyz, int rq,
                             const LdsQuad& lay, uint32_t* out, hipStream_t st);
 hipError_t launch_rank(const RankArgs& a, hipStream_t st);
+// sq[c] = sqrt(c), rs[c] = 1/sqrt(c) (rs[0] = 0) for c < n, by the mean-shift search's device code.
+hipError_t launch_count_roots(int n, double* sq, double* rs, hipStream_t st);
 int max_blocks_ms(int hist_words, int maxB);
 int max_blocks_quad(size_t lds_bytes, int maxB);
 

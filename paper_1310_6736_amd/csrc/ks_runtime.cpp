@@ -99,8 +99,7 @@ static ks_status hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? KS_E
 ks_status Buffer::ensure(size_t bytes, int* generation) {
     if (bytes <= cap) return KS_OK;
     // grow by at least 1.5x so that a slowly rising size reallocates rarely
-    size_t want = std::max(bytes, cap + cap / 2);
-    want = (want + 4095) & ~(size_t)4095;
+    const size_t want = granule(exact ? bytes : std::max(bytes, cap + cap / 2));
     if (ptr) hipFree(ptr);
     ptr = nullptr;
     cap = 0;
@@ -170,6 +169,7 @@ ks_status Context::init(int32_t dev) {
     for (int i = 0; i < kEvents; ++i) KS_HIP(hipEventCreate(&ev[i]));
     KS_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
     KS_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+    KS_HIP(hipEventCreateWithFlags(&order_ev, hipEventDisableTiming));
     return KS_OK;
 }
 
@@ -189,6 +189,7 @@ void Context::destroy() {
         if (ev[i]) hipEventDestroy(ev[i]);
     if (fork_ev) hipEventDestroy(fork_ev);
     if (join_ev) hipEventDestroy(join_ev);
+    if (order_ev) hipEventDestroy(order_ev);
 }
 
 // ------------------------------------------------------------ planning
@@ -238,6 +239,84 @@ int pick_quad_rq(int maxS, int maxB, int pref) {
     int rq = pref;
     while (rq > 0 && quad_layout(maxS, maxB, rq).bytes > 64 * 1024) --rq;
     return rq;
+}
+
+// Byte layout of the result allocation: regions, per-volume region counts, the
+// counter block.
+static void result_layout(size_t nvol, int64_t regs, size_t* nf_off, size_t* cnt_off, size_t* bytes) {
+    *nf_off = sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 0);
+    *cnt_off = (*nf_off + sizeof(int) * nvol + 63) & ~(size_t)63;
+    *bytes = *cnt_off + sizeof(Counters);
+}
+
+void arena_needs(const std::vector<VolIn>& in, size_t need[kArenaBuffers]) {
+    int64_t traj = 0, regs = 0;
+    size_t bins = 0, seed_ints = 0, segs = 1;
+    for (const VolIn& v : in) {
+        traj += num_trajectories(v);
+        regs += v.capacity;
+        bins += bins_bytes(v.dims);
+        if (v.seeds) seed_ints += 3 * (size_t)v.n_seeds;
+        // at most one task run per scale (mean-shift) or one (quadrant)
+        segs += v.method == KS_MEANSHIFT ? (size_t)(v.scales[1] - v.scales[0] + 1) : 1;
+    }
+    const unsigned long long n_pad = next_pow2((unsigned long long)std::max<int64_t>(traj, 2));
+    size_t nf_off, cnt_off, out_bytes;
+    result_layout(in.size(), regs, &nf_off, &cnt_off, &out_bytes);
+    need[0] = std::max<size_t>(sizeof(VolDesc) * in.size() + sizeof(TaskSeg) * segs + sizeof(int32_t) * seed_ints,
+                               256);
+    need[1] = std::max<size_t>(bins, 256);
+    need[2] = sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1);
+    need[3] = 2 * sizeof(SortRec) * n_pad;
+    need[4] = sizeof(int) * (n_pad / 1024 + 2);
+    need[5] = sizeof(int) * 3 * in.size();
+    need[6] = out_bytes;
+}
+
+Buffer& Context::arena(int i) {
+    switch (i) {
+        case 0: return d_vols;
+        case 1: return d_bins;
+        case 2: return d_rec;
+        case 3: return d_sr;
+        case 4: return d_bsum;
+        case 5: return d_volint;
+        default: return d_regions;
+    }
+}
+
+size_t Context::arena_held() {
+    size_t n = 0;
+    for (int i = 0; i < kArenaBuffers; ++i) n += arena(i).cap;
+    return n;
+}
+
+size_t Context::arena_after(const std::vector<VolIn>& in) {
+    size_t need[kArenaBuffers];
+    arena_needs(in, need);
+    size_t n = 0;
+    for (int i = 0; i < kArenaBuffers; ++i) {
+        const Buffer& b = arena(i);
+        n += need[i] <= b.cap ? b.cap : granule(b.exact ? need[i] : std::max(need[i], b.cap + b.cap / 2));
+    }
+    return n;
+}
+
+size_t Context::arena_fresh(const std::vector<VolIn>& in) {
+    size_t need[kArenaBuffers];
+    arena_needs(in, need);
+    size_t n = 0;
+    for (int i = 0; i < kArenaBuffers; ++i) n += granule(need[i]);
+    return n;
+}
+
+void Context::arena_release() {
+    for (int i = 0; i < kArenaBuffers; ++i) arena(i).release();
+    ++generation;  // captured graphs hold the old addresses
+}
+
+void Context::arena_exact(bool on) {
+    for (int i = 0; i < kArenaBuffers; ++i) arena(i).exact = on;
 }
 
 ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
@@ -359,25 +438,20 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
         nt += s.count;
         segs.push_back(s);
     }
-    // Device memory.
+    // Device memory: descriptors, task segments and seed lists in one allocation
+    // laid out as the host staging area, so that one copy uploads them; results
+    // in one allocation laid out as the host copy, so that one copy downloads
+    // them (regions, per-volume region counts, the counter block).
     ks_status st;
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)nvol;
     const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     const size_t stage_bytes = vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints;
-    // descriptors, task segments and seed lists in one allocation laid out as the
-    // host staging area, so that one copy uploads them
-    if ((st = d_vols.ensure(std::max<size_t>(stage_bytes, 256), &generation)) != KS_OK) return st;
-    if ((st = d_bins.ensure(std::max<size_t>(bins_total, 256), &generation)) != KS_OK) return st;
-    if ((st = d_rec.ensure(sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1), &generation)) != KS_OK) return st;
-    if ((st = d_sr.ensure(2 * sizeof(SortRec) * p.n_pad, &generation)) != KS_OK) return st;
-    if ((st = d_bsum.ensure(sizeof(int) * (p.n_pad / 1024 + 2), &generation)) != KS_OK) return st;
-    if ((st = d_volint.ensure(sizeof(int) * 3 * (size_t)nvol, &generation)) != KS_OK) return st;
-    // results in one allocation laid out as the host copy, so that one copy
-    // downloads them: regions, per-volume region counts, the counter block
-    p.out_nf_off = sizeof(ks_region) * (size_t)std::max<int64_t>(regs, 0);
-    p.out_cnt_off = (p.out_nf_off + sizeof(int) * (size_t)nvol + 63) & ~(size_t)63;
-    p.out_bytes = p.out_cnt_off + sizeof(Counters);
-    if ((st = d_regions.ensure(p.out_bytes, &generation)) != KS_OK) return st;
+    result_layout((size_t)nvol, regs, &p.out_nf_off, &p.out_cnt_off, &p.out_bytes);
+    size_t need[kArenaBuffers];
+    arena_needs(in, need);
+    if (need[0] < stage_bytes || need[1] < bins_total) return KS_E_INVALID;  // arena_needs disagrees with the plan
+    for (int i = 0; i < kArenaBuffers; ++i)
+        if ((st = arena(i).ensure(need[i], &generation)) != KS_OK) return st;
     p.cnt = reinterpret_cast<Counters*>(static_cast<char*>(d_regions.ptr) + p.out_cnt_off);
     int* volint = static_cast<int*>(d_volint.ptr);
     for (int i = 0; i < nvol; ++i) {
@@ -561,7 +635,12 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
                                       std::vector<std::vector<ks_region>>* out, std::vector<int>* nfound) {
     KS_HIP(hipSetDevice(device));
     if (!st) {
+        // The null stream cannot be captured: run on the context's own stream,
+        // ordered after the work already queued on the null stream (which may be
+        // writing the volumes).
         if (!batch_stream) KS_HIP(hipStreamCreateWithFlags(&batch_stream, hipStreamNonBlocking));
+        KS_HIP(hipEventRecord(order_ev, nullptr));
+        KS_HIP(hipStreamWaitEvent(batch_stream, order_ev, 0));
         st = batch_stream;
     }
     Plan p;
@@ -1138,6 +1217,22 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if (hipMemcpyAsync(out, ctx->d_hook_out.ptr, out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
         return KS_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
+    return KS_OK;
+}
+
+ks_status ks_count_roots(ks_context* ctx, int32_t n, double* sq, double* rsq, void* stream) {
+    if (!ctx || !sq || !rsq || n < 1 || n > (1 << 24)) return KS_E_INVALID;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
+    const size_t bytes = (size_t)n * sizeof(double);
+    ks_status s = ctx->d_hook_out.ensure(2 * bytes, &ctx->generation);
+    if (s != KS_OK) return s;
+    double* d = static_cast<double*>(ctx->d_hook_out.ptr);
+    if (launch_count_roots(n, d, d + n, st) != hipSuccess) return KS_E_DEVICE;
+    if (hipMemcpyAsync(sq, d, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(rsq, d + n, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return KS_E_DEVICE;
     return KS_OK;
 }
 

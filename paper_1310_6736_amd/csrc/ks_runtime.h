@@ -11,13 +11,17 @@
 
 namespace ks {
 
-// Grow-only device allocation.
+// Grow-only device allocation: by at least 1.5x, or to exactly the size asked
+// for (4 KiB granules) when `exact` is set.
 struct Buffer {
     void* ptr = nullptr;
     size_t cap = 0;
+    bool exact = false;
     ks_status ensure(size_t bytes, int* generation);
     void release();
 };
+
+inline size_t granule(size_t bytes) { return (bytes + 4095) & ~(size_t)4095; }
 
 struct PinnedBuffer {
     void* ptr = nullptr;
@@ -61,6 +65,14 @@ struct Plan {
     size_t seed_ints = 0;
 };
 
+// The per-call arena of a context: descriptors + task segments + seed lists,
+// bin volumes, trajectory records, sort records, block sums, per-volume ints,
+// results (in this order).
+constexpr int kArenaBuffers = 7;
+
+// Bytes that plan() asks of each arena buffer for `in`.
+void arena_needs(const std::vector<VolIn>& in, size_t need[kArenaBuffers]);
+
 struct GraphEntry {
     std::vector<int64_t> key;
     hipGraphExec_t exec = nullptr;
@@ -90,12 +102,20 @@ struct Context {
     hipStream_t aux = nullptr;
     hipStream_t batch_stream = nullptr;
     hipEvent_t ev[kEvents] = {};
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, order_ev = nullptr;
     std::vector<GraphEntry> graphs;
     ks_run_stats last{};
 
     ks_status init(int32_t dev);
     void destroy();
+    Buffer& arena(int i);
+    // Device bytes the arena holds now, after a plan(in) (buffers only grow), and
+    // for `in` alone (freshly allocated).
+    size_t arena_held();
+    size_t arena_after(const std::vector<VolIn>& in);
+    static size_t arena_fresh(const std::vector<VolIn>& in);
+    void arena_release();
+    void arena_exact(bool on);
     ks_status plan(const std::vector<VolIn>& in, Plan& p);
     ks_status upload(const Plan& p, hipStream_t st);
     ks_status enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed);

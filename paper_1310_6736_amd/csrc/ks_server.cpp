@@ -1,10 +1,10 @@
 // Continuous-batching detection server.
 //
 // A scheduler thread owns the GPU work.  Each tick it admits, oldest first, the
-// pending requests whose device footprint fits the remaining HBM budget, up to
-// about ten milliseconds of estimated device work, groups them into one batched
-// launch sequence on a free slot (own context and stream), and retires slots
-// whose completion event has fired.  Several slots are in flight at once, so the
+// pending requests whose device memory fits beside the busy slots' within the
+// HBM budget, up to about ten milliseconds of estimated device work, groups them
+// into one batched launch sequence on a free slot (own context and stream), and
+// retires slots whose completion event has fired.  Several slots are in flight at once, so the
 // next batch's upload and launch overlap the current one and its blocks fill
 // the device as the current launch's tail drains.  A
 // request's result does not depend on what it was batched with: every trajectory
@@ -35,7 +35,7 @@ double now_ms() {
 struct SrvReq {
     ks::VolIn in;
     std::vector<uint8_t> host;     // copy of the submitted volume
-    size_t footprint = 0;
+    size_t footprint = 0;          // device bytes it needs alone, at most
     double work = 0;               // estimated voxel visits
     double t_submit = 0, t_done = 0;
     int status = KS_E_NOT_READY;
@@ -64,8 +64,15 @@ struct Slot {
     std::vector<ks::VolIn> in;
     ks::Plan plan;
     bool busy = false;
-    size_t bytes = 0;
+    // device bytes held for requests: the context's per-call arena and the volumes
+    size_t held() { return ctx.arena_held() + raw.cap; }
+    void release() {
+        ctx.arena_release();
+        raw.release();
+    }
 };
+
+const int32_t kNoSeeds[3] = {0, 0, 0};  // an empty start list (not the grid)
 
 }  // namespace
 
@@ -84,7 +91,7 @@ struct ks_server {
     std::map<uint64_t, SrvReq> reqs;
     std::map<int64_t, Track> tracks;
     std::vector<Slot*> slots;
-    size_t in_use = 0;
+    size_t in_use = 0, peak = 0;   // device bytes the slots hold for requests
     int64_t submitted = 0, admitted = 0, completed = 0, refused = 0, in_flight = 0;
     double first_submit = -1, last_done = 0;
     std::vector<double> latencies;
@@ -93,19 +100,14 @@ struct ks_server {
 
     void run();
     bool tick();
+    void account();
     ks_status submit(const ks_request* req, int64_t track, int32_t max_seeds, uint64_t* ticket);
 };
 
-// Device bytes a request holds while admitted: its volume, bin volume, trajectory
-// and sort records.
-static size_t footprint(const ks::VolIn& v, int64_t ntraj) {
-    const size_t esz = v.dtype == KS_U8 ? 1 : 2;
-    const size_t raw = esz * (size_t)v.dims[0] * v.dims[1] * v.dims[2];
-    const size_t n = (size_t)ntraj;
-    size_t pad = 2;
-    while (pad < n) pad <<= 1;
-    return raw + ks::bins_bytes(v.dims) + n * (sizeof(ks::TrajRec) + 12) +
-           pad * (2 * sizeof(ks::SortRec) + sizeof(int)) + (size_t)v.capacity * sizeof(ks_region) + (1 << 16);
+// Device bytes a request holds while it runs alone on a slot: its volume copy
+// and the per-call arena of its plan.
+static size_t request_bytes(const ks::VolIn& v, size_t host_bytes) {
+    return ks::Context::arena_fresh({v}) + ks::granule((host_bytes + 255) & ~(size_t)255);
 }
 
 static double percentile(std::vector<double> v, double q) {
@@ -190,19 +192,24 @@ bool ks_server::tick() {
             in_flight -= 1;
             last_done = t;
         }
-        in_use -= sl->bytes;
         sl->busy = false;
         sl->tickets.clear();
         worked = true;
         done_cv.notify_all();
     }
-    // Admit pending requests into a free slot as one batch.
+    // Admit pending requests into a free slot as one batch, oldest first, while
+    // the busy slots' bytes plus the batch's own (its volumes and a freshly
+    // sized arena) fit the budget.
     Slot* free_slot = nullptr;
     for (Slot* sl : slots)
         if (!sl->busy) { free_slot = sl; break; }
     if (!free_slot) return worked;
+    size_t busy_bytes = 0;
+    for (Slot* sl : slots)
+        if (sl->busy) busy_bytes += sl->held();
     std::vector<uint64_t> take;
-    size_t bytes = 0;
+    std::vector<ks::VolIn> batch;
+    size_t raw_bytes = 0;
     {
         std::lock_guard<std::mutex> lk(mu);
         double work = 0;
@@ -213,35 +220,60 @@ bool ks_server::tick() {
                 ++it;
                 continue;
             }
-            if (in_use + bytes + r.footprint > budget) break;   // oldest first: no overtaking
             if (!take.empty() && work + r.work > kBatchWork) break;
+            // the start positions it will run from: its own list, or the track's
+            const std::vector<int32_t>* list = r.own_seeds ? &r.seeds : nullptr;
+            if (r.track >= 0 && !tracks[r.track].seeds.empty()) list = &tracks[r.track].seeds;
+            ks::VolIn v = r.in;
+            if (list) {
+                v.seeds = list->empty() ? kNoSeeds : list->data();
+                v.n_seeds = (int64_t)list->size() / 3;
+            }
+            batch.push_back(v);
+            const size_t rb = raw_bytes + ((r.host.size() + 255) & ~(size_t)255);
+            if (busy_bytes + ks::Context::arena_fresh(batch) + ks::granule(rb) > budget) {
+                batch.pop_back();
+                break;   // oldest first: no overtaking
+            }
+            raw_bytes = rb;
             work += r.work;
-            bytes += r.footprint;
-            bool listed = r.own_seeds;
             if (r.track >= 0) {
                 Track& tr = tracks[r.track];
                 tr.busy = true;
-                if (!tr.seeds.empty()) {
-                    r.seeds = tr.seeds;
-                    listed = true;
-                }
+                if (!tr.seeds.empty()) r.seeds = tr.seeds;
             }
-            if (listed) {
-                static const int32_t kNone[3] = {0, 0, 0};  // an empty list is not the grid
-                r.in.seeds = r.seeds.empty() ? kNone : r.seeds.data();
+            if (list) {
+                r.in.seeds = r.seeds.empty() ? kNoSeeds : r.seeds.data();
                 r.in.n_seeds = (int64_t)r.seeds.size() / 3;
             }
             take.push_back(*it);
             it = pending.erase(it);
         }
-        in_use += bytes;
         admitted += (int64_t)take.size();
         in_flight += (int64_t)take.size();
     }
     if (take.empty()) return worked;
     Slot* sl = free_slot;
+    // Room for the batch: its slot's buffers grow to exactly what it needs; while
+    // the total would pass the budget, idle slots give their buffers back
+    // (largest first), then this slot (it then allocates the batch's size only).
+    auto total_after = [&]() {
+        size_t t = 0;
+        for (Slot* o : slots)
+            t += o != sl ? o->held()
+                         : sl->ctx.arena_after(batch) + (raw_bytes <= sl->raw.cap ? sl->raw.cap : ks::granule(raw_bytes));
+        return t;
+    };
+    std::vector<Slot*> idle;
+    for (Slot* o : slots)
+        if (!o->busy && o != sl && o->held() > 0) idle.push_back(o);
+    std::sort(idle.begin(), idle.end(), [](Slot* a, Slot* b) { return a->held() > b->held(); });
+    for (Slot* o : idle) {
+        if (total_after() <= budget) break;
+        o->release();
+    }
+    if (total_after() > budget) sl->release();
     sl->busy = true;
-    sl->bytes = bytes;
     sl->tickets = take;
     sl->in.clear();
     size_t raw_total = 0;
@@ -270,6 +302,7 @@ bool ks_server::tick() {
         st = KS_E_DEVICE;
     if (st == KS_OK) st = sl->ctx.begin_detect(sl->in, sl->stream, sl->plan);
     if (st == KS_OK && hipEventRecord(sl->done, sl->stream) != hipSuccess) st = KS_E_DEVICE;
+    account();
     if (st != KS_OK) {
         std::lock_guard<std::mutex> lk(mu);
         for (uint64_t t : take) {
@@ -280,12 +313,20 @@ bool ks_server::tick() {
             in_flight -= 1;
             if (r.track >= 0) hand_over(tracks[r.track], r);
         }
-        in_use -= bytes;
         sl->busy = false;
         if (st == KS_E_DEVICE) fatal = st;
         done_cv.notify_all();
     }
     return true;
+}
+
+// Device bytes the slots hold for requests, and their high-water mark.
+void ks_server::account() {
+    size_t t = 0;
+    for (Slot* o : slots) t += o->held();
+    std::lock_guard<std::mutex> lk(mu);
+    in_use = t;
+    peak = std::max(peak, t);
 }
 
 void ks_server::run() {
@@ -297,6 +338,8 @@ void ks_server::run() {
         // blocks of the launch before it retire, so the device never runs a
         // partial grid once the other slots have drained
         st = sl->ctx.init(device);
+        sl->ctx.arena_exact(true);
+        sl->raw.exact = true;
         if (st == KS_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) st = KS_E_DEVICE;
         if (st == KS_OK && hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) st = KS_E_DEVICE;
         slots.push_back(sl);
@@ -377,7 +420,15 @@ ks_status ks_server::submit(const ks_request* req, int64_t track, int32_t max_se
                           : ks::num_trajectories(req->dims, req->seed_spacing, req->scales, KS_QUADRANT);
     if (track >= 0) n_start = std::max<int64_t>(n_start, max_seeds);
     r.in.capacity = (int32_t)std::min<int64_t>(std::max<int64_t>(n_start * per, 1), 1 << 20);
-    r.footprint = footprint(r.in, n_start * per);
+    const size_t esz = req->dtype == KS_U8 ? 1 : 2;
+    const size_t bytes = esz * (size_t)req->dims[0] * req->dims[1] * req->dims[2];
+    {
+        // the most it can need alone: n_start listed start positions
+        ks::VolIn u = r.in;
+        u.seeds = kNoSeeds;
+        u.n_seeds = n_start;
+        r.footprint = request_bytes(u, bytes);
+    }
     r.work = work_estimate(r.in, n_start);
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->stop) return KS_E_SHUTDOWN;
@@ -386,8 +437,6 @@ ks_status ks_server::submit(const ks_request* req, int64_t track, int32_t max_se
         s->refused += 1;
         return KS_E_TOO_LARGE;
     }
-    const size_t esz = req->dtype == KS_U8 ? 1 : 2;
-    const size_t bytes = esz * (size_t)req->dims[0] * req->dims[1] * req->dims[2];
     lk.unlock();
     r.host.assign(static_cast<const uint8_t*>(req->volume), static_cast<const uint8_t*>(req->volume) + bytes);
     lk.lock();
@@ -454,6 +503,7 @@ ks_status ks_server_stats(ks_server* s, ks_server_stats_t* out) {
     out->in_flight = s->in_flight;
     out->bytes_in_use = (int64_t)s->in_use;
     out->budget_bytes = (int64_t)s->budget;
+    out->bytes_peak = (int64_t)s->peak;
     out->p50_ms = percentile(s->latencies, 0.50);
     out->p99_ms = percentile(s->latencies, 0.99);
     double sum = 0;

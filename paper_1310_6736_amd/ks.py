@@ -28,7 +28,7 @@ EXPORTS = [
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
     "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap", "ks_context_autotune",
-    "ks_context_set_ms_group",
+    "ks_context_set_ms_group", "ks_count_roots",
 ]
 
 
@@ -96,7 +96,7 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("refused", C.c_int64),
                 ("queued_now", C.c_int64), ("in_flight", C.c_int64), ("bytes_in_use", C.c_int64),
                 ("budget_bytes", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
-                ("mean_ms", C.c_double), ("volumes_per_s", C.c_double)]
+                ("mean_ms", C.c_double), ("volumes_per_s", C.c_double), ("bytes_peak", C.c_int64)]
 
 
 _lib = None
@@ -142,6 +142,7 @@ def lib():
     L.ks_server_reset_stats.argtypes = [vp]
     L.ks_server_destroy.argtypes = [vp]
     L.ks_roofline.argtypes = [i32, i32, C.POINTER(C.c_double)]
+    L.ks_count_roots.argtypes = [vp, i32, vp, vp, vp]
     for name in EXPORTS:
         if name != "ks_status_str":
             getattr(L, name).restype = i32
@@ -405,6 +406,15 @@ def ks_histograms(ctx: Context, volume, bins, kind, xyz, scale=None, scale_range
     return out
 
 
+def ks_count_roots(ctx: Context, n: int, stream=None):
+    """(sqrt(c), 1/sqrt(c)) for c in 0..n-1 as the mean-shift search computes them."""
+    sq = np.empty(int(n), np.float64)
+    rs = np.empty(int(n), np.float64)
+    _check(lib().ks_count_roots(ctx.handle, int(n), C.c_void_p(sq.ctypes.data), C.c_void_p(rs.ctypes.data),
+                                _stream_ptr(stream)), "ks_count_roots")
+    return sq, rs
+
+
 def make_request(volume, bins, seed_spacing, scales, method, max_iter, host=False, opts=None,
                  seeds=None) -> Request:
     """One batch or server request; seeds = [(x, y, z), ...] replaces the grid (the
@@ -443,8 +453,7 @@ def ks_detect_batch(ctx: Context, requests, capacity=1024, stream=None):
     for i in range(n):
         res[i].regions = C.cast(bufs[i][1], C.POINTER(Region))
         res[i].capacity = int(capacity)
-    _check(lib().ks_detect_batch(ctx.handle, n, reqs, res, _stream_ptr(stream) if stream is not None else None),
-           "ks_detect_batch")
+    _check(lib().ks_detect_batch(ctx.handle, n, reqs, res, _stream_ptr(stream)), "ks_detect_batch")
     return [(_regions(bufs[i][0], res[i].n_found, capacity), res[i].n_found) for i in range(n)]
 
 

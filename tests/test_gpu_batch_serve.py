@@ -62,6 +62,27 @@ def same_regions(a, b):
     return a[1] == b[1] and np.array_equal(a[0], b[0])
 
 
+RTOL = 1e-5
+
+
+def close32(got, want):
+    """float32 reported values within 1e-5 relative of the oracle's doubles, and
+    exactly zero where those are zero."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    ok = np.abs(got - want) <= RTOL * np.abs(want)
+    return bool(np.all(np.where(want == 0.0, got == 0.0, ok)))
+
+
+def assert_matches_oracle(got, n_got, want, n_want, label):
+    assert n_got == n_want, (label, n_got, n_want)
+    assert len(got) == len(want), label
+    for f in ("x", "y", "z", "scale", "seed"):
+        assert np.array_equal(got[f], want[f]), (label, f)
+    for f in ("saliency", "entropy", "pdf_change"):
+        assert close32(got[f], want[f]), (label, f)
+
+
 def test_batch_equals_alone_and_oracle(torch_dev, ctx):
     ws = small_mix()
     note(f"batch of {len(ws)} small volumes")
@@ -73,9 +94,7 @@ def test_batch_equals_alone_and_oracle(torch_dev, ctx):
         alone = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
         assert same_regions(batch[i], alone), i
         want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
-        assert batch[i][1] == n_want, i
-        for f in ("x", "y", "z", "scale", "seed"):
-            assert np.array_equal(batch[i][0][f], want[f]), (i, f)
+        assert_matches_oracle(batch[i][0], batch[i][1], want, n_want, i)
 
 
 def test_batch_graph_replays_are_stable(torch_dev, ctx):
@@ -115,9 +134,29 @@ def test_batch_of_64_uneven_volumes(torch_dev, ctx):
         w = ws[i]
         note(f"oracle on batch volume {i} ({w.name})")
         want, n_want, _ = oracle.detect(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=256)
-        assert batch[i][1] == n_want, i
-        for f in ("x", "y", "z", "scale", "seed"):
-            assert np.array_equal(batch[i][0][f], want[f]), (i, f)
+        assert_matches_oracle(batch[i][0], batch[i][1], want, n_want, i)
+
+
+def test_batch_without_stream_waits_for_the_volume_writes(torch_dev, ctx):
+    """A batch called without a stream runs on the context's own stream, after
+    the work queued on the null stream before the call: here a chain of matrix
+    products and then the copy that writes the volume."""
+    w = small_mix()[3]
+    note("batch without a stream after a device write of its volume")
+    src = torch_dev.from_numpy(w.volume).to("cuda:0")
+    alone = ks.ks_detect_device(ctx, src, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=4096)
+    torch_dev.cuda.synchronize()
+    for rep in range(2):
+        t = torch_dev.zeros_like(src)
+        a = torch_dev.ones((2048, 2048), dtype=torch_dev.float32, device="cuda:0")
+        torch_dev.cuda.synchronize()
+        for _ in range(6):   # several milliseconds of queued work before the write
+            a = (a @ a) * (1.0 / 2048.0)
+        t.copy_(src)
+        got = ks.ks_detect_batch(ctx, [ks.make_request(t, w.bins, w.spacing, w.scales, w.method, w.max_iter)],
+                                 capacity=4096)[0]
+        assert same_regions(got, alone), rep
+    torch_dev.cuda.synchronize()
 
 
 def test_server_results_equal_alone(torch_dev, ctx):
@@ -174,6 +213,36 @@ def test_server_small_budget_queues_and_refuses(torch_dev, ctx):
         assert srv.stats()["refused"] == 1
     finally:
         srv.close()
+
+
+def test_server_budget_bounds_the_device_memory_of_its_slots(torch_dev, ctx):
+    """A large request (the PET-like volume, mean-shift: about 15 MB of device
+    memory alone), then many small ones that run on the other slots while it
+    does, then the large one again: the bytes the slots hold never exceed the
+    budget (idle slots give back what a new batch would not fit beside), and
+    every result equals the volume run alone."""
+    big = synth.pet_shell(ks.KS_MEANSHIFT)
+    ws = [big] + small_mix() * 3 + [big]
+    budget = 24 << 20
+    note("server: device memory of the slots within the budget")
+    srv = ks.Server(0, hbm_budget=budget, max_slots=4)
+    try:
+        tickets = [(w, srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter)) for w in ws]
+        srv.drain()
+        st = srv.stats()
+        got = [(w, srv.poll(t, capacity=100000)) for w, t in tickets]
+    finally:
+        srv.close()
+    assert st["refused"] == 0 and st["completed"] == len(ws)
+    assert 0 < st["bytes_peak"] <= budget, st
+    assert st["bytes_in_use"] <= budget, st
+    alone = {}
+    for w, res in got:
+        if w.name not in alone:
+            v = torch_dev.from_numpy(w.volume).to("cuda:0")
+            alone[w.name] = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter,
+                                                capacity=100000)
+        assert same_regions(res, alone[w.name]), w.name
 
 
 def moving_frames(n, seed, shape=(36, 40, 44)):

@@ -295,16 +295,55 @@ def test_traces_meanshift_update_settings(torch_dev, ctx, update):
     compare_traces(got[ids], want, f"{w.name} update={update}")
 
 
-def test_traces_mr_blobs_sampled(torch_dev, ctx):
+def mr_oracle_run():
+    """The oracle's run of every MR-like trajectory, computed by the host pool
+    that started at collection."""
+    import oracle_pool
+
+    if not oracle_pool.started():
+        pytest.skip("the oracle pool did not start (no GPU device node at collection)")
+    arr, st, wall = oracle_pool.result()
+    note(f"oracle pool: {len(arr)} trajectories in {wall:.1f} s on {oracle_pool.workers()} processes")
+    return arr, st
+
+
+def test_traces_mr_blobs_full(torch_dev, ctx):
+    """Every one of the 430,080 mean-shift trajectories of the MR-like volume (256 x
+    256 x 160 int16, 64 bins, spacing 8, scales 4..24, 100 iterations) against the
+    oracle: positions, iterations, stop reasons, scales, kept flags, the double
+    objective and saliency bit-identical, float32 values within 1e-5."""
     w = synth.mr_blobs()
-    note(f"traces {w.name} (full GPU run, sampled oracle)")
+    note(f"traces {w.name} (full GPU run, full oracle run)")
     got = ks.ks_seed_traces(ctx, dev(torch_dev, w.volume), w.bins, w.spacing, w.scales, w.method, w.max_iter)
-    S = w.scales[1] - w.scales[0] + 1
-    n_seeds = len(got) // S
-    seeds = np.arange(0, n_seeds, 97)
-    ids = (seeds[:, None] * S + np.arange(S)[None, :]).ravel()
-    want, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, ids=ids)
-    compare_traces(got[ids], want, w.name)
+    want, _ = mr_oracle_run()
+    compare_traces(got, want, w.name)
+
+
+def test_detect_mr_blobs_full_matches_oracle(torch_dev, ctx):
+    """The ranked detection of the MR-like volume at full size (343,194 regions from
+    430,080 trajectories: the compaction, the 524,288-record sort and the dedup at
+    their largest tested size) against the oracle's ranking of its own full run:
+    positions, scales and seeds bit-identical in rank order, float32 saliency,
+    entropy and pdf change within 1e-5 with exact zeros; then the top 1,000 alone,
+    the work counters against the oracle's, and the same volume through a batch
+    request and the captured graph."""
+    w = synth.mr_blobs()
+    note(f"detect {w.name} full")
+    t = dev(torch_dev, w.volume)
+    n_traj = oracle.num_trajectories(w.dims, w.spacing, w.scales, w.method)
+    got, n = ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=n_traj)
+    st = ks.ks_last_stats(ctx)
+    traj, ost = mr_oracle_run()
+    want, n_want = oracle.rank(traj, capacity=n_traj)
+    compare_regions(got, n, want, n_want, w.name)
+    # the work counters count what the oracle counts
+    assert st["evals"] == ost["evals"] and st["window_evals"] == ost["window_evals"]
+    assert st["voxel_visits"] + st["final_visits"] == ost["voxel_visits"]
+    top, n2 = ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=1000)
+    assert n2 == n_want and np.array_equal(top, got[:1000])
+    (bg, bn), = ks.ks_detect_batch(ctx, [ks.make_request(t, w.bins, w.spacing, w.scales, w.method, w.max_iter)],
+                                   capacity=n_traj)
+    assert bn == n and np.array_equal(bg, got)
 
 
 EDGE_CASES = [
@@ -833,3 +872,24 @@ def test_meanshift_scale_groups_give_the_same_traces(torch_dev, ctx, group):
         ks.ks_context_set_ms_group(ctx, 0)
     with pytest.raises(ks.KsError):
         ks.ks_context_set_ms_group(ctx, 9)
+
+
+# ------------------------------------------------------ device square roots
+
+def test_device_count_roots_equal_host_for_every_window_count(torch_dev, ctx):
+    """The mean-shift decisions take sqrt(c) and 1/sqrt(c) of window counts on the
+    device (Sec. 2.3: the bin weights of Eq. 5 and the coefficient).  Both
+    operations are correctly rounded in IEEE double, so for every count a window
+    can hold (up to the cube of half-width 33, the largest count a table covers)
+    they must equal the host's values bit for bit."""
+    n = 67 ** 3 + 2
+    note(f"device square roots of 0..{n - 1}")
+    sq, rs = ks.ks_count_roots(ctx, n)
+    c = np.arange(n, dtype=np.float64)
+    want_sq = np.sqrt(c)
+    with np.errstate(divide="ignore"):
+        want_rs = np.where(c > 0, 1.0 / want_sq, 0.0)
+    assert np.array_equal(sq.view(np.uint64), want_sq.view(np.uint64))
+    assert np.array_equal(rs.view(np.uint64), want_rs.view(np.uint64))
+    with pytest.raises(ks.KsError):
+        ks.ks_count_roots(ctx, 0)
