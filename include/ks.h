@@ -213,9 +213,10 @@ ks_status ks_context_set_ms_group(ks_context* ctx, int32_t scales_per_task);
  * not depend on it. */
 ks_status ks_context_set_overlap(ks_context* ctx, int32_t on);
 
-/* Counters and times of the last detect/batch call on this context.  With
- * profiling on, ks_detect_batch runs its launch sequence directly instead of
- * through a captured graph, so that the phases can be timed. */
+/* Counters and times of the last detect/batch call on this context.  Times are
+ * taken with profiling on: HIP events on the launch streams around the phases
+ * and each search (in ks_detect_batch, event-record nodes of its captured
+ * graph). */
 ks_status ks_last_stats(ks_context* ctx, ks_run_stats* out);
 
 /* Detection on a host volume (synchronous).  Uses a library-owned context on

@@ -498,18 +498,37 @@ ks_status Context::upload(const Plan& p, hipStream_t st) {
     return KS_OK;
 }
 
+// Records ev on st.  Inside a stream capture the record becomes an explicit
+// event-record node after the stream's current capture dependencies (an event
+// that hipEventRecord records during a capture cannot be timed after a replay
+// on this runtime, while event-record nodes can).
+static hipError_t mark(hipEvent_t ev, hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusActive) return hipEventRecord(ev, st);
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    if ((e = hipStreamGetCaptureInfo_v2(st, &cs, &id, &g, &deps, &nd)) != hipSuccess) return e;
+    hipGraphNode_t node;
+    if ((e = hipGraphAddEventRecordNode(&node, g, deps, nd, ev)) != hipSuccess) return e;
+    return hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies);
+}
+
 ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed) {
     VolDesc* dv = static_cast<VolDesc*>(d_vols.ptr);
     TaskSeg* ds = reinterpret_cast<TaskSeg*>(static_cast<char*>(d_vols.ptr) + sizeof(VolDesc) * (size_t)p.nvol);
     Counters* dc = p.cnt;
     TrajRec* rec = static_cast<TrajRec*>(d_rec.ptr);
-    if (timed) KS_HIP(hipEventRecord(ev[0], st));
+    if (timed) KS_HIP(mark(ev[0], st));
     PrepArgs pa;
     pa.vols = dv; pa.nvol = p.nvol; pa.cnt = dc; pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base;
     pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     KS_HIP(launch_prep(pa, st));
-    if (timed) KS_HIP(hipEventRecord(ev[1], st));
+    if (timed) KS_HIP(mark(ev[1], st));
     SearchArgs sq;
     sq.vols = dv; sq.segs = ds; sq.nseg = (int)p.segs_q.size(); sq.ntask = p.ntask_q; sq.tb = tables;
     sq.rec = rec; sq.cnt = dc;
@@ -526,9 +545,9 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
     if (p.ntask_q > 0) {
         const int per_cu = max_blocks_quad(p.lay.bytes, p.maxB_quad);
         const long long g = std::min<long long>(p.ntask_q, std::max<long long>(1, (long long)per_cu * num_cu * grid_pct / 100));
-        if (timed) KS_HIP(hipEventRecord(ev[6], st));
+        if (timed) KS_HIP(mark(ev[6], st));
         KS_HIP(launch_search_quad(sq, (int)g, p.rq, p.lay, p.maxB_quad, st));
-        if (timed) KS_HIP(hipEventRecord(ev[7], st));
+        if (timed) KS_HIP(mark(ev[7], st));
     }
     if (p.ntask_m > 0) {
         const int per_cu = max_blocks_ms(p.ms_hist_words, p.maxB_ms);
@@ -540,15 +559,15 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         tune.incr_pct = ms_incr_pct;
         tune.group = p.ms_group;
         tune.pad = 0;
-        if (timed) KS_HIP(hipEventRecord(ev[4], sm_st));
+        if (timed) KS_HIP(mark(ev[4], sm_st));
         KS_HIP(launch_search_ms(sm, (int)g, tune, p.ms_hist_words, p.maxB_ms, sm_st));
-        if (timed) KS_HIP(hipEventRecord(ev[5], sm_st));
+        if (timed) KS_HIP(mark(ev[5], sm_st));
     }
     if (fork) {
         KS_HIP(hipEventRecord(join_ev, aux));
         KS_HIP(hipStreamWaitEvent(st, join_ev, 0));
     }
-    if (timed) KS_HIP(hipEventRecord(ev[2], st));
+    if (timed) KS_HIP(mark(ev[2], st));
     if (with_rank) {
         RankArgs ra;
         ra.vols = dv; ra.nvol = p.nvol; ra.rec = rec; ra.sr = static_cast<SortRec*>(d_sr.ptr); ra.cnt = dc;
@@ -557,7 +576,7 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         ra.regions = static_cast<ks_region_dev*>(d_regions.ptr);
         KS_HIP(launch_rank(ra, st));
     }
-    if (timed) KS_HIP(hipEventRecord(ev[3], st));
+    if (timed) KS_HIP(mark(ev[3], st));
     return KS_OK;
 }
 
@@ -646,8 +665,12 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     Plan p;
     ks_status s = plan(in, p);
     if (s != KS_OK) return s;
+    // with profiling on, the graph also holds event-record nodes around the
+    // phases and the searches
+    const bool timed = profiling;
     std::vector<int64_t> key;
     key.push_back(generation);
+    key.push_back(timed ? 1 : 0);
     key.push_back(ms_rl_pref);
     key.push_back(ms_rl_small_pref);
     key.push_back(ms_s_small);
@@ -672,7 +695,7 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     if (!exec) {
         hipGraph_t graph = nullptr;
         KS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        ks_status cs = enqueue_search(p, st, true, false);
+        ks_status cs = enqueue_search(p, st, true, timed);
         if (cs == KS_OK) cs = download(p, st);
         hipError_t e = hipStreamEndCapture(st, &graph);
         if (cs != KS_OK) {
@@ -692,16 +715,9 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
         ge.exec = exec;
         graphs.push_back(ge);
     }
-    if (profiling) KS_HIP(hipEventRecord(ev[0], st));
     KS_HIP(hipGraphLaunch(exec, st));
-    if (profiling) KS_HIP(hipEventRecord(ev[3], st));
     KS_HIP(hipStreamSynchronize(st));
-    collect_stats(p, false);
-    if (profiling) {
-        float ms = 0;
-        hipEventElapsedTime(&ms, ev[0], ev[3]);
-        last.ms_total = ms;
-    }
+    collect_stats(p, timed);
     const char* h = static_cast<const char*>(h_out.ptr);
     const ks_region* regs = reinterpret_cast<const ks_region*>(h);
     const int* nf = reinterpret_cast<const int*>(h + p.out_nf_off);
@@ -1259,9 +1275,7 @@ ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks
     if (n == 0) return KS_OK;
     std::vector<std::vector<ks_region>> res;
     std::vector<int> nf;
-    // with profiling on, the direct launch sequence (per-phase and per-search events)
-    ks_status s = ctx->profiling ? ctx->detect_volumes(in, static_cast<hipStream_t>(stream), &res, &nf)
-                                 : ctx->detect_batch_graph(in, static_cast<hipStream_t>(stream), &res, &nf);
+    ks_status s = ctx->detect_batch_graph(in, static_cast<hipStream_t>(stream), &res, &nf);
     if (s != KS_OK) return s;
     for (int i = 0; i < n; ++i) {
         if (!res[(size_t)i].empty())
