@@ -319,7 +319,7 @@ void Context::arena_exact(bool on) {
     for (int i = 0; i < kArenaBuffers; ++i) arena(i).exact = on;
 }
 
-ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
+ks_status Context::plan(const std::vector<VolIn>& in, Plan& p, const FixedArena* fixed) {
     p = Plan();
     const int nvol = (int)in.size();
     p.nvol = nvol;
@@ -449,26 +449,44 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
     result_layout((size_t)nvol, regs, &p.out_nf_off, &p.out_cnt_off, &p.out_bytes);
     size_t need[kArenaBuffers];
     arena_needs(in, need);
-    if (need[0] < stage_bytes || need[1] < bins_total) return KS_E_INVALID;  // arena_needs disagrees with the plan
-    for (int i = 0; i < kArenaBuffers; ++i)
-        if ((st = arena(i).ensure(need[i], &generation)) != KS_OK) return st;
-    p.cnt = reinterpret_cast<Counters*>(static_cast<char*>(d_regions.ptr) + p.out_cnt_off);
-    int* volint = static_cast<int*>(d_volint.ptr);
+    if (need[kArVols] < stage_bytes || need[kArBins] < bins_total || need[kArOut] != p.out_bytes)
+        return KS_E_INVALID;  // arena_needs disagrees with the plan
+    if (fixed) {
+        // the caller's ranges: KS_E_TOO_LARGE if the plan does not fit them
+        size_t off = 0;
+        for (int i = 0; i < kArenaBuffers; ++i) {
+            p.dev[i] = fixed->dev + off;
+            off += (need[i] + 255) & ~(size_t)255;
+        }
+        if (off > fixed->dev_bytes || stage_bytes > fixed->stage_bytes || p.out_bytes > fixed->out_bytes)
+            return KS_E_TOO_LARGE;
+        p.stage = fixed->stage;
+        p.hout = fixed->out;
+    } else {
+        for (int i = 0; i < kArenaBuffers; ++i) {
+            if ((st = arena(i).ensure(need[i], &generation)) != KS_OK) return st;
+            p.dev[i] = static_cast<char*>(arena(i).ptr);
+        }
+        // host staging (descriptors, segments, seed lists) and the result copy
+        if ((st = h_stage.ensure(stage_bytes)) != KS_OK) return st;
+        if ((st = h_out.ensure(p.out_bytes)) != KS_OK) return st;
+        p.stage = static_cast<char*>(h_stage.ptr);
+        p.hout = static_cast<char*>(h_out.ptr);
+    }
+    p.cnt = reinterpret_cast<Counters*>(p.dev[kArOut] + p.out_cnt_off);
+    int* volint = reinterpret_cast<int*>(p.dev[kArVolInt]);
     for (int i = 0; i < nvol; ++i) {
-        p.vols[i].bins = static_cast<uint8_t*>(d_bins.ptr) + bins_off[i];
+        p.vols[i].bins = reinterpret_cast<uint8_t*>(p.dev[kArBins]) + bins_off[i];
         p.vols[i].bins_t = p.vols[i].bins + bins_x_bytes(in[i].dims);
         p.vols[i].minmax = volint + 2 * i;
-        p.vols[i].seeds = in[i].seeds ? reinterpret_cast<const int32_t*>(static_cast<char*>(d_vols.ptr) + vol_bytes +
-                                                                          seg_bytes) + p.seed_off[i]
+        p.vols[i].seeds = in[i].seeds ? reinterpret_cast<const int32_t*>(p.dev[kArVols] + vol_bytes + seg_bytes) +
+                                            p.seed_off[i]
                                       : nullptr;
     }
     p.seed_src.resize(nvol);
     for (int i = 0; i < nvol; ++i) p.seed_src[i] = in[i].seeds;
-    p.vol_nfound = reinterpret_cast<int*>(static_cast<char*>(d_regions.ptr) + p.out_nf_off);
+    p.vol_nfound = reinterpret_cast<int*>(p.dev[kArOut] + p.out_nf_off);
     p.vol_base = volint + 2 * nvol;
-    // Host staging: vols, segs, seed lists.
-    if ((st = h_stage.ensure(stage_bytes)) != KS_OK) return st;
-    if ((st = h_out.ensure(p.out_bytes)) != KS_OK) return st;
     p.rl = pick_ms_rl(std::max(p.maxB_ms, 2), ms_rl_pref);
     p.rl_small = pick_ms_rl(std::max(p.maxB_ms, 2), ms_rl_small_pref);
     p.rq = pick_quad_rq(std::max(p.maxS_quad, 1), std::max(p.maxB_quad, 2), quad_rq_pref);
@@ -480,7 +498,7 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p) {
 
 // Writes the plan's tables into the pinned staging buffer and queues their upload.
 ks_status Context::upload(const Plan& p, hipStream_t st) {
-    char* h = static_cast<char*>(h_stage.ptr);
+    char* h = p.stage;
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)p.nvol;
     const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     std::memcpy(h, p.vols.data(), vol_bytes);
@@ -493,7 +511,7 @@ ks_status Context::upload(const Plan& p, hipStream_t st) {
     for (int i = 0; i < p.nvol; ++i)
         if (p.seed_src[i])
             std::memcpy(hseed + p.seed_off[i], p.seed_src[i], sizeof(int32_t) * 3 * (size_t)p.vols[i].gx);
-    KS_HIP(hipMemcpyAsync(d_vols.ptr, h, vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints,
+    KS_HIP(hipMemcpyAsync(p.dev[kArVols], h, vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints,
                           hipMemcpyHostToDevice, st));
     return KS_OK;
 }
@@ -518,10 +536,10 @@ static hipError_t mark(hipEvent_t ev, hipStream_t st) {
 }
 
 ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed) {
-    VolDesc* dv = static_cast<VolDesc*>(d_vols.ptr);
-    TaskSeg* ds = reinterpret_cast<TaskSeg*>(static_cast<char*>(d_vols.ptr) + sizeof(VolDesc) * (size_t)p.nvol);
+    VolDesc* dv = reinterpret_cast<VolDesc*>(p.dev[kArVols]);
+    TaskSeg* ds = reinterpret_cast<TaskSeg*>(p.dev[kArVols] + sizeof(VolDesc) * (size_t)p.nvol);
     Counters* dc = p.cnt;
-    TrajRec* rec = static_cast<TrajRec*>(d_rec.ptr);
+    TrajRec* rec = reinterpret_cast<TrajRec*>(p.dev[kArRec]);
     if (timed) KS_HIP(mark(ev[0], st));
     PrepArgs pa;
     pa.vols = dv; pa.nvol = p.nvol; pa.cnt = dc; pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base;
@@ -570,10 +588,10 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
     if (timed) KS_HIP(mark(ev[2], st));
     if (with_rank) {
         RankArgs ra;
-        ra.vols = dv; ra.nvol = p.nvol; ra.rec = rec; ra.sr = static_cast<SortRec*>(d_sr.ptr); ra.cnt = dc;
-        ra.n_pad = p.n_pad; ra.max_traj = p.max_traj; ra.bsum = static_cast<int*>(d_bsum.ptr);
+        ra.vols = dv; ra.nvol = p.nvol; ra.rec = rec; ra.sr = reinterpret_cast<SortRec*>(p.dev[kArSort]); ra.cnt = dc;
+        ra.n_pad = p.n_pad; ra.max_traj = p.max_traj; ra.bsum = reinterpret_cast<int*>(p.dev[kArBsum]);
         ra.vol_base = p.vol_base; ra.vol_nfound = p.vol_nfound;
-        ra.regions = static_cast<ks_region_dev*>(d_regions.ptr);
+        ra.regions = reinterpret_cast<ks_region_dev*>(p.dev[kArOut]);
         KS_HIP(launch_rank(ra, st));
     }
     if (timed) KS_HIP(mark(ev[3], st));
@@ -581,12 +599,12 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
 }
 
 ks_status Context::download(const Plan& p, hipStream_t st) {
-    KS_HIP(hipMemcpyAsync(h_out.ptr, d_regions.ptr, p.out_bytes, hipMemcpyDeviceToHost, st));
+    KS_HIP(hipMemcpyAsync(p.hout, p.dev[kArOut], p.out_bytes, hipMemcpyDeviceToHost, st));
     return KS_OK;
 }
 
 void Context::collect_stats(const Plan& p, bool timed) {
-    const char* h = static_cast<const char*>(h_out.ptr);
+    const char* h = p.hout;
     const int* nf = reinterpret_cast<const int*>(h + p.out_nf_off);
     Counters c;
     std::memcpy(&c, h + p.out_cnt_off, sizeof(Counters));
@@ -624,7 +642,7 @@ ks_status Context::begin_detect(const std::vector<VolIn>& in, hipStream_t st, Pl
 void Context::end_detect(const std::vector<VolIn>& in, const Plan& p, std::vector<std::vector<ks_region>>* out,
                          std::vector<int>* nfound) {
     collect_stats(p, profiling);
-    const char* h = static_cast<const char*>(h_out.ptr);
+    const char* h = p.hout;
     const ks_region* regs = reinterpret_cast<const ks_region*>(h);
     const int* nf = reinterpret_cast<const int*>(h + p.out_nf_off);
     out->assign(in.size(), {});
@@ -718,7 +736,7 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     KS_HIP(hipGraphLaunch(exec, st));
     KS_HIP(hipStreamSynchronize(st));
     collect_stats(p, timed);
-    const char* h = static_cast<const char*>(h_out.ptr);
+    const char* h = p.hout;
     const ks_region* regs = reinterpret_cast<const ks_region*>(h);
     const int* nf = reinterpret_cast<const int*>(h + p.out_nf_off);
     out->assign(in.size(), {});
@@ -1001,7 +1019,7 @@ ks_status ks_seed_traces(ks_context* ctx, const void* d_volume, ks_dtype dtype, 
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     if ((s = ctx->enqueue_search(p, st, false, false)) != KS_OK) return s;
     std::vector<TrajRec> rec((size_t)p.total_traj);
-    if (!rec.empty() && hipMemcpyAsync(rec.data(), ctx->d_rec.ptr, sizeof(TrajRec) * rec.size(),
+    if (!rec.empty() && hipMemcpyAsync(rec.data(), p.dev[kArRec], sizeof(TrajRec) * rec.size(),
                                        hipMemcpyDeviceToHost, st) != hipSuccess)
         return KS_E_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
@@ -1035,7 +1053,7 @@ ks_status ks_bin_volume(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
+    pa.vols = reinterpret_cast<VolDesc*>(p.dev[kArVols]); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
@@ -1065,7 +1083,7 @@ ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype,
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
+    pa.vols = reinterpret_cast<VolDesc*>(p.dev[kArVols]); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[0], st));
@@ -1074,7 +1092,7 @@ ks_status ks_saliency_map(ks_context* ctx, const void* d_volume, ks_dtype dtype,
     const long long rows = (long long)dims[1] * dims[2];
     const int grid = (int)std::min<long long>(rows, (long long)max_blocks_map(K, bins) * ctx->num_cu);
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[1], st));
-    if (launch_saliency_map(static_cast<VolDesc*>(ctx->d_vols.ptr), ctx->tables, d_saliency, d_scale,
+    if (launch_saliency_map(reinterpret_cast<VolDesc*>(p.dev[kArVols]), ctx->tables, d_saliency, d_scale,
                             p.cnt, K, bins, grid, st) != hipSuccess)
         return KS_E_DEVICE;
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[2], st));
@@ -1124,7 +1142,7 @@ ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const
         return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
+    pa.vols = reinterpret_cast<VolDesc*>(p.dev[kArVols]); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (ctx->profiling) KS_HIP(hipEventRecord(ctx->ev[0], st));
@@ -1136,7 +1154,7 @@ ks_status ks_abmsod(ks_context* ctx, const void* d_volume, ks_dtype dtype, const
         a.replicas = abmsod_replicas(bins);
         a.threshold = threshold;
         const int grid = (int)std::min<int64_t>(total, (int64_t)abmsod_blocks_per_cu() * ctx->num_cu);
-        if (launch_abmsod(static_cast<VolDesc*>(ctx->d_vols.ptr), a, bins, grid,
+        if (launch_abmsod(reinterpret_cast<VolDesc*>(p.dev[kArVols]), a, bins, grid,
                           static_cast<ks_ellipsoid*>(ctx->d_abm.ptr), p.cnt,
                           st) != hipSuccess)
             return KS_E_DEVICE;
@@ -1196,7 +1214,7 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if ((s = ctx->plan({v}, p)) != KS_OK) return s;
     if ((s = ctx->upload(p, st)) != KS_OK) return s;
     PrepArgs pa;
-    pa.vols = static_cast<VolDesc*>(ctx->d_vols.ptr); pa.nvol = 1; pa.cnt = p.cnt;
+    pa.vols = reinterpret_cast<VolDesc*>(p.dev[kArVols]); pa.nvol = 1; pa.cnt = p.cnt;
     pa.vol_nfound = p.vol_nfound; pa.vol_base = p.vol_base; pa.max_voxels = p.max_voxels; pa.max_words = p.max_words;
     pa.max_tx = p.max_tx; pa.max_ty = p.max_ty; pa.max_z = p.max_z;
     if (launch_prep(pa, st) != hipSuccess) return KS_E_DEVICE;
@@ -1221,12 +1239,12 @@ ks_status ks_histograms(ks_context* ctx, const void* d_volume, ks_dtype dtype, c
     if (per_window) {
         const int rl = pick_ms_rl(bins, ctx->ms_rl_pref);
         const int hook_kind = kind == KS_HIST_CUBE ? 0 : kind == KS_HIST_MEANSHIFT ? 1 : kind == KS_HIST_MS_MOVE ? 2 : 3;
-        e = launch_hook_ms(static_cast<VolDesc*>(ctx->d_vols.ptr), hook_kind, n, dxyz, dsc, rl,
+        e = launch_hook_ms(reinterpret_cast<VolDesc*>(p.dev[kArVols]), hook_kind, n, dxyz, dsc, rl,
                            ((bins + 1) << rl) + 64, bins, ctx->d_hook_out.ptr, st);
     } else {
         const int rq = pick_quad_rq(K, bins, ctx->quad_rq_pref);
         const LdsQuad lay = quad_layout(K, bins, rq);
-        e = launch_hook_quad(static_cast<VolDesc*>(ctx->d_vols.ptr), kind, range[0], range[1], n, dxyz, rq, lay,
+        e = launch_hook_quad(reinterpret_cast<VolDesc*>(p.dev[kArVols]), kind, range[0], range[1], n, dxyz, rq, lay,
                              static_cast<uint32_t*>(ctx->d_hook_out.ptr), st);
     }
     if (e != hipSuccess) return KS_E_DEVICE;

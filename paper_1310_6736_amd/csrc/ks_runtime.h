@@ -44,7 +44,31 @@ struct VolIn {
     int64_t n_seeds = 0;
 };
 
+// The per-call arena of a context: descriptors + task segments + seed lists,
+// bin volumes, trajectory records, sort records, block sums, per-volume ints,
+// results (in this order).
+constexpr int kArenaBuffers = 7;
+enum { kArVols = 0, kArBins, kArRec, kArSort, kArBsum, kArVolInt, kArOut };
+
+// Bytes that plan() asks of each arena buffer for `in`.
+void arena_needs(const std::vector<VolIn>& in, size_t need[kArenaBuffers]);
+
+// Memory a plan places its arena and host copies in, instead of the context's
+// grow-only buffers: one device range (each arena buffer at a 256-byte aligned
+// offset) and two host ranges, all owned by the caller.
+struct FixedArena {
+    char* dev;
+    size_t dev_bytes;
+    char* stage;        // host staging of the upload
+    size_t stage_bytes;
+    char* out;          // host copy of the results
+    size_t out_bytes;
+};
+
 struct Plan {
+    char* dev[kArenaBuffers] = {};  // the arena buffers this plan uses
+    char* stage = nullptr;          // host staging of the upload
+    char* hout = nullptr;           // host copy of the results
     int nvol = 0;
     std::vector<VolDesc> vols;
     std::vector<TaskSeg> segs_q, segs_m;
@@ -64,14 +88,6 @@ struct Plan {
     std::vector<const int32_t*> seed_src;  // per volume: the caller's host list, or null
     size_t seed_ints = 0;
 };
-
-// The per-call arena of a context: descriptors + task segments + seed lists,
-// bin volumes, trajectory records, sort records, block sums, per-volume ints,
-// results (in this order).
-constexpr int kArenaBuffers = 7;
-
-// Bytes that plan() asks of each arena buffer for `in`.
-void arena_needs(const std::vector<VolIn>& in, size_t need[kArenaBuffers]);
 
 struct GraphEntry {
     std::vector<int64_t> key;
@@ -116,7 +132,7 @@ struct Context {
     static size_t arena_fresh(const std::vector<VolIn>& in);
     void arena_release();
     void arena_exact(bool on);
-    ks_status plan(const std::vector<VolIn>& in, Plan& p);
+    ks_status plan(const std::vector<VolIn>& in, Plan& p, const FixedArena* fixed = nullptr);
     ks_status upload(const Plan& p, hipStream_t st);
     ks_status enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed);
     ks_status download(const Plan& p, hipStream_t st);
