@@ -234,6 +234,27 @@ ks_status ks_detect_device(ks_context* ctx, const void* d_volume, ks_dtype dtype
                            int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
                            int32_t max_iter, ks_region* out, int32_t capacity, int32_t* n_found, void* stream);
 
+/* ks_detect_device for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * detection, kernels and results, with the work memory (descriptors, bin
+ * volumes, trajectory and sort records, results) in a static device array of
+ * 96 MiB that the library holds on each GPU it runs on until the process ends.
+ * The call allocates no device or pinned host memory (no hipMalloc,
+ * hipHostMalloc or hipFree); it copies through pageable host memory.  The
+ * caller passes the volume and the output as for ks_detect_device, and the
+ * context (created beforehand) supplies the decision tables, options and seed
+ * list.  KS_E_TOO_LARGE when the detection's work memory exceeds the array (it
+ * holds, for example, the MR-like 256 x 256 x 160 mean-shift detection of
+ * 430,080 trajectories with a capacity of a few thousand regions); otherwise
+ * the errors of ks_detect_device.  Every call on one GPU uses that GPU's array,
+ * whatever the context: calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller.  Returns when the results
+ * are in `out`. */
+ks_status ks_detect_device_noalloc(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                                   int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                                   int32_t max_iter, ks_region* out, int32_t capacity, int32_t* n_found,
+                                   void* stream);
+
 /* Per-trajectory final states of a search on a device volume (test and debug
  * hook).  out: host array of capacity traces in trajectory-id order; *n is the
  * number of trajectories. */

@@ -2108,6 +2108,30 @@ hipError_t launch_count_roots(int n, double* sq, double* rs, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Device memory of the allocation-free detection entry point: one array per
+// GPU, alive until the process ends.  Host code never uses the array's name as
+// an address: scratch_address() looks up this GPU's copy once and hands out
+// that pointer.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** ptr) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    // the caller has made `device` current
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+    *ptr = p;
+    return hipSuccess;
+}
+
 hipError_t launch_rank(const RankArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_compact, dim3(grid_for(a.max_traj, 256, 1024), a.nvol), dim3(256), 0, st, a.vols, a.rec,
                        a.sr, a.cnt);

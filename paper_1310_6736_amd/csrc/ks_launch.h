@@ -72,6 +72,10 @@ int max_blocks_map(int K, int B);
 hipError_t launch_hook_quad(const VolDesc* vols, int kind, int lo, int hi, int n, const int* xyz, int rq,
                             const LdsQuad& lay, uint32_t* out, hipStream_t st);
 hipError_t launch_rank(const RankArgs& a, hipStream_t st);
+// Size of the static device array of the allocation-free entry point, and the
+// address of `device`'s copy (looked up once per device, with it current).
+constexpr size_t kScratchBytes = (size_t)96 << 20;
+hipError_t scratch_address(int device, void** ptr);
 // sq[c] = sqrt(c), rs[c] = 1/sqrt(c) (rs[0] = 0) for c < n, by the mean-shift search's device code.
 hipError_t launch_count_roots(int n, double* sq, double* rs, hipStream_t st);
 int max_blocks_ms(int hist_words, int maxB);

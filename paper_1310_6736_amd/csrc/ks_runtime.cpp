@@ -170,6 +170,10 @@ ks_status Context::init(int32_t dev) {
     KS_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
     KS_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
     KS_HIP(hipEventCreateWithFlags(&order_ev, hipEventDisableTiming));
+    // the device's static array of the allocation-free entry point (null if the
+    // lookup fails: that entry point then reports KS_E_DEVICE)
+    void* sp = nullptr;
+    scratch = scratch_address(dev, &sp) == hipSuccess ? static_cast<char*>(sp) : nullptr;
     return KS_OK;
 }
 
@@ -968,6 +972,46 @@ ks_status ks_detect_device(ks_context* ctx, const void* d_volume, ks_dtype dtype
     if (s != KS_OK) return s;
     if (!res[0].empty()) std::memcpy(out, res[0].data(), sizeof(ks_region) * res[0].size());
     *n_found = nf[0];
+    return KS_OK;
+}
+
+ks_status ks_detect_device_noalloc(ks_context* ctx, const void* d_volume, ks_dtype dtype, const int32_t dims[3],
+                                   int32_t bins, int32_t seed_spacing, const int32_t scales[2], ks_method method,
+                                   int32_t max_iter, ks_region* out, int32_t capacity, int32_t* n_found,
+                                   void* stream) {
+    if (!ctx) return KS_E_INVALID;
+    ks_status s = check_request(d_volume, dtype, dims, bins, seed_spacing, scales, method, max_iter);
+    if (s != KS_OK) return s;
+    if ((s = check_out(out, capacity, n_found)) != KS_OK) return s;
+    VolIn v;
+    v.raw = d_volume; v.dtype = dtype; std::memcpy(v.dims, dims, sizeof(v.dims)); v.bins = bins;
+    v.spacing = seed_spacing; v.scales[0] = scales[0]; v.scales[1] = scales[1]; v.method = method;
+    v.max_iter = max_iter; v.capacity = capacity;
+    v.opt = ctx->opts;
+    if (!options_fit(v.opt, bins)) return KS_E_INVALID;
+    if ((s = apply_ctx_seeds(ctx, v)) != KS_OK) return s;
+    if (!ctx->scratch) return KS_E_DEVICE;
+    // the arena in the device's static array; the host copies in pageable memory
+    size_t need[kArenaBuffers];
+    arena_needs({v}, need);
+    size_t dev_bytes = 0;
+    for (int i = 0; i < kArenaBuffers; ++i) dev_bytes += (need[i] + 255) & ~(size_t)255;
+    if (dev_bytes > kScratchBytes) return KS_E_TOO_LARGE;
+    std::vector<char> stage(need[kArVols]), hout(need[kArOut]);
+    const FixedArena fx = {ctx->scratch, kScratchBytes, stage.data(), stage.size(), hout.data(), hout.size()};
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return KS_E_DEVICE;
+    Plan p;
+    if ((s = ctx->plan({v}, p, &fx)) != KS_OK) return s;
+    if ((s = ctx->upload(p, st)) != KS_OK) return s;
+    if ((s = ctx->enqueue_search(p, st, true, ctx->profiling)) != KS_OK) return s;
+    if ((s = ctx->download(p, st)) != KS_OK) return s;
+    if (hipStreamSynchronize(st) != hipSuccess) return KS_E_DEVICE;
+    ctx->collect_stats(p, ctx->profiling);
+    const int nf = *reinterpret_cast<const int*>(p.hout + p.out_nf_off);
+    const int w = std::min(nf, capacity);
+    if (w > 0) std::memcpy(out, p.hout, sizeof(ks_region) * (size_t)w);
+    *n_found = nf;
     return KS_OK;
 }
 

@@ -121,6 +121,7 @@ struct Context {
     hipEvent_t fork_ev = nullptr, join_ev = nullptr, order_ev = nullptr;
     std::vector<GraphEntry> graphs;
     ks_run_stats last{};
+    char* scratch = nullptr;   // this device's static array (allocation-free entry point), or null
 
     ks_status init(int32_t dev);
     void destroy();

@@ -28,7 +28,7 @@ EXPORTS = [
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
     "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap", "ks_context_autotune",
-    "ks_context_set_ms_group", "ks_count_roots",
+    "ks_context_set_ms_group", "ks_count_roots", "ks_detect_device_noalloc",
 ]
 
 
@@ -143,6 +143,7 @@ def lib():
     L.ks_server_destroy.argtypes = [vp]
     L.ks_roofline.argtypes = [i32, i32, C.POINTER(C.c_double)]
     L.ks_count_roots.argtypes = [vp, i32, vp, vp, vp]
+    L.ks_detect_device_noalloc.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, vp, i32, i32p, vp]
     for name in EXPORTS:
         if name != "ks_status_str":
             getattr(L, name).restype = i32
@@ -343,6 +344,19 @@ def ks_detect_device(ctx: Context, volume, bins, seed_spacing, scales, method, m
     nf = C.c_int32()
     _check(lib().ks_detect_device(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method, max_iter, out,
                                   int(capacity), C.byref(nf), _stream_ptr(stream)), "ks_detect_device")
+    return _regions(buf, nf.value, capacity), nf.value
+
+
+def ks_detect_device_noalloc(ctx: Context, volume, bins, seed_spacing, scales, method, max_iter, capacity=1024,
+                             stream=None):
+    """ks_detect_device with its work memory in the library's static device array
+    (no allocation by the call)."""
+    ptr, dt, dims = _volume_args(volume)
+    buf, out = _region_buffer(capacity)
+    nf = C.c_int32()
+    _check(lib().ks_detect_device_noalloc(ctx.handle, ptr, dt, dims, bins, seed_spacing, _i2(scales), method,
+                                          max_iter, out, int(capacity), C.byref(nf), _stream_ptr(stream)),
+           "ks_detect_device_noalloc")
     return _regions(buf, nf.value, capacity), nf.value
 
 
