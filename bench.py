@@ -94,50 +94,71 @@ def batch_section(ks, torch, ctx):
             "batched_ms": tb * 1e3, "plain_ms": tp * 1e3, "speedup": tp / tb, "identical_results": bool(same)}
 
 
-def serving_section(ks, torch, ctx, n_req):
-    """Poisson streams of the 50/30/20 mix at native sizes: the continuous-batching
-    server against a plain loop that serves requests one launch sequence at a
-    time in arrival order (both copy each host volume to the device).  Arrival
-    rates 0.5, 0.7, 0.9 and 1.2 x the plain loop's measured capacity, a saturated
-    stream (all requests at t = 0), and the saturated stream under a budget that
-    holds one large request at a time."""
+def _stream_volume(job):
+    """Volume of request i of the serving stream: generator type `kind` at its
+    native size, volume seed 2000 + i (type-1 requests alternate methods)."""
     from paper_1310_6736_amd import synth
 
-    pool = {0: [synth.typed_workload(0, 2000 + i, synth.TYPE_DIMS[0]) for i in range(4)],
-            1: [synth.typed_workload(1, 2100 + i, synth.TYPE_DIMS[1], method_parity=i) for i in range(4)],
-            2: [synth.typed_workload(2, 2200 + i, synth.TYPE_DIMS[2]) for i in range(2)]}
+    kind, seed, parity = job
+    return synth.typed_workload(kind, seed, synth.TYPE_DIMS[kind], method_parity=parity)
+
+
+def stream_workloads(n_req, workers):
+    """One volume per request of the serving stream (the type sequence is the
+    same at every arrival rate), generated on the host cores before the GPU is
+    initialised (the pool forks)."""
+    import multiprocessing as mp
+
+    from paper_1310_6736_amd import synth
+
+    jobs = [(k, seed, parity) for _, k, seed, parity in synth.arrival_trace(1.0, n=n_req)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_stream_volume, jobs, chunksize=1)
+
+
+def serving_section(ks, torch, ctx, ws):
+    """Poisson streams of the 50/30/20 mix at native sizes, one volume per
+    request: the continuous-batching server against a plain loop that serves
+    requests one launch sequence at a time in arrival order (both copy each host
+    volume to the device).  Arrival rates 0.5, 0.7, 0.9 and 1.2 x the plain
+    loop's measured capacity, a saturated stream (all requests at t = 0), and the
+    saturated stream under a budget that holds one large request at a time."""
+    from paper_1310_6736_amd import synth
+
+    n_req = len(ws)
     cap = 64
     tdt = {np.dtype(np.uint8): torch.uint8, np.dtype(np.int16): torch.int16,
            np.dtype(np.uint16): getattr(torch, "uint16", None)}
-    dev_buf = {k: [torch.empty(w.volume.shape, dtype=tdt[w.volume.dtype], device="cuda:0") for w in ws]
-               for k, ws in pool.items()}
+    dev_buf = {}
+    for w in ws:
+        key = (w.volume.shape, w.volume.dtype)
+        if key not in dev_buf:
+            dev_buf[key] = torch.empty(w.volume.shape, dtype=tdt[w.volume.dtype], device="cuda:0")
 
-    def plain_one(kind, j):
-        w = pool[kind][j]
-        d = dev_buf[kind][j]
+    def plain_one(i):
+        w = ws[i]
+        d = dev_buf[(w.volume.shape, w.volume.dtype)]
         d.copy_(torch.from_numpy(w.volume))
         return ks.ks_detect_device(ctx, d, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
 
     # plain capacity on the mix (saturated, arrival order)
-    trace = synth.arrival_trace(1.0, n=n_req)
-    order = [(k, (seed % len(pool[k]))) for _, k, seed, _ in trace]
-    for k, j in order[:8]:
-        plain_one(k, j)
+    for i in range(8):
+        plain_one(i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k, j in order:
-        plain_one(k, j)
+    for i in range(n_req):
+        plain_one(i)
     torch.cuda.synchronize()
     c_plain = n_req / (time.perf_counter() - t0)
 
     def run_plain(trace):
         lat = []
         start = time.perf_counter()
-        for t_arr, k, seed, _ in trace:
+        for t_arr, _, _, i in trace:
             now = time.perf_counter() - start
             if now < t_arr:
                 time.sleep(t_arr - now)
-            plain_one(k, seed % len(pool[k]))
+            plain_one(i)
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - start - t_arr) * 1e3)
         span = time.perf_counter() - start
@@ -148,22 +169,23 @@ def serving_section(ks, torch, ctx, n_req):
         srv.reset_stats()
         tickets = []
         start = time.perf_counter()
-        for t_arr, k, seed, _ in trace:
+        for t_arr, _, _, i in trace:
             now = time.perf_counter() - start
             if now < t_arr:
                 time.sleep(t_arr - now)
-            w = pool[k][seed % len(pool[k])]
+            w = ws[i]
             tickets.append(srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter))
         srv.drain()
         st = srv.stats()
         for t in tickets:
             srv.poll(t, capacity=cap)
         return {"volumes_per_s": st["volumes_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                "mean_ms": st["mean_ms"], "refused": int(st["refused"])}
+                "mean_ms": st["mean_ms"], "refused": int(st["refused"]), "peak_device_bytes": int(st["bytes_peak"])}
 
-    sat = [(0.0, k, seed, i) for _, k, seed, i in trace]
+    sat = [(0.0, k, seed, i) for _, k, seed, i in synth.arrival_trace(1.0, n=n_req)]
     out = {"workload": "%d requests, Poisson arrivals, 50/30/20 mix of the 64^3 spheres, 128x128x64 PET-like "
-                       "(quadrant/mean-shift alternating) and 256x256x160 MR-like generators" % n_req,
+                       "(quadrant/mean-shift alternating) and 256x256x160 MR-like generators, one volume per "
+                       "request (volume seed 2000 + i)" % n_req,
            "plain_capacity_volumes_per_s": c_plain}
     srv = ks.Server(0, hbm_budget=8 << 30, max_slots=4)
     run_server(srv, sat)  # warm-up: the slots' device buffers grow to the mix's sizes
@@ -530,8 +552,10 @@ def main():
         section_only(args.section)
         return
     cpu = None
+    workers = max(1, min(16, os.cpu_count() or 1))
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_sample_stride, args.cpu_single_stride, max(1, min(16, os.cpu_count() or 1)))
+        cpu = cpu_baseline(args.cpu_sample_stride, args.cpu_single_stride, workers)
+    stream_ws = None if (args.no_serve or args.main_only) else stream_workloads(args.serve_requests, workers)
     import torch
 
     from paper_1310_6736_amd import ks, synth
@@ -621,7 +645,7 @@ def main():
     if not (args.no_batch or args.main_only):
         line["batch"] = batch_section(ks, torch, ctx)
     if not (args.no_serve or args.main_only):
-        line["serving"] = serving_section(ks, torch, ctx, args.serve_requests)
+        line["serving"] = serving_section(ks, torch, ctx, stream_ws)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     ctx.close()
