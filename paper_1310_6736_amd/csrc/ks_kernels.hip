@@ -41,8 +41,20 @@ namespace ks {
 // Sweep pipelines: rows per group of loads, groups of loads in flight (measured:
 // the mean-shift sweeps, many of them a few rows long, run best with a short
 // pipeline; the quadrant brick sweep with narrow groups).
-constexpr int kMsUnroll = 4, kMsDepth = 1;
-constexpr int kQuadUnroll = 2, kQuadDepth = 2;
+#ifndef KS_MS_UNROLL
+#define KS_MS_UNROLL 4
+#endif
+#ifndef KS_MS_DEPTH
+#define KS_MS_DEPTH 1
+#endif
+#ifndef KS_QUAD_UNROLL
+#define KS_QUAD_UNROLL 2
+#endif
+#ifndef KS_QUAD_DEPTH
+#define KS_QUAD_DEPTH 2
+#endif
+constexpr int kMsUnroll = KS_MS_UNROLL, kMsDepth = KS_MS_DEPTH;
+constexpr int kQuadUnroll = KS_QUAD_UNROLL, kQuadDepth = KS_QUAD_DEPTH;
 // Load offset past the end of every bin volume (volumes stay below 2^31 bytes):
 // the buffer range check turns such a load into 0 without a memory access.
 constexpr uint32_t kPastEnd = 0x80000000u;
@@ -142,16 +154,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t layout_rsrc(const Layout& L) {
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
 }
 
+// floor(a / d) for 0 <= a <= 1024 and 1 <= d <= 1024 from the hardware float
+// reciprocal: (a + 1/2) / d is at least 1/(2d) away from an integer, far more
+// than the rounding of the reciprocal (1 ulp) and of the product (checked for
+// every such a and d with the reciprocal off by one ulp either way).  Box
+// extents, dword counts and lane indices of the sweeps are all in that range.
+__device__ __forceinline__ int small_div(int a, int d) {
+    return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 // A box of a layout swept by NT lanes: fast coordinates [fa, fb], nr rows
 // ra, ra + rstep, ... and ns slices sa, sa + sstep, ...  Each active lane owns one
 // dword column of one row of a ty x tz tile of rows; the tile then steps through
 // the box, first along the rows, then along the slices.  All fields except the
 // lane ones are uniform.
 struct Sweep {
-    int ny, nz, nd, ty, tz, nsteps;
+    int ny, nz, nd, ty, tz;
     uint32_t pr, ps;    // bytes between consecutive rows, slices of the box
     // lane part
-    bool on;
+    int lim_y, lim_z;   // rows and slices of the box from the lane's tile position on (lim_y -1: lane unused)
     int oy, oz, x0;     // row and slice index in the tile, fast coordinate of byte 0
     uint32_t voff;      // byte offset of the lane's dword at the first step
 };
@@ -166,74 +187,103 @@ __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int
     w.ps = L.slab * (uint32_t)sstep;
     const int da = fa >> 2;
     w.nd = (fb >> 2) - da + 1;
-    w.ty = min(w.ny, NT / w.nd);
-    w.tz = min(w.nz, NT / (w.ty * w.nd));
-    const int steps_y = (w.ny + w.ty - 1) / w.ty;
-    w.nsteps = steps_y * ((w.nz + w.tz - 1) / w.tz);
+    w.ty = min(w.ny, uniform(small_div(NT, w.nd)));
     const int per_z = w.ty * w.nd;
-    w.on = tid < w.tz * per_z;
-    w.oz = tid / per_z;
+    w.tz = min(w.nz, uniform(small_div(NT, per_z)));
+    w.oz = small_div(tid, per_z);
     const int rem = tid - w.oz * per_z;
-    w.oy = rem / w.nd;
+    w.oy = small_div(rem, w.nd);
     const int d = rem - w.oy * w.nd;
     w.x0 = (da + d) * 4;
+    const bool on = tid < w.tz * per_z;
+    w.lim_y = on ? w.ny - w.oy : -1;
+    w.lim_z = w.nz - w.oz;
     w.voff = (uint32_t)sa * L.slab + (uint32_t)ra * L.pitch + (uint32_t)w.oz * w.ps + (uint32_t)w.oy * w.pr +
              (uint32_t)w.x0;
     return w;
 }
 
-// Walks the sweep's steps in groups of U rows, keeping D groups of loads in
-// flight: the loads of group g + D are issued right after group g
-// is scattered.  Calls f(word, iy0, iz0) for every step in which the lane's row
-// lies inside the box (word: 4 voxels; iy0, iz0: the step's row and slice offset).
-// `used` counts the voxels each lane has scattered since the last flush, across
-// calls: before a group that would take it past `limit`, flush() runs
-// (uniformly) and the count restarts.  Loads for steps past the last one get an
-// offset beyond the descriptor's end: they return 0 without a memory access.
+// Walks the sweep's steps in groups of U steps, keeping D groups of loads in
+// flight: the loads of group g + D are issued right after group g is scattered.
+// Calls f(word, iy0, iz0, acc) for every step in which the lane's row lies
+// inside the box (word: 4 voxels; iy0, iz0: the step's row and slice offset;
+// acc = iy0 * ay + iz0 * az, a uniform 64-bit value the caller adds to its
+// per-lane terms).  The load offset and acc advance by additions; a group of
+// steps whose tiles lie wholly inside the box skips the per-lane row tests.  `used` counts
+// the voxels each lane has scattered since the last flush, across calls:
+// before a group that would take it past `limit`, flush() runs (uniformly) and
+// the count restarts.  Loads for steps past the last one get an offset beyond
+// the descriptor's end: they return 0 without a memory access.
 template <int U, int D, typename F, typename G>
-__device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, int& used, int limit, F&& f,
-                                          G&& flush) {
+__device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, uint64_t ay, uint64_t az, int& used,
+                                          int limit, F&& f, G&& flush) {
     const __amdgpu_buffer_rsrc_t rs = layout_rsrc(L);
     const uint32_t xp = (uint32_t)uniform((int)w.pr), slice = (uint32_t)uniform((int)w.ps);
-    const int nz = uniform(w.nz);
-    const int ny = uniform(w.ny), ty = uniform(w.ty), tz = uniform(w.tz), nsteps = uniform(w.nsteps);
-    const int lim_y = w.ny - w.oy, lim_z = w.nz - w.oz;
+    const int nz = uniform(w.nz), ny = uniform(w.ny), ty = uniform(w.ty), tz = uniform(w.tz);
+    const uint32_t dy = (uint32_t)ty * xp, dz = (uint32_t)tz * slice;
+    const uint64_t day = (uint64_t)(uint32_t)ty * ay, daz = (uint64_t)(uint32_t)tz * az;
+    const int lim_y = w.lim_y, lim_z = w.lim_z;
     constexpr int kGroupVoxels = U * 4;
+    // the step about to be loaded
     int iy0 = 0, iz0 = 0;
+    uint32_t off = 0, zoff = 0;
+    uint64_t acc = 0, zacc = 0;
     uint32_t buf[D][U];
     int by[D][U], bz[D][U];
+    uint64_t bacc[D][U];
+    bool full[D][U];
+    auto load = [&](int g, int u) {
+        by[g][u] = iy0;
+        bz[g][u] = iz0;
+        bacc[g][u] = acc;
+        full[g][u] = iy0 + ty <= ny && iz0 + tz <= nz;
+        buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? off : kPastEnd, 0);
+        iy0 += ty;
+        off += dy;
+        acc += day;
+        if (iy0 >= ny) {
+            iy0 = 0;
+            iz0 += tz;
+            zoff += dz;
+            zacc += daz;
+            off = zoff;
+            acc = zacc;
+        }
+    };
 #pragma unroll
     for (int g = 0; g < D; ++g) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            by[g][u] = iy0;
-            bz[g][u] = iz0;
-            buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? iz0 * slice + iy0 * xp : kPastEnd, 0);
-            iy0 += ty;
-            if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
-        }
+        for (int u = 0; u < U; ++u) load(g, u);
     }
-    for (int t = 0; t < nsteps; t += U * D) {
+    bool live = true;
+    while (live) {
 #pragma unroll
         for (int g = 0; g < D; ++g) {
-            if (t + g * U < nsteps) {
+            // a group that starts past the last step ends the sweep
+            live = live && bz[g][0] < nz;
+            if (live) {
                 if (used + kGroupVoxels > limit) {
                     used = 0;
                     flush();
                 }
+                bool gfull = true;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (w.on && by[g][u] < lim_y && bz[g][u] < lim_z) f(buf[g][u], by[g][u], bz[g][u]);
+                for (int u = 0; u < U; ++u) gfull = gfull && full[g][u];
+                if (gfull) {
+                    // every step's tile inside the box: only the unused lanes sit out
+                    if (lim_y >= 0) {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) f(buf[g][u], by[g][u], bz[g][u], bacc[g][u]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (by[g][u] < lim_y && bz[g][u] < lim_z) f(buf[g][u], by[g][u], bz[g][u], bacc[g][u]);
+                    }
                 }
                 used += kGroupVoxels;
-            }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                by[g][u] = iy0;
-                bz[g][u] = iz0;
-                buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? iz0 * slice + iy0 * xp : kPastEnd, 0);
-                iy0 += ty;
-                if (iy0 >= ny) { iy0 = 0; iz0 += tz; }
+                for (int u = 0; u < U; ++u) load(g, u);
             }
         }
     }
@@ -468,11 +518,6 @@ struct Box {
     int xs, ys, zs;
 };
 
-__device__ __forceinline__ int64_t box_volume(const Box& b) {
-    if (b.xa > b.xb || b.ya > b.yb || b.za > b.zb) return 0;
-    return (int64_t)((b.xb - b.xa) / b.xs + 1) * ((b.yb - b.ya) / b.ys + 1) * ((b.zb - b.za) / b.zs + 1);
-}
-
 // The one or two face coordinates c - s, c + s that lie in [0, n-1], as a strided
 // range lo, hi, step (empty: lo > hi).
 __device__ __forceinline__ void face_range(int c, int s, int n, int& lo, int& hi, int& step) {
@@ -567,14 +612,17 @@ __device__ __forceinline__ Box box_at(const VolDesc& v, const BoxSet& bs, int i,
     return b;
 }
 
-__device__ __forceinline__ int64_t boxes_volume(const VolDesc& v, const BoxSet& bs) {
-    int64_t n = 0;
-    const int nb = box_count(bs);
-    for (int i = 0; i < nb; ++i) {
-        int sg;
-        n += box_volume(box_at(v, bs, i, sg));
-    }
-    return n;
+// Voxels that a running-window update from P to Q sweeps: |W(P)| + |W(Q)| minus
+// twice their intersection (a box: per axis the overlap of the two clipped
+// ranges), which equals the summed volumes of the six move boxes.
+__device__ __forceinline__ int64_t move_volume(const VolDesc& v, int px, int py, int pz, int qx, int qy, int qz,
+                                               int s) {
+    auto overlap = [s](int p, int q, int n) {
+        const int lo = max(max(p, q) - s, 0), hi = min(min(p, q) + s, n - 1);
+        return (int64_t)max(hi - lo + 1, 0);
+    };
+    const int64_t both = overlap(px, qx, v.X) * overlap(py, qy, v.Y) * overlap(pz, qz, v.Z);
+    return cube_count(v, px, py, pz, s) + cube_count(v, qx, qy, qz, s) - 2 * both;
 }
 
 // Sweeps the boxes of bs into the packed LDS histogram and adds them (with their
@@ -582,9 +630,14 @@ __device__ __forceinline__ int64_t boxes_volume(const VolDesc& v, const BoxSet& 
 // point.  Each box is swept a dword column per lane; bytes outside it go to the
 // trash slots at trash_base, past every bin layout.  The flush budget runs across
 // the boxes.
+// Voxels per replica between flushes for a running-window update at half-width
+// s: the fields are signed and |d'| <= 3s, so 511 * 3s < 2^15 bounds them.
+__device__ __forceinline__ int move_budget(int s) { return min(511, 32767 / (3 * s)); }
+
 template <int M>
-__device__ __forceinline__ unsigned int ms_sweep(const VolDesc& v, BoxSet bs, int rl, int trash_base,
-                                                 unsigned long long* hist, int lane, BinAcc<M>& acc) {
+__device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet bs, int rl, int trash_base,
+                                                       int move_per_rep, unsigned long long* hist, int lane,
+                                                       BinAcc<M>& acc) {
     bs.kind = uniform(bs.kind); bs.px = uniform(bs.px); bs.py = uniform(bs.py); bs.pz = uniform(bs.pz);
     bs.qx = uniform(bs.qx); bs.qy = uniform(bs.qy); bs.qz = uniform(bs.qz); bs.s = uniform(bs.s);
     rl = uniform(rl);
@@ -597,9 +650,8 @@ __device__ __forceinline__ unsigned int ms_sweep(const VolDesc& v, BoxSet bs, in
     const uint32_t trash = (uint32_t)(trash_base + rep) << 3;
     const uint32_t repoff = (uint32_t)rep << 3;
     // Voxels per replica between flushes: without leaving voxels every field is
-    // non-negative and 1023 * 2s < 2^16; with them the fields are signed and
-    // |d'| <= 3s.
-    const int per_rep = mv ? min(511, 32767 / (3 * s)) : 1023;
+    // non-negative and 1023 * 2s < 2^16; with them, move_budget(s).
+    const int per_rep = mv ? uniform(move_per_rep) : 1023;
     const int limit = (per_rep << rl) >> 6;
     char* hb = reinterpret_cast<char*>(hist);
     auto flush = [&]() {
@@ -609,10 +661,16 @@ __device__ __forceinline__ unsigned int ms_sweep(const VolDesc& v, BoxSet bs, in
         __syncthreads();
     };
     int used = 0;
-    unsigned int ops = 0;
+    unsigned long long ops = 0;   // LDS atomic operations of all lanes (uniform)
     const int nb = box_count(bs);
 #pragma unroll 1
     for (int i = 0; i < nb; ++i) {
+        // a move box lies outside the other window along axis i % 3: none if the
+        // move has no component along it
+        if (mv) {
+            const int a = i >= 3 ? i - 3 : i;
+            if ((a == 0 ? bs.qx - bs.px : a == 1 ? bs.qy - bs.py : bs.qz - bs.pz) == 0) continue;
+        }
         int sg;
         const Box b = box_at(v, bs, i, sg);
         const int xa = uniform(b.xa), xb = uniform(b.xb), ya = uniform(b.ya), yb = uniform(b.yb);
@@ -624,7 +682,8 @@ __device__ __forceinline__ unsigned int ms_sweep(const VolDesc& v, BoxSet bs, in
         // in x than in y; the fast axis is never strided
         const bool tr = xs != 1 || (ys == 1 && xb - xa < yb - ya);
         const Layout L = tr ? layout_t(v) : layout_x(v);
-        const int ny = (yb - ya) / ys + 1, nz = (zb - za) / zs + 1, nx = (xb - xa) / xs + 1;
+        const int ny = uniform(small_div(yb - ya, ys)) + 1, nz = uniform(small_div(zb - za, zs)) + 1;
+        const int nx = uniform(small_div(xb - xa, xs)) + 1;
         const Sweep w = tr ? make_sweep<64>(L, ya, yb, za, nz, zs, xa, nx, xs, lane)
                            : make_sweep<64>(L, xa, xb, ya, ny, ys, za, nz, zs, lane);
         // axes (fast, row, slice) -> packed fields: x at bit 10, y at 32, z at 48
@@ -648,16 +707,16 @@ __device__ __forceinline__ unsigned int ms_sweep(const VolDesc& v, BoxSet bs, in
         }
         const unsigned long long smr = (unsigned long long)((long long)sg * mr);
         const unsigned long long sms = (unsigned long long)((long long)sg * ms);
+        // every (row, dword) of the box is scattered once, four adds each
+        ops += 4ull * (unsigned)(w.nd * w.ny * w.nz);
         run_sweep<kMsUnroll, kMsDepth>(
-            L, w, used, limit,
-            [&](uint32_t word, int iy0, int iz0) {
-                const unsigned long long step = (unsigned long long)(uint32_t)iy0 * smr + (unsigned long long)(uint32_t)iz0 * sms;
+            L, w, smr, sms, used, limit,
+            [&](uint32_t word, int, int, uint64_t step) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const uint32_t bin = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
                     atomicAdd(reinterpret_cast<unsigned long long*>(hb + (bin << shift) + off[k]), cp[k] + step);
                 }
-                ops += 4;
             },
             flush);
     }
@@ -860,6 +919,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
     __syncthreads();
     LocalCounts lc = {0, 0, 0, 0, 0, 0u};
+    unsigned long long ms_ops = 0;   // LDS atomic operations of the wave's lanes
     const int trash_base = hist_words - 64;
     // A window level's sentinel bin B is scattered into but never read or
     // cleared; its words, at B << rl, hold counts until the replica layout
@@ -884,6 +944,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         for (int s = uniform(sg.scale); s <= s_last; ++s) {
         // replicas per wavefront by window size class
         const int rl = s <= tune.s_small ? tune.rl_small : tune.rl;
+        const int move_per_rep = move_budget(s);
         const int sentinel = v.win ? (v.B << rl) : -1;
         if (dirty >= 0 && (dirty != sentinel || dirty_len != (1 << rl))) {
             for (int i = lane; i < dirty_len; i += 64) hist[dirty + i] = 0ull;
@@ -909,7 +970,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
             if (phase == 1) {
                 const int64_t nq = cube_count(v, qx, qy, qz, s);
                 const BoxSet mv = {kMove, wx, wy, wz, qx, qy, qz, s};
-                const int64_t nd = boxes_volume(v, mv);
+                const int64_t nd = move_volume(v, wx, wy, wz, qx, qy, qz, s);
 #pragma unroll
                 for (int k = 0; k < M; ++k) cprev[k] = a.c[k];
                 if (100 * nd < (int64_t)tune.incr_pct * nq) {
@@ -951,7 +1012,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
             } else {
                 lc.swept += (unsigned long long)cube_count(v, px, py, pz, s);
             }
-            lc.lds_ops += ms_sweep<M>(v, bs, rl, trash_base, hist, lane, a);
+            ms_ops += ms_sweep<M>(v, bs, rl, trash_base, move_per_rep, hist, lane, a);
             if (phase == 2) break;
             if (GROUPED && phase == 0) first = a;
             // an evaluation at W (= P0 in phase 0, Q in phase 1)
@@ -1004,8 +1065,7 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
         atomicAdd(&cnt->final_visits, lc.final_visits);
         atomicAdd(&cnt->swept, lc.swept);
     }
-    const unsigned long long ops = (unsigned long long)bfly_sumll((long long)lc.lds_ops);
-    if (lane == 0) atomicAdd(&cnt->lds_ops, ops);
+    if (lane == 0) atomicAdd(&cnt->lds_ops, ms_ops);
 }
 
 // ------------------------------------------------ quadrant: bucketed scatter
@@ -1035,8 +1095,8 @@ __device__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya,
     int used = 0;
     unsigned int ops = 0;
     run_sweep<kQuadUnroll, kQuadDepth>(
-        L, w, used, INT_MAX,
-        [&](uint32_t word, int iy0, int iz0) {
+        L, w, 0, 0, used, INT_MAX,
+        [&](uint32_t word, int iy0, int iz0, uint64_t) {
             const int rr = max(max(abs(dy0 + iy0), abs(dz0 + iz0)) - base, 0);
             const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
 #pragma unroll
@@ -1090,8 +1150,8 @@ __device__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz,
     int used = 0;
     unsigned int ops = 0;
     run_sweep<kQuadUnroll, kQuadDepth>(
-        L, w, used, INT_MAX,
-        [&](uint32_t word, int iy0, int iz0) {
+        L, w, 0, 0, used, INT_MAX,
+        [&](uint32_t word, int iy0, int iz0, uint64_t) {
             const int dy = dy0 + iy0, dz = dz0 + iz0;
             const uint32_t RR = __umul24((uint32_t)max(max(abs(dy), abs(dz)) - base, 0), rowbytes) + rep4;
             const uint32_t ayz = (dy > 0 ? ry2 : 0u) + (dz > 0 ? rz4 : 0u);
@@ -1478,8 +1538,8 @@ __device__ __forceinline__ unsigned int map_box(const VolDesc& v, int xa, int xb
     unsigned int ops = 0;
     int used = 0;
     run_sweep<kMsUnroll, kMsDepth>(
-        L, w, used, INT_MAX,
-        [&](uint32_t word, int, int) {
+        L, w, 0, 0, used, INT_MAX,
+        [&](uint32_t word, int, int, uint64_t) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t bin = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
@@ -1639,7 +1699,7 @@ __global__ __launch_bounds__(64) void k_hook_ms(const VolDesc* vols, int kind, i
         BinAcc<M> a, e;
         acc_clear<M>(a);
         acc_clear<M>(e);
-        ms_sweep<M>(v, BoxSet{kFull, px, py, pz, 0, 0, 0, s}, rl, trash_base, hist, lane, a);
+        ms_sweep<M>(v, BoxSet{kFull, px, py, pz, 0, 0, 0, s}, rl, trash_base, move_budget(s), hist, lane, a);
         int sh[M], bx[M];
         if (kind == 2) {
             const int qx = xyz[6 * w + 3], qy = xyz[6 * w + 4], qz = xyz[6 * w + 5];
@@ -1649,13 +1709,13 @@ __global__ __launch_bounds__(64) void k_hook_ms(const VolDesc* vols, int kind, i
                 a.f2[k] -= a.c[k] * (qy - py);
                 a.f3[k] -= a.c[k] * (qz - pz);
             }
-            ms_sweep<M>(v, BoxSet{kMove, px, py, pz, qx, qy, qz, s}, rl, trash_base, hist, lane, a);
+            ms_sweep<M>(v, BoxSet{kMove, px, py, pz, qx, qy, qz, s}, rl, trash_base, move_budget(s), hist, lane, a);
         } else if (kind == 3) {
-            ms_sweep<M>(v, BoxSet{kShell, px, py, pz, 0, 0, 0, s}, rl, trash_base, hist, lane, e);
+            ms_sweep<M>(v, BoxSet{kShell, px, py, pz, 0, 0, 0, s}, rl, trash_base, move_budget(s), hist, lane, e);
 #pragma unroll
             for (int k = 0; k < M; ++k) sh[k] = a.c[k] - e.c[k];
             acc_clear<M>(e);
-            ms_sweep<M>(v, BoxSet{kInner, px, py, pz, 0, 0, 0, s}, rl, trash_base, hist, lane, e);
+            ms_sweep<M>(v, BoxSet{kInner, px, py, pz, 0, 0, 0, s}, rl, trash_base, move_budget(s), hist, lane, e);
 #pragma unroll
             for (int k = 0; k < M; ++k) bx[k] = e.c[k];
         }
