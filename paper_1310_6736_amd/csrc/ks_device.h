@@ -56,18 +56,26 @@ struct VolDesc {
     const int32_t* seeds;   // explicit start positions (x, y, z) x gx, or null: the seed grid
 };
 
-// A run of tasks with the same window sizes: task task_begin + i is seed
-// seed_begin + i of volume `vol`: its quadrant trajectory, or its mean-shift
-// trajectories of the scales scale .. scale_hi, run in that order by one
-// wavefront (each starts from the previous one's window at the seed).
+// A run of tasks with the same window sizes: task task_begin + i is the i-th
+// start position, x fastest, of the box [bx, bx + bw) x [by, by + bh) x [bz, ..)
+// of the seed grid (or of the seed list, gx x 1 x 1) of volume `vol`: its
+// quadrant trajectory, or its mean-shift trajectories of the scales scale ..
+// scale_hi, run in that order by one wavefront (each starts from the previous
+// one's window at the seed).
 struct TaskSeg {
     int64_t task_begin;
-    int64_t count;
+    int64_t count;          // bw * bh * (box depth)
     int32_t vol;
     int32_t scale;          // mean-shift: the first scale of the group; quadrant: 0
-    int64_t seed_begin;     // first seed id of the run
     int32_t scale_hi;       // mean-shift: the last scale of the group; quadrant: 0
-    int32_t pad;
+    int32_t bx, by, bz, bw, bh;
+};
+
+// Mean-shift task queues: one per XCD (workgroups are dispatched to the 8 XCDs
+// round robin); queue k holds tasks begin[k] .. begin[k + 1] - 1.
+constexpr int kXcds = 8;
+struct XcdQueues {
+    int64_t begin[kXcds + 1];
 };
 
 // Result of one trajectory (80 bytes).
@@ -94,7 +102,8 @@ struct SortRec {
 
 struct Counters {
     unsigned long long evals, window_evals, voxel_visits, final_visits;
-    unsigned long long queue_head[2];   // task queues (quadrant, mean-shift)
+    unsigned long long queue_head[2];   // task queues (quadrant; ABMSOD candidates)
+    unsigned long long xq_head[kXcds];  // mean-shift task queues, one per XCD
     unsigned long long n_sort;          // kept trajectories
     unsigned long long swept;           // voxels actually swept by the searches
     unsigned long long lds_ops;         // lane-level LDS atomic operations of the searches
@@ -109,6 +118,15 @@ struct MsTune {
     int32_t rl, rl_small, s_small, incr_pct;
     int32_t group, pad;
 };
+
+// Seed id of task i of a run (its box's points in x-fastest order).
+__device__ __forceinline__ long long seg_seed(const VolDesc& v, const TaskSeg& sg, long long i) {
+    const long long row = i / sg.bw;
+    const long long ix = i - row * sg.bw;
+    const long long iz = row / sg.bh;
+    const long long iy = row - iz * sg.bh;
+    return (sg.bx + ix) + (long long)v.gx * ((sg.by + iy) + (long long)v.gy * (sg.bz + iz));
+}
 
 // Start position of seed `seed` of a volume: the listed position, or grid point
 // (o + kx sp, o + ky sp, o + kz sp) with the seed index x fastest.

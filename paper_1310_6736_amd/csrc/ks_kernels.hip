@@ -42,7 +42,7 @@ namespace ks {
 // the mean-shift sweeps, many of them a few rows long, run best with a short
 // pipeline; the quadrant brick sweep with narrow groups).
 #ifndef KS_MS_UNROLL
-#define KS_MS_UNROLL 4
+#define KS_MS_UNROLL 2
 #endif
 #ifndef KS_MS_DEPTH
 #define KS_MS_DEPTH 1
@@ -302,6 +302,7 @@ __global__ void k_prep_init(VolDesc* vols, int nvol, Counters* cnt, int* vol_nfo
     if (t == 0) {
         cnt->evals = cnt->window_evals = cnt->voxel_visits = cnt->final_visits = 0;
         cnt->queue_head[0] = cnt->queue_head[1] = 0;
+        for (int k = 0; k < kXcds; ++k) cnt->xq_head[k] = 0;
         cnt->n_sort = 0;
         cnt->swept = 0;
         cnt->lds_ops = 0;
@@ -664,7 +665,12 @@ __device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet 
     unsigned long long ops = 0;   // LDS atomic operations of all lanes (uniform)
     const int nb = box_count(bs);
 #pragma unroll 1
-    for (int i = 0; i < nb; ++i) {
+    for (int i0 = 0; i0 < nb; ++i0) {
+        // an index the compiler cannot see through: each box's geometry is
+        // computed where it is swept instead of all six up front (which would
+        // not fit the scalar registers)
+        int i = uniform(i0);
+        asm volatile("" : "+s"(i));
         // a move box lies outside the other window along axis i % 3: none if the
         // move has no component along it
         if (mv) {
@@ -911,9 +917,9 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 // the scatter code is instantiated once.
 template <int M, bool GROUPED>
 __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols,
-                                                  const TaskSeg* __restrict__ segs, int nseg, long long ntask,
-                                                  Tables tb, TrajRec* out, Counters* cnt, MsTune tune,
-                                                  int hist_words) {
+                                                  const TaskSeg* __restrict__ segs, int nseg,
+                                                  const XcdQueues* __restrict__ xq, Tables tb, TrajRec* out,
+                                                  Counters* cnt, MsTune tune, int hist_words) {
     extern __shared__ unsigned long long hist[];
     const int lane = threadIdx.x;
     for (int i = lane; i < hist_words; i += 64) hist[i] = 0ull;
@@ -925,15 +931,28 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
     // cleared; its words, at B << rl, hold counts until the replica layout
     // changes, where they would be read as bins below B: cleared then.
     int dirty = -1, dirty_len = 0;
+    // The wave's XCD queue first (its tasks cover one part of each volume, so
+    // the XCD's L2 holds their windows), then the other XCDs' queues in turn.
+    const int xcd = (int)(blockIdx.x & (kXcds - 1));
+    unsigned int drained = 0;   // lane 0: queues found empty
     for (;;) {
-        long long t = 0;
-        if (lane == 0) t = (long long)atomicAdd(&cnt->queue_head[1], 1ull);
+        long long t = -1;
+        if (lane == 0) {
+            for (int k = 0; k < kXcds && t < 0; ++k) {
+                const int q = (xcd + k) & (kXcds - 1);
+                if (drained & (1u << q)) continue;
+                const long long i = (long long)atomicAdd(&cnt->xq_head[q], 1ull);
+                const long long b = xq->begin[q];
+                if (b + i < xq->begin[q + 1]) t = b + i;
+                else drained |= 1u << q;
+            }
+        }
         t = __shfl(t, 0, 64);
-        if (t >= ntask) break;
+        if (t < 0) break;
         const int si = uniform(find_seg(segs, nseg, t));
         const TaskSeg sg = segs[si];
         const VolDesc& v = vols[sg.vol];
-        const long long seed = sg.seed_begin + (t - sg.task_begin);
+        const long long seed = seg_seed(v, sg, t - sg.task_begin);
         int p0[3];
         seed_pos(v, seed, p0);
         // The group's scales in ascending order: the first window of scale s is
@@ -1480,7 +1499,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __r
         const int si = uniform(find_seg(segs, nseg, t));
         const TaskSeg sg = segs[si];
         const VolDesc& v = vols[sg.vol];
-        const long long seed = sg.seed_begin + (t - sg.task_begin);
+        const long long seed = seg_seed(v, sg, t - sg.task_begin);
         int p0[3];
         seed_pos(v, seed, p0);
         const TrajOut o = run_trajectory(
@@ -2098,15 +2117,15 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
 
 int bins_per_lane_host(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
 
-hipError_t launch_search_ms(const SearchArgs& a, int grid, const MsTune& tune, int hist_words, int maxB,
-                            hipStream_t st) {
+hipError_t launch_search_ms(const SearchArgs& a, const XcdQueues* xq, int grid, const MsTune& tune, int hist_words,
+                            int maxB, hipStream_t st) {
     if (a.ntask <= 0) return hipSuccess;
     const size_t lds = (size_t)hist_words * 8;
     const int M = bins_per_lane_host(maxB);
     // one scale per task: the kernel without the group bookkeeping (fewer registers)
 #define KS_LAUNCH_MS(MM, GG)                                                                                   \
-    hipLaunchKernelGGL((k_search_ms<MM, GG>), dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, a.ntask, \
-                       a.tb, a.rec, a.cnt, tune, hist_words)
+    hipLaunchKernelGGL((k_search_ms<MM, GG>), dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, xq, a.tb, \
+                       a.rec, a.cnt, tune, hist_words)
     const bool g = tune.group > 1;
     if (M == 1) { if (g) KS_LAUNCH_MS(1, true); else KS_LAUNCH_MS(1, false); }
     else if (M == 2) { if (g) KS_LAUNCH_MS(2, true); else KS_LAUNCH_MS(2, false); }

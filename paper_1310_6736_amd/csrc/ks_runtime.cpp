@@ -261,13 +261,14 @@ void arena_needs(const std::vector<VolIn>& in, size_t need[kArenaBuffers]) {
         regs += v.capacity;
         bins += bins_bytes(v.dims);
         if (v.seeds) seed_ints += 3 * (size_t)v.n_seeds;
-        // at most one task run per scale (mean-shift) or one (quadrant)
-        segs += v.method == KS_MEANSHIFT ? (size_t)(v.scales[1] - v.scales[0] + 1) : 1;
+        // at most one task run per scale and XCD (mean-shift) or one (quadrant)
+        segs += v.method == KS_MEANSHIFT ? (size_t)(v.scales[1] - v.scales[0] + 1) * kXcds : 1;
     }
     const unsigned long long n_pad = next_pow2((unsigned long long)std::max<int64_t>(traj, 2));
     size_t nf_off, cnt_off, out_bytes;
     result_layout(in.size(), regs, &nf_off, &cnt_off, &out_bytes);
-    need[0] = std::max<size_t>(sizeof(VolDesc) * in.size() + sizeof(TaskSeg) * segs + sizeof(int32_t) * seed_ints,
+    need[0] = std::max<size_t>(sizeof(VolDesc) * in.size() + sizeof(XcdQueues) + sizeof(TaskSeg) * segs +
+                                   sizeof(int32_t) * seed_ints,
                                256);
     need[1] = std::max<size_t>(bins, 256);
     need[2] = sizeof(TrajRec) * (size_t)std::max<int64_t>(traj, 1);
@@ -401,54 +402,86 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p, const FixedArena*
     }
     G = std::max(1, G);
     p.ms_group = G;
-    // Task runs, longest windows first (largest-processing-time order).
-    struct Run { TaskSeg s; double cost; int method; };
+    // Task runs, longest windows first (largest-processing-time order).  The
+    // mean-shift tasks go to one queue per XCD: each run's start positions are
+    // cut into 2 x 2 x 2 boxes (halves of the grid along each axis; a seed list
+    // into 8 ranges) and box k goes to XCD k's queue, so that the windows an XCD
+    // works on at once lie in one part of the volume and share its L2; each
+    // queue holds its runs longest windows first.
+    struct Run { TaskSeg s; double cost; int method; int xcd; };
     std::vector<Run> runs;
     for (int i = 0; i < nvol; ++i) {
         const VolDesc& v = p.vols[i];
         const int64_t seeds = (int64_t)v.gx * v.gy * v.gz;
         if (seeds == 0) continue;
+        Run r;
+        r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = 0; r.s.scale_hi = 0;
+        r.s.bx = r.s.by = r.s.bz = 0; r.s.bw = v.gx; r.s.bh = v.gy;
+        r.xcd = 0;
         if (v.method == KS_QUADRANT) {
-            Run r;
-            r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = 0; r.s.seed_begin = 0;
-            r.s.scale_hi = 0; r.s.pad = 0;
             const double w = 2.0 * v.s_max + 2.0;
             r.cost = w * w * w;
             r.method = KS_QUADRANT;
             runs.push_back(r);
-        } else {
-            // groups of G consecutive scales, the largest group first
-            for (int hi = v.s_max; hi >= v.s_min; hi -= G) {
-                const int lo = std::max(v.s_min, hi - G + 1);
-                Run r;
-                r.s.task_begin = 0; r.s.count = seeds; r.s.vol = i; r.s.scale = lo; r.s.seed_begin = 0;
-                r.s.scale_hi = hi; r.s.pad = 0;
-                r.cost = 0.0;
-                for (int s = lo; s <= hi; ++s) {
-                    const double w = 2.0 * s + 1.0;
-                    r.cost += w * w * w;
+            continue;
+        }
+        r.method = KS_MEANSHIFT;
+        // groups of G consecutive scales, the largest group first
+        for (int hi = v.s_max; hi >= v.s_min; hi -= G) {
+            const int lo = std::max(v.s_min, hi - G + 1);
+            r.s.scale = lo;
+            r.s.scale_hi = hi;
+            r.cost = 0.0;
+            for (int s = lo; s <= hi; ++s) {
+                const double w = 2.0 * s + 1.0;
+                r.cost += w * w * w;
+            }
+            const bool list = in[i].seeds != nullptr;
+            for (int k = 0; k < kXcds; ++k) {
+                Run b = r;
+                b.xcd = k;
+                int x0, x1, y0 = 0, y1 = v.gy, z0 = 0, z1 = v.gz;
+                if (list) {  // a seed list: 8 ranges of the list
+                    x0 = (int)((int64_t)v.gx * k / kXcds);
+                    x1 = (int)((int64_t)v.gx * (k + 1) / kXcds);
+                } else {
+                    const int hx = (v.gx + 1) / 2, hy = (v.gy + 1) / 2, hz = (v.gz + 1) / 2;
+                    x0 = (k & 1) ? hx : 0; x1 = (k & 1) ? v.gx : hx;
+                    y0 = (k & 2) ? hy : 0; y1 = (k & 2) ? v.gy : hy;
+                    z0 = (k & 4) ? hz : 0; z1 = (k & 4) ? v.gz : hz;
                 }
-                r.method = KS_MEANSHIFT;
-                runs.push_back(r);
+                const int64_t n = (int64_t)(x1 - x0) * (y1 - y0) * (z1 - z0);
+                if (n <= 0) continue;
+                b.s.count = n;
+                b.s.bx = x0; b.s.by = y0; b.s.bz = z0; b.s.bw = x1 - x0; b.s.bh = y1 - y0;
+                runs.push_back(b);
             }
         }
     }
-    std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.cost > b.cost; });
+    std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
+        if (a.xcd != b.xcd) return a.xcd < b.xcd;
+        return a.cost > b.cost;
+    });
+    int next_q = 0;
     for (const Run& r : runs) {
         std::vector<TaskSeg>& segs = r.method == KS_QUADRANT ? p.segs_q : p.segs_m;
         long long& nt = r.method == KS_QUADRANT ? p.ntask_q : p.ntask_m;
+        if (r.method == KS_MEANSHIFT)
+            while (next_q <= r.xcd) p.xq.begin[next_q++] = nt;
         TaskSeg s = r.s;
         s.task_begin = nt;
         nt += s.count;
         segs.push_back(s);
     }
+    while (next_q <= kXcds) p.xq.begin[next_q++] = p.ntask_m;
     // Device memory: descriptors, task segments and seed lists in one allocation
     // laid out as the host staging area, so that one copy uploads them; results
     // in one allocation laid out as the host copy, so that one copy downloads
     // them (regions, per-volume region counts, the counter block).
     ks_status st;
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)nvol;
-    const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
+    // after the descriptors: the mean-shift queue ranges, then the task segments
+    const size_t seg_bytes = sizeof(XcdQueues) + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     const size_t stage_bytes = vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints;
     result_layout((size_t)nvol, regs, &p.out_nf_off, &p.out_cnt_off, &p.out_bytes);
     size_t need[kArenaBuffers];
@@ -504,9 +537,10 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p, const FixedArena*
 ks_status Context::upload(const Plan& p, hipStream_t st) {
     char* h = p.stage;
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)p.nvol;
-    const size_t seg_bytes = sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
+    const size_t seg_bytes = sizeof(XcdQueues) + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     std::memcpy(h, p.vols.data(), vol_bytes);
-    TaskSeg* hs = reinterpret_cast<TaskSeg*>(h + vol_bytes);
+    std::memcpy(h + vol_bytes, &p.xq, sizeof(XcdQueues));
+    TaskSeg* hs = reinterpret_cast<TaskSeg*>(h + vol_bytes + sizeof(XcdQueues));
     size_t ns = 0;
     for (const TaskSeg& s : p.segs_q) hs[ns++] = s;
     for (const TaskSeg& s : p.segs_m) hs[ns++] = s;
@@ -541,7 +575,8 @@ static hipError_t mark(hipEvent_t ev, hipStream_t st) {
 
 ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed) {
     VolDesc* dv = reinterpret_cast<VolDesc*>(p.dev[kArVols]);
-    TaskSeg* ds = reinterpret_cast<TaskSeg*>(p.dev[kArVols] + sizeof(VolDesc) * (size_t)p.nvol);
+    const XcdQueues* dxq = reinterpret_cast<const XcdQueues*>(p.dev[kArVols] + sizeof(VolDesc) * (size_t)p.nvol);
+    TaskSeg* ds = reinterpret_cast<TaskSeg*>(p.dev[kArVols] + sizeof(VolDesc) * (size_t)p.nvol + sizeof(XcdQueues));
     Counters* dc = p.cnt;
     TrajRec* rec = reinterpret_cast<TrajRec*>(p.dev[kArRec]);
     if (timed) KS_HIP(mark(ev[0], st));
@@ -582,7 +617,7 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         tune.group = p.ms_group;
         tune.pad = 0;
         if (timed) KS_HIP(mark(ev[4], sm_st));
-        KS_HIP(launch_search_ms(sm, (int)g, tune, p.ms_hist_words, p.maxB_ms, sm_st));
+        KS_HIP(launch_search_ms(sm, dxq, (int)g, tune, p.ms_hist_words, p.maxB_ms, sm_st));
         if (timed) KS_HIP(mark(ev[5], sm_st));
     }
     if (fork) {

@@ -73,6 +73,7 @@ struct Plan {
     std::vector<VolDesc> vols;
     std::vector<TaskSeg> segs_q, segs_m;
     long long ntask_q = 0, ntask_m = 0;
+    XcdQueues xq{};                  // the mean-shift tasks' queue ranges
     long long total_traj = 0, total_regions = 0, max_traj = 0, max_voxels = 0, max_words = 0;
     int max_tx = 0, max_ty = 0, max_z = 0;  // mean-shift volumes: 64-voxel x, y tiles and Z
     unsigned long long n_pad = 2;
