@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6  # MI355X fp64 vector, published
 
 
-SECTIONS = ("dense_map", "window_level", "tracking", "abmsod")
+SECTIONS = ("dense_map", "window_level", "tracking", "abmsod", "pet_like", "batch", "serving")
 
 
 def parse():
@@ -174,7 +174,7 @@ def serving_section(ks, torch, ctx, ws):
             if now < t_arr:
                 time.sleep(t_arr - now)
             w = ws[i]
-            tickets.append(srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter))
+            tickets.append(srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, max_regions=cap))
         srv.drain()
         st = srv.stats()
         for t in tickets:
@@ -447,15 +447,23 @@ def cpu_baseline(stride: int, stride_one: int, workers: int):
                                       "to one core; %.1f s wall" % (stride_one, ids1.size, wall1)}}
 
 
-def section_only(name):
+def section_only(name, args):
     """One extra section alone, on a fresh context: the workload of a kernel-trace
     profile of that section."""
+    stream_ws = stream_workloads(args.serve_requests, max(1, min(16, os.cpu_count() or 1))) \
+        if name == "serving" else None
     import torch
 
     from paper_1310_6736_amd import ks
 
     ctx = ks.Context(0)
-    if name == "dense_map":
+    if name == "serving":
+        rec = serving_section(ks, torch, ctx, stream_ws)
+    elif name == "batch":
+        rec = batch_section(ks, torch, ctx)
+    elif name == "pet_like":
+        rec = pet_section(ks, torch, ctx, args.steps, args.warmup)
+    elif name == "dense_map":
         rec = dense_section(ks, torch, ctx, None)
     elif name == "window_level":
         rec = window_level_section(ks, torch, ctx)
@@ -549,7 +557,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.section:
-        section_only(args.section)
+        section_only(args.section, args)
         return
     cpu = None
     workers = max(1, min(16, os.cpu_count() or 1))

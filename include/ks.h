@@ -207,6 +207,13 @@ ks_status ks_context_set_seeds(ks_context* ctx, const int32_t* seeds, int64_t n_
  * resident wavefront.  Results do not depend on it. */
 ks_status ks_context_set_ms_group(ks_context* ctx, int32_t scales_per_task);
 
+/* Splits each mean-shift search into `launches` launches (1..8, default 1), each
+ * taking an equal share of every queue's tasks, so that work of other streams
+ * (other server slots, other callers) gets the device between them instead of
+ * waiting for one long persistent launch to drain.  Results do not depend on
+ * it. */
+ks_status ks_context_set_ms_chunks(ks_context* ctx, int32_t launches);
+
 /* Runs the quadrant and mean-shift searches of one call (a batch holding both
  * methods) concurrently on two streams, so that the blocks of each fill the
  * other's tail (on = 1, the default), or one after the other (0).  Results do
@@ -381,6 +388,11 @@ typedef struct {
      * copies it at submit); NULL: the grid of seed_spacing. */
     const int32_t* seeds;
     int64_t n_seeds;
+    /* Server requests: the most regions a poll of this request will return, in
+     * rank order (0: every region); the server keeps and copies only those.
+     * ks_detect_batch takes the capacity of each ks_result instead. */
+    int32_t max_regions;
+    int32_t reserved;      /* 0 */
 } ks_request;
 
 typedef struct {
@@ -430,13 +442,17 @@ typedef struct {
  * batch per free slot; a slot's buffers grow to exactly what its batches need,
  * and idle slots give theirs back when a new batch would not fit beside them.
  * A batch that arrives while others run is launched at once on its own stream
- * and its work overlaps theirs on the device.  Outside the budget, each slot
- * holds the fixed decision tables (7.2 MB) from creation to destruction. */
+ * and its work overlaps theirs on the device.  A large request (a full-size
+ * mean-shift search of the MR-like kind) runs alone in its batch, one at a time,
+ * while smaller requests pass it in the queue and run beside it.  Outside the budget, each slot holds the
+ * fixed decision tables (7.2 MB) from creation to destruction. */
 ks_status ks_server_create(int32_t device, size_t hbm_budget, int32_t max_slots, ks_server** out);
 /* Copies the host volume; returns a ticket.  KS_E_TOO_LARGE if the request
  * alone would need more device memory than the budget. */
 ks_status ks_server_submit(ks_server* s, const ks_request* req, uint64_t* ticket);
-/* KS_E_NOT_READY until the request is done; then writes its regions once. */
+/* KS_E_NOT_READY until the request is done; then writes its regions once:
+ * min(capacity, *n_found, the request's max_regions when set) of them in rank
+ * order, *n_found being the total the request found. */
 ks_status ks_server_poll(ks_server* s, uint64_t ticket, ks_region* out, int32_t capacity, int32_t* n_found);
 /* A request of a tracked sequence (Sec. 4: tracking seeded from the converged
  * regions of the previous frame).  Frames of one track (any int64 id) are run in

@@ -71,11 +71,15 @@ struct TaskSeg {
     int32_t bx, by, bz, bw, bh;
 };
 
-// Mean-shift task queues: one per XCD (workgroups are dispatched to the 8 XCDs
-// round robin); queue k holds tasks begin[k] .. begin[k + 1] - 1.
+// Mean-shift task queues of one launch: one per XCD (workgroups are dispatched
+// to the 8 XCDs round robin); queue k holds tasks begin[k] .. end[k] - 1.  A
+// search split into several launches has one such block per launch; launch c
+// counts the tasks taken from queue k in Counters::xq_head[c][k].
 constexpr int kXcds = 8;
+constexpr int kMaxMsChunks = 8;
 struct XcdQueues {
-    int64_t begin[kXcds + 1];
+    int64_t begin[kXcds];
+    int64_t end[kXcds];
 };
 
 // Result of one trajectory (80 bytes).
@@ -103,7 +107,7 @@ struct SortRec {
 struct Counters {
     unsigned long long evals, window_evals, voxel_visits, final_visits;
     unsigned long long queue_head[2];   // task queues (quadrant; ABMSOD candidates)
-    unsigned long long xq_head[kXcds];  // mean-shift task queues, one per XCD
+    unsigned long long xq_head[kMaxMsChunks][kXcds];  // mean-shift queues, per launch and XCD
     unsigned long long n_sort;          // kept trajectories
     unsigned long long swept;           // voxels actually swept by the searches
     unsigned long long lds_ops;         // lane-level LDS atomic operations of the searches

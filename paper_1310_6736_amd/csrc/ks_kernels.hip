@@ -302,7 +302,8 @@ __global__ void k_prep_init(VolDesc* vols, int nvol, Counters* cnt, int* vol_nfo
     if (t == 0) {
         cnt->evals = cnt->window_evals = cnt->voxel_visits = cnt->final_visits = 0;
         cnt->queue_head[0] = cnt->queue_head[1] = 0;
-        for (int k = 0; k < kXcds; ++k) cnt->xq_head[k] = 0;
+        for (int c = 0; c < kMaxMsChunks; ++c)
+            for (int k = 0; k < kXcds; ++k) cnt->xq_head[c][k] = 0;
         cnt->n_sort = 0;
         cnt->swept = 0;
         cnt->lds_ops = 0;
@@ -918,7 +919,8 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 template <int M, bool GROUPED>
 __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols,
                                                   const TaskSeg* __restrict__ segs, int nseg,
-                                                  const XcdQueues* __restrict__ xq, Tables tb, TrajRec* out,
+                                                  const XcdQueues* __restrict__ xq, int chunk, Tables tb,
+                                                  TrajRec* out,
                                                   Counters* cnt, MsTune tune, int hist_words) {
     extern __shared__ unsigned long long hist[];
     const int lane = threadIdx.x;
@@ -941,9 +943,9 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
             for (int k = 0; k < kXcds && t < 0; ++k) {
                 const int q = (xcd + k) & (kXcds - 1);
                 if (drained & (1u << q)) continue;
-                const long long i = (long long)atomicAdd(&cnt->xq_head[q], 1ull);
+                const long long i = (long long)atomicAdd(&cnt->xq_head[chunk][q], 1ull);
                 const long long b = xq->begin[q];
-                if (b + i < xq->begin[q + 1]) t = b + i;
+                if (b + i < xq->end[q]) t = b + i;
                 else drained |= 1u << q;
             }
         }
@@ -2117,15 +2119,15 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
 
 int bins_per_lane_host(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
 
-hipError_t launch_search_ms(const SearchArgs& a, const XcdQueues* xq, int grid, const MsTune& tune, int hist_words,
-                            int maxB, hipStream_t st) {
+hipError_t launch_search_ms(const SearchArgs& a, const XcdQueues* xq, int chunk, int grid, const MsTune& tune,
+                            int hist_words, int maxB, hipStream_t st) {
     if (a.ntask <= 0) return hipSuccess;
     const size_t lds = (size_t)hist_words * 8;
     const int M = bins_per_lane_host(maxB);
     // one scale per task: the kernel without the group bookkeeping (fewer registers)
 #define KS_LAUNCH_MS(MM, GG)                                                                                   \
-    hipLaunchKernelGGL((k_search_ms<MM, GG>), dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, xq, a.tb, \
-                       a.rec, a.cnt, tune, hist_words)
+    hipLaunchKernelGGL((k_search_ms<MM, GG>), dim3(grid), dim3(64), lds, st, a.vols, a.segs, a.nseg, xq, chunk, \
+                       a.tb, a.rec, a.cnt, tune, hist_words)
     const bool g = tune.group > 1;
     if (M == 1) { if (g) KS_LAUNCH_MS(1, true); else KS_LAUNCH_MS(1, false); }
     else if (M == 2) { if (g) KS_LAUNCH_MS(2, true); else KS_LAUNCH_MS(2, false); }

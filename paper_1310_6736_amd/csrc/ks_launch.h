@@ -60,9 +60,9 @@ struct RankArgs {
 };
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
-// xq: the queue ranges in device memory.
-hipError_t launch_search_ms(const SearchArgs& a, const XcdQueues* xq, int grid, const MsTune& tune, int hist_words,
-                            int maxB, hipStream_t st);
+// xq: the launch's queues in device memory; chunk: the launch's index within the search.
+hipError_t launch_search_ms(const SearchArgs& a, const XcdQueues* xq, int chunk, int grid, const MsTune& tune,
+                            int hist_words, int maxB, hipStream_t st);
 hipError_t launch_search_quad(const SearchArgs& a, int grid, int rq, const LdsQuad& lay, int maxB, hipStream_t st);
 hipError_t launch_hook_ms(const VolDesc* vols, int kind, int n, const int* xyz, const int* sc, int rl, int hist_words,
                           int maxB, void* out, hipStream_t st);

@@ -165,7 +165,6 @@ ks_status Context::init(int32_t dev) {
     tables.cl = base;
     tables.sq = base + n_tab;
     tables.rsq = base + 2 * n_tab;
-    KS_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
     for (int i = 0; i < kEvents; ++i) KS_HIP(hipEventCreate(&ev[i]));
     KS_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
     KS_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
@@ -267,7 +266,7 @@ void arena_needs(const std::vector<VolIn>& in, size_t need[kArenaBuffers]) {
     const unsigned long long n_pad = next_pow2((unsigned long long)std::max<int64_t>(traj, 2));
     size_t nf_off, cnt_off, out_bytes;
     result_layout(in.size(), regs, &nf_off, &cnt_off, &out_bytes);
-    need[0] = std::max<size_t>(sizeof(VolDesc) * in.size() + sizeof(XcdQueues) + sizeof(TaskSeg) * segs +
+    need[0] = std::max<size_t>(sizeof(VolDesc) * in.size() + sizeof(XcdQueues) * kMaxMsChunks + sizeof(TaskSeg) * segs +
                                    sizeof(int32_t) * seed_ints,
                                256);
     need[1] = std::max<size_t>(bins, 256);
@@ -467,21 +466,22 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p, const FixedArena*
         std::vector<TaskSeg>& segs = r.method == KS_QUADRANT ? p.segs_q : p.segs_m;
         long long& nt = r.method == KS_QUADRANT ? p.ntask_q : p.ntask_m;
         if (r.method == KS_MEANSHIFT)
-            while (next_q <= r.xcd) p.xq.begin[next_q++] = nt;
+            while (next_q <= r.xcd) p.xq_begin[next_q++] = nt;
         TaskSeg s = r.s;
         s.task_begin = nt;
         nt += s.count;
         segs.push_back(s);
     }
-    while (next_q <= kXcds) p.xq.begin[next_q++] = p.ntask_m;
+    while (next_q <= kXcds) p.xq_begin[next_q++] = p.ntask_m;
+    p.ms_chunks = std::max(1, std::min(ms_chunks, kMaxMsChunks));
     // Device memory: descriptors, task segments and seed lists in one allocation
     // laid out as the host staging area, so that one copy uploads them; results
     // in one allocation laid out as the host copy, so that one copy downloads
     // them (regions, per-volume region counts, the counter block).
     ks_status st;
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)nvol;
-    // after the descriptors: the mean-shift queue ranges, then the task segments
-    const size_t seg_bytes = sizeof(XcdQueues) + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
+    // after the descriptors: the mean-shift queues of each launch, then the task segments
+    const size_t seg_bytes = sizeof(XcdQueues) * kMaxMsChunks + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     const size_t stage_bytes = vol_bytes + seg_bytes + sizeof(int32_t) * p.seed_ints;
     result_layout((size_t)nvol, regs, &p.out_nf_off, &p.out_cnt_off, &p.out_bytes);
     size_t need[kArenaBuffers];
@@ -537,10 +537,18 @@ ks_status Context::plan(const std::vector<VolIn>& in, Plan& p, const FixedArena*
 ks_status Context::upload(const Plan& p, hipStream_t st) {
     char* h = p.stage;
     const size_t vol_bytes = sizeof(VolDesc) * (size_t)p.nvol;
-    const size_t seg_bytes = sizeof(XcdQueues) + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
+    const size_t seg_bytes = sizeof(XcdQueues) * kMaxMsChunks + sizeof(TaskSeg) * (p.segs_q.size() + p.segs_m.size() + 1);
     std::memcpy(h, p.vols.data(), vol_bytes);
-    std::memcpy(h + vol_bytes, &p.xq, sizeof(XcdQueues));
-    TaskSeg* hs = reinterpret_cast<TaskSeg*>(h + vol_bytes + sizeof(XcdQueues));
+    // launch c takes part c of every XCD queue, in the queue's longest-first order
+    XcdQueues* hq = reinterpret_cast<XcdQueues*>(h + vol_bytes);
+    std::memset(hq, 0, sizeof(XcdQueues) * kMaxMsChunks);
+    for (int c = 0; c < p.ms_chunks; ++c)
+        for (int k = 0; k < kXcds; ++k) {
+            const int64_t b = p.xq_begin[k], n = p.xq_begin[k + 1] - b;
+            hq[c].begin[k] = b + n * c / p.ms_chunks;
+            hq[c].end[k] = b + n * (c + 1) / p.ms_chunks;
+        }
+    TaskSeg* hs = reinterpret_cast<TaskSeg*>(h + vol_bytes + sizeof(XcdQueues) * kMaxMsChunks);
     size_t ns = 0;
     for (const TaskSeg& s : p.segs_q) hs[ns++] = s;
     for (const TaskSeg& s : p.segs_m) hs[ns++] = s;
@@ -573,10 +581,18 @@ static hipError_t mark(hipEvent_t ev, hipStream_t st) {
     return hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies);
 }
 
+// The second stream of two-method calls, created on first use: streams share
+// the device's few hardware queues round robin, so a context that never runs
+// both methods at once takes none.
+hipError_t Context::ensure_aux() {
+    return aux ? hipSuccess : hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+}
+
 ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed) {
     VolDesc* dv = reinterpret_cast<VolDesc*>(p.dev[kArVols]);
     const XcdQueues* dxq = reinterpret_cast<const XcdQueues*>(p.dev[kArVols] + sizeof(VolDesc) * (size_t)p.nvol);
-    TaskSeg* ds = reinterpret_cast<TaskSeg*>(p.dev[kArVols] + sizeof(VolDesc) * (size_t)p.nvol + sizeof(XcdQueues));
+    TaskSeg* ds = reinterpret_cast<TaskSeg*>(p.dev[kArVols] + sizeof(VolDesc) * (size_t)p.nvol +
+                                             sizeof(XcdQueues) * kMaxMsChunks);
     Counters* dc = p.cnt;
     TrajRec* rec = reinterpret_cast<TrajRec*>(p.dev[kArRec]);
     if (timed) KS_HIP(mark(ev[0], st));
@@ -594,6 +610,7 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
     // with both methods and overlap on, the mean-shift search runs on the aux stream
     // beside the quadrant search, so that each fills the other's tail
     const bool fork = p.ntask_q > 0 && p.ntask_m > 0 && overlap;
+    if (fork) KS_HIP(ensure_aux());
     hipStream_t sm_st = fork ? aux : st;
     if (fork) {
         KS_HIP(hipEventRecord(fork_ev, st));
@@ -617,7 +634,8 @@ ks_status Context::enqueue_search(const Plan& p, hipStream_t st, bool with_rank,
         tune.group = p.ms_group;
         tune.pad = 0;
         if (timed) KS_HIP(mark(ev[4], sm_st));
-        KS_HIP(launch_search_ms(sm, dxq, (int)g, tune, p.ms_hist_words, p.maxB_ms, sm_st));
+        for (int c = 0; c < p.ms_chunks; ++c)
+            KS_HIP(launch_search_ms(sm, dxq + c, c, (int)g, tune, p.ms_hist_words, p.maxB_ms, sm_st));
         if (timed) KS_HIP(mark(ev[5], sm_st));
     }
     if (fork) {
@@ -734,6 +752,7 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
     key.push_back(quad_rq_pref);
     key.push_back(overlap ? 1 : 0);
     key.push_back(p.ms_group);
+    key.push_back(p.ms_chunks);
     for (const VolIn& v : in) {
         key.push_back((int64_t)(intptr_t)v.raw);
         key.push_back(v.dtype); key.push_back(v.dims[0]); key.push_back(v.dims[1]); key.push_back(v.dims[2]);
@@ -745,6 +764,8 @@ ks_status Context::detect_batch_graph(const std::vector<VolIn>& in, hipStream_t 
         key.push_back(hb); key.push_back(yb); key.push_back(v.opt.rank_by);
         key.push_back(v.seeds ? v.n_seeds : -1);
     }
+    // the second stream of a two-method batch exists before the capture starts
+    if (p.ntask_q > 0 && p.ntask_m > 0 && overlap) KS_HIP(ensure_aux());
     hipGraphExec_t exec = nullptr;
     for (const GraphEntry& g : graphs)
         if (g.key == key) exec = g.exec;
@@ -943,6 +964,12 @@ ks_status ks_context_set_ms_update(ks_context* ctx, int32_t incremental_pct) {
 ks_status ks_context_set_ms_group(ks_context* ctx, int32_t scales_per_task) {
     if (!ctx || scales_per_task < 0 || scales_per_task > 8) return KS_E_INVALID;
     ctx->ms_group = scales_per_task;
+    return KS_OK;
+}
+
+ks_status ks_context_set_ms_chunks(ks_context* ctx, int32_t launches) {
+    if (!ctx || launches < 1 || launches > kMaxMsChunks) return KS_E_INVALID;
+    ctx->ms_chunks = launches;
     return KS_OK;
 }
 

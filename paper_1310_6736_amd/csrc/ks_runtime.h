@@ -73,7 +73,8 @@ struct Plan {
     std::vector<VolDesc> vols;
     std::vector<TaskSeg> segs_q, segs_m;
     long long ntask_q = 0, ntask_m = 0;
-    XcdQueues xq{};                  // the mean-shift tasks' queue ranges
+    int64_t xq_begin[kXcds + 1] = {};  // the mean-shift tasks of XCD k's queue: xq_begin[k] .. xq_begin[k + 1] - 1
+    int ms_chunks = 1;                 // launches the mean-shift search is split into
     long long total_traj = 0, total_regions = 0, max_traj = 0, max_voxels = 0, max_words = 0;
     int max_tx = 0, max_ty = 0, max_z = 0;  // mean-shift volumes: 64-voxel x, y tiles and Z
     unsigned long long n_pad = 2;
@@ -111,6 +112,7 @@ struct Context {
     std::vector<int32_t> seeds;
     int quad_rq_pref = 0;
     int grid_pct = 100;     // persistent grid size, percent of the resident capacity
+    int ms_chunks = 1;      // launches per mean-shift search (1..kMaxMsChunks)
     int generation = 0;
     Tables tables{};
     Buffer tables_buf, d_vols, d_abm, d_bins, d_rec, d_sr, d_bsum, d_volint, d_regions, d_hook,
@@ -126,6 +128,7 @@ struct Context {
 
     ks_status init(int32_t dev);
     void destroy();
+    hipError_t ensure_aux();
     Buffer& arena(int i);
     // Device bytes the arena holds now, after a plan(in) (buffers only grow), and
     // for `in` alone (freshly allocated).

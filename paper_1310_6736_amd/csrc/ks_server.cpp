@@ -34,7 +34,8 @@ double now_ms() {
 
 struct SrvReq {
     ks::VolIn in;
-    std::vector<uint8_t> host;     // copy of the submitted volume
+    void* host = nullptr;          // pinned copy of the submitted volume (from the server's pool)
+    size_t host_bytes = 0, host_cap = 0;
     size_t footprint = 0;          // device bytes it needs alone, at most
     double work = 0;               // estimated voxel visits
     double t_submit = 0, t_done = 0;
@@ -54,16 +55,61 @@ struct Track {
     std::vector<int32_t> seeds;
 };
 
+// Pinned host buffers for the submitted volumes, reused across requests: a
+// volume is copied once, at submit, and uploaded from there by DMA.  At most
+// kPoolCache bytes of free buffers are kept.
+class PinnedPool {
+  public:
+    static constexpr size_t kPoolCache = (size_t)2 << 30;
+    void* get(size_t bytes, size_t* cap) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.lower_bound(bytes);
+            if (it != free_.end() && it->first <= 2 * bytes + 4096) {
+                void* p = it->second;
+                *cap = it->first;
+                cached_ -= it->first;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, std::max<size_t>(bytes, 1), hipHostMallocDefault) != hipSuccess) return nullptr;
+        *cap = std::max<size_t>(bytes, 1);
+        return p;
+    }
+    void put(void* p, size_t cap) {
+        if (!p) return;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (cached_ + cap <= kPoolCache) {
+                free_.emplace(cap, p);
+                cached_ += cap;
+                return;
+            }
+        }
+        hipHostFree(p);
+    }
+    ~PinnedPool() {
+        for (auto& f : free_) hipHostFree(f.second);
+    }
+
+  private:
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    size_t cached_ = 0;
+};
+
 struct Slot {
     ks::Context ctx;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     ks::Buffer raw;                // device copies of the batch's volumes
-    ks::PinnedBuffer staging;      // pinned copies for the uploads
     std::vector<uint64_t> tickets;
     std::vector<ks::VolIn> in;
     ks::Plan plan;
     bool busy = false;
+    bool large = false;            // the batch is one large request
     // device bytes held for requests: the context's per-call arena and the volumes
     size_t held() { return ctx.arena_held() + raw.cap; }
     void release() {
@@ -91,6 +137,7 @@ struct ks_server {
     std::map<uint64_t, SrvReq> reqs;
     std::map<int64_t, Track> tracks;
     std::vector<Slot*> slots;
+    PinnedPool pool;
     size_t in_use = 0, peak = 0;   // device bytes the slots hold for requests
     int64_t submitted = 0, admitted = 0, completed = 0, refused = 0, in_flight = 0;
     double first_submit = -1, last_done = 0;
@@ -157,6 +204,14 @@ static void hand_over(Track& tr, const SrvReq& r) {
 
 // Work of one batch: about 10 ms of device time at the measured visit rates.
 constexpr double kBatchWork = 2.0e10;
+// A request above this estimated work (the MR-like volumes: a full-size mean-
+// shift search) is large: large requests run one at a time, each alone in its
+// batch, so that one is not slowed by another, while small requests pass them
+// in the queue and run beside them.  (Splitting the large search into several
+// launches, or giving it or the small batches beside it a part of the device,
+// measured no better at any load: the small requests gained what the large
+// ones lost.)
+constexpr double kLargeWork = 3.0e10;
 
 // One scheduler step; returns true if it did any work.
 bool ks_server::tick() {
@@ -185,8 +240,8 @@ bool ks_server::tick() {
             }
             if (r.track >= 0) hand_over(tracks[r.track], r);
             r.t_done = t;
-            r.host.clear();
-            r.host.shrink_to_fit();
+            pool.put(r.host, r.host_cap);
+            r.host = nullptr;
             latencies.push_back(t - r.t_submit);
             completed += 1;
             in_flight -= 1;
@@ -205,11 +260,16 @@ bool ks_server::tick() {
         if (!sl->busy) { free_slot = sl; break; }
     if (!free_slot) return worked;
     size_t busy_bytes = 0;
+    bool large_running = false;
     for (Slot* sl : slots)
-        if (sl->busy) busy_bytes += sl->held();
+        if (sl->busy) {
+            busy_bytes += sl->held();
+            large_running = large_running || sl->large;
+        }
     std::vector<uint64_t> take;
     std::vector<ks::VolIn> batch;
     size_t raw_bytes = 0;
+    bool large = false;
     {
         std::lock_guard<std::mutex> lk(mu);
         double work = 0;
@@ -217,6 +277,13 @@ bool ks_server::tick() {
             SrvReq& r = reqs[*it];
             // a tracked frame waits for the frame before it; others pass it
             if (r.track >= 0 && tracks[r.track].busy) {
+                ++it;
+                continue;
+            }
+            // a large request waits while another runs, and goes alone; small
+            // requests pass it meanwhile
+            const bool big = r.work > kLargeWork;
+            if (big && (large_running || !take.empty())) {
                 ++it;
                 continue;
             }
@@ -230,7 +297,7 @@ bool ks_server::tick() {
                 v.n_seeds = (int64_t)list->size() / 3;
             }
             batch.push_back(v);
-            const size_t rb = raw_bytes + ((r.host.size() + 255) & ~(size_t)255);
+            const size_t rb = raw_bytes + ((r.host_bytes + 255) & ~(size_t)255);
             if (busy_bytes + ks::Context::arena_fresh(batch) + ks::granule(rb) > budget) {
                 batch.pop_back();
                 break;   // oldest first: no overtaking
@@ -248,6 +315,10 @@ bool ks_server::tick() {
             }
             take.push_back(*it);
             it = pending.erase(it);
+            if (big) {
+                large = true;
+                break;
+            }
         }
         admitted += (int64_t)take.size();
         in_flight += (int64_t)take.size();
@@ -274,6 +345,7 @@ bool ks_server::tick() {
     }
     if (total_after() > budget) sl->release();
     sl->busy = true;
+    sl->large = large;
     sl->tickets = take;
     sl->in.clear();
     size_t raw_total = 0;
@@ -282,24 +354,23 @@ bool ks_server::tick() {
         std::lock_guard<std::mutex> lk(mu);
         for (uint64_t t : take) {
             offs.push_back(raw_total);
-            raw_total += (reqs[t].host.size() + 255) & ~(size_t)255;
+            raw_total += (reqs[t].host_bytes + 255) & ~(size_t)255;
         }
     }
     ks_status st = sl->raw.ensure(std::max<size_t>(raw_total, 256), nullptr);
-    if (st == KS_OK) st = sl->staging.ensure(std::max<size_t>(raw_total, 256));
     if (st == KS_OK) {
         std::lock_guard<std::mutex> lk(mu);
-        for (size_t i = 0; i < take.size(); ++i) {
+        for (size_t i = 0; i < take.size() && st == KS_OK; ++i) {
             SrvReq& r = reqs[take[i]];
-            std::memcpy(static_cast<char*>(sl->staging.ptr) + offs[i], r.host.data(), r.host.size());
+            char* dst = static_cast<char*>(sl->raw.ptr) + offs[i];
+            // from the request's pinned copy straight to the device
+            if (hipMemcpyAsync(dst, r.host, r.host_bytes, hipMemcpyHostToDevice, sl->stream) != hipSuccess)
+                st = KS_E_DEVICE;
             ks::VolIn v = r.in;
-            v.raw = static_cast<char*>(sl->raw.ptr) + offs[i];
+            v.raw = dst;
             sl->in.push_back(v);
         }
     }
-    if (st == KS_OK && hipMemcpyAsync(sl->raw.ptr, sl->staging.ptr, raw_total, hipMemcpyHostToDevice, sl->stream) !=
-                           hipSuccess)
-        st = KS_E_DEVICE;
     if (st == KS_OK) st = sl->ctx.begin_detect(sl->in, sl->stream, sl->plan);
     if (st == KS_OK && hipEventRecord(sl->done, sl->stream) != hipSuccess) st = KS_E_DEVICE;
     account();
@@ -315,6 +386,13 @@ bool ks_server::tick() {
         }
         sl->busy = false;
         if (st == KS_E_DEVICE) fatal = st;
+        // the pinned copies go back to the pool once the stream no longer reads them
+        hipStreamSynchronize(sl->stream);
+        for (uint64_t t : take) {
+            SrvReq& r = reqs[t];
+            pool.put(r.host, r.host_cap);
+            r.host = nullptr;
+        }
         done_cv.notify_all();
     }
     return true;
@@ -338,12 +416,14 @@ void ks_server::run() {
         // blocks of the launch before it retire, so the device never runs a
         // partial grid once the other slots have drained
         st = sl->ctx.init(device);
-        sl->ctx.arena_exact(true);
-        sl->raw.exact = true;
-        if (st == KS_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) st = KS_E_DEVICE;
         if (st == KS_OK && hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) st = KS_E_DEVICE;
         slots.push_back(sl);
     }
+    // the slots' streams one after another: streams take the device's hardware
+    // queues round robin, so consecutive ones land on different queues and one
+    // slot's work does not wait behind another's
+    for (Slot* sl : slots)
+        if (st == KS_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) st = KS_E_DEVICE;
     {
         std::lock_guard<std::mutex> lk(mu);
         init_status = st;
@@ -396,6 +476,7 @@ ks_status ks_server::submit(const ks_request* req, int64_t track, int32_t max_se
                                      req->method, req->max_iter);
     if (st != KS_OK) return st;
     if (!ks::options_ok(req->options) || !ks::options_fit(req->options, req->bins)) return KS_E_INVALID;
+    if (req->max_regions < 0) return KS_E_INVALID;
     const bool own = req->seeds || req->n_seeds;
     if (own && (st = ks::check_seeds(req->dims, req->scales, req->method, req->seeds, req->n_seeds)) != KS_OK)
         return st;
@@ -419,7 +500,10 @@ ks_status ks_server::submit(const ks_request* req, int64_t track, int32_t max_se
     int64_t n_start = own ? req->n_seeds
                           : ks::num_trajectories(req->dims, req->seed_spacing, req->scales, KS_QUADRANT);
     if (track >= 0) n_start = std::max<int64_t>(n_start, max_seeds);
-    r.in.capacity = (int32_t)std::min<int64_t>(std::max<int64_t>(n_start * per, 1), 1 << 20);
+    // every region it can find, or the top max_regions of them
+    int64_t cap = std::min<int64_t>(std::max<int64_t>(n_start * per, 1), 1 << 20);
+    if (req->max_regions > 0) cap = std::min<int64_t>(cap, req->max_regions);
+    r.in.capacity = (int32_t)cap;
     const size_t esz = req->dtype == KS_U8 ? 1 : 2;
     const size_t bytes = esz * (size_t)req->dims[0] * req->dims[1] * req->dims[2];
     {
@@ -438,7 +522,10 @@ ks_status ks_server::submit(const ks_request* req, int64_t track, int32_t max_se
         return KS_E_TOO_LARGE;
     }
     lk.unlock();
-    r.host.assign(static_cast<const uint8_t*>(req->volume), static_cast<const uint8_t*>(req->volume) + bytes);
+    r.host = s->pool.get(bytes, &r.host_cap);
+    if (!r.host) return KS_E_NOMEM;
+    r.host_bytes = bytes;
+    std::memcpy(r.host, req->volume, bytes);
     lk.lock();
     r.t_submit = now_ms();
     if (s->first_submit < 0) s->first_submit = r.t_submit;
@@ -537,11 +624,12 @@ ks_status ks_server_destroy(ks_server* s) {
         if (sl->stream) hipStreamSynchronize(sl->stream);
         sl->ctx.destroy();
         sl->raw.release();
-        sl->staging.release();
         if (sl->done) hipEventDestroy(sl->done);
         if (sl->stream) hipStreamDestroy(sl->stream);
         delete sl;
     }
+    // volumes of requests that never ran
+    for (auto& kv : s->reqs) s->pool.put(kv.second.host, kv.second.host_cap);
     delete s;
     return KS_OK;
 }

@@ -28,7 +28,7 @@ EXPORTS = [
     "ks_server_stats", "ks_server_reset_stats", "ks_server_destroy", "ks_roofline", "ks_context_set_tuning_small",
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
     "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap", "ks_context_autotune",
-    "ks_context_set_ms_group", "ks_count_roots", "ks_detect_device_noalloc",
+    "ks_context_set_ms_group", "ks_count_roots", "ks_detect_device_noalloc", "ks_context_set_ms_chunks",
 ]
 
 
@@ -84,7 +84,7 @@ class Request(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("dtype", C.c_int32), ("dims", C.c_int32 * 3), ("bins", C.c_int32),
                 ("seed_spacing", C.c_int32), ("scales", C.c_int32 * 2), ("method", C.c_int32),
                 ("max_iter", C.c_int32), ("options", Options), ("seeds", C.POINTER(C.c_int32)),
-                ("n_seeds", C.c_int64)]
+                ("n_seeds", C.c_int64), ("max_regions", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -134,6 +134,7 @@ def lib():
     L.ks_context_set_seeds.argtypes = [vp, i32p, C.c_int64]
     L.ks_context_set_overlap.argtypes = [vp, i32]
     L.ks_context_set_ms_group.argtypes = [vp, i32]
+    L.ks_context_set_ms_chunks.argtypes = [vp, i32]
     L.ks_context_autotune.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, i32, i32p, vp]
     L.ks_abmsod.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, C.c_double, vp, i32, i32p, vp]
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
@@ -306,6 +307,10 @@ def ks_context_autotune(ctx: Context, volume, bins, seed_spacing, scales, method
 
 def ks_context_set_ms_group(ctx: Context, scales_per_task: int = 0):
     _check(lib().ks_context_set_ms_group(ctx.handle, int(scales_per_task)), "ks_context_set_ms_group")
+
+
+def ks_context_set_ms_chunks(ctx: Context, launches: int = 1):
+    _check(lib().ks_context_set_ms_chunks(ctx.handle, int(launches)), "ks_context_set_ms_chunks")
 
 
 def ks_context_set_overlap(ctx: Context, on: bool):
@@ -489,18 +494,23 @@ class Server:
         _check(lib().ks_server_create(int(device), C.c_size_t(int(hbm_budget)), int(max_slots), C.byref(h)),
                "ks_server_create")
         self.handle = h
+        self._limit = {}  # ticket -> max_regions of its request (0: none)
 
     def submit(self, volume: np.ndarray, bins, seed_spacing, scales, method, max_iter, opts=None, seeds=None,
-               track=None, max_seeds=32) -> int:
+               track=None, max_seeds=32, max_regions=0) -> int:
         """Queues a host volume; with track = an int id the request is a frame of
-        that tracked sequence (started from the previous frame's regions)."""
+        that tracked sequence (started from the previous frame's regions);
+        max_regions > 0 keeps only that many top regions for the poll."""
         r = make_request(volume, bins, seed_spacing, scales, method, max_iter, host=True, opts=opts, seeds=seeds)
+        r.max_regions = int(max_regions)
         t = C.c_uint64()
         if track is None:
             _check(lib().ks_server_submit(self.handle, C.byref(r), C.byref(t)), "ks_server_submit")
         else:
             _check(lib().ks_server_submit_tracked(self.handle, C.byref(r), int(track), int(max_seeds), C.byref(t)),
                    "ks_server_submit_tracked")
+        if max_regions:
+            self._limit[t.value] = int(max_regions)
         return t.value
 
     def poll(self, ticket: int, capacity=1024):
@@ -510,7 +520,9 @@ class Server:
         if st == KS_E_NOT_READY:
             return None
         _check(st, "ks_server_poll")
-        return _regions(buf, nf.value, capacity), nf.value
+        limit = self._limit.pop(ticket, 0)
+        written = min(nf.value, capacity, limit) if limit else min(nf.value, capacity)
+        return _regions(buf, written, capacity), nf.value
 
     def drain(self):
         _check(lib().ks_server_drain(self.handle), "ks_server_drain")

@@ -245,6 +245,35 @@ def test_server_budget_bounds_the_device_memory_of_its_slots(torch_dev, ctx):
         assert same_regions(res, alone[w.name]), w.name
 
 
+def test_server_large_request_among_small_ones(torch_dev, ctx):
+    """An MR-like request (large: run alone, its search in several launches)
+    submitted between small ones, and a second one right after it: every result
+    equals the volume run alone."""
+    big = synth.mr_blobs()
+    ws = small_mix()[:3] + [big] + small_mix()[3:6] + [big] + small_mix()[6:]
+    note("server: large requests among small ones")
+    srv = ks.Server(0, hbm_budget=4 << 30, max_slots=4)
+    try:
+        # the second large request keeps only its top 100 regions
+        tickets = [(w, i, srv.submit(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter,
+                                     max_regions=100 if i == 7 else 0)) for i, w in enumerate(ws)]
+        srv.drain()
+        got = [(w, i, srv.poll(t, capacity=4096)) for w, i, t in tickets]
+    finally:
+        srv.close()
+    alone = {}
+    for w, i, res in got:
+        if w.name not in alone:
+            v = torch_dev.from_numpy(w.volume).to("cuda:0")
+            alone[w.name] = ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter,
+                                                capacity=4096)
+        if i == 7:
+            # the total found, and the top 100 in rank order
+            assert res[1] == alone[w.name][1] and np.array_equal(res[0], alone[w.name][0][:100]), w.name
+        else:
+            assert same_regions(res, alone[w.name]), w.name
+
+
 def moving_frames(n, seed, shape=(36, 40, 44)):
     """A textured sphere in noise moving 2 voxels per frame along x and 1 along y."""
     Z, Y, X = shape

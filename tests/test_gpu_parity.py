@@ -893,3 +893,29 @@ def test_device_count_roots_equal_host_for_every_window_count(torch_dev, ctx):
     assert np.array_equal(rs.view(np.uint64), want_rs.view(np.uint64))
     with pytest.raises(ks.KsError):
         ks.ks_count_roots(ctx, 0)
+
+
+def test_meanshift_search_in_several_launches(torch_dev, ctx):
+    """The mean-shift search split into several launches (each a share of every
+    queue's tasks) gives the same traces and detection as one launch, through the
+    direct launch sequence and the captured graph."""
+    w = synth.pet_shell(ks.KS_MEANSHIFT)
+    t = dev(torch_dev, w.volume)
+    base_tr = ks.ks_seed_traces(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+    base = ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=100000)
+    try:
+        for n in (2, 3, 8):
+            note(f"mean-shift search in {n} launches")
+            ks.ks_context_set_ms_chunks(ctx, n)
+            tr = ks.ks_seed_traces(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter)
+            assert np.array_equal(tr, base_tr), n
+            got = ks.ks_detect_device(ctx, t, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=100000)
+            assert got[1] == base[1] and np.array_equal(got[0], base[0]), n
+            (bg, bn), = ks.ks_detect_batch(ctx, [ks.make_request(t, w.bins, w.spacing, w.scales, w.method,
+                                                                 w.max_iter)], capacity=100000)
+            assert bn == base[1] and np.array_equal(bg, base[0]), n
+        for bad in (0, 9):
+            with pytest.raises(ks.KsError):
+                ks.ks_context_set_ms_chunks(ctx, bad)
+    finally:
+        ks.ks_context_set_ms_chunks(ctx, 1)
