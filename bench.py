@@ -64,20 +64,27 @@ def parse():
 
 def batch_section(ks, torch, ctx):
     """The 64-volume uneven batch: one ks_detect_batch (captured graph, replayed)
-    against one ks_detect_device per volume, same volumes, same results."""
+    against one ks_detect_device per volume, same volumes, same results; the
+    batch with the context's default shapes and with the shapes
+    ks_context_autotune_batch picks for it (on a context of its own)."""
     from paper_1310_6736_amd import synth
 
     ws = synth.batch_workloads()
     vols = [torch.from_numpy(w.volume).to("cuda:0") for w in ws]
+    torch.cuda.synchronize()
     reqs = [ks.make_request(v, w.bins, w.spacing, w.scales, w.method, w.max_iter) for v, w in zip(vols, ws)]
     cap = 256
-    ks.ks_detect_batch(ctx, reqs, capacity=cap)  # capture
-    torch.cuda.synchronize()
     reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        res_b = ks.ks_detect_batch(ctx, reqs, capacity=cap)
-    tb = (time.perf_counter() - t0) / reps
+
+    def timed_batch(c):
+        ks.ks_detect_batch(c, reqs, capacity=cap)  # capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = ks.ks_detect_batch(c, reqs, capacity=cap)
+        return (time.perf_counter() - t0) / reps, res
+
+    tb, res_b = timed_batch(ctx)
     for v, w in zip(vols, ws):  # warm
         ks.ks_detect_device(ctx, v, w.bins, w.spacing, w.scales, w.method, w.max_iter, capacity=cap)
     torch.cuda.synchronize()
@@ -88,10 +95,22 @@ def batch_section(ks, torch, ctx):
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t0) / reps
     same = all(a[1] == b[1] and np.array_equal(a[0], b[0]) for a, b in zip(res_b, res_p))
+    tctx = ks.Context(0)
+    t0 = time.perf_counter()
+    tuning = ks.ks_context_autotune_batch(tctx, reqs, reps=2)
+    tune_s = time.perf_counter() - t0
+    ta, res_a = timed_batch(tctx)
+    same_a = all(a[1] == b[1] and np.array_equal(a[0], b[0]) for a, b in zip(res_a, res_p))
+    tctx.close()
     return {"workload": "64 volumes, x,y in 64..192, z in 64..128, types 50/30/20 (spheres u8 / PET-like u16 / "
                         "MR-like i16), per-type bins, spacing, scales and method",
-            "batched_volumes_per_s": len(ws) / tb, "plain_volumes_per_s": len(ws) / tp,
-            "batched_ms": tb * 1e3, "plain_ms": tp * 1e3, "speedup": tp / tb, "identical_results": bool(same)}
+            "batched_volumes_per_s": len(ws) / ta, "plain_volumes_per_s": len(ws) / tp,
+            "batched_ms": ta * 1e3, "plain_ms": tp * 1e3, "speedup": tp / ta,
+            "identical_results": bool(same and same_a),
+            "autotuned": {"tuning": dict(zip(("ms_replicas_log2", "ms_small_replicas_log2", "s_small",
+                                               "quad_replicas_log2", "ms_scales_per_task"), tuning)),
+                          "tuning_seconds": tune_s, "batched_ms": ta * 1e3},
+            "default_shapes": {"batched_volumes_per_s": len(ws) / tb, "batched_ms": tb * 1e3}}
 
 
 def _stream_volume(job):

@@ -412,6 +412,22 @@ typedef struct {
  * Returns when the results are in `results`. */
 ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks_result* results, void* stream);
 
+/* Autotuning for a batch (the shapes the batch's captured launch sequence
+ * uses): runs ks_detect_batch's launch sequence over the n requests under
+ * candidate tunings and keeps, in the context, the fastest by device time of
+ * the whole sequence (prep, searches, ranking), one parameter at a time:
+ * mean-shift replicas per wave for large windows (2^3..2^5) and for small ones
+ * (2^2..2^3), the small-window half-width bound (4, 6, 8), the scales per
+ * mean-shift task (0 = by the task count, 1..4), then the quadrant replicas per
+ * workgroup (2^0..2^2, as the LDS budget allows).  Each candidate is timed reps
+ * times (1..16) after one warm-up and scored by its fastest run.  Results do
+ * not depend on the tuning.  out: NULL or the chosen {ms_replicas_log2,
+ * ms_small_replicas_log2, s_small, quad_replicas_log2, ms_scales_per_task}.
+ * KS_E_INVALID for n < 1, a null request list or reps outside 1..16, and as
+ * ks_detect_batch for the requests. */
+ks_status ks_context_autotune_batch(ks_context* ctx, int32_t n, const ks_request* reqs, int32_t reps, int32_t out[5],
+                                    void* stream);
+
 /* ------------------------------------------------------------- measurement */
 
 /* Roofline microbenchmarks behind the reported fractions (for callers measuring

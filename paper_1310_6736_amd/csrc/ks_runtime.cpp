@@ -1376,19 +1376,20 @@ ks_status ks_count_roots(ks_context* ctx, int32_t n, double* sq, double* rsq, vo
     return KS_OK;
 }
 
-ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks_result* results, void* stream) {
-    if (!ctx || n < 0 || (n > 0 && (!reqs || !results))) return KS_E_INVALID;
-    std::vector<VolIn> in((size_t)n);
+// The batch requests as runtime volumes (capacity: of each result, or 1).
+static ks_status batch_volumes(int32_t n, const ks_request* reqs, const ks_result* results, std::vector<VolIn>& in) {
+    in.assign((size_t)n, VolIn{});
     for (int i = 0; i < n; ++i) {
         const ks_request& r = reqs[i];
         ks_status s = check_request(r.volume, r.dtype, r.dims, r.bins, r.seed_spacing, r.scales, r.method, r.max_iter);
         if (s != KS_OK) return s;
-        if (results[i].capacity < 0 || (results[i].capacity > 0 && !results[i].regions)) return KS_E_INVALID;
+        if (results && (results[i].capacity < 0 || (results[i].capacity > 0 && !results[i].regions)))
+            return KS_E_INVALID;
         if (!options_ok(r.options) || !options_fit(r.options, r.bins)) return KS_E_INVALID;
         VolIn& v = in[(size_t)i];
         v.raw = r.volume; v.dtype = r.dtype; std::memcpy(v.dims, r.dims, sizeof(v.dims)); v.bins = r.bins;
         v.spacing = r.seed_spacing; v.scales[0] = r.scales[0]; v.scales[1] = r.scales[1]; v.method = r.method;
-        v.max_iter = r.max_iter; v.capacity = results[i].capacity;
+        v.max_iter = r.max_iter; v.capacity = results ? results[i].capacity : 1;
         v.opt = r.options;
         if (r.seeds || r.n_seeds) {
             if ((s = check_seeds(r.dims, r.scales, r.method, r.seeds, r.n_seeds)) != KS_OK) return s;
@@ -1396,6 +1397,79 @@ ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks
             v.n_seeds = r.n_seeds;
         }
     }
+    return KS_OK;
+}
+
+ks_status ks_context_autotune_batch(ks_context* ctx, int32_t n, const ks_request* reqs, int32_t reps, int32_t out[5],
+                                    void* stream) {
+    if (!ctx || n < 1 || !reqs || reps < 1 || reps > 16) return KS_E_INVALID;
+    std::vector<VolIn> in;
+    ks_status s = batch_volumes(n, reqs, nullptr, in);
+    if (s != KS_OK) return s;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool prof = ctx->profiling;
+    ctx->profiling = true;
+    // device time of the batch's launch sequence (prep, searches, ranking) under
+    // the context's current tuning: the fastest of reps runs after a warm-up
+    auto measure = [&](double* best) -> ks_status {
+        std::vector<std::vector<ks_region>> res;
+        std::vector<int> nf;
+        *best = 1e30;
+        for (int r = 0; r <= reps; ++r) {
+            ks_status e = ctx->detect_volumes(in, st, &res, &nf);
+            if (e != KS_OK) return e;
+            if (r > 0 && ctx->last.ms_total < *best) *best = ctx->last.ms_total;
+        }
+        return KS_OK;
+    };
+    bool has_ms = false, has_q = false;
+    int maxS_q = 1, maxB_q = 2;
+    for (const VolIn& v : in) {
+        if (v.method == KS_MEANSHIFT) has_ms = true;
+        else {
+            has_q = true;
+            maxS_q = std::max(maxS_q, v.scales[1] - v.scales[0] + 1);
+            maxB_q = std::max(maxB_q, v.bins);
+        }
+    }
+    // one parameter at a time, each kept at its best before the next
+    double best = 1e30, t;
+    auto tryv = [&](int* knob, int value) {
+        if (s != KS_OK) return;
+        const int old = *knob;
+        *knob = value;
+        if ((s = measure(&t)) != KS_OK) return;
+        if (t < best) best = t;
+        else *knob = old;
+    };
+    s = measure(&best);
+    if (has_ms) {
+        const int base_rl = ctx->ms_rl_pref, base_rls = ctx->ms_rl_small_pref, base_ss = ctx->ms_s_small;
+        for (int rl = 3; rl <= 5; ++rl) if (rl != base_rl) tryv(&ctx->ms_rl_pref, rl);
+        for (int rls = 2; rls <= 3; ++rls) if (rls != base_rls) tryv(&ctx->ms_rl_small_pref, rls);
+        for (int ss = 4; ss <= 8; ss += 2) if (ss != base_ss) tryv(&ctx->ms_s_small, ss);
+        const int base_g = ctx->ms_group;
+        for (int g = 0; g <= 4; ++g) if (g != base_g) tryv(&ctx->ms_group, g);
+    }
+    if (has_q) {
+        const int base_rq = ctx->quad_rq_pref;
+        for (int rq = 0; rq <= 2; ++rq)
+            if (rq != base_rq && pick_quad_rq(maxS_q, maxB_q, rq) == rq) tryv(&ctx->quad_rq_pref, rq);
+    }
+    ctx->profiling = prof;
+    if (s != KS_OK) return s;
+    if (out) {
+        out[0] = ctx->ms_rl_pref; out[1] = ctx->ms_rl_small_pref; out[2] = ctx->ms_s_small; out[3] = ctx->quad_rq_pref;
+        out[4] = ctx->ms_group;
+    }
+    return KS_OK;
+}
+
+ks_status ks_detect_batch(ks_context* ctx, int32_t n, const ks_request* reqs, ks_result* results, void* stream) {
+    if (!ctx || n < 0 || (n > 0 && (!reqs || !results))) return KS_E_INVALID;
+    std::vector<VolIn> in;
+    ks_status bs = batch_volumes(n, reqs, results, in);
+    if (bs != KS_OK) return bs;
     if (n == 0) return KS_OK;
     std::vector<std::vector<ks_region>> res;
     std::vector<int> nf;

@@ -29,6 +29,7 @@ EXPORTS = [
     "ks_context_set_ms_update", "ks_context_set_options", "ks_saliency_map", "ks_context_set_seeds",
     "ks_server_submit_tracked", "ks_abmsod", "ks_context_set_overlap", "ks_context_autotune",
     "ks_context_set_ms_group", "ks_count_roots", "ks_detect_device_noalloc", "ks_context_set_ms_chunks",
+    "ks_context_autotune_batch",
 ]
 
 
@@ -135,6 +136,7 @@ def lib():
     L.ks_context_set_overlap.argtypes = [vp, i32]
     L.ks_context_set_ms_group.argtypes = [vp, i32]
     L.ks_context_set_ms_chunks.argtypes = [vp, i32]
+    L.ks_context_autotune_batch.argtypes = [vp, i32, C.POINTER(Request), i32, i32p, vp]
     L.ks_context_autotune.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, i32, i32, i32p, vp]
     L.ks_abmsod.argtypes = [vp, vp, i32, i32p, i32, i32, i32p, i32, C.c_double, vp, i32, i32p, vp]
     L.ks_server_poll.argtypes = [vp, C.c_uint64, vp, i32, i32p]
@@ -474,6 +476,17 @@ def ks_detect_batch(ctx: Context, requests, capacity=1024, stream=None):
         res[i].capacity = int(capacity)
     _check(lib().ks_detect_batch(ctx.handle, n, reqs, res, _stream_ptr(stream)), "ks_detect_batch")
     return [(_regions(bufs[i][0], res[i].n_found, capacity), res[i].n_found) for i in range(n)]
+
+
+def ks_context_autotune_batch(ctx: Context, requests, reps=2, stream=None):
+    """Tunes the context for this batch; returns the chosen (ms_replicas_log2,
+    ms_small_replicas_log2, s_small, quad_replicas_log2, ms_scales_per_task)."""
+    n = len(requests)
+    reqs = (Request * max(n, 1))(*requests)
+    out = (C.c_int32 * 5)()
+    _check(lib().ks_context_autotune_batch(ctx.handle, n, reqs, int(reps), out, _stream_ptr(stream)),
+           "ks_context_autotune_batch")
+    return tuple(out)
 
 
 KS_ROOF_COPY, KS_ROOF_LDS_ADD64, KS_ROOF_LDS_ADD32, KS_ROOF_LDS_ADD64_SHARED4 = 0, 1, 2, 3

@@ -392,3 +392,26 @@ def test_batch_window_levels_and_scale_groups_match_oracle(torch_dev, ctx):
         for f in ("x", "y", "z", "scale", "seed"):
             assert np.array_equal(got[f], want[f]), (name, f)
         assert np.allclose(got["saliency"], want["saliency"], rtol=1e-5, atol=0), name
+
+
+def test_batch_autotune_keeps_results(torch_dev):
+    """The batch autotuner picks shapes within their ranges, and the batch run
+    with them equals the batch with the default shapes."""
+    ws = small_mix()
+    vols = [torch_dev.from_numpy(w.volume).to("cuda:0") for w in ws]
+    reqs = [ks.make_request(v, w.bins, w.spacing, w.scales, w.method, w.max_iter) for v, w in zip(vols, ws)]
+    note("batch autotune")
+    base_ctx = ks.Context(0)
+    ctx = ks.Context(0)
+    try:
+        base = ks.ks_detect_batch(base_ctx, reqs, capacity=4096)
+        t = ks.ks_context_autotune_batch(ctx, reqs, reps=1)
+        assert 3 <= t[0] <= 5 and 2 <= t[1] <= 3 and t[2] in (4, 6, 8) and 0 <= t[3] <= 2 and 0 <= t[4] <= 4, t
+        got = ks.ks_detect_batch(ctx, reqs, capacity=4096)
+        for i, (a, b) in enumerate(zip(base, got)):
+            assert same_regions(a, b), i
+        with pytest.raises(ks.KsError):
+            ks.ks_context_autotune_batch(ctx, reqs, reps=0)
+    finally:
+        ctx.close()
+        base_ctx.close()
