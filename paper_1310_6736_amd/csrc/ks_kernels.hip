@@ -187,9 +187,28 @@ __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int
     w.ps = L.slab * (uint32_t)sstep;
     const int da = fa >> 2;
     w.nd = (fb >> 2) - da + 1;
-    w.ty = min(w.ny, uniform(small_div(NT, w.nd)));
+    const int rmax = uniform(small_div(NT, w.nd));  // rows one step can take
+    w.ty = min(w.ny, rmax);
+    w.tz = min(w.nz, uniform(small_div(rmax, w.ty)));
+    if (NT > 64) {
+        // a workgroup's tile: the ty x tz with ty * tz <= rmax that takes the
+        // fewest steps ceil(ny / ty) * ceil(nz / tz) (ty = min(ny, rmax) alone
+        // leaves most lanes idle in the last row tile of a box a little taller
+        // than rmax)
+        int best = small_div(w.ny + w.ty - 1, w.ty) * small_div(w.nz + w.tz - 1, w.tz);
+        for (int tz = 2; tz <= min(w.nz, rmax); ++tz) {
+            const int ty = min(w.ny, small_div(rmax, tz));
+            const int st = small_div(w.ny + ty - 1, ty) * small_div(w.nz + tz - 1, tz);
+            if (st < best) {
+                best = st;
+                w.ty = ty;
+                w.tz = tz;
+            }
+        }
+        w.ty = uniform(w.ty);
+        w.tz = uniform(w.tz);
+    }
     const int per_z = w.ty * w.nd;
-    w.tz = min(w.nz, uniform(small_div(NT, per_z)));
     w.oz = small_div(tid, per_z);
     const int rem = tid - w.oz * per_z;
     w.oy = small_div(rem, w.nd);
@@ -282,6 +301,11 @@ __device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, uint6
                     }
                 }
                 used += kGroupVoxels;
+            }
+            // with several groups in flight, refilled on every path (past the end
+            // the loads touch no memory), so that the waits on the loads in flight
+            // are the same on all of them
+            if (D > 1 || live) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) load(g, u);
             }
@@ -1091,12 +1115,30 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
 
 // ------------------------------------------------ quadrant: bucketed scatter
 
+// Adds the lane's four voxels (LDS byte addresses a[0..3]) into their u32
+// counters: voxels that share a counter go in as one add of their number, so
+// lanes of a wave that hit one counter (a flat background bins most voxels of
+// a shell row alike) contend less.  Returns the adds issued.
+__device__ __forceinline__ unsigned int add4_merged(char* hb, const uint32_t* a) {
+    const bool e01 = a[0] == a[1], e02 = a[0] == a[2], e03 = a[0] == a[3];
+    const bool e12 = a[1] == a[2], e13 = a[1] == a[3], e23 = a[2] == a[3];
+    const uint32_t c0 = 1u + (uint32_t)e01 + (uint32_t)e02 + (uint32_t)e03;
+    const uint32_t c1 = 1u + (uint32_t)e12 + (uint32_t)e13;
+    const uint32_t c2 = 1u + (uint32_t)e23;
+    const bool n1 = !e01, n2 = !(e02 || e12), n3 = !(e03 || e13 || e23);
+    atomicAdd(reinterpret_cast<uint32_t*>(hb + a[0]), c0);
+    if (n1) atomicAdd(reinterpret_cast<uint32_t*>(hb + a[1]), c1);
+    if (n2) atomicAdd(reinterpret_cast<uint32_t*>(hb + a[2]), c2);
+    if (n3) atomicAdd(reinterpret_cast<uint32_t*>(hb + a[3]), 1u);
+    return 1u + (uint32_t)n1 + (uint32_t)n2 + (uint32_t)n3;
+}
+
 // Scatter the box into hist (uint32 counters) at byte offset
 //   region + ((row*B + bin) << rq)*4 + replica*4,
 // row = max(max(|x-cx|,|y-cy|,|z-cz|) - base, 0); bytes outside the box go to
 // row trash_row.
 template <int NT>
-__device__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx,
+__device__ __forceinline__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx,
                                        int cy, int cz, int base, int trash_row, int rq, uint32_t region,
                                        uint32_t* hist, int tid) {
     const Layout L = layout_x(v);
@@ -1120,13 +1162,13 @@ __device__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya,
         [&](uint32_t word, int iy0, int iz0, uint64_t) {
             const int rr = max(max(abs(dy0 + iy0), abs(dz0 + iz0)) - base, 0);
             const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
+            uint32_t a[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t b = (word >> (8 * k)) & 0xFFu;
-                const uint32_t addr = max(rx[k], RR) + (b << bshift);
-                atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(hist) + addr), 1u);
+                a[k] = max(rx[k], RR) + (b << bshift);
             }
-            ops += 4;
+            ops += add4_merged(reinterpret_cast<char*>(hist), a);
         },
         []() {});
     return ops;
@@ -1136,11 +1178,12 @@ __device__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya,
 // at offset d goes to octant j (bit a set when d_a > 0), and to the mirrored
 // octants along every axis with d_a = 0 (the planes through P belong to both
 // sides); row = max(max|d_a| - base, 0), octant j's region at byte
-// j * region_bytes.  Per voxel: one bit-field extract, one max, two adds and one
-// LDS add; the x-plane voxel of a lane costs one more add per step, and the rare
-// rows on the y or z plane take a separate path.
+// j * region_bytes.  Per voxel: one bit-field extract, one max and two adds; a
+// lane's four voxels then go in through add4_merged (one LDS add per distinct
+// counter); the x-plane voxel of a lane costs one more add per step, and the
+// rare rows on the y or z plane take a separate path.
 template <int NT>
-__device__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base, int trash_row,
+__device__ __forceinline__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base, int trash_row,
                                        int rq, uint32_t region_bytes, uint32_t* hist, int tid) {
     const int xa = max(px - Rr, 0), xb = min(px + Rr, v.X - 1);
     const int ya = max(py - Rr, 0), yb = min(py + Rr, v.Y - 1);
@@ -1176,11 +1219,13 @@ __device__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz,
             const int dy = dy0 + iy0, dz = dz0 + iz0;
             const uint32_t RR = __umul24((uint32_t)max(max(abs(dy), abs(dz)) - base, 0), rowbytes) + rep4;
             const uint32_t ayz = (dy > 0 ? ry2 : 0u) + (dz > 0 ? rz4 : 0u);
+            uint32_t a[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t b = __builtin_amdgcn_ubfe(word, 8 * k, 8);
-                atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rx[k], RR) + (b << bshift) + ax[k] + ayz)), 1u);
+                a[k] = max(rx[k], RR) + (b << bshift) + ax[k] + ayz;
             }
+            ops += add4_merged(hb, a);
             if (xdup) {
                 const uint32_t b = __builtin_amdgcn_ubfe(word, kxs, 8);
                 atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rxd, RR) + (b << bshift) + region_bytes + ayz)), 1u);
@@ -1200,7 +1245,7 @@ __device__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz,
                 }
                 ops += (xdup ? 5u : 4u) * ((ym ? 1u : 0u) + (zm ? 1u : 0u) + (ym && zm ? 1u : 0u));
             }
-            ops += xdup ? 5u : 4u;
+            ops += xdup ? 1u : 0u;
         },
         []() {});
     return ops;
@@ -1208,25 +1253,37 @@ __device__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz,
 
 // Sum the replicas of every (region, bin) and prefix over rows 0..nrows-1, in
 // place: replica 0 of row r then holds the voxels of bin b in rows 0..r; other
-// replicas and the trash row are cleared.
+// replicas and the trash row are cleared.  Rows go kMergeRows at a time: their
+// loads are issued together, then the prefix and the stores.
+constexpr int kMergeRows = 8;
+
 template <int NT>
-__device__ void bucket_merge(uint32_t* hist, int nreg, int nrows, int B, int rq, int tid) {
+__device__ __forceinline__ void bucket_merge(uint32_t* hist, int nreg, int nrows, int B, int rq, int tid) {
     const int R = 1 << rq;
     const int rows_total = nrows + 1;
     const int Bs = row_stride(B);
     for (int p = tid; p < nreg * B; p += NT) {
         const int g = p / B, b = p - g * B;
+        const int e0 = (g * rows_total * Bs + b) << rq, de = Bs << rq;
         uint32_t acc = 0;
-        for (int r = 0; r <= nrows; ++r) {
-            const int e = ((g * rows_total + r) * Bs + b) << rq;
-            uint32_t sum = 0;
-            for (int q = 0; q < R; ++q) {
-                sum += hist[e + q];
-                hist[e + q] = 0u;
+        for (int r0 = 0; r0 <= nrows; r0 += kMergeRows) {
+            uint32_t c[kMergeRows];
+#pragma unroll
+            for (int i = 0; i < kMergeRows; ++i) {
+                const int e = e0 + (r0 + i) * de;
+                c[i] = 0;
+                if (r0 + i <= nrows) {
+                    c[i] = hist[e];
+                    for (int q = 1; q < R; ++q) c[i] += hist[e + q];
+                }
             }
-            if (r < nrows) {
-                acc += sum;
-                hist[e] = acc;
+#pragma unroll
+            for (int i = 0; i < kMergeRows; ++i) {
+                const int r = r0 + i, e = e0 + r * de;
+                if (r > nrows) break;
+                for (int q = 1; q < R; ++q) hist[e + q] = 0u;
+                acc += c[i];
+                hist[e] = r < nrows ? acc : 0u;
             }
         }
     }
@@ -1261,8 +1318,10 @@ __device__ __forceinline__ QuadLds quad_lds(char* smem, const LdsQuad& L) {
 // Entropy H64 = (cl[N] - sum_b cl[c_b]) / N of merged rows; wave w takes rows
 // w, w + NW, ..., kRowBatch at a time so that their table loads are in flight
 // together; N of a row from nrow(g, r), or (win) the row's counted voxels, and
-// H = 0 for a row that counts none.  The replica-0 counters read here are
-// cleared.
+// H = 0 for a row that counts none.  Lane i of the wave finishes row i of the
+// batch (its cl[N] load, issued with the bins' loads when N is known up front,
+// and the division), so the batch's tails run side by side.  The replica-0
+// counters read here are cleared.
 constexpr int kRowBatch = 8;
 
 template <int NT, int M, typename NF>
@@ -1272,6 +1331,16 @@ __device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows
     const int rows_total = nrows + 1;
     const int nq = nreg * nrows;
     for (int q0 = wave; q0 < nq; q0 += kRowBatch * (NT / 64)) {
+        // the row this lane finishes (lanes 0 .. kRowBatch-1)
+        const int qm = q0 + lane * (NT / 64);
+        const bool mine = lane < kRowBatch && qm < nq;
+        int64_t Nm = 0;
+        double clN = 0.0;
+        if (!win && mine) {
+            const int g = qm / nrows, r = qm - g * nrows;
+            Nm = nrow(g, r);
+            clN = tb.cl[Nm];
+        }
         double v[kRowBatch][M];
         int cn[kRowBatch];
 #pragma unroll
@@ -1292,24 +1361,29 @@ __device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows
                 cn[i] += (int)c;
             }
         }
+        double Sm = 0.0;
+        long long wm = 0;
 #pragma unroll
         for (int i = 0; i < kRowBatch; ++i) {
-            const int q = q0 + i * (NT / 64);
             const double S = bfly_sum(local_pw<M>(v[i]));
-            const long long wn = win ? bfly_sumll((long long)cn[i]) : 0ll;
-            if (lane == 0 && q < nq) {
-                const int g = q / nrows, r = q - g * nrows;
-                const int64_t N = win ? (int64_t)wn : nrow(g, r);
-                out[q] = N > 0 ? (tb.cl[N] - S) / (double)N : 0.0;
+            Sm = lane == i ? S : Sm;
+            if (win) {
+                const long long wn = bfly_sumll((long long)cn[i]);
+                wm = lane == i ? wn : wm;
             }
         }
+        if (win && mine) {
+            Nm = (int64_t)wm;
+            clN = tb.cl[Nm];
+        }
+        if (mine) out[qm] = Nm > 0 ? (clN - Sm) / (double)Nm : 0.0;
     }
 }
 
 // Alg. 1 body in 3D: octant entropies for every scale, per octant the first
 // maximising scale, E = sum of the 8 maxima, move = sum_j eps_j k*_j sigma_j / E.
 template <int NT, int M>
-__device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq, const QuadLds& L,
+__device__ __forceinline__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq, const QuadLds& L,
                              int tid, unsigned int& ops) {
     px = uniform(px); py = uniform(py); pz = uniform(pz);
     const int S = v.S, B = v.B;
@@ -1371,7 +1445,7 @@ __device__ EvalOut quad_eval(const VolDesc& v, const Tables& tb, int px, int py,
 // half-width s in [s_min-1, s_max+1], entropy peaks over s in [s_min, s_max], the
 // peak with the largest H*W (first on ties).
 template <int NT, int M>
-__device__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq,
+__device__ __forceinline__ Saliency quad_saliency(const VolDesc& v, const Tables& tb, int px, int py, int pz, int rq,
                                   const QuadLds& L, int tid, unsigned int& ops) {
     px = uniform(px); py = uniform(py); pz = uniform(pz);
     const int S = v.S, B = v.B;
