@@ -53,6 +53,9 @@ namespace ks {
 #ifndef KS_QUAD_DEPTH
 #define KS_QUAD_DEPTH 2
 #endif
+#ifndef KS_QUAD_THREADS
+#define KS_QUAD_THREADS 256
+#endif
 constexpr int kMsUnroll = KS_MS_UNROLL, kMsDepth = KS_MS_DEPTH;
 constexpr int kQuadUnroll = KS_QUAD_UNROLL, kQuadDepth = KS_QUAD_DEPTH;
 // Load offset past the end of every bin volume (volumes stay below 2^31 bytes):
@@ -1380,6 +1383,93 @@ __device__ __forceinline__ void rows_entropy(uint32_t* hist, int nreg, int nrows
     }
 }
 
+// Merge and entropy in one pass for the octant regions: wave w takes regions
+// w, w + NW, ...; a lane keeps the running sum over rows of its bins' counts
+// (replicas summed), so row r's counts (the cube of half-width s_min + r) never
+// go back to LDS; RB rows at a time, their table loads in flight together, and
+// lane i finishes row i of the batch as in rows_entropy.  Every counter of the
+// regions, trash rows included, is cleared.
+template <int NT, int M, typename NF>
+__device__ __forceinline__ void merge_entropy(uint32_t* hist, int nreg, int nrows, int B, int rq, const Tables& tb,
+                                              NF&& nrow, bool win, double* out, int tid) {
+    constexpr int RB = 8;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int rows_total = nrows + 1, Bs = row_stride(B), R = 1 << rq;
+    for (int g = wave; g < nreg; g += NT / 64) {
+        uint32_t acc[M];
+#pragma unroll
+        for (int t = 0; t < M; ++t) acc[t] = 0u;
+        const int gb = g * rows_total * Bs;
+        for (int r0 = 0; r0 < nrows; r0 += RB) {
+            const int rm = r0 + lane;
+            const bool mine = lane < RB && rm < nrows;
+            int64_t Nm = 0;
+            double clN = 0.0;
+            if (!win && mine) {
+                Nm = nrow(g, rm);
+                clN = tb.cl[Nm];
+            }
+            uint32_t c[RB][M];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    const int b = lane * M + t;
+                    c[i][t] = 0u;
+                    if (r0 + i < nrows && b < B) {
+                        const int e = (gb + (r0 + i) * Bs + b) << rq;
+                        c[i][t] = hist[e];
+                        for (int q = 1; q < R; ++q) c[i][t] += hist[e + q];
+                    }
+                }
+            }
+            double v[RB][M];
+            int cn[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                cn[i] = 0;
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    const int b = lane * M + t;
+                    const bool ok = r0 + i < nrows && b < B;
+                    if (ok) {
+                        const int e = (gb + (r0 + i) * Bs + b) << rq;
+                        for (int q = 0; q < R; ++q) hist[e + q] = 0u;
+                    }
+                    acc[t] += c[i][t];
+                    v[i][t] = tb.cl[ok ? acc[t] : 0u];
+                    cn[i] += ok ? (int)acc[t] : 0;
+                }
+            }
+            double Sm = 0.0;
+            long long wm = 0;
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const double S = bfly_sum(local_pw<M>(v[i]));
+                Sm = lane == i ? S : Sm;
+                if (win) {
+                    const long long wn = bfly_sumll((long long)cn[i]);
+                    wm = lane == i ? wn : wm;
+                }
+            }
+            if (win && mine) {
+                Nm = (int64_t)wm;
+                clN = tb.cl[Nm];
+            }
+            if (mine) out[g * nrows + rm] = Nm > 0 ? (clN - Sm) / (double)Nm : 0.0;
+        }
+        // the trash row
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const int b = lane * M + t;
+            if (b < B) {
+                const int e = (gb + nrows * Bs + b) << rq;
+                for (int q = 0; q < R; ++q) hist[e + q] = 0u;
+            }
+        }
+    }
+}
+
 // Alg. 1 body in 3D: octant entropies for every scale, per octant the first
 // maximising scale, E = sum of the 8 maxima, move = sum_j eps_j k*_j sigma_j / E.
 template <int NT, int M>
@@ -1390,9 +1480,7 @@ __device__ __forceinline__ EvalOut quad_eval(const VolDesc& v, const Tables& tb,
     const uint32_t region_bytes = (uint32_t)(S + 1) * (uint32_t)row_stride(B) << (rq + 2);
     ops += octant_scatter<NT>(v, px, py, pz, v.s_max, v.s_min, S, rq, region_bytes, L.hist, tid);
     __syncthreads();
-    bucket_merge<NT>(L.hist, 8, S, B, rq, tid);
-    __syncthreads();
-    rows_entropy<NT, M>(
+    merge_entropy<NT, M>(
         L.hist, 8, S, B, rq, tb,
         [&](int j, int r) {
             const int k = v.s_min + r;
@@ -1549,7 +1637,7 @@ __device__ __forceinline__ Saliency quad_saliency(const VolDesc& v, const Tables
 
 // --------------------------------------------------------- quadrant kernel
 
-constexpr int kQuadThreads = 256;  // threads per trajectory (one workgroup)
+constexpr int kQuadThreads = KS_QUAD_THREADS;  // threads per trajectory (one workgroup)
 
 template <int M>
 __global__ __launch_bounds__(kQuadThreads) void k_search_quad(const VolDesc* __restrict__ vols,
