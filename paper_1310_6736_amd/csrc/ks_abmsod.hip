@@ -32,7 +32,15 @@ constexpr double kUnfix = 1.0 / 1099511627776.0;
 constexpr double kFixM = 4294967296.0;           // 2^32
 constexpr double kUnfixM = 1.0 / 4294967296.0;
 constexpr double kTol = 0.01;
-constexpr int kBlocksPerCu = 12;
+// Occupancy: the kernel is held to 128 VGPRs (4 waves per SIMD; what does not
+// fit is spilled outside the voxel loops) and launched with 16 waves per CU.
+#ifndef KS_ABM_BLOCKS
+#define KS_ABM_BLOCKS 16
+#endif
+#ifndef KS_ABM_WAVES
+#define KS_ABM_WAVES 4
+#endif
+constexpr int kBlocksPerCu = KS_ABM_BLOCKS;
 
 enum { kHist = 0, kHistMean = 1, kCov = 2 };
 
@@ -208,8 +216,12 @@ __device__ __forceinline__ unsigned long long abm_fold(unsigned long long* hist,
     return tot;
 }
 
-__global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, ks_ellipsoid* out, Counters* cnt) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KS_ABM_WAVES))) void k_abmsod(const VolDesc* vols, AbmArgs a,
+                                                                                              ks_ellipsoid* out, Counters* cnt) {
     extern __shared__ unsigned long long smem[];
+    // the best-so-far centre, bandwidth, coefficient and entropy of the wave's
+    // candidate (written and read by lane 0 only; kept out of registers)
+    __shared__ double s_keep[11];
     const VolDesc& v = vols[0];
     const int lane = threadIdx.x;
     const int B = v.B;
@@ -236,8 +248,13 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
         const double h0 = (r + 0.5) * (r + 0.5) / 5.0;
         double h[6] = {h0, h0, h0, 0.0, 0.0, 0.0};
         double inv[6];
-        double best = 0.0, xo[3] = {x[0], x[1], x[2]}, ho[6], rho_o = 0.0, ent_o = 0.0;
-        for (int k = 0; k < 6; ++k) ho[k] = h[k];
+        double best = 0.0;
+        if (lane == 0) {
+            for (int k = 0; k < 3; ++k) s_keep[k] = x[k];
+            for (int k = 0; k < 6; ++k) s_keep[3 + k] = h[k];
+            s_keep[9] = 0.0;
+            s_keep[10] = 0.0;
+        }
         int it = 0, stop = KS_ABM_MAX_ITER;
         unsigned visits = 0;
         int evals = 0;
@@ -276,10 +293,12 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
             const double delta = best - rho;
             if (rho > best) {
                 best = rho;
-                for (int k = 0; k < 3; ++k) xo[k] = xn[k];
-                for (int k = 0; k < 6; ++k) ho[k] = hn[k];
-                rho_o = rho;
-                ent_o = ent;
+                if (lane == 0) {
+                    for (int k = 0; k < 3; ++k) s_keep[k] = xn[k];
+                    for (int k = 0; k < 6; ++k) s_keep[3 + k] = hn[k];
+                    s_keep[9] = rho;
+                    s_keep[10] = ent;
+                }
             }
             ++it;
             double dx = 0.0, dh = 0.0, hd = h[0];
@@ -296,10 +315,10 @@ __global__ __launch_bounds__(64) void k_abmsod(const VolDesc* vols, AbmArgs a, k
             ks_ellipsoid e;
             e.x0 = p0[0]; e.y0 = p0[1]; e.z0 = p0[2];
             e.radius = r;
-            for (int k = 0; k < 3; ++k) e.x[k] = xo[k];
-            for (int k = 0; k < 6; ++k) e.h[k] = ho[k];
-            e.rho = rho_o;
-            e.entropy = ent_o;
+            for (int k = 0; k < 3; ++k) e.x[k] = s_keep[k];
+            for (int k = 0; k < 6; ++k) e.h[k] = s_keep[3 + k];
+            e.rho = s_keep[9];
+            e.entropy = s_keep[10];
             e.iters = it;
             e.stop = stop;
             out[id] = e;
