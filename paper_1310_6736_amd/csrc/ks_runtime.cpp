@@ -99,7 +99,7 @@ static ks_status hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? KS_E
 ks_status Buffer::ensure(size_t bytes, int* generation) {
     if (bytes <= cap) return KS_OK;
     // grow by at least 1.5x so that a slowly rising size reallocates rarely
-    const size_t want = granule(exact ? bytes : std::max(bytes, cap + cap / 2));
+    const size_t want = granule(std::max(bytes, cap + cap / 2));
     if (ptr) hipFree(ptr);
     ptr = nullptr;
     cap = 0;
@@ -301,7 +301,7 @@ size_t Context::arena_after(const std::vector<VolIn>& in) {
     size_t n = 0;
     for (int i = 0; i < kArenaBuffers; ++i) {
         const Buffer& b = arena(i);
-        n += need[i] <= b.cap ? b.cap : granule(b.exact ? need[i] : std::max(need[i], b.cap + b.cap / 2));
+        n += need[i] <= b.cap ? b.cap : granule(std::max(need[i], b.cap + b.cap / 2));
     }
     return n;
 }
@@ -317,10 +317,6 @@ size_t Context::arena_fresh(const std::vector<VolIn>& in) {
 void Context::arena_release() {
     for (int i = 0; i < kArenaBuffers; ++i) arena(i).release();
     ++generation;  // captured graphs hold the old addresses
-}
-
-void Context::arena_exact(bool on) {
-    for (int i = 0; i < kArenaBuffers; ++i) arena(i).exact = on;
 }
 
 ks_status Context::plan(const std::vector<VolIn>& in, Plan& p, const FixedArena* fixed) {

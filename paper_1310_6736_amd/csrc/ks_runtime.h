@@ -11,12 +11,10 @@
 
 namespace ks {
 
-// Grow-only device allocation: by at least 1.5x, or to exactly the size asked
-// for (4 KiB granules) when `exact` is set.
+// Grow-only device allocation: by at least 1.5x (4 KiB granules).
 struct Buffer {
     void* ptr = nullptr;
     size_t cap = 0;
-    bool exact = false;
     ks_status ensure(size_t bytes, int* generation);
     void release();
 };
@@ -136,7 +134,6 @@ struct Context {
     size_t arena_after(const std::vector<VolIn>& in);
     static size_t arena_fresh(const std::vector<VolIn>& in);
     void arena_release();
-    void arena_exact(bool on);
     ks_status plan(const std::vector<VolIn>& in, Plan& p, const FixedArena* fixed = nullptr);
     ks_status upload(const Plan& p, hipStream_t st);
     ks_status enqueue_search(const Plan& p, hipStream_t st, bool with_rank, bool timed);

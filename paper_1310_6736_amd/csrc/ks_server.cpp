@@ -325,9 +325,10 @@ bool ks_server::tick() {
     }
     if (take.empty()) return worked;
     Slot* sl = free_slot;
-    // Room for the batch: its slot's buffers grow to exactly what it needs; while
-    // the total would pass the budget, idle slots give their buffers back
-    // (largest first), then this slot (it then allocates the batch's size only).
+    // Room for the batch: its slot's buffers grow (by at least 1.5x) to what it
+    // needs; while the total would pass the budget, idle slots give their buffers
+    // back (largest first), then this slot (it then allocates the batch's size
+    // only).
     auto total_after = [&]() {
         size_t t = 0;
         for (Slot* o : slots)
