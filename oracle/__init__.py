@@ -6,6 +6,7 @@ anything here.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -97,8 +98,21 @@ def lib():
         L.kso_abmsod.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_int32, i32p, C.c_int32, C.c_void_p, C.c_int64,
                                  i32p, C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(Stats)]
         L.kso_rank.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int32, i32p]
+        L.kso_set_readings.argtypes = [C.c_int32, C.c_int32]
         _lib = L
     return _lib
+
+
+@contextlib.contextmanager
+def readings(sequential_sums=False, ln_n_form=False):
+    """Runs the oracle under other readings of two points the paper leaves open
+    (sums over bins in ascending order instead of the pairwise tree; H64 =
+    ln N - S/N instead of (N ln N - S)/N), then restores the default ones."""
+    lib().kso_set_readings(int(sequential_sums), int(ln_n_form))
+    try:
+        yield
+    finally:
+        lib().kso_set_readings(0, 0)
 
 
 def _i3(v):

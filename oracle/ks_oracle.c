@@ -68,7 +68,23 @@ static double pairwise(const double* v, int32_t n, int32_t lo, int32_t len) {
     return pairwise(v, n, lo, len / 2) + pairwise(v, n, lo + len / 2, len / 2);
 }
 
-static double sum_bins(const double* v, int32_t bins) { return pairwise(v, bins, 0, padded_terms(bins)); }
+/* Alternative readings, for tests that check that the choice does not change
+ * the results: sums over bins in ascending bin order, and H64 = ln N - S/N. */
+static int g_sequential_sums = 0, g_ln_n_form = 0;
+
+void kso_set_readings(int sequential_sums, int ln_n_form) {
+    g_sequential_sums = sequential_sums != 0;
+    g_ln_n_form = ln_n_form != 0;
+}
+
+static double sum_bins(const double* v, int32_t bins) {
+    if (g_sequential_sums) {
+        double s = 0.0;
+        for (int32_t b = 0; b < bins; ++b) s += v[b];
+        return s;
+    }
+    return pairwise(v, bins, 0, padded_terms(bins));
+}
 
 static double sum_octants(const double* e) { return ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7])); }
 
@@ -121,6 +137,7 @@ static double entropy64_n(const uint32_t* c, int32_t bins, int64_t N) {
     for (int32_t b = 0; b < bins; ++b) t[b] = c[b] > 0 ? (double)c[b] * log((double)c[b]) : 0.0;
     double S = sum_bins(t, bins);
     free(t);
+    if (g_ln_n_form) return log((double)N) - S / (double)N;
     return ((double)N * log((double)N) - S) / (double)N;
 }
 

@@ -60,6 +60,12 @@ int kso_bin_volume_window(const void* vol, int32_t dtype, const int32_t dims[3],
                           int32_t hi, uint8_t* out);
 
 /* Entropies of one count vector: decision precision (H64) and accurate (Href). */
+/* Alternative readings of points the paper leaves open, for tests that check
+ * that the choice does not change the results (default 0, 0): sums over bins in
+ * ascending bin order instead of the pairwise tree, and H64 = ln N - S/N instead
+ * of (N ln N - S)/N.  Process-wide; not thread-safe. */
+void kso_set_readings(int sequential_sums, int ln_n_form);
+
 double kso_entropy64(const uint32_t* counts, int32_t bins);
 double kso_entropy_ref(const uint32_t* counts, int32_t bins);
 
