@@ -99,6 +99,7 @@ def lib():
                                  i32p, C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(Stats)]
         L.kso_rank.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int32, i32p]
         L.kso_set_readings.argtypes = [C.c_int32, C.c_int32]
+        L.kso_set_abm_readings.argtypes = [C.c_int32, C.c_int32]
         _lib = L
     return _lib
 
@@ -113,6 +114,17 @@ def readings(sequential_sums=False, ln_n_form=False):
         yield
     finally:
         lib().kso_set_readings(0, 0)
+
+
+@contextlib.contextmanager
+def abm_readings(convergence_stop=True, bandwidth_cap=True):
+    """Runs the oracle's ABMSOD search with or without its two additions to
+    Alg. 2 (the convergence stop; the bandwidth cap), then restores both."""
+    lib().kso_set_abm_readings(int(convergence_stop), int(bandwidth_cap))
+    try:
+        yield
+    finally:
+        lib().kso_set_abm_readings(1, 1)
 
 
 def _i3(v):

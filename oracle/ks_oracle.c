@@ -77,6 +77,14 @@ void kso_set_readings(int sequential_sums, int ln_n_form) {
     g_ln_n_form = ln_n_form != 0;
 }
 
+/* The two additions to Alg. 2 (readings R32, R33), on by default. */
+static int g_abm_convergence_stop = 1, g_abm_bandwidth_cap = 1;
+
+void kso_set_abm_readings(int convergence_stop, int bandwidth_cap) {
+    g_abm_convergence_stop = convergence_stop != 0;
+    g_abm_bandwidth_cap = bandwidth_cap != 0;
+}
+
 static double sum_bins(const double* v, int32_t bins) {
     if (g_sequential_sums) {
         double s = 0.0;
@@ -745,7 +753,7 @@ static void abm_trajectory(abm_ctx* c, const int32_t p0[3], int32_t r, int32_t r
         double hmax = hn[0] > hn[1] ? hn[0] : hn[1];
         if (hn[2] > hmax) hmax = hn[2];
         const double cap2 = (r_cap + 0.5) * (r_cap + 0.5);
-        if (5.0 * hmax > cap2) {
+        if (g_abm_bandwidth_cap && 5.0 * hmax > cap2) {
             double f = cap2 / (5.0 * hmax);
             for (int k = 0; k < 6; ++k) hn[k] *= f;
         }
@@ -766,7 +774,10 @@ static void abm_trajectory(abm_ctx* c, const int32_t p0[3], int32_t r, int32_t r
         memcpy(x, xn, sizeof(xn));
         memcpy(h, hn, sizeof(hn));
         if (delta > threshold) { stop = KSO_ABM_DETERIORATED; break; }
-        if (dx < KSO_ABM_TOL && dh < KSO_ABM_TOL * hd) { stop = KSO_ABM_CONVERGED; break; }
+        if (g_abm_convergence_stop && dx < KSO_ABM_TOL && dh < KSO_ABM_TOL * hd) {
+            stop = KSO_ABM_CONVERGED;
+            break;
+        }
     }
     t->iters = it;
     t->stop = stop;

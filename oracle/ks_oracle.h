@@ -66,6 +66,11 @@ int kso_bin_volume_window(const void* vol, int32_t dtype, const int32_t dims[3],
  * of (N ln N - S)/N.  Process-wide; not thread-safe. */
 void kso_set_readings(int sequential_sums, int ln_n_form);
 
+/* The two additions to Alg. 2 that the ABMSOD search makes (default 1, 1): the
+ * stop when the centre and the bandwidth no longer move, and the cap on the
+ * bandwidth at the largest start window.  For tests; process-wide. */
+void kso_set_abm_readings(int convergence_stop, int bandwidth_cap);
+
 double kso_entropy64(const uint32_t* counts, int32_t bins);
 double kso_entropy_ref(const uint32_t* counts, int32_t bins);
 

@@ -941,3 +941,20 @@ def test_entropy_form_gives_exact_zero_for_one_bin_windows():
         b, _ = oracle.run(w.volume, w.bins, w.spacing, w.scales, w.method, w.max_iter, ids=ids)
     moved = (a["x"] != b["x"]) | (a["y"] != b["y"]) | (a["z"] != b["z"]) | (a["iters"] != b["iters"])
     assert 0 < int(moved.sum()) < len(a) // 100
+
+
+def test_abmsod_convergence_stop_changes_only_the_candidates_it_stops():
+    """Reading R32 adds a convergence stop to Alg. 2 (centre and bandwidth moving
+    less than 0.01).  Without it, every sampled PET-like candidate that ended for
+    another reason ends identically; only candidates it stopped run on (and may
+    find a slightly higher coefficient)."""
+    w = synth.pet_shell(0)
+    ids = np.arange(0, 4851 * 13, 97)
+    a, _ = oracle.abmsod(w.volume, w.bins, w.spacing, (4, 16), 20, ids=ids)
+    with oracle.abm_readings(convergence_stop=False):
+        b, _ = oracle.abmsod(w.volume, w.bins, w.spacing, (4, 16), 20, ids=ids)
+    conv = a["stop"] == 1
+    assert conv.any() and not (b["stop"] == 1).any()
+    for f in ("x", "h", "rho", "entropy", "iters", "stop"):
+        assert np.array_equal(a[f][~conv], b[f][~conv]), f
+    assert np.all(b["rho"][conv] >= a["rho"][conv])
