@@ -1118,24 +1118,6 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
 
 // ------------------------------------------------ quadrant: bucketed scatter
 
-// Adds the lane's four voxels (LDS byte addresses a[0..3]) into their u32
-// counters: voxels that share a counter go in as one add of their number, so
-// lanes of a wave that hit one counter (a flat background bins most voxels of
-// a shell row alike) contend less.  Returns the adds issued.
-__device__ __forceinline__ unsigned int add4_merged(char* hb, const uint32_t* a) {
-    const bool e01 = a[0] == a[1], e02 = a[0] == a[2], e03 = a[0] == a[3];
-    const bool e12 = a[1] == a[2], e13 = a[1] == a[3], e23 = a[2] == a[3];
-    const uint32_t c0 = 1u + (uint32_t)e01 + (uint32_t)e02 + (uint32_t)e03;
-    const uint32_t c1 = 1u + (uint32_t)e12 + (uint32_t)e13;
-    const uint32_t c2 = 1u + (uint32_t)e23;
-    const bool n1 = !e01, n2 = !(e02 || e12), n3 = !(e03 || e13 || e23);
-    atomicAdd(reinterpret_cast<uint32_t*>(hb + a[0]), c0);
-    if (n1) atomicAdd(reinterpret_cast<uint32_t*>(hb + a[1]), c1);
-    if (n2) atomicAdd(reinterpret_cast<uint32_t*>(hb + a[2]), c2);
-    if (n3) atomicAdd(reinterpret_cast<uint32_t*>(hb + a[3]), 1u);
-    return 1u + (uint32_t)n1 + (uint32_t)n2 + (uint32_t)n3;
-}
-
 // Scatter the box into hist (uint32 counters) at byte offset
 //   region + ((row*B + bin) << rq)*4 + replica*4,
 // row = max(max(|x-cx|,|y-cy|,|z-cz|) - base, 0); bytes outside the box go to
@@ -1165,13 +1147,13 @@ __device__ __forceinline__ unsigned int bucket_scatter(const VolDesc& v, int xa,
         [&](uint32_t word, int iy0, int iz0, uint64_t) {
             const int rr = max(max(abs(dy0 + iy0), abs(dz0 + iz0)) - base, 0);
             const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
-            uint32_t a[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t b = (word >> (8 * k)) & 0xFFu;
-                a[k] = max(rx[k], RR) + (b << bshift);
+                const uint32_t addr = max(rx[k], RR) + (b << bshift);
+                atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(hist) + addr), 1u);
             }
-            ops += add4_merged(reinterpret_cast<char*>(hist), a);
+            ops += 4;
         },
         []() {});
     return ops;
@@ -1181,10 +1163,9 @@ __device__ __forceinline__ unsigned int bucket_scatter(const VolDesc& v, int xa,
 // at offset d goes to octant j (bit a set when d_a > 0), and to the mirrored
 // octants along every axis with d_a = 0 (the planes through P belong to both
 // sides); row = max(max|d_a| - base, 0), octant j's region at byte
-// j * region_bytes.  Per voxel: one bit-field extract, one max and two adds; a
-// lane's four voxels then go in through add4_merged (one LDS add per distinct
-// counter); the x-plane voxel of a lane costs one more add per step, and the
-// rare rows on the y or z plane take a separate path.
+// j * region_bytes.  Per voxel: one bit-field extract, one max, two adds and one
+// LDS add; the x-plane voxel of a lane costs one more add per step, and the rare
+// rows on the y or z plane take a separate path.
 template <int NT>
 __device__ __forceinline__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base, int trash_row,
                                        int rq, uint32_t region_bytes, uint32_t* hist, int tid) {
@@ -1222,13 +1203,11 @@ __device__ __forceinline__ unsigned int octant_scatter(const VolDesc& v, int px,
             const int dy = dy0 + iy0, dz = dz0 + iz0;
             const uint32_t RR = __umul24((uint32_t)max(max(abs(dy), abs(dz)) - base, 0), rowbytes) + rep4;
             const uint32_t ayz = (dy > 0 ? ry2 : 0u) + (dz > 0 ? rz4 : 0u);
-            uint32_t a[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t b = __builtin_amdgcn_ubfe(word, 8 * k, 8);
-                a[k] = max(rx[k], RR) + (b << bshift) + ax[k] + ayz;
+                atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rx[k], RR) + (b << bshift) + ax[k] + ayz)), 1u);
             }
-            ops += add4_merged(hb, a);
             if (xdup) {
                 const uint32_t b = __builtin_amdgcn_ubfe(word, kxs, 8);
                 atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rxd, RR) + (b << bshift) + region_bytes + ayz)), 1u);
@@ -1248,7 +1227,7 @@ __device__ __forceinline__ unsigned int octant_scatter(const VolDesc& v, int px,
                 }
                 ops += (xdup ? 5u : 4u) * ((ym ? 1u : 0u) + (zm ? 1u : 0u) + (ym && zm ? 1u : 0u));
             }
-            ops += xdup ? 1u : 0u;
+            ops += xdup ? 5u : 4u;
         },
         []() {});
     return ops;
