@@ -48,16 +48,20 @@ namespace ks {
 #define KS_MS_DEPTH 1
 #endif
 #ifndef KS_QUAD_UNROLL
-#define KS_QUAD_UNROLL 2
+#define KS_QUAD_UNROLL 1
 #endif
 #ifndef KS_QUAD_DEPTH
 #define KS_QUAD_DEPTH 2
+#endif
+#ifndef KS_QUAD_WB
+#define KS_QUAD_WB 8
 #endif
 #ifndef KS_QUAD_THREADS
 #define KS_QUAD_THREADS 256
 #endif
 constexpr int kMsUnroll = KS_MS_UNROLL, kMsDepth = KS_MS_DEPTH;
 constexpr int kQuadUnroll = KS_QUAD_UNROLL, kQuadDepth = KS_QUAD_DEPTH;
+constexpr int kQuadWB = KS_QUAD_WB;  // bytes (voxels) per lane and step of the octant scatter
 // Load offset past the end of every bin volume (volumes stay below 2^31 bytes):
 // the buffer range check turns such a load into 0 without a memory access.
 constexpr uint32_t kPastEnd = 0x80000000u;
@@ -168,7 +172,7 @@ __device__ __forceinline__ int small_div(int a, int d) {
 
 // A box of a layout swept by NT lanes: fast coordinates [fa, fb], nr rows
 // ra, ra + rstep, ... and ns slices sa, sa + sstep, ...  Each active lane owns one
-// dword column of one row of a ty x tz tile of rows; the tile then steps through
+// column of WB bytes (a dword or a qword) of one row of a ty x tz tile of rows; the tile then steps through
 // the box, first along the rows, then along the slices.  All fields except the
 // lane ones are uniform.
 struct Sweep {
@@ -180,16 +184,18 @@ struct Sweep {
     uint32_t voff;      // byte offset of the lane's dword at the first step
 };
 
-template <int NT>
+template <int NT, int WB = 4>
 __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int ra, int nr, int rstep, int sa,
                                             int ns, int sstep, int tid) {
+    static_assert(WB == 4 || WB == 8, "a lane loads a dword or a qword");
+    constexpr int kShift = WB == 8 ? 3 : 2;
     Sweep w;
     w.ny = nr;
     w.nz = ns;
     w.pr = L.pitch * (uint32_t)rstep;
     w.ps = L.slab * (uint32_t)sstep;
-    const int da = fa >> 2;
-    w.nd = (fb >> 2) - da + 1;
+    const int da = fa >> kShift;
+    w.nd = (fb >> kShift) - da + 1;
     const int rmax = uniform(small_div(NT, w.nd));  // rows one step can take
     w.ty = min(w.ny, rmax);
     w.tz = min(w.nz, uniform(small_div(rmax, w.ty)));
@@ -216,7 +222,7 @@ __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int
     const int rem = tid - w.oz * per_z;
     w.oy = small_div(rem, w.nd);
     const int d = rem - w.oy * w.nd;
-    w.x0 = (da + d) * 4;
+    w.x0 = (da + d) * WB;
     const bool on = tid < w.tz * per_z;
     w.lim_y = on ? w.ny - w.oy : -1;
     w.lim_z = w.nz - w.oz;
@@ -228,7 +234,8 @@ __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int
 // Walks the sweep's steps in groups of U steps, keeping D groups of loads in
 // flight: the loads of group g + D are issued right after group g is scattered.
 // Calls f(word, iy0, iz0, acc) for every step in which the lane's row lies
-// inside the box (word: 4 voxels; iy0, iz0: the step's row and slice offset;
+// inside the box (word: WB voxels, a dword or a qword; iy0, iz0: the step's row
+// and slice offset;
 // acc = iy0 * ay + iz0 * az, a uniform 64-bit value the caller adds to its
 // per-lane terms).  The load offset and acc advance by additions; a group of
 // steps whose tiles lie wholly inside the box skips the per-lane row tests.  `used` counts
@@ -236,21 +243,40 @@ __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int
 // before a group that would take it past `limit`, flush() runs (uniformly) and
 // the count restarts.  Loads for steps past the last one get an offset beyond
 // the descriptor's end: they return 0 without a memory access.
-template <int U, int D, typename F, typename G>
+template <int WB>
+struct LaneWord;
+template <>
+struct LaneWord<4> {
+    using T = uint32_t;
+    static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t off) {
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, voff, off, 0);
+    }
+};
+template <>
+struct LaneWord<8> {
+    using T = uint64_t;
+    static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, off, 0);
+        return ((uint64_t)v[1] << 32) | v[0];
+    }
+};
+
+template <int U, int D, int WB = 4, typename F, typename G>
 __device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, uint64_t ay, uint64_t az, int& used,
                                           int limit, F&& f, G&& flush) {
+    using Word = typename LaneWord<WB>::T;
     const __amdgpu_buffer_rsrc_t rs = layout_rsrc(L);
     const uint32_t xp = (uint32_t)uniform((int)w.pr), slice = (uint32_t)uniform((int)w.ps);
     const int nz = uniform(w.nz), ny = uniform(w.ny), ty = uniform(w.ty), tz = uniform(w.tz);
     const uint32_t dy = (uint32_t)ty * xp, dz = (uint32_t)tz * slice;
     const uint64_t day = (uint64_t)(uint32_t)ty * ay, daz = (uint64_t)(uint32_t)tz * az;
     const int lim_y = w.lim_y, lim_z = w.lim_z;
-    constexpr int kGroupVoxels = U * 4;
+    constexpr int kGroupVoxels = U * WB;
     // the step about to be loaded
     int iy0 = 0, iz0 = 0;
     uint32_t off = 0, zoff = 0;
     uint64_t acc = 0, zacc = 0;
-    uint32_t buf[D][U];
+    Word buf[D][U];
     int by[D][U], bz[D][U];
     uint64_t bacc[D][U];
     bool full[D][U];
@@ -259,7 +285,7 @@ __device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, uint6
         bz[g][u] = iz0;
         bacc[g][u] = acc;
         full[g][u] = iy0 + ty <= ny && iz0 + tz <= nz;
-        buf[g][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, w.voff, iz0 < nz ? off : kPastEnd, 0);
+        buf[g][u] = LaneWord<WB>::load(rs, w.voff, iz0 < nz ? off : kPastEnd);
         iy0 += ty;
         off += dy;
         acc += day;
@@ -1167,20 +1193,22 @@ __device__ __forceinline__ unsigned int bucket_scatter(const VolDesc& v, int xa,
 // LDS add; the x-plane voxel of a lane costs one more add per step, and the rare
 // rows on the y or z plane take a separate path.
 template <int NT>
-__device__ __forceinline__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base, int trash_row,
-                                       int rq, uint32_t region_bytes, uint32_t* hist, int tid) {
+__device__ __forceinline__ unsigned int octant_scatter(const VolDesc& v, int px, int py, int pz, int Rr, int base,
+                                                       int trash_row, int rq, uint32_t region_bytes, uint32_t* hist,
+                                                       int tid) {
+    constexpr int WB = kQuadWB;  // voxels per lane and step
     const int xa = max(px - Rr, 0), xb = min(px + Rr, v.X - 1);
     const int ya = max(py - Rr, 0), yb = min(py + Rr, v.Y - 1);
     const int za = max(pz - Rr, 0), zb = min(pz + Rr, v.Z - 1);
     const Layout L = layout_x(v);
-    const Sweep w = make_sweep<NT>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, tid);
+    const Sweep w = make_sweep<NT, WB>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, tid);
     const uint32_t rowbytes = (uint32_t)row_stride(v.B) << (rq + 2);
     const uint32_t rep4 = (uint32_t)(tid & ((1 << rq) - 1)) << 2;
     const uint32_t bshift = (uint32_t)rq + 2;
-    uint32_t rx[4], ax[4];
+    uint32_t rx[WB], ax[WB];
     int kx = -1;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < WB; ++k) {
         const int x = w.x0 + k;
         const bool ok = x >= xa && x <= xb;
         const int r = ok ? max(abs(x - px) - base, 0) : trash_row;
@@ -1190,44 +1218,45 @@ __device__ __forceinline__ unsigned int octant_scatter(const VolDesc& v, int px,
     }
     // the lane's voxel on the plane x = px (if any): byte kx, mirrored to the + side
     const bool xdup = kx >= 0;
-    const uint32_t kxs = xdup ? 8u * (uint32_t)kx : 0u;
+    const bool kxhi = kx >= 4;
+    const uint32_t kxs = xdup ? 8u * (uint32_t)(kx & 3) : 0u;
     const uint32_t rxd = rep4;  // |x - px| = 0: row max(-base, 0) = 0
     const int dy0 = ya + w.oy - py, dz0 = za + w.oz - pz;
     const uint32_t ry2 = 2u * region_bytes, rz4 = 4u * region_bytes;
     char* hb = reinterpret_cast<char*>(hist);
     int used = 0;
     unsigned int ops = 0;
-    run_sweep<kQuadUnroll, kQuadDepth>(
+    run_sweep<kQuadUnroll, kQuadDepth, WB>(
         L, w, 0, 0, used, INT_MAX,
-        [&](uint32_t word, int iy0, int iz0, uint64_t) {
+        [&](typename LaneWord<WB>::T word, int iy0, int iz0, uint64_t) {
+            const uint32_t lo = (uint32_t)word, hi = (uint32_t)((uint64_t)word >> 32);
             const int dy = dy0 + iy0, dz = dz0 + iz0;
             const uint32_t RR = __umul24((uint32_t)max(max(abs(dy), abs(dz)) - base, 0), rowbytes) + rep4;
             const uint32_t ayz = (dy > 0 ? ry2 : 0u) + (dz > 0 ? rz4 : 0u);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t b = __builtin_amdgcn_ubfe(word, 8 * k, 8);
+            for (int k = 0; k < WB; ++k) {
+                const uint32_t b = __builtin_amdgcn_ubfe(k < 4 ? lo : hi, 8 * (k & 3), 8);
                 atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rx[k], RR) + (b << bshift) + ax[k] + ayz)), 1u);
             }
             if (xdup) {
-                const uint32_t b = __builtin_amdgcn_ubfe(word, kxs, 8);
+                const uint32_t b = __builtin_amdgcn_ubfe(kxhi ? hi : lo, kxs, 8);
                 atomicAdd(reinterpret_cast<uint32_t*>(hb + (max(rxd, RR) + (b << bshift) + region_bytes + ayz)), 1u);
             }
             if (dy == 0 || dz == 0) {
                 // rows on the y or z plane: the mirrored copies
                 const uint32_t ym = dy == 0 ? ry2 : 0u, zm = dz == 0 ? rz4 : 0u;
-                for (int k = 0; k < 5; ++k) {
-                    if (k == 4 && !xdup) break;
-                    const uint32_t b = __builtin_amdgcn_ubfe(word, k < 4 ? 8u * (uint32_t)k : kxs, 8);
-                    const uint32_t rk = k == 0 ? rx[0] : k == 1 ? rx[1] : k == 2 ? rx[2] : k == 3 ? rx[3] : rxd;
-                    const uint32_t xk = k == 0 ? ax[0] : k == 1 ? ax[1] : k == 2 ? ax[2] : k == 3 ? ax[3] : region_bytes;
+                auto mirror = [&](uint32_t b, uint32_t rk, uint32_t xk) {
                     const uint32_t ak = max(rk, RR) + (b << bshift) + xk + ayz;
                     if (ym) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + ym), 1u);
                     if (zm) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + zm), 1u);
                     if (ym && zm) atomicAdd(reinterpret_cast<uint32_t*>(hb + ak + ym + zm), 1u);
-                }
-                ops += (xdup ? 5u : 4u) * ((ym ? 1u : 0u) + (zm ? 1u : 0u) + (ym && zm ? 1u : 0u));
+                };
+#pragma unroll
+                for (int k = 0; k < WB; ++k) mirror(__builtin_amdgcn_ubfe(k < 4 ? lo : hi, 8 * (k & 3), 8), rx[k], ax[k]);
+                if (xdup) mirror(__builtin_amdgcn_ubfe(kxhi ? hi : lo, kxs, 8), rxd, region_bytes);
+                ops += (xdup ? WB + 1u : (unsigned)WB) * ((ym ? 1u : 0u) + (zm ? 1u : 0u) + (ym && zm ? 1u : 0u));
             }
-            ops += xdup ? 5u : 4u;
+            ops += xdup ? WB + 1u : (unsigned)WB;
         },
         []() {});
     return ops;
