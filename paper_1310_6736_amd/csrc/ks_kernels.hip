@@ -1149,17 +1149,18 @@ __global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vo
 // row = max(max(|x-cx|,|y-cy|,|z-cz|) - base, 0); bytes outside the box go to
 // row trash_row.
 template <int NT>
-__device__ __forceinline__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb, int cx,
-                                       int cy, int cz, int base, int trash_row, int rq, uint32_t region,
-                                       uint32_t* hist, int tid) {
+__device__ __forceinline__ unsigned int bucket_scatter(const VolDesc& v, int xa, int xb, int ya, int yb, int za, int zb,
+                                                       int cx, int cy, int cz, int base, int trash_row, int rq,
+                                                       uint32_t region, uint32_t* hist, int tid) {
+    constexpr int WB = kQuadWB;  // voxels per lane and step
     const Layout L = layout_x(v);
-    const Sweep w = make_sweep<NT>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, tid);
+    const Sweep w = make_sweep<NT, WB>(L, xa, xb, ya, yb - ya + 1, 1, za, zb - za + 1, 1, tid);
     const uint32_t rowbytes = (uint32_t)row_stride(v.B) << (rq + 2);
     const uint32_t rep4 = ((uint32_t)(tid & ((1 << rq) - 1)) << 2) + region;
     const uint32_t bshift = (uint32_t)rq + 2;
-    uint32_t rx[4];
+    uint32_t rx[WB];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < WB; ++k) {
         const int x = w.x0 + k;
         const bool ok = x >= xa && x <= xb;
         const int r = ok ? max(abs(x - cx) - base, 0) : trash_row;
@@ -1168,18 +1169,19 @@ __device__ __forceinline__ unsigned int bucket_scatter(const VolDesc& v, int xa,
     const int dy0 = ya + w.oy - cy, dz0 = za + w.oz - cz;
     int used = 0;
     unsigned int ops = 0;
-    run_sweep<kQuadUnroll, kQuadDepth>(
+    run_sweep<kQuadUnroll, kQuadDepth, WB>(
         L, w, 0, 0, used, INT_MAX,
-        [&](uint32_t word, int iy0, int iz0, uint64_t) {
+        [&](typename LaneWord<WB>::T word, int iy0, int iz0, uint64_t) {
+            const uint32_t lo = (uint32_t)word, hi = (uint32_t)((uint64_t)word >> 32);
             const int rr = max(max(abs(dy0 + iy0), abs(dz0 + iz0)) - base, 0);
             const uint32_t RR = (uint32_t)rr * rowbytes + rep4;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t b = (word >> (8 * k)) & 0xFFu;
+            for (int k = 0; k < WB; ++k) {
+                const uint32_t b = __builtin_amdgcn_ubfe(k < 4 ? lo : hi, 8 * (k & 3), 8);
                 const uint32_t addr = max(rx[k], RR) + (b << bshift);
                 atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(hist) + addr), 1u);
             }
-            ops += 4;
+            ops += WB;
         },
         []() {});
     return ops;
