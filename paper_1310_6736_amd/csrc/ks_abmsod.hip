@@ -124,13 +124,49 @@ __device__ __forceinline__ unsigned abm_sweep(const VolDesc& v, const double x[3
     const double ey = sqrt(5.0 * h[1]), ez = sqrt(5.0 * h22);
     const int ylo = clampi((int)ceil(x[1] - ey) - 1, 0, v.Y - 1), yhi = clampi((int)floor(x[1] + ey) + 1, 0, v.Y - 1);
     const int zlo = clampi((int)ceil(x[2] - ez) - 1, 0, v.Z - 1), zhi = clampi((int)floor(x[2] + ez) + 1, 0, v.Z - 1);
-    const int ny = yhi - ylo + 1, nrow = ny * (zhi - zlo + 1);
     const double k0 = h[4] / h22, k1 = h[5] / h22;
     const double c00 = h[0] - h[4] * k0, c11 = h[1] - h[5] * k1, c01 = h[3] - h[4] * k1;
     const double qy = c01 / c11, c00r = c00 - c01 * qy;
-    for (int row = lane; row < nrow; row += 64) {
-        const int zr = row / ny;
-        const int vz = zlo + zr, vy = ylo + (row - zr * ny);
+    // The rows that can touch the ellipse, slice by slice: at z the row y meets it
+    // when (y - x_y - c k1)^2 <= c11 (5 - c^2 / H_zz + 1), the bound of the exact
+    // test below; the range is widened by a row at each end so that rounding
+    // cannot drop a row the test would take.  Lane l of the wave takes slice
+    // z0 + l; the slices' rows are laid end to end and dealt to the lanes, so
+    // that no lane idles on a row outside the ellipse.
+    for (int z0 = zlo; z0 <= zhi; z0 += 64) {
+        int ya = 0, cnt = 0;
+        if (z0 + lane <= zhi) {
+            const double c = (z0 + lane) - x[2];
+            const double rr1 = 5.0 - c * c / h22 + 1.0;
+            if (rr1 >= 0.0) {
+                const double yc = x[1] + c * k1, half = sqrt(c11 * rr1);
+                ya = max((int)ceil(yc - half) - 1, ylo);
+                const int yb = min((int)floor(yc + half) + 1, yhi);
+                cnt = max(yb - ya + 1, 0);
+            }
+        }
+        int pre = cnt;  // inclusive prefix over the lanes' slices
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(pre, o, 64);
+            if (lane >= o) pre += t;
+        }
+        const int total = __shfl(pre, 63, 64);
+        for (int row0 = 0; row0 < total; row0 += 64) {
+            // the slice of this row: the number of slices whose prefix is <= row
+            // (the lane shuffles run with every lane active; rows past the end
+            // are dropped after them)
+            const int row = row0 + lane;
+            int l = 0;
+#pragma unroll
+            for (int b = 32; b >= 1; b >>= 1) {
+                const int pl = __shfl(pre, l + b - 1, 64);
+                l += pl <= row ? b : 0;
+            }
+            const int before = __shfl(pre, l > 0 ? l - 1 : 0, 64);
+            const int yl = __shfl(ya, l, 64);
+            if (row >= total) continue;
+            const int vz = z0 + l, vy = yl + (row - (l > 0 ? before : 0));
         const double c = vz - x[2];
         const double rr = 5.0 - c * c / h22;
         const double t = vy - (x[1] + c * k1);
@@ -148,6 +184,7 @@ __device__ __forceinline__ unsigned abm_sweep(const VolDesc& v, const double x[3
                 if (vx < xa || vx > xb) continue;
                 abm_voxel<KIND>(v, vx, vy, vz, (word >> (8 * k)) & 0xFFu, x, inv, hist, wtab, acc, visits);
             }
+        }
         }
     }
     return visits;
