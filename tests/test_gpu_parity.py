@@ -783,6 +783,23 @@ def test_abmsod_pet_sampled(torch_dev, ctx):
     compare_ellipsoids(got[ids], want, w.name)
 
 
+def test_abmsod_largest_radii_matches_oracle(torch_dev, ctx):
+    """Start radii up to 32, the largest allowed: a start window spans 68 slices,
+    more than a wavefront's lanes, so a sweep deals its rows in two slice chunks."""
+    v = random_volume(64, (72, 40, 44), np.uint8, 0, 255)
+    v[20:52, 8:32, 10:34] //= 3          # a darker block: an uneven pmf
+    Z, Y, X = v.shape
+    seeds = np.array([(22, 20, 36), (5, 30, 60), (40, 2, 10)], np.int32)
+    note("abmsod radii 30..32 on 44x40x72, seed list")
+    ks.ks_context_set_seeds(ctx, seeds)
+    try:
+        got = ks.ks_abmsod(ctx, dev(torch_dev, v), 16, 3, (30, 32), 4)
+    finally:
+        ks.ks_context_set_seeds(ctx, None)
+    want, _ = oracle.abmsod(v, 16, 3, (30, 32), 4, seeds=seeds)
+    compare_ellipsoids(got, want, "radii 30..32")
+
+
 def test_abmsod_validation(torch_dev, ctx):
     v = dev(torch_dev, random_volume(63, (8, 9, 10), np.uint8, 0, 255))
     for radii, it, thr in (((0, 3), 5, 0.0), ((4, 3), 5, 0.0), ((1, 33), 5, 0.0), ((1, 3), -1, 0.0),
