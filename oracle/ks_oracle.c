@@ -69,7 +69,8 @@ static double pairwise(const double* v, int32_t n, int32_t lo, int32_t len) {
 }
 
 /* Alternative readings, for tests that check that the choice does not change
- * the results: sums over bins in ascending bin order, and H64 = ln N - S/N. */
+ * the results: sums over bins (and over the 8 octants) in ascending order, and
+ * H64 = ln N - S/N. */
 static int g_sequential_sums = 0, g_ln_n_form = 0;
 
 void kso_set_readings(int sequential_sums, int ln_n_form) {
@@ -85,6 +86,11 @@ void kso_set_abm_readings(int convergence_stop, int bandwidth_cap) {
     g_abm_bandwidth_cap = bandwidth_cap != 0;
 }
 
+static double sum_octants(const double* e) {
+    if (g_sequential_sums) return ((((((e[0] + e[1]) + e[2]) + e[3]) + e[4]) + e[5]) + e[6]) + e[7];
+    return ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
+}
+
 static double sum_bins(const double* v, int32_t bins) {
     if (g_sequential_sums) {
         double s = 0.0;
@@ -94,7 +100,6 @@ static double sum_bins(const double* v, int32_t bins) {
     return pairwise(v, bins, 0, padded_terms(bins));
 }
 
-static double sum_octants(const double* e) { return ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7])); }
 
 /* ---------------------------------------------------------------- binning */
 

@@ -61,9 +61,9 @@ int kso_bin_volume_window(const void* vol, int32_t dtype, const int32_t dims[3],
 
 /* Entropies of one count vector: decision precision (H64) and accurate (Href). */
 /* Alternative readings of points the paper leaves open, for tests that check
- * that the choice does not change the results (default 0, 0): sums over bins in
- * ascending bin order instead of the pairwise tree, and H64 = ln N - S/N instead
- * of (N ln N - S)/N.  Process-wide; not thread-safe. */
+ * that the choice does not change the results (default 0, 0): sums over bins and
+ * over the 8 octants in ascending order instead of the pairwise trees, and
+ * H64 = ln N - S/N instead of (N ln N - S)/N.  Process-wide; not thread-safe. */
 void kso_set_readings(int sequential_sums, int ln_n_form);
 
 /* The two additions to Alg. 2 that the ABMSOD search makes (default 1, 1): the

@@ -902,8 +902,9 @@ _READING_SAMPLES = [("spheres", lambda: synth.spheres_64(), 1), ("pet_quadrant",
 
 @pytest.mark.parametrize("name,make,step", _READING_SAMPLES, ids=[s[0] for s in _READING_SAMPLES])
 def test_summation_order_does_not_change_the_results(name, make, step):
-    """Reading R26 (the paper fixes no order for the sums over bins; the oracle
-    takes a pairwise tree): with the sums in ascending bin order instead, every
+    """Reading R26 (the paper fixes no order for the sums over bins or over the
+    8 octants; the oracle takes pairwise trees): with both sums in ascending
+    order instead, every
     trajectory of a sample of each workload ends at the same position after the
     same iterations with the same stop reason, scale and kept flag, and the
     objectives differ by a few ulps only."""
