@@ -184,6 +184,24 @@ struct Sweep {
     uint32_t voff;      // byte offset of the lane's dword at the first step
 };
 
+// The lane part of a sweep whose uniform fields (ny, nz, nd, ty, tz, pr, ps) are
+// set: the lane's tile position, limits and first offset.  da is the box's first
+// dword (or qword) of the fast axis, ra and sa its first row and slice.
+template <int WB = 4>
+__device__ __forceinline__ void sweep_lane(const Layout& L, Sweep& w, int da, int ra, int sa, int tid) {
+    const int per_z = w.ty * w.nd;
+    w.oz = small_div(tid, per_z);
+    const int rem = tid - w.oz * per_z;
+    w.oy = small_div(rem, w.nd);
+    const int d = rem - w.oy * w.nd;
+    w.x0 = (da + d) * WB;
+    const bool on = tid < w.tz * per_z;
+    w.lim_y = on ? w.ny - w.oy : -1;
+    w.lim_z = w.nz - w.oz;
+    w.voff = (uint32_t)sa * L.slab + (uint32_t)ra * L.pitch + (uint32_t)w.oz * w.ps + (uint32_t)w.oy * w.pr +
+             (uint32_t)w.x0;
+}
+
 template <int NT, int WB = 4>
 __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int ra, int nr, int rstep, int sa,
                                             int ns, int sstep, int tid) {
@@ -217,17 +235,7 @@ __device__ __forceinline__ Sweep make_sweep(const Layout& L, int fa, int fb, int
         w.ty = uniform(w.ty);
         w.tz = uniform(w.tz);
     }
-    const int per_z = w.ty * w.nd;
-    w.oz = small_div(tid, per_z);
-    const int rem = tid - w.oz * per_z;
-    w.oy = small_div(rem, w.nd);
-    const int d = rem - w.oy * w.nd;
-    w.x0 = (da + d) * WB;
-    const bool on = tid < w.tz * per_z;
-    w.lim_y = on ? w.ny - w.oy : -1;
-    w.lim_z = w.nz - w.oz;
-    w.voff = (uint32_t)sa * L.slab + (uint32_t)ra * L.pitch + (uint32_t)w.oz * w.ps + (uint32_t)w.oy * w.pr +
-             (uint32_t)w.x0;
+    sweep_lane<WB>(L, w, da, ra, sa, tid);
     return w;
 }
 
@@ -718,37 +726,58 @@ __device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet 
     int used = 0;
     unsigned long long ops = 0;   // LDS atomic operations of all lanes (uniform)
     const int nb = box_count(bs);
-#pragma unroll 1
-    for (int i0 = 0; i0 < nb; ++i0) {
-        // an index the compiler cannot see through: each box's geometry is
-        // computed where it is swept instead of all six up front (which would
-        // not fit the scalar registers)
-        int i = uniform(i0);
-        asm volatile("" : "+s"(i));
+    // Lane i < nb works out box i of the set and its tiling, all boxes at once in
+    // vector registers; the loop reads box i's figures from lane i.  (Box by box
+    // in scalar registers, the geometry of a small box cost more scalar
+    // instructions than its sweep.)
+    const int bi = lane < nb ? lane : 0;
+    int bsg;
+    const Box b = box_at(v, bs, bi, bsg);
+    bool has = lane < nb && b.xa <= b.xb && b.ya <= b.yb && b.za <= b.zb;
+    if (mv) {
         // a move box lies outside the other window along axis i % 3: none if the
         // move has no component along it
-        if (mv) {
-            const int a = i >= 3 ? i - 3 : i;
-            if ((a == 0 ? bs.qx - bs.px : a == 1 ? bs.qy - bs.py : bs.qz - bs.pz) == 0) continue;
-        }
-        int sg;
-        const Box b = box_at(v, bs, i, sg);
-        const int xa = uniform(b.xa), xb = uniform(b.xb), ya = uniform(b.ya), yb = uniform(b.yb);
-        const int za = uniform(b.za), zb = uniform(b.zb);
-        const int xs = uniform(b.xs), ys = uniform(b.ys), zs = uniform(b.zs);
-        sg = uniform(sg);
-        if (xa > xb || ya > yb || za > zb) continue;
-        // sweep along y (the y-fast copy) when x is strided or the box is thinner
-        // in x than in y; the fast axis is never strided
-        const bool tr = xs != 1 || (ys == 1 && xb - xa < yb - ya);
+        const int a = bi >= 3 ? bi - 3 : bi;
+        has = has && (a == 0 ? bs.qx - bs.px : a == 1 ? bs.qy - bs.py : bs.qz - bs.pz) != 0;
+    }
+    // sweep along y (the y-fast copy) when x is strided or the box is thinner in
+    // x than in y; the fast axis is never strided.  Axes (fast, row, slice):
+    // (x, y, z), or (y, z, x) on the y-fast copy.
+    const bool btr = b.xs != 1 || (b.ys == 1 && b.xb - b.xa < b.yb - b.ya);
+    const int bfa = btr ? b.ya : b.xa, bfb = btr ? b.yb : b.xb;
+    const int bra = btr ? b.za : b.ya, brs = btr ? b.zs : b.ys;
+    const int bsa = btr ? b.xa : b.za, bss = btr ? b.xs : b.zs;
+    const int bnr = small_div((btr ? b.zb : b.yb) - bra, brs) + 1;
+    const int bns = small_div((btr ? b.xb : b.zb) - bsa, bss) + 1;
+    // the tile of make_sweep<64>: as many rows as 64 lanes hold, then slices
+    const int bnd = (bfb >> 2) - (bfa >> 2) + 1;
+    const int brmax = small_div(64, bnd);
+    const int bty = min(bnr, brmax);
+    const int btz = min(bns, small_div(brmax, bty));
+    // signs and strides (a stride is 1 or 2s) in one word: fewer reads per box
+    const int bflags = (btr ? 1 : 0) | (bsg < 0 ? 2 : 0) | (brs << 2) | (bss << 10);
+    unsigned long long todo = __ballot(has);
+#pragma unroll 1
+    while (todo) {
+        const int i = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        auto pick = [i](int x) { return __builtin_amdgcn_readlane(x, i); };
+        const int flags = pick(bflags);
+        const bool tr = (flags & 1) != 0;
+        const int sg = (flags & 2) ? -1 : 1;
+        const int rst = (flags >> 2) & 0xFF, sst = flags >> 10;
+        const int fa = pick(bfa), fb = pick(bfb), ra = pick(bra), sa = pick(bsa);
         const Layout L = tr ? layout_t(v) : layout_x(v);
-        const int ny = uniform(small_div(yb - ya, ys)) + 1, nz = uniform(small_div(zb - za, zs)) + 1;
-        const int nx = uniform(small_div(xb - xa, xs)) + 1;
-        const Sweep w = tr ? make_sweep<64>(L, ya, yb, za, nz, zs, xa, nx, xs, lane)
-                           : make_sweep<64>(L, xa, xb, ya, ny, ys, za, nz, zs, lane);
+        Sweep w;
+        w.ny = pick(bnr);
+        w.nz = pick(bns);
+        w.nd = pick(bnd);
+        w.ty = pick(bty);
+        w.tz = pick(btz);
+        w.pr = L.pitch * (uint32_t)rst;
+        w.ps = L.slab * (uint32_t)sst;
+        sweep_lane<4>(L, w, fa >> 2, ra, sa, lane);
         // axes (fast, row, slice) -> packed fields: x at bit 10, y at 32, z at 48
-        const int fa = tr ? ya : xa, fb = tr ? yb : xb, ra = tr ? za : ya, sa = tr ? xa : za;
-        const int rst = tr ? zs : ys, sst = tr ? xs : zs;
         const int fr = tr ? ry : rx, rr = tr ? rz : ry, sr = tr ? rx : rz;
         const long long mf = tr ? (1ll << 32) : (1ll << 10);
         const long long mr = (tr ? (1ll << 48) : (1ll << 32)) * rst;
