@@ -756,6 +756,7 @@ __device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet 
     const int btz = min(bns, small_div(brmax, bty));
     // signs and strides (a stride is 1 or 2s) in one word: fewer reads per box
     const int bflags = (btr ? 1 : 0) | (bsg < 0 ? 2 : 0) | (brs << 2) | (bss << 10);
+    const Layout Lx = layout_x(v), Lt = layout_t(v);
     unsigned long long todo = __ballot(has);
 #pragma unroll 1
     while (todo) {
@@ -767,7 +768,7 @@ __device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet 
         const int sg = (flags & 2) ? -1 : 1;
         const int rst = (flags >> 2) & 0xFF, sst = flags >> 10;
         const int fa = pick(bfa), fb = pick(bfb), ra = pick(bra), sa = pick(bsa);
-        const Layout L = tr ? layout_t(v) : layout_x(v);
+        const Layout L = tr ? Lt : Lx;
         Sweep w;
         w.ny = pick(bnr);
         w.nz = pick(bns);
@@ -779,23 +780,30 @@ __device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet 
         sweep_lane<4>(L, w, fa >> 2, ra, sa, lane);
         // axes (fast, row, slice) -> packed fields: x at bit 10, y at 32, z at 48
         const int fr = tr ? ry : rx, rr = tr ? rz : ry, sr = tr ? rx : rz;
-        const long long mf = tr ? (1ll << 32) : (1ll << 10);
-        const long long mr = (tr ? (1ll << 48) : (1ll << 32)) * rst;
-        const long long ms = (tr ? (1ll << 10) : (1ll << 48)) * sst;
-        const long long lanepart = (long long)(ra - rr + s) * (tr ? (1ll << 48) : (1ll << 32)) + (long long)w.oy * mr +
-                                   (long long)(sa - sr + s) * (tr ? (1ll << 10) : (1ll << 48)) + (long long)w.oz * ms;
+        const int shf = tr ? 32 : 10, shr = tr ? 48 : 32, shs = tr ? 10 : 48;
+        // the box's sign applied to a packed value (two's complement: -x = ~x + 1)
+        const unsigned long long neg = sg < 0 ? ~0ull : 0ull;
+        auto signed_ = [neg](unsigned long long x) { return (x ^ neg) - neg; };
+        // the lane's first voxel: a count of 1 and its offsets d + s from the
+        // reference point along the fast, row and slice axes (negative offsets
+        // wrap, as their sums do)
+        auto field = [](int d, int sh) { return (unsigned long long)(long long)d << sh; };
+        const unsigned long long cp0 =
+            signed_(1ull + field(w.x0 - fr + s, shf) + field(ra + w.oy * rst - rr + s, shr) +
+                    field(sa + w.oz * sst - sr + s, shs));
+        const unsigned long long cdf = signed_(1ull << shf);
         unsigned long long cp[4];
         uint32_t off[4], wid[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int f = w.x0 + k;
             const bool ok = f >= fa && f <= fb;
-            cp[k] = (unsigned long long)((long long)sg * (1ll + (long long)(f - fr + s) * mf + lanepart));
+            cp[k] = k == 0 ? cp0 : cp[k - 1] + cdf;
             off[k] = ok ? repoff : trash;
             wid[k] = ok ? 8u : 0u;
         }
-        const unsigned long long smr = (unsigned long long)((long long)sg * mr);
-        const unsigned long long sms = (unsigned long long)((long long)sg * ms);
+        const unsigned long long smr = signed_(field(rst, shr));
+        const unsigned long long sms = signed_(field(sst, shs));
         // every (row, dword) of the box is scattered once, four adds each
         ops += 4ull * (unsigned)(w.nd * w.ny * w.nz);
         run_sweep<kMsUnroll, kMsDepth>(
