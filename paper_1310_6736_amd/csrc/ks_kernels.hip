@@ -350,6 +350,75 @@ __device__ __forceinline__ void run_sweep(const Layout& L, const Sweep& w, uint6
     }
 }
 
+// run_sweep for a box whose tiles form one line: all its rows fit in one tile
+// (ty == ny: the tile steps through the slices) or it has one slice (nz == 1: the
+// tile steps through the rows).  One counter and one offset advance per step, with
+// no wrap from rows to slices; same calls of f and flush as run_sweep.
+template <int U, int D, int WB = 4, typename F, typename G>
+__device__ __forceinline__ void run_sweep_line(const Layout& L, const Sweep& w, uint64_t ay, uint64_t az, int& used,
+                                               int limit, F&& f, G&& flush) {
+    using Word = typename LaneWord<WB>::T;
+    const __amdgpu_buffer_rsrc_t rs = layout_rsrc(L);
+    const int ny = uniform(w.ny), nz = uniform(w.nz), ty = uniform(w.ty), tz = uniform(w.tz);
+    const bool rows = ty < ny;   // then nz == 1
+    const int n = rows ? ny : nz, t = rows ? ty : tz;
+    const uint32_t dd = rows ? (uint32_t)ty * (uint32_t)uniform((int)w.pr) : (uint32_t)tz * (uint32_t)uniform((int)w.ps);
+    const uint64_t dacc = rows ? (uint64_t)(uint32_t)ty * ay : (uint64_t)(uint32_t)tz * az;
+    // rows (or slices) of the line from the lane's tile position on; -1: lane unused
+    const int lim = w.lim_y < 0 ? -1 : (rows ? w.lim_y : w.lim_z);
+    constexpr int kGroupVoxels = U * WB;
+    int i0 = 0;   // the step about to be loaded
+    uint32_t off = 0;
+    uint64_t acc = 0;
+    Word buf[D][U];
+    int bi[D][U];
+    uint64_t bacc[D][U];
+    auto load = [&](int g, int u) {
+        bi[g][u] = i0;
+        bacc[g][u] = acc;
+        buf[g][u] = LaneWord<WB>::load(rs, w.voff, i0 < n ? off : kPastEnd);
+        i0 += t;
+        off += dd;
+        acc += dacc;
+    };
+#pragma unroll
+    for (int g = 0; g < D; ++g) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) load(g, u);
+    }
+    bool live = true;
+    while (live) {
+#pragma unroll
+        for (int g = 0; g < D; ++g) {
+            live = live && bi[g][0] < n;
+            if (live) {
+                if (used + kGroupVoxels > limit) {
+                    used = 0;
+                    flush();
+                }
+                // the group's last tile inside the line: all of them are
+                if (bi[g][U - 1] + t <= n) {
+                    if (lim >= 0) {
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            f(buf[g][u], rows ? bi[g][u] : 0, rows ? 0 : bi[g][u], bacc[g][u]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (bi[g][u] < lim) f(buf[g][u], rows ? bi[g][u] : 0, rows ? 0 : bi[g][u], bacc[g][u]);
+                    }
+                }
+                used += kGroupVoxels;
+            }
+            if (D > 1 || live) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) load(g, u);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ prep
 
 __global__ void k_prep_init(VolDesc* vols, int nvol, Counters* cnt, int* vol_nfound, int* vol_base) {
@@ -806,16 +875,18 @@ __device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet 
         const unsigned long long sms = signed_(field(sst, shs));
         // every (row, dword) of the box is scattered once, four adds each
         ops += 4ull * (unsigned)(w.nd * w.ny * w.nz);
-        run_sweep<kMsUnroll, kMsDepth>(
-            L, w, smr, sms, used, limit,
-            [&](uint32_t word, int, int, uint64_t step) {
+        auto scatter = [&](uint32_t word, int, int, uint64_t step) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t bin = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
-                    atomicAdd(reinterpret_cast<unsigned long long*>(hb + (bin << shift) + off[k]), cp[k] + step);
-                }
-            },
-            flush);
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t bin = __builtin_amdgcn_ubfe(word, 8 * k, wid[k]);
+                atomicAdd(reinterpret_cast<unsigned long long*>(hb + (bin << shift) + off[k]), cp[k] + step);
+            }
+        };
+        // a move box one voxel thick (the usual case) is a line of tiles
+        if (w.ty >= w.ny || w.nz == 1)
+            run_sweep_line<kMsUnroll, kMsDepth>(L, w, smr, sms, used, limit, scatter, flush);
+        else
+            run_sweep<kMsUnroll, kMsDepth>(L, w, smr, sms, used, limit, scatter, flush);
     }
     if (used > 0) flush();
     return ops;
@@ -1005,9 +1076,10 @@ __device__ __forceinline__ void write_rec(TrajRec* dst, const int* p0, const Tra
 // evaluation: the whole window first, later the difference regions when they
 // are the smaller sweep), and the final pass reuses the counts of the window at
 // P*.  Every sweep of the kernel goes through the one ms_sweep call below, so
-// the scatter code is instantiated once.
+// the scatter code is instantiated once per tile walk (line and general).
+// Up to 64 bins (one per lane) the kernel is held to 128 VGPRs: four waves per SIMD.
 template <int M, bool GROUPED>
-__global__ __launch_bounds__(64) void k_search_ms(const VolDesc* __restrict__ vols,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(M == 1 ? 4 : 1))) void k_search_ms(const VolDesc* __restrict__ vols,
                                                   const TaskSeg* __restrict__ segs, int nseg,
                                                   const XcdQueues* __restrict__ xq, int chunk, Tables tb,
                                                   TrajRec* out,
