@@ -40,9 +40,13 @@ namespace ks {
 
 // Sweep pipelines: rows per group of loads, groups of loads in flight (measured:
 // the mean-shift sweeps, many of them a few rows long, run best with a short
-// pipeline; the quadrant brick sweep with narrow groups).
+// pipeline; the quadrant brick sweep with narrow groups).  The mean-shift line
+// walk, with less loop control per step, runs best with groups of three.
 #ifndef KS_MS_UNROLL
 #define KS_MS_UNROLL 2
+#endif
+#ifndef KS_MS_LINE_UNROLL
+#define KS_MS_LINE_UNROLL 3
 #endif
 #ifndef KS_MS_DEPTH
 #define KS_MS_DEPTH 1
@@ -59,7 +63,7 @@ namespace ks {
 #ifndef KS_QUAD_THREADS
 #define KS_QUAD_THREADS 256
 #endif
-constexpr int kMsUnroll = KS_MS_UNROLL, kMsDepth = KS_MS_DEPTH;
+constexpr int kMsUnroll = KS_MS_UNROLL, kMsDepth = KS_MS_DEPTH, kMsLineUnroll = KS_MS_LINE_UNROLL;
 constexpr int kQuadUnroll = KS_QUAD_UNROLL, kQuadDepth = KS_QUAD_DEPTH;
 constexpr int kQuadWB = KS_QUAD_WB;  // bytes (voxels) per lane and step of the octant scatter
 // Load offset past the end of every bin volume (volumes stay below 2^31 bytes):
@@ -884,7 +888,7 @@ __device__ __forceinline__ unsigned long long ms_sweep(const VolDesc& v, BoxSet 
         };
         // a move box one voxel thick (the usual case) is a line of tiles
         if (w.ty >= w.ny || w.nz == 1)
-            run_sweep_line<kMsUnroll, kMsDepth>(L, w, smr, sms, used, limit, scatter, flush);
+            run_sweep_line<kMsLineUnroll, kMsDepth>(L, w, smr, sms, used, limit, scatter, flush);
         else
             run_sweep<kMsUnroll, kMsDepth>(L, w, smr, sms, used, limit, scatter, flush);
     }
