@@ -710,8 +710,10 @@ def test_batch_with_seed_lists(torch_dev, ctx):
 
 def compare_ellipsoids(got, want, label, atol=1e-8):
     """Starts, radii, iterations and stop reasons equal; centres (voxels),
-    bandwidths (voxel^2), coefficients and entropies within atol (the GPU sums
-    the Gaussian profile in 2^-40 fixed point, the oracle in double)."""
+    bandwidths (voxel^2), coefficients and entropies within atol (the GPU takes
+    the Gaussian profile along each row by a recurrence anchored on exact exps
+    and sums it in 2^-40 fixed point; the oracle takes exp per voxel and sums in
+    double)."""
     assert len(got) == len(want), label
     for f in ("x0", "y0", "z0", "radius", "iters", "stop"):
         bad = np.nonzero(got[f] != want[f])[0]
